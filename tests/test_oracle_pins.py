@@ -1,0 +1,375 @@
+"""Pins of the CPU oracle against what the paper and the mathematics fix (no GPU, no HIP library).
+
+Each test names the passage or the mathematical fact it rests on. Together they are chosen so that a
+plausible slip in the oracle (a dropped term, a wrong sign, a wrong divisor, a skipped index, a transposed
+operand, a wrong loop count) fails at least one of them; tests/test_oracle_mutants.py checks that claim by
+planting such slips in a copy of the oracle.
+"""
+from __future__ import annotations
+
+import math
+import os
+from fractions import Fraction
+
+import mpmath
+import numpy as np
+import pytest
+import scipy.linalg
+
+import workloads
+from conftest import GOLDEN
+
+mpmath.mp.dps = 50
+
+
+# ---------------------------------------------------------------------------------------------- helpers
+def closed_form(n: int, m: int, k: int):
+    """Boyer-Brassard-Hoyer-Tapp closed form of Grover's amplitudes after k iterations from the uniform state:
+    each marked amplitude sin((2k+1) theta)/sqrt(M), each unmarked cos((2k+1) theta)/sqrt(N-M),
+    theta = arcsin sqrt(M/N); evaluated at 50 digits."""
+    N = mpmath.mpf(2) ** n
+    theta = mpmath.asin(mpmath.sqrt(mpmath.mpf(m) / N))
+    a = mpmath.sin((2 * k + 1) * theta) / mpmath.sqrt(m) if m > 0 else mpmath.mpf(0)
+    b = mpmath.cos((2 * k + 1) * theta) / mpmath.sqrt(N - m) if m < N else mpmath.mpf(0)
+    return float(a), float(b)
+
+
+def dense_diffusion(n: int) -> np.ndarray:
+    """Eq. 2 written out: Delta_ii = 2/N - 1, Delta_ij = 2/N for i != j."""
+    N = 1 << n
+    return np.full((N, N), 2.0 / N) - np.eye(N)
+
+
+def dense_oracle(n: int, marks) -> np.ndarray:
+    """The phase oracle of the Background section as a matrix: diag((-1)^f(x))."""
+    s = np.ones(1 << n)
+    s[np.asarray(marks, dtype=np.int64)] = -1.0
+    return np.diag(s)
+
+
+def sylvester_hadamard(n: int) -> np.ndarray:
+    """H^(x)n = Walsh-Hadamard matrix / sqrt(N) (scipy's Sylvester construction)."""
+    return scipy.linalg.hadamard(1 << n).astype(np.float64) / math.sqrt(1 << n)
+
+
+def read_fig2():
+    rows = []
+    with open(os.path.join(GOLDEN, "fig2_three_qubit.txt")) as f:
+        for line in f:
+            if line.strip() and not line.startswith("#"):
+                state, pct = line.split()
+                rows.append((int(state, 2), float(pct)))
+    return dict(rows)
+
+
+# ------------------------------------------------------------------------------------- worked example
+def test_fig2_worked_example(orc):
+    """Fig. 2: 3 qubits, solution |101>, after the algorithm's iterations the measured probabilities are
+    94.531 % for |101> and 0.781 % for each other state (printed to 3 decimals)."""
+    printed = read_fig2()
+    k = orc.optimal_iterations(3, 1)
+    psi = orc.search(3, [5], k)
+    p = np.abs(psi) ** 2 * 100.0
+    for i in range(8):
+        assert round(p[i], 3) == pytest.approx(printed[i], abs=1e-9), (i, p[i], printed[i])
+    # exact values behind the printed ones: 121/128 and 1/128
+    assert abs(p[5] / 100 - 121 / 128) < 1e-15
+    assert np.all(np.abs(np.delete(p, 5) / 100 - 1 / 128) < 1e-15)
+
+
+def test_fig2_pins_iteration_count(orc):
+    """Fig. 2 fixes floor(pi/4 sqrt(N)) = 2 iterations at N = 8; running the printed loop bound literally
+    (iter < pi sqrt(N)/4, i.e. 3 passes) would give 169/512 = 33 %, not the printed 94.531 %."""
+    assert orc.optimal_iterations(3, 1) == 2
+    psi3 = orc.search(3, [5], 3)
+    assert abs(abs(psi3[5]) ** 2 - 169 / 512) < 1e-15
+    assert round(abs(psi3[5]) ** 2 * 100, 3) != read_fig2()[5]
+
+
+def test_iteration_counts_of_the_workloads(orc):
+    """floor(pi/4 sqrt(N/M)) at the workload sizes; none lies within 1e-3 of an integer, so binary64 floor is
+    safe (checked here at 50 digits)."""
+    for n, m, k in [(3, 1, 2), (10, 1, 25), (28, 8, 4549), (26, 4, 3216), (20, 1, 804), (20, 3, 464)]:
+        exact = mpmath.pi / 4 * mpmath.sqrt(mpmath.mpf(2) ** n / m)
+        assert int(mpmath.floor(exact)) == k
+        assert orc.optimal_iterations(n, m) == k
+    assert orc.optimal_iterations(10, 0) == 0
+    assert workloads.PLAIN_N10.iterations == orc.optimal_iterations(10, 1)
+    assert workloads.HASH_N28.iterations == orc.optimal_iterations(28, 8)
+
+
+# ---------------------------------------------------------------------------------------- closed form
+@pytest.mark.parametrize("n,m", [(4, 1), (5, 2), (6, 3), (8, 1), (9, 5), (10, 1), (11, 7), (12, 4)])
+def test_closed_form(orc, n, m):
+    """Grover's closed form sin((2k+1)theta)/sqrt(M) (marked) and cos((2k+1)theta)/sqrt(N-M) (unmarked),
+    for every k up to twice the optimal count (past the peak as well)."""
+    marks = workloads.distinct_marks(n, m, seed=1000 * n + m)
+    mask = np.zeros(1 << n, dtype=bool)
+    mask[marks.astype(np.int64)] = True
+    kopt = orc.optimal_iterations(n, m)
+    psi = orc.init_uniform(n)
+    for k in range(0, 2 * kopt + 2):
+        a, b = closed_form(n, m, k)
+        assert np.max(np.abs(psi[mask] - a)) < 1e-13, k
+        assert np.max(np.abs(psi[~mask] - b)) < 1e-13, k
+        assert np.all(psi.imag == 0.0)
+        orc.iterate(psi, marks, 1)
+
+
+@pytest.mark.parametrize("n,m,k", [(20, 1, 804), (20, 3, 464), (26, 4, 3216), (28, 8, 4549), (16, 1, 201)])
+def test_two_class_closed_form_large(orc, n, m, k):
+    """The oracle's two-class form against the closed form at the paper's and the workloads' sizes."""
+    a, b = orc.two_class(n, m, k)
+    ea, eb = closed_form(n, m, k)
+    assert abs(a - ea) < 1e-12 and abs(b - eb) < 1e-12
+
+
+@pytest.mark.parametrize("n,m", [(3, 1), (6, 2), (9, 3), (12, 8)])
+def test_two_class_equals_full_state(orc, n, m):
+    """The two-class form is the full iteration restricted to a two-valued state."""
+    marks = workloads.distinct_marks(n, m, seed=n * 31 + m)
+    mask = np.zeros(1 << n, dtype=bool)
+    mask[marks.astype(np.int64)] = True
+    k = orc.optimal_iterations(n, m) + 3
+    psi = orc.search(n, marks, k)
+    a, b = orc.two_class(n, m, k)
+    assert np.max(np.abs(psi[mask] - a)) < 1e-14
+    assert np.max(np.abs(psi[~mask] - b)) < 1e-14
+
+
+# ------------------------------------------------------------------------------ dense definition (Eq. 2)
+@pytest.mark.parametrize("n,m,k", [(1, 1, 3), (2, 1, 2), (3, 2, 4), (5, 3, 7), (6, 1, 9), (7, 5, 4)])
+def test_dense_eq2_on_general_states(orc, n, m, k):
+    """Eq. 2 (Delta = 2J/N - I) times the oracle, as explicit matrices, applied k times to a random complex
+    state: pins the mean over all N amplitudes, the divisor N, the absence of conjugation and the order
+    (oracle first, then inversion about the mean)."""
+    marks = workloads.distinct_marks(n, m, seed=7 * n + m)
+    psi0 = workloads.random_state(n, seed=100 + n)
+    G = dense_diffusion(n) @ dense_oracle(n, marks)
+    want = psi0.copy()
+    for _ in range(k):
+        want = G @ want
+    got = orc.iterate(psi0.copy(), marks, k)
+    assert np.max(np.abs(got - want)) < 1e-13
+
+
+@pytest.mark.parametrize("n", [1, 2, 3, 4, 6])
+def test_oracle_and_mean_separately(orc, n):
+    """Algorithm 3 alone is the diagonal sign matrix, Algorithm 4 alone is Eq. 2."""
+    marks = workloads.distinct_marks(n, max(1, (1 << n) // 3), seed=n)
+    psi0 = workloads.random_state(n, seed=200 + n)
+    got = orc.oracle(psi0.copy(), marks)
+    assert np.array_equal(got, dense_oracle(n, marks) @ psi0)
+    got = orc.inversion_about_mean(psi0.copy())
+    assert np.max(np.abs(got - dense_diffusion(n) @ psi0)) < 1e-14
+
+
+# ------------------------------------------------------------------------------- gate level (Alg. 1, 2)
+@pytest.mark.parametrize("n", [1, 2, 3, 5, 7])
+def test_hadamard_all_is_walsh_hadamard(orc, n):
+    """n applications of Algorithm 1 with U = H give the Walsh-Hadamard matrix (scipy's Sylvester matrix)."""
+    N = 1 << n
+    H = sylvester_hadamard(n)
+    got = np.empty((N, N), dtype=np.complex128)
+    for j in range(N):
+        e = np.zeros(N, dtype=np.complex128)
+        e[j] = 1.0
+        got[:, j] = orc.hadamard_all(e)
+    assert np.max(np.abs(got - H)) < 1e-14
+    psi = workloads.random_state(n, seed=n)
+    twice = orc.hadamard_all(orc.hadamard_all(psi.copy()))
+    assert np.max(np.abs(twice - psi)) < 1e-14
+
+
+@pytest.mark.parametrize("n,q", [(1, 0), (2, 0), (2, 1), (4, 1), (5, 4), (6, 2)])
+def test_unitary_1q_matches_kronecker(orc, n, q):
+    """Algorithm 1 / Eq. 1 for a general complex unitary U on qubit q equals I (x) ... U ... (x) I acting
+    on the state (qubit q = bit q of the index): pins the a12 / a21 orientation and the bit convention."""
+    rng = np.random.default_rng(17 + n * 8 + q)
+    z = rng.normal(size=(2, 2)) + 1j * rng.normal(size=(2, 2))
+    U, _ = np.linalg.qr(z)
+    full = np.kron(np.kron(np.eye(1 << (n - 1 - q)), U), np.eye(1 << q))
+    psi = workloads.random_state(n, seed=300 + n + q)
+    got = orc.unitary_1q(psi.copy(), q, U)
+    assert np.max(np.abs(got - full @ psi)) < 1e-14
+
+
+@pytest.mark.parametrize("n", [1, 2, 3, 4, 6])
+def test_conditional_phase_shift_gives_eq2(orc, n):
+    """Steps 3-5 of the Background list (H^n, 2|0><0| - I, H^n) equal the inversion about the mean, Eq. 2;
+    checked column by column through the oracle's own gate routines."""
+    N = 1 << n
+    got = np.empty((N, N), dtype=np.complex128)
+    for j in range(N):
+        e = np.zeros(N, dtype=np.complex128)
+        e[j] = 1.0
+        orc.hadamard_all(e)
+        orc.conditional_phase_shift(e)
+        orc.hadamard_all(e)
+        got[:, j] = e
+    assert np.max(np.abs(got - dense_diffusion(n))) < 1e-13
+    e0 = np.zeros(N, dtype=np.complex128)
+    e0[0] = 1.0
+    assert np.array_equal(orc.conditional_phase_shift(e0.copy()), e0)
+
+
+@pytest.mark.parametrize("n,m", [(1, 1), (2, 1), (3, 1), (4, 2), (6, 3), (8, 1), (8, 5)])
+def test_gate_level_equals_proposed(orc, n, m):
+    """The conventional simulator (Algorithm 2) and the proposed one (Algorithm 5) reach the same state
+    (Discussion: the two are mathematically equivalent)."""
+    marks = workloads.distinct_marks(n, m, seed=55 * n + m)
+    k = max(orc.optimal_iterations(n, m), 1) + 1
+    a = orc.gate_search(n, marks, k)
+    b = orc.search(n, marks, k)
+    assert np.max(np.abs(a - b)) < 1e-13
+    # and both equal the dense matrix power
+    G = dense_diffusion(n) @ dense_oracle(n, marks)
+    want = np.full(1 << n, 1 / math.sqrt(1 << n), dtype=np.complex128)
+    for _ in range(k):
+        want = G @ want
+    assert np.max(np.abs(b - want)) < 1e-13
+
+
+# ------------------------------------------------------------------------------------- invariants
+def test_uniform_amplitude_correctly_rounded(orc):
+    for n in range(0, 40):
+        want = float(mpmath.mpf(2) ** (-mpmath.mpf(n) / 2))
+        assert orc.uniform_amplitude(n) == want, n
+
+
+@pytest.mark.parametrize("n", [1, 4, 9, 10])
+def test_degenerate_marked_sets(orc, n):
+    """M = 0: the uniform state is a fixed point (Eq. 2 maps the uniform vector to itself); bit for bit when
+    n is even (the amplitude is a power of two, every partial sum exact), to rounding when n is odd.
+    M = N: every iteration only flips the global sign."""
+    N = 1 << n
+    psi = orc.search(n, [], 7)
+    if n % 2 == 0:
+        assert np.array_equal(psi, orc.init_uniform(n))
+    else:
+        assert np.max(np.abs(psi - orc.init_uniform(n))) < 1e-15
+    allm = np.arange(N, dtype=np.uint64)
+    for k in range(4):
+        psi = orc.search(n, allm, k)
+        want = (-1) ** k * orc.init_uniform(n)
+        if n % 2 == 0:
+            assert np.array_equal(psi, want)
+        else:
+            assert np.max(np.abs(psi - want)) < 1e-15
+
+
+@pytest.mark.parametrize("n,m", [(5, 1), (9, 3), (13, 2)])
+def test_norm_is_one(orc, n, m):
+    """Background, Quantum State: sum |c_i|^2 = 1, and the iteration is unitary."""
+    marks = workloads.distinct_marks(n, m, seed=n)
+    psi = orc.init_uniform(n)
+    for _ in range(3):
+        orc.iterate(psi, marks, 5)
+        assert abs(orc.norm(psi) - 1.0) < 1e-13
+    psi = workloads.random_state(n, seed=9)
+    assert abs(orc.norm(orc.iterate(psi, marks, 11)) - 1.0) < 1e-13
+
+
+def test_norm_matches_definition(orc):
+    psi = workloads.random_state(7, seed=3) * 1.7
+    assert abs(orc.norm(psi) - float(np.sum(np.abs(psi) ** 2))) < 1e-14
+    assert orc.norm(np.zeros(8, dtype=np.complex128)) == 0.0
+
+
+def test_exact_rational_recurrence(orc):
+    """Exact dyadic arithmetic of the two-class iteration (Fractions) against the binary64 oracle at n = 10."""
+    n, m, k = 10, 1, 25
+    N = 1 << n
+    A = B = Fraction(1)  # amplitudes scaled by sqrt(N)
+    for _ in range(k):
+        S = -m * A + (N - m) * B
+        A, B = 2 * S / N + A, 2 * S / N - B
+    psi = orc.search(n, [3], k)
+    scale = 1 / math.sqrt(N)
+    assert abs(psi[3].real - float(A) * scale) < 1e-15
+    assert abs(psi[0].real - float(B) * scale) < 1e-15
+
+
+# ------------------------------------------------------------------------------------ random numbers
+def test_splitmix64_published_vectors(orc):
+    with open(os.path.join(GOLDEN, "splitmix64_vectors.txt")) as f:
+        rows = [tuple(int(x) for x in line.split()) for line in f if line.strip() and not line.startswith("#")]
+    assert rows
+    for seed, j, out in rows:
+        assert orc.splitmix64(seed, j) == out
+        assert int(workloads.splitmix64(seed, 1, start=j)[0]) == out
+    u = orc.uniforms_u53(1234567, 5)
+    assert np.array_equal(u, workloads.uniforms_u53(1234567, 5))
+    assert np.all(u < (1 << 53))
+
+
+def test_hash_marks_brute_force(orc):
+    """The hash predicate (low bits of SplitMix64_i(seed) all zero) against numpy enumeration."""
+    n, seed, bits = 16, 0xDEADBEEF, 6
+    h = workloads.splitmix64(seed, 1 << n)
+    want = np.nonzero((h & np.uint64((1 << bits) - 1)) == 0)[0].astype(np.uint64)
+    got, count = orc.hash_marks(n, seed, bits, cap=1 << 12)
+    assert count == want.size and np.array_equal(got, want)
+    _, c0 = orc.hash_marks(10, seed, 0, cap=0)
+    assert c0 == 1 << 10  # zero-width test: every index is marked
+
+
+def test_hash_workload_marks(orc):
+    """The single-large-instance workload's seed gives exactly 8 marks over 2^28 (stored by make_golden.py)."""
+    w = workloads.HASH_N28
+    with open(os.path.join(GOLDEN, "hash_marks_n28.txt")) as f:
+        stored = [int(x) for x in f if x.strip() and not x.startswith("#")]
+    assert len(stored) == w.m
+    # re-derive a subset cheaply: each stored index satisfies the predicate (numpy generator)
+    for i in stored:
+        assert int(workloads.splitmix64(w.hash_seed, 1, start=i)[0]) & ((1 << w.hash_bits) - 1) == 0
+
+
+# --------------------------------------------------------------------------------------- measurement
+@pytest.mark.parametrize("n", [2, 4, 8, 10])
+def test_sample_uniform_state_closed_form(orc, n):
+    """For the uniform state (even n) every p_i = 2^-n is exact, and inverse transform sampling reduces to
+    index = floor(U N / 2^53) = U >> (53 - n)."""
+    psi = orc.init_uniform(n)
+    u = workloads.uniforms_u53(99, 20000)
+    u = np.concatenate([u, np.array([0, (1 << 53) - 1, 1 << 52], dtype=np.uint64)])
+    got = orc.sample(psi, u)
+    assert np.array_equal(got, u >> np.uint64(53 - n))
+
+
+@pytest.mark.parametrize("n", [1, 3, 5])
+def test_sample_inverse_transform_on_a_grid(orc, n):
+    """Inverse transform sampling: over a uniform grid of 2^20 U values the fraction of shots landing on
+    index i equals p_i to within the grid spacing plus the 2^-62 quantisation (a single ordered sweep)."""
+    psi = workloads.random_state(n, seed=40 + n)
+    psi[1] = 0.0  # a zero-probability index is never selected
+    psi /= np.sqrt(np.sum(np.abs(psi) ** 2))
+    grid = np.arange(1 << 20, dtype=np.uint64) << np.uint64(33)
+    got = orc.sample(psi, grid)
+    assert np.all(np.diff(got.astype(np.int64)) >= 0)  # monotone in U
+    counts = np.bincount(got.astype(np.int64), minlength=1 << n) / float(1 << 20)
+    p = np.abs(psi) ** 2
+    assert counts[1] == 0.0
+    assert np.max(np.abs(counts - p)) <= 2.0 ** -20 + 1e-12
+
+
+def test_sample_chi_square(orc):
+    """10^6 shots from a random 32-state distribution pass a chi-square goodness-of-fit test."""
+    import scipy.stats
+
+    psi = workloads.random_state(5, seed=5)
+    u = workloads.uniforms_u53(2024, 1_000_000)
+    got = orc.sample(psi, u)
+    obs = np.bincount(got.astype(np.int64), minlength=32)
+    exp = np.abs(psi) ** 2 * u.size
+    stat = float(np.sum((obs - exp) ** 2 / exp))
+    assert scipy.stats.chi2.sf(stat, df=31) > 1e-4
+
+
+def test_sample_point_mass(orc):
+    psi = np.zeros(16, dtype=np.complex128)
+    psi[11] = -1j
+    got = orc.sample(psi, workloads.uniforms_u53(1, 1000))
+    assert np.all(got == 11)
+    with pytest.raises(ValueError):
+        orc.sample(np.zeros(16, dtype=np.complex128), np.zeros(3, dtype=np.uint64))

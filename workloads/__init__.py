@@ -1,0 +1,141 @@
+"""Seeded synthetic inputs for the Grover hot path.
+
+This module is shared by the tests, the benchmark and the CPU oracle's callers. It produces inputs only:
+problem sizes, marked index lists, hash seeds, random starting states and the uniform variates that
+measurement consumes. It holds none of the arithmetic of the search itself (no oracle sign, no mean,
+no update, no CDF).
+
+The paper uses no dataset: its workloads are a 3-qubit example and single-solution searches at
+n = 10, 16, 18 and 20 qubits (Simulation Results, Fig. 2 and Table 1). Everything here is synthetic by
+construction.
+
+Random numbers come from SplitMix64 (Steele, Lea and Flood, "Fast splittable pseudorandom number
+generators", OOPSLA 2014), used as a counter-based generator: output j of the generator seeded with s is
+mix64(s + (j + 1) * 0x9E3779B97F4A7C15), mix64 being the published variant with the multipliers
+0xBF58476D1CE4E5B9 and 0x94D049BB133111EB.
+"""
+from __future__ import annotations
+
+import dataclasses
+from typing import Optional
+
+import numpy as np
+
+_GAMMA = np.uint64(0x9E3779B97F4A7C15)
+_MIX1 = np.uint64(0xBF58476D1CE4E5B9)
+_MIX2 = np.uint64(0x94D049BB133111EB)
+
+
+def splitmix64(seed: int, count: int, start: int = 0) -> np.ndarray:
+    """Outputs start .. start+count-1 of SplitMix64 seeded with `seed`, as uint64."""
+    with np.errstate(over="ignore"):
+        j = np.arange(start + 1, start + count + 1, dtype=np.uint64)
+        z = np.uint64(seed & 0xFFFFFFFFFFFFFFFF) + j * _GAMMA
+        z = (z ^ (z >> np.uint64(30))) * _MIX1
+        z = (z ^ (z >> np.uint64(27))) * _MIX2
+        return z ^ (z >> np.uint64(31))
+
+
+def uniforms_u53(seed: int, shots: int) -> np.ndarray:
+    """53-bit uniform integers U_j = SplitMix64_j(seed) >> 11 in [0, 2^53), one per measurement shot."""
+    return splitmix64(seed, shots) >> np.uint64(11)
+
+
+def marked_index_from_seed(n: int, seed: int) -> int:
+    """One index drawn uniformly from [0, 2^n): the top n bits of output 0 (no modulo bias)."""
+    return int(splitmix64(seed, 1)[0]) >> (64 - n) if n > 0 else 0
+
+
+def distinct_marks(n: int, m: int, seed: int) -> np.ndarray:
+    """m distinct indices in [0, 2^n), sorted, drawn from SplitMix64(seed) top bits with rejection."""
+    N = 1 << n
+    if m > N:
+        raise ValueError("m > N")
+    if m > N // 2:
+        # draw the complement instead so the rejection loop stays short
+        rest = set(distinct_marks(n, N - m, seed ^ 0x5DEECE66D).tolist())
+        return np.array([i for i in range(N) if i not in rest], dtype=np.uint64)
+    out: set[int] = set()
+    j = 0
+    while len(out) < m:
+        batch = splitmix64(seed, 64, start=j)
+        j += 64
+        for v in batch.tolist():
+            idx = v >> (64 - n) if n > 0 else 0
+            if idx not in out:
+                out.add(idx)
+                if len(out) == m:
+                    break
+    return np.array(sorted(out), dtype=np.uint64)
+
+
+def random_state(n: int, seed: int, real: bool = False) -> np.ndarray:
+    """A normalised random state of 2^n amplitudes (complex128), used to exercise general, non-uniform inputs."""
+    N = 1 << n
+    u = splitmix64(seed, 2 * N).astype(np.float64) * (2.0 ** -64) - 0.5
+    psi = u[0::2] + (0.0 if real else 1j) * u[1::2]
+    psi = psi.astype(np.complex128)
+    return psi / np.sqrt(np.sum(np.abs(psi) ** 2))
+
+
+@dataclasses.dataclass(frozen=True)
+class Workload:
+    """One synthetic search problem.
+
+    name        short identifier
+    n           qubit count, N = 2^n amplitudes
+    dtype       storage type of the amplitudes: "f64" (real), "c64" (complex64) or "c128" (complex128)
+    m           number of marked indices
+    marks       explicit marked list (oracle given as a list), or None when a hash predicate defines them
+    hash_seed   seed of the hash predicate (low `hash_bits` bits of SplitMix64_i(hash_seed) all zero)
+    hash_bits   width of the predicate's zero test
+    iterations  Grover iterations, floor(pi/4 * sqrt(N/M))
+    shots       measurement shots
+    shot_seed   seed of the uniforms that measurement consumes
+    """
+
+    name: str
+    n: int
+    dtype: str
+    m: int
+    marks: Optional[tuple]
+    hash_seed: Optional[int]
+    hash_bits: int
+    iterations: int
+    shots: int
+    shot_seed: int
+
+
+# Plain Grover, n = 10, real FP64, one marked index drawn from a seed, 25 iterations, 10^4 shots.
+PLAIN_N10_SEED = 20050463
+PLAIN_N10 = Workload(
+    name="plain_n10_f64_m1",
+    n=10,
+    dtype="f64",
+    m=1,
+    marks=(marked_index_from_seed(10, PLAIN_N10_SEED),),
+    hash_seed=None,
+    hash_bits=0,
+    iterations=25,
+    shots=10_000,
+    shot_seed=7,
+)
+
+# Single large instance, n = 28 complex64, M = 8 marked indices defined by the hash predicate
+# (hash(i, seed) mod 2^25 == 0).  The seed is the first one at or above 0x6A09E667F3BCC908 whose predicate
+# has exactly 8 hits over 2^28 indices; `oracle/find_hash_seed.py` searched it with the CPU oracle only.
+HASH_N28_SEED = 0x6A09E667F3BCC910
+HASH_N28 = Workload(
+    name="hash_n28_c64_m8",
+    n=28,
+    dtype="c64",
+    m=8,
+    marks=None,
+    hash_seed=HASH_N28_SEED,
+    hash_bits=25,
+    iterations=4549,
+    shots=1_000_000,
+    shot_seed=11,
+)
+
+WORKLOADS = {w.name: w for w in (PLAIN_N10, HASH_N28)}
