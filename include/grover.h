@@ -1,0 +1,176 @@
+/*
+ * grover.h — C ABI of libgrover, an MI355X (gfx950) implementation of the fast Grover-search simulation of
+ * Chattopadhyay and Menon, "Fast simulation of Grover's quantum search on classical computer"
+ * (arXiv:2005.04635).
+ *
+ * The library keeps an N = 2^n amplitude state vector in device memory and advances it by Grover iterations
+ * computed the paper's way: a sign flip of the marked amplitudes (the proposed Oracle, Algorithm 3) followed
+ * by inversion about the mean, c_i <- 2*mean - c_i (Eq. 2 and Algorithm 4), repeated as in Algorithm 5.
+ * For comparison it also runs the conventional gate-level iteration of Algorithm 2 (H^n built from the
+ * 1-qubit unitary of Algorithm 1, the conditional phase shift 2|0><0| - I, H^n again).
+ *
+ * Conventions shared by every call
+ *   - State layout (Background, "Quantum State"): a contiguous array indexed by basis state i, 0 <= i < N;
+ *     bit q of i is qubit q.  Element types: GROVER_F64_REAL = one double per amplitude (imaginary part 0);
+ *     GROVER_C64 = interleaved float (re, im); GROVER_C128 = interleaved double (re, im).
+ *   - Signs: the oracle negates marked amplitudes; the diffusion is 2|psi><psi| - I with |psi> the uniform
+ *     superposition, i.e. c_i <- 2*S/N - c_i with S = sum_i c_i (real and imaginary parts, no conjugation)
+ *     of the oracle-flipped state.  The conditional phase shift is 2|0><0| - I.
+ *   - Every function returns an int status (GROVER_OK = 0, or a negative GROVER_E_* code) and never aborts
+ *     or throws.  grover_last_error(ctx) gives a message for the last failure on that context.
+ *   - Device work is enqueued on the context's HIP stream and is asynchronous unless stated otherwise.
+ *     Calls that deliver results to host memory synchronise that stream before returning.
+ *   - A context is not thread-safe; distinct contexts are independent.  All pointers are plain host or
+ *     device addresses; no torch or other framework type crosses this boundary.
+ */
+#ifndef GROVER_H
+#define GROVER_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ------------------------------------------------------------------------------------------ status */
+#define GROVER_OK 0
+#define GROVER_E_INVAL (-1)       /* invalid argument (sizes, pointers, marked list, enum values) */
+#define GROVER_E_NOMEM (-2)       /* device or host allocation failed */
+#define GROVER_E_HIP (-3)         /* a HIP runtime call failed; message in grover_last_error */
+#define GROVER_E_COOP (-4)        /* the persistent grid cannot be made co-resident on this device */
+#define GROVER_E_UNSUPPORTED (-5) /* valid request this build does not implement (e.g. form/size mismatch) */
+#define GROVER_E_PREDICATE (-6)   /* hash predicate hit count differs from the requested m */
+#define GROVER_E_TIMEOUT (-7)     /* a device-side grid barrier exceeded its time limit (reported by grover_sync) */
+
+/* ----------------------------------------------------------------------------------------- enums */
+typedef enum grover_dtype {
+    GROVER_F64_REAL = 0, /* double per amplitude, imaginary parts identically 0 */
+    GROVER_C64 = 1,      /* complex64: float re, float im; update computed in binary64, stored rounded */
+    GROVER_C128 = 2      /* complex128: double re, double im */
+} grover_dtype;
+
+typedef enum grover_oracle_kind {
+    GROVER_ORACLE_LIST = 0, /* marked set given as an explicit list of indices (Algorithm 3's k[]) */
+    GROVER_ORACLE_HASH = 1  /* i is marked iff the low hash_bits bits of SplitMix64_i(hash_seed) are 0 */
+} grover_oracle_kind;
+
+typedef enum grover_form {
+    GROVER_FORM_AUTO = 0,     /* RESIDENT for n <= 14, FUSED above */
+    GROVER_FORM_FUSED = 1,    /* one persistent cooperative kernel per grover_iterate call, one grid
+                                 barrier per iteration, update fused with the next iteration's sum */
+    GROVER_FORM_RESIDENT = 2, /* one workgroup holds the whole state on chip (n <= 14) */
+    GROVER_FORM_TWO_PASS = 3  /* plain form: per iteration an oracle flip, a sum pass and an update pass,
+                                 launched from the host (Algorithms 3 and 4 as separate kernels) */
+} grover_form;
+
+/* ---------------------------------------------------------------------------------------- config */
+typedef struct grover_config {
+    uint32_t n;              /* qubits, 1 <= n <= 34; N = 2^n amplitudes */
+    uint32_t dtype;          /* grover_dtype */
+    uint32_t oracle_kind;    /* grover_oracle_kind */
+    uint32_t hash_bits;      /* HASH only: width of the zero test, 0 <= hash_bits <= 64 */
+    const uint64_t *marked;  /* LIST only: host array of m distinct indices < N, any order; copied */
+    uint64_t m;              /* LIST: length of `marked`; HASH: required number of hits (checked) */
+    uint64_t hash_seed;      /* HASH only: SplitMix64 seed of the predicate */
+    uint32_t form;           /* grover_form */
+    uint32_t flags;          /* reserved, must be 0 */
+} grover_config;
+
+typedef struct grover_ctx grover_ctx;
+
+/* grover_init — create a context and prepare the initial state (Algorithm 5: psi = H^n |0>).
+ *   out         receives the new context (set to NULL on failure).
+ *   cfg         problem description, validated: n range, dtype/form/kind values, flags == 0, marked
+ *               indices distinct and < N, m <= N; for HASH the predicate is evaluated on the device over
+ *               all N indices, its hits compacted into the marked list, and GROVER_E_PREDICATE returned
+ *               when their number differs from cfg->m.
+ *   hip_stream  hipStream_t to run on (e.g. torch.cuda.current_stream().cuda_stream), NULL = default
+ *               stream.  The device is the one current when grover_init is called.
+ *   state_dev   optional caller-owned device buffer of at least state_bytes = N * element size bytes,
+ *               16-byte aligned; the library uses it as the state and never frees it.  NULL: the context
+ *               allocates and owns the state.
+ *   state_bytes size of state_dev in bytes (ignored when state_dev is NULL).
+ * The state is written as the uniform superposition 2^(-n/2) (correctly rounded to the element type).
+ * Synchronises the stream once (HASH: to read back the hit count). */
+int grover_init(grover_ctx **out, const grover_config *cfg, void *hip_stream, void *state_dev,
+                size_t state_bytes);
+
+/* grover_reset — overwrite the state with the uniform superposition again (marked set unchanged). */
+int grover_reset(grover_ctx *ctx);
+
+/* grover_iterate — k Grover iterations of the proposed method (Algorithm 5's loop body: Algorithm 3 then
+ * Algorithm 4) in the context's form.  k = 0 is a no-op.  The sum of the current state is recomputed at the
+ * start of every call, so edits made through grover_write_state or the device pointer are honoured, and
+ * grover_iterate(a) followed by grover_iterate(b) gives bit for bit the state of grover_iterate(a + b).
+ * Asynchronous. */
+int grover_iterate(grover_ctx *ctx, uint64_t k);
+
+/* grover_gate_iterate — k iterations of the conventional gate-level simulator (Algorithm 2's loop body):
+ * oracle sign flip, H^n as n single-qubit passes (Algorithm 1 with U = H), the conditional phase shift
+ * 2|0><0| - I, H^n again.  Asynchronous. */
+int grover_gate_iterate(grover_ctx *ctx, uint64_t k);
+
+/* grover_apply_hadamard_all — psi <- H^n psi as n single-qubit passes (Algorithm 1).  Asynchronous. */
+int grover_apply_hadamard_all(grover_ctx *ctx);
+
+/* grover_sample — measurement (Background, step 6; the paper gives no procedure, this library defines it):
+ *   p_i = re_i^2 + im_i^2 in binary64 (no fused multiply-add), q_i = floor(p_i * 2^62) as uint64,
+ *   Q_i = q_0 + ... + q_i (exact integer prefix sum), and for shot j with 53-bit uniform U_j:
+ *   t_j = floor(U_j * Q_{N-1} / 2^53), index_j = the smallest i with Q_i > t_j.
+ * Because the CDF is an integer prefix sum, the result depends only on the state's bits, not on the order
+ * of the device's scan.
+ *   shots        number of shots (0 allowed).
+ *   seed         U_j = SplitMix64_j(seed) >> 11, generated on the device.
+ *   out          shots uint64 indices; a device pointer when out_is_device != 0, else host memory (the call
+ *                then synchronises).  Returns GROVER_E_INVAL when every q_i is 0 (reported after a sync).
+ * Allocates an N-entry uint64 CDF on first use (kept by the context). */
+int grover_sample(grover_ctx *ctx, uint64_t shots, uint64_t seed, uint64_t *out, int out_is_device);
+
+/* grover_sample_u53 — as grover_sample with caller-supplied uniforms u53[0..shots) (host or device memory
+ * as u53_is_device says); only their low 53 bits are used. */
+int grover_sample_u53(grover_ctx *ctx, const uint64_t *u53, int u53_is_device, uint64_t shots,
+                      uint64_t *out, int out_is_device);
+
+/* grover_norm — sum_i |c_i|^2 in binary64 with a fixed summation order (Background: it equals 1).
+ * Synchronises; *out receives the value. */
+int grover_norm(grover_ctx *ctx, double *out);
+
+/* grover_read_state / grover_write_state — copy the whole state to / from host memory (bytes must equal
+ * N * element size).  Synchronous. */
+int grover_read_state(grover_ctx *ctx, void *host, size_t bytes);
+int grover_write_state(grover_ctx *ctx, const void *host, size_t bytes);
+
+/* grover_state_device — device address and size in bytes of the state. */
+int grover_state_device(grover_ctx *ctx, void **dev_ptr, size_t *bytes);
+
+/* grover_marked — the marked list, sorted ascending: writes min(cap, m) entries to host `out` and the total
+ * count to *count. */
+int grover_marked(grover_ctx *ctx, uint64_t *out, uint64_t cap, uint64_t *count);
+
+/* grover_sync — wait for the context's stream and report device-side failures (GROVER_E_TIMEOUT when a
+ * grid barrier gave up; the context is then usable again and the state undefined until reset/written). */
+int grover_sync(grover_ctx *ctx);
+
+/* grover_query — launch facts for diagnostics.  key: 0 = resolved form, 1 = persistent grid size
+ * (workgroups), 2 = workgroup size, 3 = element size in bytes, 4 = N, 5 = number of marked indices. */
+int grover_query(grover_ctx *ctx, int key, int64_t *value);
+
+/* grover_optimal_iterations — floor(pi/4 * sqrt(2^n / m)) (Algorithm 5's iteration count with m
+ * solutions; the Fig. 2 example fixes the floor), 0 when m == 0 or m > 2^n or n > 63. */
+uint64_t grover_optimal_iterations(uint32_t n, uint64_t m);
+
+/* grover_destroy — release the context and everything it owns (not a caller-provided state buffer).
+ * Waits for the stream first.  NULL is ignored. */
+void grover_destroy(grover_ctx *ctx);
+
+/* grover_status_str — static text for a status code.  grover_last_error — the last failure message on ctx
+ * (empty string when none; a static message when ctx is NULL). */
+const char *grover_status_str(int status);
+const char *grover_last_error(const grover_ctx *ctx);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* GROVER_H */

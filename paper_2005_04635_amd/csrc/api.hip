@@ -1,0 +1,513 @@
+// C ABI of libgrover (declared and documented in grover.h): validation, context and buffer management,
+// error reporting, and the dispatch of each call to the kernel launchers of the other translation units.
+#include <algorithm>
+#include <cmath>
+#include <cstdlib>
+#include <cstring>
+#include <new>
+
+#include "internal.h"
+
+using namespace grover;
+
+namespace {
+
+constexpr uint64_t kDefaultTimeoutMs = 10000;  // grid-barrier wait limit before a kernel gives up
+
+int fail(grover_ctx *c, int status, const std::string &msg)
+{
+    if (c)
+        c->last_error = msg;
+    return status;
+}
+
+int hip_fail(grover_ctx *c, hipError_t e, const char *what)
+{
+    (void)hipGetLastError();  // clear the runtime's sticky copy
+    int status = GROVER_E_HIP;
+    if (e == hipErrorOutOfMemory || e == hipErrorMemoryAllocation)
+        status = GROVER_E_NOMEM;
+    else if (e == hipErrorCooperativeLaunchTooLarge)
+        status = GROVER_E_COOP;
+    return fail(c, status, std::string(what) + ": " + hipGetErrorString(e));
+}
+
+#define GROVER_HIP(ctx, expr, what)                 \
+    do {                                            \
+        const hipError_t e_ = (expr);               \
+        if (e_ != hipSuccess)                       \
+            return hip_fail((ctx), e_, (what));     \
+    } while (0)
+
+template <class P>
+hipError_t dev_alloc(P **p, size_t bytes)
+{
+    void *v = nullptr;
+    const hipError_t e = hipMalloc(&v, bytes > 0 ? bytes : 16);
+    *p = static_cast<P *>(v);
+    return e;
+}
+
+void release(grover_ctx *c)
+{
+    if (!c)
+        return;
+    if (c->owns_state && c->state)
+        (void)hipFree(c->state);
+    for (void *p : {(void *)c->marks_dev, (void *)c->partials, (void *)c->sync, (void *)c->red_partials,
+                    (void *)c->red_out, (void *)c->cdf, (void *)c->block_sums, (void *)c->shots_buf,
+                    (void *)c->u53_buf, (void *)c->flag_dev})
+        if (p)
+            (void)hipFree(p);
+    if (c->host_pinned)
+        (void)hipHostFree(c->host_pinned);
+    delete c;
+}
+
+int check_ctx(const grover_ctx *c) { return c ? GROVER_OK : GROVER_E_INVAL; }
+
+int run_iterations(grover_ctx *c, uint64_t k)
+{
+    if (k == 0)
+        return GROVER_OK;
+    switch (c->form) {
+    case GROVER_FORM_FUSED: GROVER_HIP(c, launch_fused_iterate(c, k), "fused iterate launch"); break;
+    case GROVER_FORM_RESIDENT: GROVER_HIP(c, launch_resident_iterate(c, k), "resident iterate launch"); break;
+    case GROVER_FORM_TWO_PASS: GROVER_HIP(c, launch_twopass_iterate(c, k), "two-pass iterate launch"); break;
+    default: return fail(c, GROVER_E_INVAL, "context has no iteration form");
+    }
+    return GROVER_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+uint64_t grover_optimal_iterations(uint32_t n, uint64_t m)
+{
+    if (m == 0 || n > 63 || m > (uint64_t(1) << n))
+        return 0;
+    const double pi_over_4 = 0.78539816339744830961566084581987572104929234984378;
+    return uint64_t(std::floor(pi_over_4 * std::sqrt(std::ldexp(1.0, int(n)) / double(m))));
+}
+
+const char *grover_status_str(int status)
+{
+    switch (status) {
+    case GROVER_OK: return "ok";
+    case GROVER_E_INVAL: return "invalid argument";
+    case GROVER_E_NOMEM: return "out of memory";
+    case GROVER_E_HIP: return "HIP runtime error";
+    case GROVER_E_COOP: return "persistent grid cannot be co-resident";
+    case GROVER_E_UNSUPPORTED: return "unsupported request";
+    case GROVER_E_PREDICATE: return "hash predicate hit count differs from m";
+    case GROVER_E_TIMEOUT: return "device grid barrier timed out";
+    default: return "unknown status";
+    }
+}
+
+const char *grover_last_error(const grover_ctx *ctx)
+{
+    return ctx ? ctx->last_error.c_str() : "no context";
+}
+
+int grover_init(grover_ctx **out, const grover_config *cfg, void *hip_stream, void *state_dev, size_t state_bytes)
+{
+    if (!out)
+        return GROVER_E_INVAL;
+    *out = nullptr;
+    if (!cfg)
+        return GROVER_E_INVAL;
+    if (cfg->n < 1 || cfg->n > kMaxQubits || cfg->dtype > GROVER_C128 || cfg->oracle_kind > GROVER_ORACLE_HASH ||
+        cfg->form > GROVER_FORM_TWO_PASS || cfg->flags != 0 || cfg->hash_bits > 64)
+        return GROVER_E_INVAL;
+    const uint64_t N = uint64_t(1) << cfg->n;
+    if (cfg->m > N)
+        return GROVER_E_INVAL;
+    uint32_t form = cfg->form;
+    if (form == GROVER_FORM_AUTO)
+        form = cfg->n <= kResidentMaxQubits ? GROVER_FORM_RESIDENT : GROVER_FORM_FUSED;
+    if (form == GROVER_FORM_RESIDENT && cfg->n > kResidentMaxQubits)
+        return GROVER_E_UNSUPPORTED;
+    if (cfg->oracle_kind == GROVER_ORACLE_HASH && cfg->m > kHashMarkCap)
+        return GROVER_E_UNSUPPORTED;
+
+    grover_ctx *c = new (std::nothrow) grover_ctx;
+    if (!c)
+        return GROVER_E_NOMEM;
+    int status = GROVER_OK;
+    try {
+        c->n = cfg->n;
+        c->N = N;
+        c->dtype = cfg->dtype;
+        c->form = form;
+        c->kind = cfg->oracle_kind;
+        c->stream = static_cast<hipStream_t>(hip_stream);
+        const size_t eb = elem_bytes(cfg->dtype);
+        const size_t need = size_t(N) * eb;
+
+        if (cfg->oracle_kind == GROVER_ORACLE_LIST) {
+            if (cfg->m > 0 && !cfg->marked) {
+                release(c);
+                return GROVER_E_INVAL;
+            }
+            c->marks.assign(cfg->marked, cfg->marked + cfg->m);
+            std::sort(c->marks.begin(), c->marks.end());
+            for (size_t i = 0; i < c->marks.size(); ++i) {
+                if (c->marks[i] >= N || (i > 0 && c->marks[i] == c->marks[i - 1])) {
+                    release(c);
+                    return GROVER_E_INVAL;
+                }
+            }
+        }
+        if (state_dev) {
+            if (state_bytes < need || (reinterpret_cast<uintptr_t>(state_dev) & 15u) != 0) {
+                release(c);
+                return GROVER_E_INVAL;
+            }
+            c->state = state_dev;
+            c->owns_state = false;
+        }
+
+        hipError_t e = hipGetDevice(&c->device);
+        if (e == hipSuccess)
+            e = hipDeviceGetAttribute(&c->cu_count, hipDeviceAttributeMultiprocessorCount, c->device);
+        int clock_khz = 0;
+        if (e == hipSuccess)
+            e = hipDeviceGetAttribute(&clock_khz, hipDeviceAttributeWallClockRate, c->device);
+        if (e != hipSuccess) {
+            status = hip_fail(c, e, "device query");
+            throw status;
+        }
+        uint64_t timeout_ms = kDefaultTimeoutMs;
+        if (const char *env = getenv("GROVER_BARRIER_TIMEOUT_MS"))
+            timeout_ms = strtoull(env, nullptr, 10);
+        c->timeout_ticks = uint64_t(clock_khz > 0 ? clock_khz : 100000) * timeout_ms;
+
+        if (!c->state) {
+            e = dev_alloc(&c->state, need);
+            if (e != hipSuccess) {
+                status = hip_fail(c, e, "state allocation");
+                throw status;
+            }
+            c->owns_state = true;
+        }
+        c->state_bytes = c->owns_state ? need : state_bytes;
+
+        // reduction scratch shared by the two-pass form and the norm
+        e = dev_alloc(&c->red_partials, 2 * 2048 * sizeof(double));
+        if (e == hipSuccess)
+            e = dev_alloc(&c->red_out, 2 * sizeof(double));
+        if (e == hipSuccess)
+            e = dev_alloc(&c->flag_dev, sizeof(uint32_t));
+        if (e == hipSuccess)
+            e = hipMemsetAsync(c->flag_dev, 0, sizeof(uint32_t), c->stream);
+        if (e == hipSuccess) {
+            void *hp = nullptr;
+            e = hipHostMalloc(&hp, 4 * sizeof(double), hipHostMallocDefault);
+            c->host_pinned = static_cast<double *>(hp);
+        }
+        if (e != hipSuccess) {
+            status = hip_fail(c, e, "scratch allocation");
+            throw status;
+        }
+
+        if (form == GROVER_FORM_FUSED) {
+            e = fused_configure(c, &c->grid, &c->block);
+            if (e != hipSuccess) {
+                status = hip_fail(c, e, "persistent grid configuration");
+                throw status;
+            }
+            e = dev_alloc(&c->partials, size_t(2) * c->grid * 2 * sizeof(double));
+            if (e == hipSuccess)
+                e = dev_alloc(&c->sync, sizeof(GridSync));
+            if (e == hipSuccess)
+                e = hipMemsetAsync(c->sync, 0, sizeof(GridSync), c->stream);
+            if (e != hipSuccess) {
+                status = hip_fail(c, e, "barrier allocation");
+                throw status;
+            }
+        } else if (form == GROVER_FORM_RESIDENT) {
+            c->grid = 1;
+            c->block = kResidentBlock;
+        } else {
+            c->grid = twopass_blocks(c);
+            c->block = 256;
+        }
+
+        if (cfg->oracle_kind == GROVER_ORACLE_HASH) {
+            // Evaluate the predicate over all N indices, compact the hits, check their number.
+            const uint64_t cap = cfg->m + 1;
+            uint64_t *list = nullptr;
+            unsigned long long *count = nullptr;
+            e = dev_alloc(&list, cap * sizeof(uint64_t));
+            if (e == hipSuccess)
+                e = dev_alloc(&count, sizeof(unsigned long long));
+            if (e == hipSuccess)
+                e = hipMemsetAsync(count, 0, sizeof(unsigned long long), c->stream);
+            if (e == hipSuccess)
+                e = launch_hash_marks(c, cfg->hash_seed, cfg->hash_bits, list, cap, count);
+            unsigned long long hits = 0;
+            if (e == hipSuccess)
+                e = hipMemcpyAsync(&hits, count, sizeof(hits), hipMemcpyDeviceToHost, c->stream);
+            if (e == hipSuccess)
+                e = hipStreamSynchronize(c->stream);
+            if (e == hipSuccess && hits == cfg->m) {
+                c->marks.resize(hits);
+                if (hits > 0)
+                    e = hipMemcpy(c->marks.data(), list, hits * sizeof(uint64_t), hipMemcpyDeviceToHost);
+            }
+            if (count)
+                (void)hipFree(count);
+            if (e != hipSuccess) {
+                if (list)
+                    (void)hipFree(list);
+                status = hip_fail(c, e, "hash predicate");
+                throw status;
+            }
+            if (hits != cfg->m) {
+                (void)hipFree(list);
+                status = fail(c, GROVER_E_PREDICATE, "hash predicate hit count differs from m");
+                throw status;
+            }
+            std::sort(c->marks.begin(), c->marks.end());
+            c->marks_dev = list;
+        } else if (!c->marks.empty()) {
+            e = dev_alloc(&c->marks_dev, c->marks.size() * sizeof(uint64_t));
+            if (e != hipSuccess) {
+                status = hip_fail(c, e, "marked list allocation");
+                throw status;
+            }
+        }
+        if (!c->marks.empty()) {
+            e = hipMemcpyAsync(c->marks_dev, c->marks.data(), c->marks.size() * sizeof(uint64_t),
+                               hipMemcpyHostToDevice, c->stream);
+            if (e == hipSuccess)
+                e = hipStreamSynchronize(c->stream);  // the host vector must outlive the copy
+            if (e != hipSuccess) {
+                status = hip_fail(c, e, "marked list upload");
+                throw status;
+            }
+        }
+        e = launch_fill_uniform(c);
+        if (e != hipSuccess) {
+            status = hip_fail(c, e, "initial state");
+            throw status;
+        }
+    } catch (int) {
+        release(c);
+        return status;
+    } catch (...) {
+        release(c);
+        return GROVER_E_NOMEM;
+    }
+    *out = c;
+    return GROVER_OK;
+}
+
+int grover_reset(grover_ctx *ctx)
+{
+    if (check_ctx(ctx))
+        return GROVER_E_INVAL;
+    GROVER_HIP(ctx, launch_fill_uniform(ctx), "initial state");
+    return GROVER_OK;
+}
+
+int grover_iterate(grover_ctx *ctx, uint64_t k)
+{
+    if (check_ctx(ctx))
+        return GROVER_E_INVAL;
+    return run_iterations(ctx, k);
+}
+
+int grover_gate_iterate(grover_ctx *ctx, uint64_t k)
+{
+    if (check_ctx(ctx))
+        return GROVER_E_INVAL;
+    for (uint64_t it = 0; it < k; ++it) {
+        GROVER_HIP(ctx, launch_oracle_flip(ctx), "oracle flip");
+        GROVER_HIP(ctx, launch_hadamard_all(ctx), "hadamard passes");
+        GROVER_HIP(ctx, launch_conditional_phase_shift(ctx), "conditional phase shift");
+        GROVER_HIP(ctx, launch_hadamard_all(ctx), "hadamard passes");
+    }
+    return GROVER_OK;
+}
+
+int grover_apply_hadamard_all(grover_ctx *ctx)
+{
+    if (check_ctx(ctx))
+        return GROVER_E_INVAL;
+    GROVER_HIP(ctx, launch_hadamard_all(ctx), "hadamard passes");
+    return GROVER_OK;
+}
+
+static int sample_impl(grover_ctx *c, const uint64_t *u53, int u53_is_device, bool device_uniforms, uint64_t seed,
+                       uint64_t shots, uint64_t *out, int out_is_device)
+{
+    if (shots > 0 && !out)
+        return fail(c, GROVER_E_INVAL, "null output");
+    if (!device_uniforms && shots > 0 && !u53)
+        return fail(c, GROVER_E_INVAL, "null uniforms");
+    if (!c->cdf) {
+        GROVER_HIP(c, dev_alloc(&c->cdf, size_t(c->N) * sizeof(uint64_t)), "CDF allocation");
+        GROVER_HIP(c, dev_alloc(&c->block_sums, sample_block_count(c->N) * sizeof(uint64_t)), "CDF allocation");
+    }
+    const uint64_t *u_dev = nullptr;
+    if (!device_uniforms && shots > 0) {
+        if (u53_is_device) {
+            u_dev = u53;
+        } else {
+            if (c->u53_cap < shots) {
+                if (c->u53_buf)
+                    (void)hipFree(c->u53_buf);
+                c->u53_buf = nullptr;
+                c->u53_cap = 0;
+                GROVER_HIP(c, dev_alloc(&c->u53_buf, shots * sizeof(uint64_t)), "uniform buffer");
+                c->u53_cap = shots;
+            }
+            GROVER_HIP(c, hipMemcpyAsync(c->u53_buf, u53, shots * sizeof(uint64_t), hipMemcpyHostToDevice, c->stream),
+                       "uniform upload");
+            u_dev = c->u53_buf;
+        }
+    }
+    uint64_t *o_dev = out;
+    if (!out_is_device && shots > 0) {
+        if (c->shots_cap < shots) {
+            if (c->shots_buf)
+                (void)hipFree(c->shots_buf);
+            c->shots_buf = nullptr;
+            c->shots_cap = 0;
+            GROVER_HIP(c, dev_alloc(&c->shots_buf, shots * sizeof(uint64_t)), "shot buffer");
+            c->shots_cap = shots;
+        }
+        o_dev = c->shots_buf;
+    }
+    GROVER_HIP(c, launch_sample(c, u_dev, seed, device_uniforms, shots, o_dev), "sampler launch");
+    if (!out_is_device && shots > 0) {
+        GROVER_HIP(c, hipMemcpyAsync(out, o_dev, shots * sizeof(uint64_t), hipMemcpyDeviceToHost, c->stream),
+                   "shot download");
+        return grover_sync(c);
+    }
+    return GROVER_OK;
+}
+
+int grover_sample(grover_ctx *ctx, uint64_t shots, uint64_t seed, uint64_t *out, int out_is_device)
+{
+    if (check_ctx(ctx))
+        return GROVER_E_INVAL;
+    return sample_impl(ctx, nullptr, 0, true, seed, shots, out, out_is_device);
+}
+
+int grover_sample_u53(grover_ctx *ctx, const uint64_t *u53, int u53_is_device, uint64_t shots, uint64_t *out,
+                      int out_is_device)
+{
+    if (check_ctx(ctx))
+        return GROVER_E_INVAL;
+    return sample_impl(ctx, u53, u53_is_device, false, 0, shots, out, out_is_device);
+}
+
+int grover_norm(grover_ctx *ctx, double *out)
+{
+    if (check_ctx(ctx) || !out)
+        return fail(ctx, GROVER_E_INVAL, "null argument");
+    GROVER_HIP(ctx, launch_norm(ctx, ctx->red_out), "norm launch");
+    GROVER_HIP(ctx, hipMemcpyAsync(ctx->host_pinned, ctx->red_out, sizeof(double), hipMemcpyDeviceToHost, ctx->stream),
+               "norm download");
+    GROVER_HIP(ctx, hipStreamSynchronize(ctx->stream), "stream synchronise");
+    *out = ctx->host_pinned[0];
+    return GROVER_OK;
+}
+
+int grover_read_state(grover_ctx *ctx, void *host, size_t bytes)
+{
+    if (check_ctx(ctx) || !host)
+        return fail(ctx, GROVER_E_INVAL, "null argument");
+    if (bytes != size_t(ctx->N) * elem_bytes(ctx->dtype))
+        return fail(ctx, GROVER_E_INVAL, "byte count differs from the state size");
+    GROVER_HIP(ctx, hipMemcpyAsync(host, ctx->state, bytes, hipMemcpyDeviceToHost, ctx->stream), "state download");
+    GROVER_HIP(ctx, hipStreamSynchronize(ctx->stream), "stream synchronise");
+    return GROVER_OK;
+}
+
+int grover_write_state(grover_ctx *ctx, const void *host, size_t bytes)
+{
+    if (check_ctx(ctx) || !host)
+        return fail(ctx, GROVER_E_INVAL, "null argument");
+    if (bytes != size_t(ctx->N) * elem_bytes(ctx->dtype))
+        return fail(ctx, GROVER_E_INVAL, "byte count differs from the state size");
+    GROVER_HIP(ctx, hipMemcpyAsync(ctx->state, host, bytes, hipMemcpyHostToDevice, ctx->stream), "state upload");
+    GROVER_HIP(ctx, hipStreamSynchronize(ctx->stream), "stream synchronise");
+    return GROVER_OK;
+}
+
+int grover_state_device(grover_ctx *ctx, void **dev_ptr, size_t *bytes)
+{
+    if (check_ctx(ctx) || !dev_ptr || !bytes)
+        return fail(ctx, GROVER_E_INVAL, "null argument");
+    *dev_ptr = ctx->state;
+    *bytes = size_t(ctx->N) * elem_bytes(ctx->dtype);
+    return GROVER_OK;
+}
+
+int grover_marked(grover_ctx *ctx, uint64_t *out, uint64_t cap, uint64_t *count)
+{
+    if (check_ctx(ctx) || !count || (cap > 0 && !out))
+        return fail(ctx, GROVER_E_INVAL, "null argument");
+    const uint64_t m = ctx->marks.size();
+    const uint64_t w = m < cap ? m : cap;
+    if (w > 0)
+        memcpy(out, ctx->marks.data(), w * sizeof(uint64_t));
+    *count = m;
+    return GROVER_OK;
+}
+
+int grover_sync(grover_ctx *ctx)
+{
+    if (check_ctx(ctx))
+        return GROVER_E_INVAL;
+    GROVER_HIP(ctx, hipStreamSynchronize(ctx->stream), "stream synchronise");
+    uint32_t err = 0;
+    GROVER_HIP(ctx, hipMemcpy(&err, ctx->flag_dev, sizeof(err), hipMemcpyDeviceToHost), "status download");
+    if (err) {
+        GROVER_HIP(ctx, hipMemset(ctx->flag_dev, 0, sizeof(uint32_t)), "status reset");
+        GROVER_HIP(ctx, hipDeviceSynchronize(), "status reset");
+        return fail(ctx, GROVER_E_INVAL, "every outcome probability rounds to zero");
+    }
+    if (ctx->sync) {
+        GridSync gs;
+        GROVER_HIP(ctx, hipMemcpy(&gs, ctx->sync, sizeof(gs), hipMemcpyDeviceToHost), "barrier status download");
+        if (gs.error) {
+            GROVER_HIP(ctx, hipMemset(ctx->sync, 0, sizeof(GridSync)), "barrier reset");
+            GROVER_HIP(ctx, hipDeviceSynchronize(), "barrier reset");
+            ctx->generation = 0;
+            return fail(ctx, GROVER_E_TIMEOUT, "a grid barrier wait exceeded its limit; state undefined");
+        }
+    }
+    return GROVER_OK;
+}
+
+int grover_query(grover_ctx *ctx, int key, int64_t *value)
+{
+    if (check_ctx(ctx) || !value)
+        return fail(ctx, GROVER_E_INVAL, "null argument");
+    switch (key) {
+    case 0: *value = ctx->form; break;
+    case 1: *value = ctx->grid; break;
+    case 2: *value = ctx->block; break;
+    case 3: *value = int64_t(elem_bytes(ctx->dtype)); break;
+    case 4: *value = int64_t(ctx->N); break;
+    case 5: *value = int64_t(ctx->marks.size()); break;
+    default: return fail(ctx, GROVER_E_INVAL, "unknown query key");
+    }
+    return GROVER_OK;
+}
+
+void grover_destroy(grover_ctx *ctx)
+{
+    if (!ctx)
+        return;
+    (void)hipStreamSynchronize(ctx->stream);
+    release(ctx);
+}
+
+}  // extern "C"

@@ -1,0 +1,86 @@
+// Initial state and marked set (Algorithm 5's preparation; Algorithm 3's solution list k[]).
+//   - fill: psi = H^n|0> written directly as the uniform superposition, 2^(-n/2) in every amplitude;
+//   - hash predicate: i is marked iff the low `bits` bits of SplitMix64_i(seed) are zero; every index is
+//     tested on the device and the hits are compacted into a list (sorted afterwards by the host).
+#include "internal.h"
+
+namespace grover {
+namespace {
+
+constexpr int kBlock = 256;
+
+template <class T>
+__global__ __launch_bounds__(kBlock) void fill_kernel(void *state, uint64_t nvec, typename T::vec value)
+{
+    typename T::vec *st = static_cast<typename T::vec *>(state);
+    const uint64_t stride = uint64_t(gridDim.x) * kBlock;
+    for (uint64_t v = uint64_t(blockIdx.x) * kBlock + threadIdx.x; v < nvec; v += stride)
+        st[v] = value;
+}
+
+__global__ __launch_bounds__(kBlock) void hash_marks_kernel(uint64_t N, uint64_t seed, uint64_t mask,
+                                                            uint64_t *out, uint64_t cap,
+                                                            unsigned long long *count)
+{
+    const uint64_t stride = uint64_t(gridDim.x) * kBlock;
+    for (uint64_t i = uint64_t(blockIdx.x) * kBlock + threadIdx.x; i < N; i += stride) {
+        if ((splitmix64(seed, i) & mask) == 0) {
+            const unsigned long long pos = atomicAdd(count, 1ull);
+            if (pos < cap)
+                out[pos] = i;
+        }
+    }
+}
+
+unsigned grid_for(uint64_t work, int cu_count)
+{
+    const uint64_t want = (work + kBlock - 1) / kBlock;
+    const uint64_t cap = uint64_t(cu_count > 0 ? cu_count : 256) * 16;
+    return unsigned(want < cap ? (want > 0 ? want : 1) : cap);
+}
+
+}  // namespace
+
+hipError_t launch_fill_uniform(grover_ctx *c)
+{
+    // 2^(-n/2), correctly rounded: exact for even n; sqrt(2) * 2^(-(n+1)/2) for odd n.
+    const double a = (c->n % 2 == 0) ? ldexp(1.0, -int(c->n / 2)) : ldexp(sqrt(2.0), -int((c->n + 1) / 2));
+    void *state = c->state;
+    switch (c->dtype) {
+    case GROVER_F64_REAL: {
+        uint64_t nvec = c->N / 2;
+        double2 v = make_double2(a, a);
+        void *args[] = {&state, &nvec, &v};
+        return hipLaunchKernel(reinterpret_cast<const void *>(&fill_kernel<F64Real>),
+                               dim3(grid_for(nvec, c->cu_count)), dim3(kBlock), args, 0, c->stream);
+    }
+    case GROVER_C64: {
+        uint64_t nvec = c->N / 2;
+        const float af = float(a);
+        float4 v = make_float4(af, 0.0f, af, 0.0f);
+        void *args[] = {&state, &nvec, &v};
+        return hipLaunchKernel(reinterpret_cast<const void *>(&fill_kernel<C64>),
+                               dim3(grid_for(nvec, c->cu_count)), dim3(kBlock), args, 0, c->stream);
+    }
+    case GROVER_C128: {
+        uint64_t nvec = c->N;
+        double2 v = make_double2(a, 0.0);
+        void *args[] = {&state, &nvec, &v};
+        return hipLaunchKernel(reinterpret_cast<const void *>(&fill_kernel<C128>),
+                               dim3(grid_for(nvec, c->cu_count)), dim3(kBlock), args, 0, c->stream);
+    }
+    default: return hipErrorInvalidValue;
+    }
+}
+
+hipError_t launch_hash_marks(grover_ctx *c, uint64_t seed, uint32_t bits, uint64_t *out, uint64_t cap,
+                             unsigned long long *count)
+{
+    uint64_t N = c->N;
+    uint64_t mask = bits >= 64 ? ~uint64_t(0) : ((uint64_t(1) << bits) - 1u);
+    void *args[] = {&N, &seed, &mask, &out, &cap, &count};
+    return hipLaunchKernel(reinterpret_cast<const void *>(&hash_marks_kernel), dim3(grid_for(N, c->cu_count)),
+                           dim3(kBlock), args, 0, c->stream);
+}
+
+}  // namespace grover

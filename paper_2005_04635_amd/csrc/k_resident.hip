@@ -1,0 +1,119 @@
+// On-chip iteration for small states (n <= 14): one workgroup of 1024 threads loads the whole state into
+// registers once, runs all k iterations of Algorithm 5's loop body there (oracle sign, sum, update), and
+// writes it back once.  The only synchronisation per iteration is the workgroup barrier of the sum, so
+// small searches (e.g. n = 10, 25 iterations) cost one launch instead of 2k passes over memory.
+#include "internal.h"
+
+namespace grover {
+namespace {
+
+constexpr int kBlock = kResidentBlock;
+
+struct ResidentArgs {
+    void *state;
+    uint64_t nvec;
+    double N;
+    const uint64_t *marks;
+    uint64_t m;
+    uint64_t iters;
+};
+
+// E = 16-byte vectors per thread; vector v = e * kBlock + threadIdx.x (coalesced load and store).
+template <class T, int E>
+__global__ __launch_bounds__(kBlock) void resident_iterate_kernel(ResidentArgs a)
+{
+    using V = typename T::vec;
+    __shared__ double red[2 * (kBlock / kWave)];
+    __shared__ double bsum[2];
+    V *st = static_cast<V *>(a.state);
+    const unsigned tid = threadIdx.x;
+    V x[E];
+    unsigned bits[E];
+#pragma unroll
+    for (int e = 0; e < E; ++e) {
+        const uint64_t v = uint64_t(e) * kBlock + tid;
+        if (v < a.nvec) {
+            x[e] = st[v];
+            bits[e] = marked_bits<T::EPV>(a.marks, 0, a.m, v * T::EPV);
+        } else {
+            bits[e] = 0u;
+        }
+    }
+    double sr = 0.0, si = 0.0;
+#pragma unroll
+    for (int e = 0; e < E; ++e)
+        if (uint64_t(e) * kBlock + tid < a.nvec)
+            accum_vec<T>(x[e], bits[e], sr, si);
+    block_sum2(sr, si, red);
+    if (tid == 0) {
+        bsum[0] = sr;
+        bsum[1] = si;
+    }
+    __syncthreads();
+    sr = bsum[0];
+    si = bsum[1];
+    for (uint64_t it = 0; it < a.iters; ++it) {
+        const double mr = (sr * 2.0) / a.N, mi = (si * 2.0) / a.N;
+        double ar = 0.0, ai = 0.0;
+#pragma unroll
+        for (int e = 0; e < E; ++e)
+            if (uint64_t(e) * kBlock + tid < a.nvec)
+                update_vec<T>(x[e], mr, mi, bits[e], ar, ai);
+        block_sum2(ar, ai, red);
+        if (tid == 0) {
+            bsum[0] = ar;
+            bsum[1] = ai;
+        }
+        __syncthreads();
+        sr = bsum[0];
+        si = bsum[1];
+    }
+#pragma unroll
+    for (int e = 0; e < E; ++e) {
+        const uint64_t v = uint64_t(e) * kBlock + tid;
+        if (v < a.nvec)
+            st[v] = x[e];
+    }
+}
+
+template <class T>
+const void *pick(uint64_t vec_per_thread)
+{
+    switch (vec_per_thread) {
+    case 1: return reinterpret_cast<const void *>(&resident_iterate_kernel<T, 1>);
+    case 2: return reinterpret_cast<const void *>(&resident_iterate_kernel<T, 2>);
+    case 4: return reinterpret_cast<const void *>(&resident_iterate_kernel<T, 4>);
+    case 8: return reinterpret_cast<const void *>(&resident_iterate_kernel<T, 8>);
+    case 16: return reinterpret_cast<const void *>(&resident_iterate_kernel<T, 16>);
+    default: return nullptr;
+    }
+}
+
+}  // namespace
+
+hipError_t launch_resident_iterate(grover_ctx *c, uint64_t k)
+{
+    ResidentArgs a;
+    a.state = c->state;
+    a.nvec = c->N / (c->dtype == GROVER_C128 ? 1 : 2);
+    a.N = double(c->N);
+    a.marks = c->marks_dev;
+    a.m = c->marks.size();
+    a.iters = k;
+    uint64_t per = (a.nvec + kBlock - 1) / kBlock;
+    uint64_t e = 1;
+    while (e < per)
+        e <<= 1;
+    const void *fn = nullptr;
+    switch (c->dtype) {
+    case GROVER_F64_REAL: fn = pick<F64Real>(e); break;
+    case GROVER_C64: fn = pick<C64>(e); break;
+    case GROVER_C128: fn = pick<C128>(e); break;
+    }
+    if (!fn)
+        return hipErrorInvalidValue;
+    void *args[] = {&a};
+    return hipLaunchKernel(fn, dim3(1), dim3(kBlock), args, 0, c->stream);
+}
+
+}  // namespace grover

@@ -1,0 +1,336 @@
+"""ctypes binding of libgrover's C ABI (include/grover.h), with the same function names.
+
+Argument marshalling only: every step of the simulation runs in the library's HIP kernels. PyTorch, when
+used (the `Grover` class), only provides device memory for the state and the HIP stream.
+
+The library is loaded after `import torch` so that both share one HIP runtime in the process. Loading fails
+loudly when libgrover.so has not been built; there is no fallback implementation.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import threading
+from typing import Optional
+
+import numpy as np
+
+_PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_PKG, "libgrover.so")
+
+GROVER_OK = 0
+GROVER_E_INVAL = -1
+GROVER_E_NOMEM = -2
+GROVER_E_HIP = -3
+GROVER_E_COOP = -4
+GROVER_E_UNSUPPORTED = -5
+GROVER_E_PREDICATE = -6
+GROVER_E_TIMEOUT = -7
+
+GROVER_F64_REAL, GROVER_C64, GROVER_C128 = 0, 1, 2
+GROVER_ORACLE_LIST, GROVER_ORACLE_HASH = 0, 1
+GROVER_FORM_AUTO, GROVER_FORM_FUSED, GROVER_FORM_RESIDENT, GROVER_FORM_TWO_PASS = 0, 1, 2, 3
+
+DTYPES = {"f64": GROVER_F64_REAL, "c64": GROVER_C64, "c128": GROVER_C128}
+FORMS = {"auto": GROVER_FORM_AUTO, "fused": GROVER_FORM_FUSED, "resident": GROVER_FORM_RESIDENT,
+         "two_pass": GROVER_FORM_TWO_PASS}
+ELEM_BYTES = {GROVER_F64_REAL: 8, GROVER_C64: 8, GROVER_C128: 16}
+NUMPY_DTYPES = {GROVER_F64_REAL: np.float64, GROVER_C64: np.complex64, GROVER_C128: np.complex128}
+
+# grover_query keys
+Q_FORM, Q_GRID, Q_BLOCK, Q_ELEM_BYTES, Q_N, Q_M = 0, 1, 2, 3, 4, 5
+
+
+class GroverError(RuntimeError):
+    def __init__(self, status: int, message: str):
+        super().__init__(f"{message} (status {status})")
+        self.status = status
+
+
+class grover_config(ctypes.Structure):
+    _fields_ = [
+        ("n", ctypes.c_uint32),
+        ("dtype", ctypes.c_uint32),
+        ("oracle_kind", ctypes.c_uint32),
+        ("hash_bits", ctypes.c_uint32),
+        ("marked", ctypes.POINTER(ctypes.c_uint64)),
+        ("m", ctypes.c_uint64),
+        ("hash_seed", ctypes.c_uint64),
+        ("form", ctypes.c_uint32),
+        ("flags", ctypes.c_uint32),
+    ]
+
+
+EXPORTS = [
+    "grover_init", "grover_reset", "grover_iterate", "grover_gate_iterate", "grover_apply_hadamard_all",
+    "grover_sample", "grover_sample_u53", "grover_norm", "grover_read_state", "grover_write_state",
+    "grover_state_device", "grover_marked", "grover_sync", "grover_query", "grover_optimal_iterations",
+    "grover_destroy", "grover_status_str", "grover_last_error",
+]
+
+_lock = threading.Lock()
+_lib = None
+
+
+def load(path: str = LIB_PATH):
+    """Load libgrover.so (after torch, so the HIP runtime is shared) and declare its prototypes."""
+    global _lib
+    with _lock:
+        if _lib is not None:
+            return _lib
+        if not os.path.exists(path):
+            raise RuntimeError(f"{path} is not built: run `python -m paper_2005_04635_amd.build` "
+                               "(the HIP library is required; there is no fallback)")
+        try:
+            import torch  # noqa: F401  (shares its HIP runtime with the library)
+        except ImportError:
+            pass
+        lib = ctypes.CDLL(path)
+        P, u64, u32, i32 = ctypes.c_void_p, ctypes.c_uint64, ctypes.c_uint32, ctypes.c_int
+        pu64 = ctypes.POINTER(ctypes.c_uint64)
+        sig = {
+            "grover_init": (i32, [ctypes.POINTER(P), ctypes.POINTER(grover_config), P, P, ctypes.c_size_t]),
+            "grover_reset": (i32, [P]),
+            "grover_iterate": (i32, [P, u64]),
+            "grover_gate_iterate": (i32, [P, u64]),
+            "grover_apply_hadamard_all": (i32, [P]),
+            "grover_sample": (i32, [P, u64, u64, P, i32]),
+            "grover_sample_u53": (i32, [P, P, i32, u64, P, i32]),
+            "grover_norm": (i32, [P, ctypes.POINTER(ctypes.c_double)]),
+            "grover_read_state": (i32, [P, P, ctypes.c_size_t]),
+            "grover_write_state": (i32, [P, P, ctypes.c_size_t]),
+            "grover_state_device": (i32, [P, ctypes.POINTER(P), ctypes.POINTER(ctypes.c_size_t)]),
+            "grover_marked": (i32, [P, pu64, u64, pu64]),
+            "grover_sync": (i32, [P]),
+            "grover_query": (i32, [P, i32, ctypes.POINTER(ctypes.c_int64)]),
+            "grover_optimal_iterations": (u64, [u32, u64]),
+            "grover_destroy": (None, [P]),
+            "grover_status_str": (ctypes.c_char_p, [i32]),
+            "grover_last_error": (ctypes.c_char_p, [P]),
+        }
+        for name, (res, args) in sig.items():
+            fn = getattr(lib, name)
+            fn.restype = res
+            fn.argtypes = args
+        _lib = lib
+        return lib
+
+
+def _check(ctx, status: int) -> None:
+    if status != GROVER_OK:
+        lib = load()
+        msg = lib.grover_last_error(ctx).decode() if ctx else ""
+        if not msg:
+            msg = lib.grover_status_str(status).decode()
+        raise GroverError(status, msg)
+
+
+# ------------------------------------------------------------------------- one wrapper per C function
+def grover_init(cfg: grover_config, hip_stream: int = 0, state_dev: int = 0, state_bytes: int = 0):
+    ctx = ctypes.c_void_p()
+    st = load().grover_init(ctypes.byref(ctx), ctypes.byref(cfg), hip_stream or None, state_dev or None,
+                            state_bytes)
+    _check(None, st)
+    return ctx
+
+
+def grover_reset(ctx) -> None:
+    _check(ctx, load().grover_reset(ctx))
+
+
+def grover_iterate(ctx, k: int) -> None:
+    _check(ctx, load().grover_iterate(ctx, k))
+
+
+def grover_gate_iterate(ctx, k: int) -> None:
+    _check(ctx, load().grover_gate_iterate(ctx, k))
+
+
+def grover_apply_hadamard_all(ctx) -> None:
+    _check(ctx, load().grover_apply_hadamard_all(ctx))
+
+
+def grover_sample(ctx, shots: int, seed: int, out: int, out_is_device: bool) -> None:
+    _check(ctx, load().grover_sample(ctx, shots, seed & (2**64 - 1), out or None, int(out_is_device)))
+
+
+def grover_sample_u53(ctx, u53: int, u53_is_device: bool, shots: int, out: int, out_is_device: bool) -> None:
+    _check(ctx, load().grover_sample_u53(ctx, u53 or None, int(u53_is_device), shots, out or None,
+                                         int(out_is_device)))
+
+
+def grover_norm(ctx) -> float:
+    v = ctypes.c_double()
+    _check(ctx, load().grover_norm(ctx, ctypes.byref(v)))
+    return v.value
+
+
+def grover_read_state(ctx, host: int, nbytes: int) -> None:
+    _check(ctx, load().grover_read_state(ctx, host, nbytes))
+
+
+def grover_write_state(ctx, host: int, nbytes: int) -> None:
+    _check(ctx, load().grover_write_state(ctx, host, nbytes))
+
+
+def grover_state_device(ctx):
+    p, b = ctypes.c_void_p(), ctypes.c_size_t()
+    _check(ctx, load().grover_state_device(ctx, ctypes.byref(p), ctypes.byref(b)))
+    return p.value, b.value
+
+
+def grover_marked(ctx, cap: int) -> np.ndarray:
+    out = np.zeros(max(cap, 1), dtype=np.uint64)
+    count = ctypes.c_uint64()
+    _check(ctx, load().grover_marked(ctx, out.ctypes.data_as(ctypes.POINTER(ctypes.c_uint64)), cap,
+                                     ctypes.byref(count)))
+    return out[: min(cap, count.value)].copy()
+
+
+def grover_sync(ctx) -> None:
+    _check(ctx, load().grover_sync(ctx))
+
+
+def grover_query(ctx, key: int) -> int:
+    v = ctypes.c_int64()
+    _check(ctx, load().grover_query(ctx, key, ctypes.byref(v)))
+    return v.value
+
+
+def grover_optimal_iterations(n: int, m: int) -> int:
+    return int(load().grover_optimal_iterations(n, m))
+
+
+def grover_destroy(ctx) -> None:
+    if ctx:
+        load().grover_destroy(ctx)
+
+
+def grover_status_str(status: int) -> str:
+    return load().grover_status_str(status).decode()
+
+
+def grover_last_error(ctx) -> str:
+    return load().grover_last_error(ctx).decode()
+
+
+# --------------------------------------------------------------------------------- convenience class
+class Grover:
+    """One search instance: a state on the current GPU plus its marked set.
+
+    n          qubits (N = 2^n amplitudes)
+    dtype      "f64" (real), "c64" or "c128"
+    marks      explicit marked indices (oracle list), or None with hash_seed/hash_bits/m for the predicate
+    form       "auto", "fused", "resident" or "two_pass"
+    state      optional torch tensor (on the current device) to adopt as the state; otherwise one is made
+    The state tensor is `self.state` (torch, 1-D, N elements of the dtype); kernels run on torch's
+    current stream at construction.
+    """
+
+    def __init__(self, n: int, dtype: str = "c64", marks=None, *, hash_seed: Optional[int] = None,
+                 hash_bits: int = 0, m: Optional[int] = None, form: str = "auto", state=None):
+        import torch
+
+        self.n = n
+        self.dtype = DTYPES[dtype]
+        N = 1 << n
+        tdt = {GROVER_F64_REAL: torch.float64, GROVER_C64: torch.complex64, GROVER_C128: torch.complex128}[self.dtype]
+        self.state = state if state is not None else torch.empty(N, dtype=tdt, device="cuda")
+        if self.state.dtype != tdt or self.state.numel() != N or not self.state.is_contiguous():
+            raise ValueError("state tensor must be contiguous with N elements of the requested dtype")
+        self.stream = torch.cuda.current_stream()
+        cfg = grover_config()
+        cfg.n = n
+        cfg.dtype = self.dtype
+        cfg.form = FORMS[form]
+        cfg.flags = 0
+        if hash_seed is not None:
+            cfg.oracle_kind = GROVER_ORACLE_HASH
+            cfg.hash_seed = hash_seed & (2**64 - 1)
+            cfg.hash_bits = hash_bits
+            cfg.m = int(m if m is not None else 0)
+            self._marks = None
+        else:
+            self._marks = np.ascontiguousarray(np.asarray(marks if marks is not None else [], dtype=np.uint64))
+            cfg.oracle_kind = GROVER_ORACLE_LIST
+            cfg.m = self._marks.size
+            cfg.marked = self._marks.ctypes.data_as(ctypes.POINTER(ctypes.c_uint64))
+        nbytes = N * ELEM_BYTES[self.dtype]
+        self.ctx = grover_init(cfg, self.stream.cuda_stream, self.state.data_ptr(), nbytes)
+        self.N = N
+        self.nbytes = nbytes
+
+    # -- operations
+    def reset(self) -> "Grover":
+        grover_reset(self.ctx)
+        return self
+
+    def iterate(self, k: int) -> "Grover":
+        grover_iterate(self.ctx, k)
+        return self
+
+    def gate_iterate(self, k: int) -> "Grover":
+        grover_gate_iterate(self.ctx, k)
+        return self
+
+    def hadamard_all(self) -> "Grover":
+        grover_apply_hadamard_all(self.ctx)
+        return self
+
+    def sample(self, shots: int, seed: Optional[int] = None, u53=None, device_out: bool = False):
+        """Measurement shots: device-generated uniforms from `seed`, or the given 53-bit uniforms `u53`
+        (numpy array or torch device tensor of uint64/int64).  Returns numpy uint64 (host) or a torch
+        int64 device tensor (device_out=True)."""
+        import torch
+
+        if device_out:
+            out = torch.empty(shots, dtype=torch.int64, device=self.state.device)
+            optr, odev = out.data_ptr(), True
+        else:
+            out = np.empty(shots, dtype=np.uint64)
+            optr, odev = out.ctypes.data, False
+        if u53 is None:
+            grover_sample(self.ctx, shots, int(seed or 0), optr, odev)
+        elif isinstance(u53, np.ndarray):
+            u = np.ascontiguousarray(u53, dtype=np.uint64)
+            grover_sample_u53(self.ctx, u.ctypes.data, False, shots, optr, odev)
+        else:
+            grover_sample_u53(self.ctx, u53.data_ptr(), True, shots, optr, odev)
+        return out
+
+    def norm(self) -> float:
+        return grover_norm(self.ctx)
+
+    def read_state(self) -> np.ndarray:
+        out = np.empty(self.N, dtype=NUMPY_DTYPES[self.dtype])
+        grover_read_state(self.ctx, out.ctypes.data, self.nbytes)
+        return out
+
+    def write_state(self, psi: np.ndarray) -> "Grover":
+        a = np.ascontiguousarray(psi, dtype=NUMPY_DTYPES[self.dtype])
+        grover_write_state(self.ctx, a.ctypes.data, self.nbytes)
+        return self
+
+    def marked(self) -> np.ndarray:
+        return grover_marked(self.ctx, grover_query(self.ctx, Q_M))
+
+    def sync(self) -> None:
+        grover_sync(self.ctx)
+
+    def query(self, key: int) -> int:
+        return grover_query(self.ctx, key)
+
+    def close(self) -> None:
+        if getattr(self, "ctx", None):
+            grover_destroy(self.ctx)
+            self.ctx = None
+
+    def __del__(self):
+        import sys
+
+        if sys.is_finalizing():  # the HIP runtime may already be torn down
+            return
+        try:
+            self.close()
+        except Exception:
+            pass

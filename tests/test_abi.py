@@ -1,0 +1,130 @@
+"""The C-ABI library loads and exports what include/grover.h declares; host-only paths (no GPU needed)."""
+from __future__ import annotations
+
+import ctypes
+import os
+import re
+import subprocess
+
+import pytest
+
+from conftest import ROOT
+
+HEADER = os.path.join(ROOT, "include", "grover.h")
+LIB = os.path.join(ROOT, "paper_2005_04635_amd", "libgrover.so")
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(grover_[a-z0-9_]+)\s*\(", text)))
+
+
+@pytest.fixture(scope="module")
+def lib():
+    if not os.path.exists(LIB):
+        from paper_2005_04635_amd import build
+
+        build.build()
+    import paper_2005_04635_amd as pkg
+
+    return pkg.load()
+
+
+def test_header_declares_the_entry_points():
+    names = declared_functions()
+    for must in ["grover_init", "grover_iterate", "grover_sample", "grover_sample_u53", "grover_gate_iterate",
+                 "grover_apply_hadamard_all", "grover_norm", "grover_optimal_iterations", "grover_destroy"]:
+        assert must in names
+
+
+def test_library_exports_every_declared_symbol(lib):
+    from paper_2005_04635_amd import EXPORTS
+
+    names = declared_functions()
+    assert sorted(EXPORTS) == names, "binding and header disagree"
+    for name in names:
+        assert hasattr(lib, name), name
+    out = subprocess.run(["nm", "-D", "--defined-only", LIB], capture_output=True, text=True, check=True).stdout
+    exported = set(re.findall(r"\bT (grover_\w+)", out))
+    assert set(names) <= exported
+
+
+def test_library_is_gfx950_device_code():
+    """The shared object embeds a gfx950 code object bundle."""
+    data = open(LIB, "rb").read()
+    assert b"gfx950" in data
+
+
+def test_optimal_iterations_host_only(lib):
+    from paper_2005_04635_amd import grover_optimal_iterations as k
+
+    assert k(3, 1) == 2 and k(10, 1) == 25 and k(28, 8) == 4549 and k(26, 4) == 3216 and k(20, 3) == 464
+    assert k(10, 0) == 0 and k(3, 9) == 0 and k(64, 1) == 0
+    assert k(1, 1) == 1 and k(1, 2) == 0  # N = 2: one marked -> floor(pi/4 * sqrt 2) = 1
+
+
+def test_status_strings_and_null_handling(lib):
+    assert lib.grover_status_str(0) == b"ok"
+    for code in range(-7, 0):
+        assert lib.grover_status_str(code) not in (b"", b"unknown status")
+    assert lib.grover_status_str(-99) == b"unknown status"
+    assert lib.grover_last_error(None) == b"no context"
+    assert lib.grover_iterate(None, 5) == -1
+    assert lib.grover_sync(None) == -1
+    lib.grover_destroy(None)
+
+
+@pytest.mark.parametrize("field,value", [("n", 0), ("n", 35), ("dtype", 3), ("oracle_kind", 2), ("form", 4),
+                                         ("flags", 1), ("hash_bits", 65)])
+def test_init_rejects_invalid_config_before_touching_the_device(lib, field, value):
+    from paper_2005_04635_amd.grover import grover_config
+
+    cfg = grover_config()
+    cfg.n = 10
+    setattr(cfg, field, value)
+    ctx = ctypes.c_void_p()
+    assert lib.grover_init(ctypes.byref(ctx), ctypes.byref(cfg), None, None, 0) == -1
+    assert not ctx.value
+
+
+def test_init_rejects_bad_marked_lists(lib):
+    from paper_2005_04635_amd.grover import grover_config
+
+    def init_with(marks, n=4):
+        arr = (ctypes.c_uint64 * max(len(marks), 1))(*marks)
+        cfg = grover_config()
+        cfg.n = n
+        cfg.m = len(marks)
+        cfg.marked = ctypes.cast(arr, ctypes.POINTER(ctypes.c_uint64))
+        ctx = ctypes.c_void_p()
+        return lib.grover_init(ctypes.byref(ctx), ctypes.byref(cfg), None, None, 0)
+
+    assert init_with([3, 3]) == -1       # duplicate: the oracle would flip it twice
+    assert init_with([16]) == -1         # out of range for n = 4
+    assert init_with(list(range(17))) == -1  # m > N
+    cfg = grover_config()
+    cfg.n = 4
+    cfg.m = 2  # list kind with a null list
+    ctx = ctypes.c_void_p()
+    assert lib.grover_init(ctypes.byref(ctx), ctypes.byref(cfg), None, None, 0) == -1
+    assert lib.grover_init(None, ctypes.byref(cfg), None, None, 0) == -1
+    assert lib.grover_init(ctypes.byref(ctx), None, None, None, 0) == -1
+
+
+def test_resident_form_limit(lib):
+    from paper_2005_04635_amd.grover import grover_config
+
+    cfg = grover_config()
+    cfg.n = 15
+    cfg.form = 2  # resident holds at most 2^14 amplitudes
+    ctx = ctypes.c_void_p()
+    assert lib.grover_init(ctypes.byref(ctx), ctypes.byref(cfg), None, None, 0) == -5
+
+
+def test_missing_library_fails_loudly(tmp_path, monkeypatch):
+    import paper_2005_04635_amd.grover as g
+
+    monkeypatch.setattr(g, "_lib", None)
+    with pytest.raises(RuntimeError, match="not built"):
+        g.load(str(tmp_path / "nope.so"))

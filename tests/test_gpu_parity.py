@@ -1,0 +1,275 @@
+"""GPU parity: the HIP library (through its C ABI) against the CPU oracle on the same seeded inputs.
+
+Tolerances (max absolute amplitude error against the binary64 oracle): 1e-12 for binary64 storage
+(f64, c128) and 1e-5 for complex64 storage, as the specification of this build fixes them. Integer results
+(marked lists, sampled indices) must match exactly.
+"""
+from __future__ import annotations
+
+import numpy as np
+import pytest
+
+import workloads
+
+pytestmark = pytest.mark.gpu
+
+TOL = {"f64": 1e-12, "c128": 1e-12, "c64": 1e-5}
+
+
+@pytest.fixture(scope="module")
+def G():
+    import torch
+
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2005_04635_amd as pkg
+
+    pkg.load()
+    return pkg
+
+
+def as_c128(psi: np.ndarray) -> np.ndarray:
+    return np.ascontiguousarray(psi.astype(np.complex128))
+
+
+def start_state(n: int, dtype: str, seed: int) -> np.ndarray:
+    """Random start state, already rounded to the storage type (the oracle starts from the same values)."""
+    psi = workloads.random_state(n, seed, real=(dtype == "f64"))
+    if dtype == "f64":
+        return psi.real.astype(np.float64)
+    return psi.astype(np.complex64 if dtype == "c64" else np.complex128)
+
+
+def assert_close(got: np.ndarray, want: np.ndarray, dtype: str, what: str = ""):
+    err = float(np.max(np.abs(as_c128(got) - want))) if want.size else 0.0
+    assert err <= TOL[dtype], f"{what} max|err| = {err:.3e} > {TOL[dtype]}"
+    return err
+
+
+# ------------------------------------------------------------------------------ the n = 10 workload
+def test_plain_n10_workload_end_to_end(G, orc):
+    """n = 10, real binary64, one marked index from a seed, 25 iterations, 10^4 shots."""
+    w = workloads.PLAIN_N10
+    g = G.Grover(w.n, w.dtype, marks=list(w.marks))
+    assert g.query(0) == 2  # resident form
+    g.iterate(w.iterations)
+    want = orc.search(w.n, list(w.marks), w.iterations)
+    got = g.read_state()
+    assert_close(got, want, "f64", "state")
+    assert abs(g.norm() - 1.0) < 1e-13
+    u = workloads.uniforms_u53(w.shot_seed, w.shots)
+    shots = g.sample(w.shots, u53=u)
+    # bit-exact on identical input: the oracle sampler on the GPU's own state
+    assert np.array_equal(shots, orc.sample(as_c128(got), u))
+    # end to end: the oracle's state gives the same shots here (state difference ~1e-16)
+    assert np.array_equal(shots, orc.sample(want, u))
+    assert np.mean(shots == w.marks[0]) > 0.99
+    g.close()
+
+
+# ----------------------------------------------------------------------------- elementwise parity
+CASES = []
+for form, ns in [("resident", [1, 2, 3, 5, 10, 12, 14]), ("fused", [1, 3, 9, 11, 13, 15, 17, 20]),
+                 ("two_pass", [1, 4, 10, 16, 19])]:
+    for n in ns:
+        for dtype in ["f64", "c64", "c128"]:
+            CASES.append((form, n, dtype))
+
+
+@pytest.mark.parametrize("form,n,dtype", CASES)
+def test_iterate_matches_oracle(G, orc, form, n, dtype):
+    """Random start state (complex unless real storage), several marked-set sizes and iteration counts."""
+    N = 1 << n
+    for mi, m in enumerate(sorted({0, 1, min(3, N), max(1, N // 3), N})):
+        marks = workloads.distinct_marks(n, m, seed=11 * n + m)
+        psi0 = start_state(n, dtype, seed=1000 + n + mi)
+        g = G.Grover(n, dtype, marks=marks, form=form)
+        g.write_state(psi0)
+        want = as_c128(psi0)
+        done = 0
+        for k in (0, 1, 6):
+            g.iterate(k)
+            orc.iterate(want, marks, k)
+            done += k
+            assert_close(g.read_state(), want, dtype, f"{form} n={n} m={m} k={done}")
+        g.close()
+
+
+@pytest.mark.parametrize("form,n,dtype", [("resident", 10, "c64"), ("fused", 16, "c64"), ("fused", 18, "c128"),
+                                          ("two_pass", 14, "f64"), ("fused", 12, "f64")])
+def test_search_to_optimum_matches_oracle_and_closed_form(G, orc, form, n, dtype):
+    m = 3
+    marks = workloads.distinct_marks(n, m, seed=n)
+    k = orc.optimal_iterations(n, m)
+    g = G.Grover(n, dtype, marks=marks, form=form)
+    g.iterate(k)
+    got = g.read_state()
+    assert_close(got, orc.search(n, marks, k), dtype, "state")
+    a, b = orc.two_class(n, m, k)
+    mask = np.zeros(1 << n, dtype=bool)
+    mask[marks.astype(np.int64)] = True
+    # two-class structure holds exactly in any precision
+    assert np.all(got[mask] == got[mask][0]) and np.all(got[~mask] == got[~mask][0])
+    assert abs(complex(got[mask][0]) - a) <= TOL[dtype] and abs(complex(got[~mask][0]) - b) <= TOL[dtype]
+    if dtype != "f64":
+        assert np.all(got.imag == 0)
+    g.close()
+
+
+@pytest.mark.parametrize("form,n", [("resident", 9), ("fused", 13), ("fused", 19), ("two_pass", 12)])
+def test_iterate_composes_bitwise(G, form, n):
+    """iterate(a); iterate(b) equals iterate(a + b) bit for bit, and reruns are bitwise identical."""
+    marks = workloads.distinct_marks(n, 5, seed=3)
+    psi0 = start_state(n, "c64", seed=77)
+    ga = G.Grover(n, "c64", marks=marks, form=form).write_state(psi0)
+    gb = G.Grover(n, "c64", marks=marks, form=form).write_state(psi0)
+    ga.iterate(7).iterate(0).iterate(13)
+    gb.iterate(20)
+    sa, sb = ga.read_state(), gb.read_state()
+    assert np.array_equal(sa.view(np.uint32), sb.view(np.uint32))
+    gb.write_state(psi0).iterate(20)
+    assert np.array_equal(gb.read_state().view(np.uint32), sb.view(np.uint32))
+    ga.close()
+    gb.close()
+
+
+def test_fused_grid_shapes(G, orc, monkeypatch):
+    """Forced persistent-grid sizes: more workgroups than tiles (empty chunks), a prime count (ragged
+    chunks) and a single workgroup."""
+    n, dtype = 15, "c128"
+    marks = workloads.distinct_marks(n, 6, seed=8)
+    psi0 = start_state(n, dtype, seed=8)
+    want = orc.iterate(as_c128(psi0), marks, 9)
+    for grid in ["1", "7", "97", "600"]:
+        monkeypatch.setenv("GROVER_FUSED_GRID", grid)
+        g = G.Grover(n, dtype, marks=marks, form="fused")
+        assert g.query(1) == int(grid)
+        g.write_state(psi0).iterate(9)
+        assert_close(g.read_state(), want, dtype, f"grid={grid}")
+        g.close()
+
+
+# ----------------------------------------------------------------------------------- hash oracle
+def test_hash_predicate_marks_match_oracle(G, orc):
+    n, bits = 20, 17
+    seed = None
+    for s in range(5000, 5200):
+        _, c = orc.hash_marks(n, s, bits, cap=0)
+        if c == 8:
+            seed = s
+            break
+    assert seed is not None
+    want, _ = orc.hash_marks(n, seed, bits, cap=64)
+    g = G.Grover(n, "c64", hash_seed=seed, hash_bits=bits, m=8)
+    assert np.array_equal(g.marked(), want)
+    k = orc.optimal_iterations(n, 8)
+    g.iterate(k)
+    assert_close(g.read_state(), orc.search(n, want, k), "c64", "hash search")
+    g.close()
+    with pytest.raises(G.GroverError) as e:
+        G.Grover(n, "c64", hash_seed=seed, hash_bits=bits, m=7)
+    assert e.value.status == -6
+
+
+# ------------------------------------------------------------------------------------- gate path
+@pytest.mark.parametrize("n,dtype", [(1, "c128"), (3, "f64"), (6, "c128"), (9, "c64"), (11, "c128")])
+def test_gate_level_path_matches_oracle(G, orc, n, dtype):
+    marks = workloads.distinct_marks(n, 2 if n > 1 else 1, seed=n)
+    psi0 = start_state(n, dtype, seed=60 + n)
+    g = G.Grover(n, dtype, marks=marks).write_state(psi0)
+    g.hadamard_all()
+    want = orc.hadamard_all(as_c128(psi0))
+    assert_close(g.read_state(), want, dtype, "H^n")
+    g.write_state(psi0).gate_iterate(3)
+    want = orc.gate_iterate(as_c128(psi0), marks, 3)
+    assert_close(g.read_state(), want, dtype, "gate iterate")
+    # the two paths agree (the paper's equivalence), here on the GPU
+    g2 = G.Grover(n, dtype, marks=marks).write_state(psi0).iterate(3)
+    assert_close(g2.read_state(), want, dtype, "gate vs proposed")
+    g.close()
+    g2.close()
+
+
+# ----------------------------------------------------------------------------------- measurement
+@pytest.mark.parametrize("n,dtype", [(1, "c64"), (4, "f64"), (12, "c64"), (13, "c128"), (18, "c64")])
+def test_sampler_bit_exact_on_identical_input(G, orc, n, dtype):
+    psi0 = start_state(n, dtype, seed=5 + n)
+    if n > 2:
+        psi0[3] = 0  # a zero-probability index
+    g = G.Grover(n, dtype, marks=[]).write_state(psi0)
+    u = workloads.uniforms_u53(31 + n, 50_000)
+    u[:3] = [0, (1 << 53) - 1, 1 << 52]
+    host = g.sample(u.size, u53=u)
+    want = orc.sample(as_c128(psi0), u)
+    assert np.array_equal(host, want)
+    dev = g.sample(u.size, u53=u, device_out=True).cpu().numpy().astype(np.uint64)
+    assert np.array_equal(dev, want)
+    import torch
+
+    ut = torch.from_numpy(u.astype(np.int64)).cuda()
+    assert np.array_equal(g.sample(u.size, u53=ut), want)
+    # device-generated uniforms: SplitMix64_j(seed) >> 11, the oracle's own generator
+    assert np.array_equal(g.sample(20_000, seed=99), orc.sample(as_c128(psi0), orc.uniforms_u53(99, 20_000)))
+    if n > 2:
+        assert not np.any(host == 3)
+    assert g.sample(0, seed=1).size == 0
+    g.close()
+
+
+def test_sampler_zero_state_is_an_error(G):
+    g = G.Grover(5, "c64", marks=[]).write_state(np.zeros(32, dtype=np.complex64))
+    with pytest.raises(G.GroverError):
+        g.sample(10, seed=1)
+    g.write_state(np.ones(32, dtype=np.complex64) / np.sqrt(32))
+    assert g.sample(10, seed=1).size == 10  # the error state was cleared
+    g.close()
+
+
+@pytest.mark.parametrize("dtype", ["f64", "c64", "c128"])
+def test_norm_matches_oracle(G, orc, dtype):
+    psi0 = start_state(16, dtype, seed=4)
+    g = G.Grover(16, dtype, marks=[]).write_state(psi0)
+    assert abs(g.norm() - orc.norm(as_c128(psi0))) < 1e-14
+    g.reset()
+    assert abs(g.norm() - 1.0) < (1e-14 if dtype != "c64" else 1e-6)
+    g.close()
+
+
+# ------------------------------------------------------------------------------ failure handling
+def test_cooperative_grid_too_large_is_reported(G, monkeypatch):
+    monkeypatch.setenv("GROVER_FUSED_GRID", str(1 << 24))
+    with pytest.raises(G.GroverError) as e:
+        G.Grover(16, "c64", marks=[1], form="fused")
+    assert e.value.status == -4
+
+
+def test_barrier_timeout_is_reported_and_recovers(G, orc, monkeypatch):
+    """A zero wait limit makes the first grid barrier give up: every workgroup exits, grover_sync reports
+    the timeout, and the context works again afterwards."""
+    monkeypatch.setenv("GROVER_BARRIER_TIMEOUT_MS", "0")
+    monkeypatch.setenv("GROVER_FUSED_GRID", "64")
+    g = G.Grover(16, "c64", marks=[5], form="fused")
+    g.iterate(3)
+    with pytest.raises(G.GroverError) as e:
+        g.sync()
+    assert e.value.status == -7
+    g.close()
+    monkeypatch.delenv("GROVER_BARRIER_TIMEOUT_MS")
+    g = G.Grover(16, "c64", marks=[5], form="fused").iterate(3)
+    g.sync()
+    assert_close(g.read_state(), orc.search(16, [5], 3), "c64")
+    g.close()
+
+
+def test_caller_buffer_is_adopted_and_size_checked(G):
+    import torch
+
+    buf = torch.zeros(1 << 12, dtype=torch.complex64, device="cuda")
+    g = G.Grover(12, "c64", marks=[7], state=buf)
+    assert G.grover_state_device(g.ctx)[0] == buf.data_ptr()
+    g.iterate(4)
+    torch.cuda.synchronize()
+    assert np.array_equal(buf.cpu().numpy(), g.read_state())
+    g.close()
+    with pytest.raises(ValueError):
+        G.Grover(12, "c64", marks=[7], state=torch.zeros(100, dtype=torch.complex64, device="cuda"))
