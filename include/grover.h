@@ -153,7 +153,8 @@ int grover_marked(grover_ctx *ctx, uint64_t *out, uint64_t cap, uint64_t *count)
 int grover_sync(grover_ctx *ctx);
 
 /* grover_query — launch facts for diagnostics.  key: 0 = resolved form, 1 = persistent grid size
- * (workgroups), 2 = workgroup size, 3 = element size in bytes, 4 = N, 5 = number of marked indices. */
+ * (workgroups), 2 = workgroup size, 3 = element size in bytes, 4 = N, 5 = number of marked indices,
+ * 6 = grid-barrier wait limit in device wall-clock ticks. */
 int grover_query(grover_ctx *ctx, int key, int64_t *value);
 
 /* grover_optimal_iterations — floor(pi/4 * sqrt(2^n / m)) (Algorithm 5's iteration count with m

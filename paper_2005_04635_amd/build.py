@@ -3,7 +3,7 @@
     python -m paper_2005_04635_amd.build
 
 Every HIP source under csrc/ is compiled to an object in csrc/../_build, in parallel, then linked into one
-shared library.  Flags that matter for results:
+shared library; the native driver csrc/tools/grover_cli.hip is linked against it as grover_cli.  Flags that matter for results:
   -ffp-contract=off       no implicit fused multiply-add, so each binary64 operation rounds as written;
   -fno-fast-math          IEEE semantics;
   -target-feature -packed-fp32-ops   no packed FP32 instructions in device code.
@@ -23,6 +23,7 @@ CSRC = os.path.join(PKG, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 BUILD = os.path.join(PKG, "_build")
 LIB = os.path.join(PKG, "libgrover.so")
+CLI = os.path.join(PKG, "grover_cli")
 ARCH = "gfx950"
 
 
@@ -73,9 +74,22 @@ def build(verbose: bool = False) -> str:
     if r.returncode != 0:
         raise RuntimeError(f"link failed: {' '.join(cmd)}\n{r.stdout}\n{r.stderr}")
     os.replace(tmp, LIB)
+    build_cli()
     if verbose:
-        print(f"built {LIB}")
+        print(f"built {LIB} and {CLI}")
     return LIB
+
+
+def build_cli() -> str:
+    """The native driver (csrc/tools/grover_cli.hip), linked against libgrover.so next to it."""
+    src = os.path.join(CSRC, "tools", "grover_cli.hip")
+    tmp = CLI + ".tmp"
+    cmd = [hipcc(), *common_flags(), "-o", tmp, src, f"-L{PKG}", "-lgrover", "-Wl,-rpath,$ORIGIN"]
+    r = subprocess.run(cmd, capture_output=True, text=True)
+    if r.returncode != 0:
+        raise RuntimeError(f"CLI build failed: {' '.join(cmd)}\n{r.stdout}\n{r.stderr}")
+    os.replace(tmp, CLI)
+    return CLI
 
 
 if __name__ == "__main__":

@@ -66,12 +66,60 @@ void release(grover_ctx *c)
 
 int check_ctx(const grover_ctx *c) { return c ? GROVER_OK : GROVER_E_INVAL; }
 
+// Clear the grid-barrier state after a wait gave up (the device grid has exited by then).
+hipError_t reset_barrier(grover_ctx *c)
+{
+    hipError_t e = hipMemsetAsync(c->sync, 0, sizeof(GridSync), c->stream);
+    if (e == hipSuccess)
+        e = hipStreamSynchronize(c->stream);
+    c->generation = 0;
+    return e;
+}
+
+// Persistent grid of the fused form.  Every workgroup of a launch must be resident at once, or the first
+// grid barrier can never complete.  The runtime's occupancy figure has proved optimistic (MI355X admits
+// fewer workgroups per CU of this kernel than it reports), so the grid is confirmed on the device: the
+// fused kernel runs with zero iterations (a read-only sum pass and one barrier) under a short wait limit,
+// and on a time-out the grid shrinks by one workgroup per CU.  GROVER_FUSED_GRID forces a grid, which must
+// pass the same check.  Allocates the barrier state and the per-workgroup partials.
+int select_persistent_grid(grover_ctx *c, int clock_khz)
+{
+    int per_cu = 0, block = 0;
+    int64_t forced = 0;
+    GROVER_HIP(c, fused_configure(c, &per_cu, &block, &forced), "persistent grid configuration");
+    const int64_t max_grid = forced > 0 ? forced : int64_t(per_cu) * c->cu_count;
+    GROVER_HIP(c, dev_alloc(&c->partials, size_t(2) * max_grid * 2 * sizeof(double)), "barrier allocation");
+    GROVER_HIP(c, dev_alloc(&c->sync, sizeof(GridSync)), "barrier allocation");
+    GROVER_HIP(c, reset_barrier(c), "barrier reset");
+    const uint64_t probe_ticks = uint64_t(clock_khz > 0 ? clock_khz : 100000) * 250;  // 0.25 s
+    const uint64_t tiles = fused_tiles(c);
+    c->block = block;
+    for (int pc = per_cu > 1 ? per_cu - 1 : 1; pc >= 1; --pc) {
+        int64_t g = forced > 0 ? forced : int64_t(pc) * c->cu_count;
+        if (forced == 0 && uint64_t(g) > tiles)
+            g = int64_t(tiles > 0 ? tiles : 1);
+        c->grid = int(g);
+        GROVER_HIP(c, launch_fused_iterate(c, 0, probe_ticks, true), "persistent grid check");
+        GROVER_HIP(c, hipStreamSynchronize(c->stream), "persistent grid check");
+        GridSync gs;
+        GROVER_HIP(c, hipMemcpy(&gs, c->sync, sizeof(gs), hipMemcpyDeviceToHost), "persistent grid check");
+        if (!gs.error)
+            return GROVER_OK;
+        GROVER_HIP(c, reset_barrier(c), "barrier reset");
+        if (forced > 0)
+            break;
+    }
+    return fail(c, GROVER_E_COOP, "no persistent grid of the fused kernel is co-resident on this device");
+}
+
 int run_iterations(grover_ctx *c, uint64_t k)
 {
     if (k == 0)
         return GROVER_OK;
     switch (c->form) {
-    case GROVER_FORM_FUSED: GROVER_HIP(c, launch_fused_iterate(c, k), "fused iterate launch"); break;
+    case GROVER_FORM_FUSED:
+        GROVER_HIP(c, launch_fused_iterate(c, k, c->timeout_ticks), "fused iterate launch");
+        break;
     case GROVER_FORM_RESIDENT: GROVER_HIP(c, launch_resident_iterate(c, k), "resident iterate launch"); break;
     case GROVER_FORM_TWO_PASS: GROVER_HIP(c, launch_twopass_iterate(c, k), "two-pass iterate launch"); break;
     default: return fail(c, GROVER_E_INVAL, "context has no iteration form");
@@ -212,22 +260,7 @@ int grover_init(grover_ctx **out, const grover_config *cfg, void *hip_stream, vo
             throw status;
         }
 
-        if (form == GROVER_FORM_FUSED) {
-            e = fused_configure(c, &c->grid, &c->block);
-            if (e != hipSuccess) {
-                status = hip_fail(c, e, "persistent grid configuration");
-                throw status;
-            }
-            e = dev_alloc(&c->partials, size_t(2) * c->grid * 2 * sizeof(double));
-            if (e == hipSuccess)
-                e = dev_alloc(&c->sync, sizeof(GridSync));
-            if (e == hipSuccess)
-                e = hipMemsetAsync(c->sync, 0, sizeof(GridSync), c->stream);
-            if (e != hipSuccess) {
-                status = hip_fail(c, e, "barrier allocation");
-                throw status;
-            }
-        } else if (form == GROVER_FORM_RESIDENT) {
+        if (form == GROVER_FORM_RESIDENT) {
             c->grid = 1;
             c->block = kResidentBlock;
         } else {
@@ -293,6 +326,12 @@ int grover_init(grover_ctx **out, const grover_config *cfg, void *hip_stream, vo
         if (e != hipSuccess) {
             status = hip_fail(c, e, "initial state");
             throw status;
+        }
+        if (form == GROVER_FORM_FUSED) {
+            // needs the marked list on the device and a written state: it runs the fused kernel
+            status = select_persistent_grid(c, clock_khz);
+            if (status != GROVER_OK)
+                throw status;
         }
     } catch (int) {
         release(c);
@@ -497,6 +536,7 @@ int grover_query(grover_ctx *ctx, int key, int64_t *value)
     case 3: *value = int64_t(elem_bytes(ctx->dtype)); break;
     case 4: *value = int64_t(ctx->N); break;
     case 5: *value = int64_t(ctx->marks.size()); break;
+    case 6: *value = int64_t(ctx->timeout_ticks); break;
     default: return fail(ctx, GROVER_E_INVAL, "unknown query key");
     }
     return GROVER_OK;

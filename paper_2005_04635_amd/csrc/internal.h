@@ -210,15 +210,22 @@ __device__ inline void block_sum2(double &a, double &b, double *red)
 }
 
 // ---------------------------------------------------------------------------- grid barrier state
-// One per context, zeroed at creation.  `flag` is a monotonically increasing barrier generation;
-// arrive[p] counts workgroups at a barrier of parity p; sum[p] is that barrier's reduced value.
+// One per context, zeroed at creation.  `flag` is a monotonically increasing barrier generation that
+// waiting workgroups poll; arrive0/arrive1 count workgroups at a barrier of parity 0/1; sum[p] is that
+// barrier's reduced value; `error` is set when a wait gives up.  Polled and atomically updated words sit
+// on separate 256-byte lines so that polling does not contend with arrivals.
 struct GridSync {
     uint64_t flag;
-    uint32_t arrive[2];
-    uint32_t error;  // nonzero: a barrier wait timed out
-    uint32_t pad;
+    uint32_t error;
+    uint32_t pad0[61];
+    uint32_t arrive0;
+    uint32_t pad1[63];
+    uint32_t arrive1;
+    uint32_t pad2[63];
     uint64_t sum[2][2];  // bit patterns of (re, im) binary64
+    uint64_t pad3[28];
 };
+static_assert(sizeof(GridSync) == 1024, "barrier words on separate lines");
 
 // ------------------------------------------------------------------------------------------ context
 }  // namespace grover
@@ -241,6 +248,9 @@ struct grover_ctx {
     int block = 0;
     double *partials = nullptr;  // 2 * grid * 2 doubles
     grover::GridSync *sync = nullptr;
+    const void *fused_kernel = nullptr;        // the fused kernel variant chosen at creation
+    const void *fused_check_kernel = nullptr;  // its code-identical twin for the residency check
+    uint64_t fused_tile = 0;             // 16-byte vectors per tile of that variant
     uint64_t generation = 0;
     uint64_t timeout_ticks = 0;
     // two-pass form and reductions
@@ -269,8 +279,12 @@ hipError_t launch_fill_uniform(grover_ctx *c);
 hipError_t launch_hash_marks(grover_ctx *c, uint64_t seed, uint32_t bits, uint64_t *out, uint64_t cap,
                              unsigned long long *count);
 
-hipError_t fused_configure(grover_ctx *c, int *grid, int *block);
-hipError_t launch_fused_iterate(grover_ctx *c, uint64_t k);
+// Occupancy of the fused kernel per CU as the runtime reports it, its workgroup size, and a grid forced by
+// GROVER_FUSED_GRID (0 when unset).
+hipError_t fused_configure(grover_ctx *c, int *per_cu, int *block, int64_t *forced_grid);
+uint64_t fused_tiles(const grover_ctx *c);
+// `check`: launch the code-identical instantiation reserved for the residency check.
+hipError_t launch_fused_iterate(grover_ctx *c, uint64_t k, uint64_t timeout_ticks, bool check = false);
 
 hipError_t launch_resident_iterate(grover_ctx *c, uint64_t k);
 

@@ -1,8 +1,8 @@
 // Fused persistent iteration (proposed method, Algorithms 3-5 of arXiv:2005.04635).
 //
-// One cooperative launch runs k Grover iterations.  Each workgroup owns a fixed, contiguous run of tiles
-// of the state for the whole launch (so every amplitude stays with one workgroup, hence one XCD and its
-// L2), and each iteration is a single streaming pass over it:
+// One cooperative launch runs k Grover iterations.  Each workgroup owns a fixed set of tiles of the state
+// for the whole launch (so every amplitude stays with one workgroup, hence one XCD and its L2), and each
+// iteration is a single streaming pass over it:
 //
 //   read c_i, flip the sign of marked amplitudes (Algorithm 3), write c_i' = 2S/N - s_i c_i (Algorithm 4's
 //   second loop), and add s_i c_i' into a binary64 accumulator — which is Algorithm 4's first loop for the
@@ -20,10 +20,6 @@
 namespace grover {
 namespace {
 
-constexpr int kBlock = 256;
-constexpr int kUnroll = 4;
-constexpr int kTile = kBlock * kUnroll;  // 16-byte vectors per tile
-
 struct FusedArgs {
     void *state;
     uint64_t nvec;  // N / EPV
@@ -37,16 +33,27 @@ struct FusedArgs {
     uint64_t timeout_ticks;
 };
 
+template <int BLOCK>
 struct Shared {
-    double red[2 * (kBlock / kWave)];
+    double red[2 * (BLOCK / kWave)];
     double sum[2];
     int last;
     int abort;
 };
 
+__device__ inline uint32_t *arrive_word(GridSync *s, unsigned p) { return p ? &s->arrive1 : &s->arrive0; }
+
 // Grid-wide sum of (xr, xi) for barrier generation `gen`.  Returns false when the wait gave up (timeout,
 // or another workgroup gave up); every thread of the workgroup gets the same answer and the sum in (xr, xi).
-__device__ bool grid_sum(double &xr, double &xi, const FusedArgs &a, uint64_t gen, Shared &sh)
+//
+// Memory ordering: a workgroup publishes its partial and then increments the arrival counter with release
+// semantics; the workgroup whose increment completes the count acquires, adds the partials in workgroup
+// order, stores the sum and releases the generation flag; the others poll the flag with relaxed loads and
+// acquire once it has advanced.  Acquire/release at agent scope make the data visible across the XCDs'
+// separate L2s.  (Letting every workgroup poll the counter and add the partials itself was measured
+// slower on MI355X: the polls contend with the increments.)
+template <int BLOCK>
+__device__ bool grid_sum(double &xr, double &xi, const FusedArgs &a, uint64_t gen, Shared<BLOCK> &sh)
 {
     const unsigned p = unsigned(gen & 1u);
     block_sum2(xr, xi, sh.red);
@@ -56,7 +63,7 @@ __device__ bool grid_sum(double &xr, double &xi, const FusedArgs &a, uint64_t ge
         __hip_atomic_store(dst + 1, (uint64_t)__double_as_longlong(xi), __ATOMIC_RELAXED,
                            __HIP_MEMORY_SCOPE_AGENT);
         const unsigned old =
-            __hip_atomic_fetch_add(&a.sync->arrive[p], 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
+            __hip_atomic_fetch_add(arrive_word(a.sync, p), 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
         sh.last = (old == gridDim.x - 1u);
         sh.abort = 0;
     }
@@ -65,7 +72,7 @@ __device__ bool grid_sum(double &xr, double &xi, const FusedArgs &a, uint64_t ge
         // Every partial of this barrier is published.  Add them in workgroup order.
         __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
         double sr = 0.0, si = 0.0;
-        for (unsigned w = threadIdx.x; w < gridDim.x; w += blockDim.x) {
+        for (unsigned w = threadIdx.x; w < gridDim.x; w += BLOCK) {
             const uint64_t *src = a.partials + (uint64_t(p) * gridDim.x + w) * 2u;
             sr += __longlong_as_double(
                 (long long)__hip_atomic_load(src, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
@@ -78,7 +85,7 @@ __device__ bool grid_sum(double &xr, double &xi, const FusedArgs &a, uint64_t ge
                                __HIP_MEMORY_SCOPE_AGENT);
             __hip_atomic_store(&a.sync->sum[p][1], (uint64_t)__double_as_longlong(si), __ATOMIC_RELAXED,
                                __HIP_MEMORY_SCOPE_AGENT);
-            __hip_atomic_store(&a.sync->arrive[p], 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            __hip_atomic_store(arrive_word(a.sync, p), 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
             __hip_atomic_store(&a.sync->flag, gen, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
             sh.sum[0] = sr;
             sh.sum[1] = si;
@@ -86,7 +93,7 @@ __device__ bool grid_sum(double &xr, double &xi, const FusedArgs &a, uint64_t ge
     } else if (threadIdx.x == 0) {
         const uint64_t t0 = wall_clock64();
         bool ok = true;
-        while (__hip_atomic_load(&a.sync->flag, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) < gen) {
+        while (__hip_atomic_load(&a.sync->flag, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < gen) {
             if (__hip_atomic_load(&a.sync->error, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0u) {
                 ok = false;
                 break;
@@ -99,6 +106,7 @@ __device__ bool grid_sum(double &xr, double &xi, const FusedArgs &a, uint64_t ge
             __builtin_amdgcn_s_sleep(2);
         }
         if (ok) {
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
             sh.sum[0] = __longlong_as_double(
                 (long long)__hip_atomic_load(&a.sync->sum[p][0], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
             sh.sum[1] = __longlong_as_double(
@@ -115,147 +123,250 @@ __device__ bool grid_sum(double &xr, double &xi, const FusedArgs &a, uint64_t ge
     return ok;
 }
 
-// One pass over tiles [t_lo, t_hi) of the state.  UPDATE: c' = 2S/N - s c written back and s c' summed;
-// otherwise s c summed.  The per-thread order of the sum is identical in both modes.
-template <class T, bool NT, bool UPDATE>
-__device__ inline void chunk_pass(const FusedArgs &a, uint64_t t_lo, uint64_t t_hi, uint64_t m_lo,
-                                  uint64_t m_hi, double mr, double mi, double &ar, double &ai)
+// First index q >= start with marks[q] >= x in the sorted list marks[0, m), given that every entry before
+// `start` is < x: exponential steps from `start`, then a binary search in the last step.  Tiles are visited
+// in increasing order, so each search starts where the previous tile's ended and costs O(log gap).
+__device__ inline uint64_t gallop_lower_bound(const uint64_t *marks, uint64_t start, uint64_t m, uint64_t x)
 {
+    if (start >= m || marks[start] >= x)
+        return start;
+    uint64_t lo = start, step = 1;  // invariant: marks[lo] < x
+    while (lo + step < m && marks[lo + step] < x) {
+        lo += step;
+        step <<= 1;
+    }
+    const uint64_t hi = lo + step < m ? lo + step : m;
+    return lower_bound_u64(marks, lo + 1, hi, x);
+}
+
+// Marks of one tile held in registers: up to kTileMarks entries of the sorted slice marks[lo, hi), padded
+// with ~0 (never equal to an amplitude index).  Longer slices fall back to a binary search per vector.
+constexpr int kTileMarks = 8;
+
+template <int EPV>
+__device__ inline unsigned bits_from_regs(const uint64_t (&mk)[kTileMarks], uint64_t i)
+{
+    unsigned bits = 0;
+#pragma unroll
+    for (int q = 0; q < kTileMarks; ++q) {
+        const uint64_t d = mk[q] - i;  // wraps to a huge value when mk[q] < i
+        bits |= d < uint64_t(EPV) ? 1u << unsigned(d) : 0u;
+    }
+    return bits;
+}
+
+constexpr int kMarkWords = 1024;  // LDS bitmap of this workgroup's tiles that hold marked amplitudes
+
+// One pass over this workgroup's tiles t = blockIdx.x + j G, j = 0, 1, ... (G = gridDim.x).  At any moment
+// the grid streams one contiguous window of the state, spread over all HBM channels, while each tile still
+// belongs to the same workgroup (hence XCD) in every iteration.  (Alternating the direction between passes,
+// to start on lines the memory-side cache might still hold, measured no faster on MI355X.)  UPDATE:
+// c' = 2S/N - s c written back and s c' summed; otherwise s c summed.  The per-thread order of the sum is
+// identical in both modes.  `slow_tiles` (when `table`) flags the workgroup's tiles holding marked
+// amplitudes; without a table every tile is checked against the marked list.
+template <class T, bool NT, int BLOCK, int UNROLL, bool UPDATE>
+__device__ inline void chunk_pass(const FusedArgs &a, const uint32_t *slow_tiles, bool table, double mr, double mi,
+                                  double &ar, double &ai)
+{
+    constexpr int kTile = BLOCK * UNROLL;  // 16-byte vectors per tile
     using V = typename T::vec;
     V *st = static_cast<V *>(a.state);
     const unsigned tid = threadIdx.x;
-    uint64_t mp = m_lo;
-    uint64_t next_mark = mp < m_hi ? a.marks[mp] : ~uint64_t(0);
-    for (uint64_t t = t_lo; t < t_hi; ++t) {
+    const uint64_t ntiles = (a.nvec + kTile - 1) / kTile;
+    const uint64_t cnt = blockIdx.x < ntiles ? (ntiles - blockIdx.x + gridDim.x - 1) / gridDim.x : 0;
+    uint64_t mp = 0;  // marked entries before this position lie in tiles already visited
+    for (uint64_t j = 0; j < cnt; ++j) {
+        const uint64_t t = blockIdx.x + j * gridDim.x;
         const uint64_t v0 = t * kTile;
-        const uint64_t end_elem = (v0 + kTile) * T::EPV;
-        if (v0 + kTile <= a.nvec && next_mark >= end_elem) {
-            // Full tile without marked amplitudes.
-            V x[kUnroll];
+        const bool full = v0 + kTile <= a.nvec;
+        const bool marked = table ? ((slow_tiles[j >> 5] >> (j & 31)) & 1u) != 0u : a.m > 0;
+        if (full && !marked) {
+            V x[UNROLL];
 #pragma unroll
-            for (int u = 0; u < kUnroll; ++u)
-                x[u] = load16<NT>(st + v0 + u * kBlock + tid);
+            for (int u = 0; u < UNROLL; ++u)
+                x[u] = load16<NT>(st + v0 + u * BLOCK + tid);
 #pragma unroll
-            for (int u = 0; u < kUnroll; ++u) {
+            for (int u = 0; u < UNROLL; ++u) {
                 if (UPDATE) {
                     update_vec<T>(x[u], mr, mi, 0u, ar, ai);
-                    store16<NT>(x[u], st + v0 + u * kBlock + tid);
+                    store16<NT>(x[u], st + v0 + u * BLOCK + tid);
                 } else {
                     accum_vec<T>(x[u], 0u, ar, ai);
                 }
             }
         } else {
-            // Ragged tail of the state, or marked amplitudes inside this tile.
-            const uint64_t mq = lower_bound_u64(a.marks, mp, m_hi, end_elem);
+            // Ragged tail of the state, or a tile that may hold marked amplitudes: the same vector loads,
+            // then each amplitude's sign from the tile's slice [mp, mq) of the sorted marked list.
+            mp = gallop_lower_bound(a.marks, mp, a.m, v0 * T::EPV);
+            const uint64_t mq = gallop_lower_bound(a.marks, mp, a.m, (v0 + kTile) * T::EPV);
+            const bool in_regs = mq - mp <= uint64_t(kTileMarks);
+            uint64_t mk[kTileMarks];
 #pragma unroll
-            for (int u = 0; u < kUnroll; ++u) {
-                const uint64_t v = v0 + u * kBlock + tid;
+            for (int q = 0; q < kTileMarks; ++q)
+                mk[q] = in_regs && mp + q < mq ? a.marks[mp + q] : ~uint64_t(0);
+            V x[UNROLL];
+#pragma unroll
+            for (int u = 0; u < UNROLL; ++u) {
+                const uint64_t v = v0 + u * BLOCK + tid;
+                if (v < a.nvec)
+                    x[u] = load16<NT>(st + v);
+            }
+#pragma unroll
+            for (int u = 0; u < UNROLL; ++u) {
+                const uint64_t v = v0 + u * BLOCK + tid;
                 if (v < a.nvec) {
-                    V x = st[v];
-                    const unsigned bits = mp < mq ? marked_bits<T::EPV>(a.marks, mp, mq, v * T::EPV) : 0u;
+                    const unsigned bits = in_regs ? bits_from_regs<T::EPV>(mk, v * T::EPV)
+                                                  : marked_bits<T::EPV>(a.marks, mp, mq, v * T::EPV);
                     if (UPDATE) {
-                        update_vec<T>(x, mr, mi, bits, ar, ai);
-                        st[v] = x;
+                        update_vec<T>(x[u], mr, mi, bits, ar, ai);
+                        store16<NT>(x[u], st + v);
                     } else {
-                        accum_vec<T>(x, bits, ar, ai);
+                        accum_vec<T>(x[u], bits, ar, ai);
                     }
                 }
             }
             mp = mq;
-            next_mark = mp < m_hi ? a.marks[mp] : ~uint64_t(0);
         }
     }
 }
 
-template <class T, bool NT>
-__global__ __launch_bounds__(kBlock) void fused_iterate_kernel(FusedArgs a)
+template <class T, bool NT, int BLOCK, int UNROLL, bool CHECK = false>
+__global__ __launch_bounds__(BLOCK) void fused_iterate_kernel(FusedArgs a)
 {
-    __shared__ Shared sh;
+    constexpr int kTile = BLOCK * UNROLL;
+    __shared__ Shared<BLOCK> sh;
+    __shared__ uint32_t slow_tiles[kMarkWords];
+    // Table of this workgroup's tiles that hold marked amplitudes, built once per launch.
     const uint64_t ntiles = (a.nvec + kTile - 1) / kTile;
-    const uint64_t t_lo = ntiles * blockIdx.x / gridDim.x;
-    const uint64_t t_hi = ntiles * (blockIdx.x + 1u) / gridDim.x;
-    const uint64_t e_lo = t_lo * kTile * T::EPV;
-    const uint64_t e_hi = t_hi * kTile * T::EPV;
-    const uint64_t m_lo = lower_bound_u64(a.marks, 0, a.m, e_lo);
-    const uint64_t m_hi = lower_bound_u64(a.marks, m_lo, a.m, e_hi);
-
+    const uint64_t cnt = blockIdx.x < ntiles ? (ntiles - blockIdx.x + gridDim.x - 1) / gridDim.x : 0;
+    const bool table = cnt <= uint64_t(kMarkWords) * 32u && a.m <= uint64_t(64) * BLOCK;
+    if (table) {
+        for (unsigned w = threadIdx.x; w < kMarkWords; w += BLOCK)
+            slow_tiles[w] = 0u;
+        __syncthreads();
+        for (uint64_t q = threadIdx.x; q < a.m; q += BLOCK) {
+            const uint64_t t = a.marks[q] / T::EPV / kTile;
+            if (t % gridDim.x == blockIdx.x) {
+                const uint64_t j = t / gridDim.x;
+                atomicOr(&slow_tiles[j >> 5], 1u << (j & 31));
+            }
+        }
+        __syncthreads();
+    }
     double sr = 0.0, si = 0.0;
-    chunk_pass<T, NT, false>(a, t_lo, t_hi, m_lo, m_hi, 0.0, 0.0, sr, si);
-    if (!grid_sum(sr, si, a, a.gen0 + 1u, sh))
+    chunk_pass<T, NT, BLOCK, UNROLL, false>(a, slow_tiles, table, 0.0, 0.0, sr, si);
+    if (!grid_sum<BLOCK>(sr, si, a, a.gen0 + 1u, sh))
         return;
     for (uint64_t it = 0; it < a.iters; ++it) {
         const double mr = (sr * 2.0) / a.N, mi = (si * 2.0) / a.N;
         double ar = 0.0, ai = 0.0;
-        chunk_pass<T, NT, true>(a, t_lo, t_hi, m_lo, m_hi, mr, mi, ar, ai);
-        if (!grid_sum(ar, ai, a, a.gen0 + 2u + it, sh))
+        chunk_pass<T, NT, BLOCK, UNROLL, true>(a, slow_tiles, table, mr, mi, ar, ai);
+        if (!grid_sum<BLOCK>(ar, ai, a, a.gen0 + 2u + it, sh))
             return;
         sr = ar;
         si = ai;
     }
 }
 
-// Streaming hint for the state's loads and stores: nontemporal unless GROVER_FUSED_NT=0.
-bool use_nontemporal()
+// Launch variant: workgroup size, unroll (16-byte vectors per thread per tile) and the streaming hint.
+// Defaults are set by measurement on MI355X; GROVER_FUSED_BLOCK / _UNROLL / _NT override them.
+struct Variant {
+    int block = 1024;
+    int unroll = 4;
+    bool nt = true;
+};
+
+Variant variant()
 {
-    const char *env = getenv("GROVER_FUSED_NT");
-    return !(env && env[0] == '0');
+    Variant v;
+    if (const char *e = getenv("GROVER_FUSED_BLOCK"))
+        v.block = atoi(e);
+    if (const char *e = getenv("GROVER_FUSED_UNROLL"))
+        v.unroll = atoi(e);
+    if (const char *e = getenv("GROVER_FUSED_NT"))
+        v.nt = e[0] != '0';
+    return v;
 }
 
-template <bool NT>
-const void *kernel_nt(uint32_t dtype)
+template <class T, bool NT, int BLOCK, bool CHECK>
+const void *pick_unroll(int unroll)
 {
-    switch (dtype) {
-    case GROVER_F64_REAL: return reinterpret_cast<const void *>(&fused_iterate_kernel<F64Real, NT>);
-    case GROVER_C64: return reinterpret_cast<const void *>(&fused_iterate_kernel<C64, NT>);
-    case GROVER_C128: return reinterpret_cast<const void *>(&fused_iterate_kernel<C128, NT>);
+    switch (unroll) {
+    case 2: return reinterpret_cast<const void *>(&fused_iterate_kernel<T, NT, BLOCK, 2, CHECK>);
+    case 4: return reinterpret_cast<const void *>(&fused_iterate_kernel<T, NT, BLOCK, 4, CHECK>);
+    case 8: return reinterpret_cast<const void *>(&fused_iterate_kernel<T, NT, BLOCK, 8, CHECK>);
     default: return nullptr;
     }
 }
 
-const void *kernel_for(uint32_t dtype)
+template <class T, bool NT, bool CHECK>
+const void *pick_block(int block, int unroll)
 {
-    return use_nontemporal() ? kernel_nt<true>(dtype) : kernel_nt<false>(dtype);
+    switch (block) {
+    case 256: return pick_unroll<T, NT, 256, CHECK>(unroll);
+    case 512: return pick_unroll<T, NT, 512, CHECK>(unroll);
+    case 1024: return pick_unroll<T, NT, 1024, CHECK>(unroll);
+    default: return nullptr;
+    }
+}
+
+template <class T, bool CHECK>
+const void *pick(const Variant &v)
+{
+    return v.nt ? pick_block<T, true, CHECK>(v.block, v.unroll) : pick_block<T, false, CHECK>(v.block, v.unroll);
+}
+
+template <bool CHECK>
+const void *kernel_for(uint32_t dtype, const Variant &v)
+{
+    switch (dtype) {
+    case GROVER_F64_REAL: return pick<F64Real, CHECK>(v);
+    case GROVER_C64: return pick<C64, CHECK>(v);
+    case GROVER_C128: return pick<C128, CHECK>(v);
+    default: return nullptr;
+    }
 }
 
 }  // namespace
 
-hipError_t fused_configure(grover_ctx *c, int *grid, int *block)
+hipError_t fused_configure(grover_ctx *c, int *per_cu, int *block, int64_t *forced_grid)
 {
-    const void *k = kernel_for(c->dtype);
+    const Variant v = variant();
+    const void *k = kernel_for<false>(c->dtype, v);
     if (!k)
         return hipErrorInvalidValue;
+    c->fused_kernel = k;
+    c->fused_check_kernel = kernel_for<true>(c->dtype, v);
+    c->fused_tile = uint64_t(v.block) * v.unroll;
     int coop = 0;
     hipError_t e = hipDeviceGetAttribute(&coop, hipDeviceAttributeCooperativeLaunch, c->device);
     if (e != hipSuccess)
         return e;
     if (!coop)
         return hipErrorCooperativeLaunchTooLarge;
-    int per_cu = 0;
-    e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k, kBlock, 0);
+    e = hipOccupancyMaxActiveBlocksPerMultiprocessor(per_cu, k, v.block, 0);
     if (e != hipSuccess)
         return e;
-    const int64_t max_grid = int64_t(per_cu) * c->cu_count;
-    const uint64_t epv = c->dtype == GROVER_C128 ? 1 : 2;
-    const uint64_t nvec = c->N / epv;
-    const uint64_t ntiles = (nvec + kTile - 1) / kTile;
-    int64_t g = max_grid;
+    *block = v.block;
+    *forced_grid = 0;
     if (const char *env = getenv("GROVER_FUSED_GRID")) {
         const long long want = atoll(env);
-        if (want > 0)
-            g = want;
-    } else if (uint64_t(g) > ntiles) {
-        g = int64_t(ntiles);
+        if (want > 0) {
+            if (want > int64_t(*per_cu) * c->cu_count)
+                return hipErrorCooperativeLaunchTooLarge;
+            *forced_grid = want;
+        }
     }
-    if (g < 1)
-        g = 1;
-    if (g > max_grid)
-        return hipErrorCooperativeLaunchTooLarge;
-    *grid = int(g);
-    *block = kBlock;
     return hipSuccess;
 }
 
-hipError_t launch_fused_iterate(grover_ctx *c, uint64_t k)
+uint64_t fused_tiles(const grover_ctx *c)
+{
+    const uint64_t nvec = c->N / (c->dtype == GROVER_C128 ? 1 : 2);
+    return (nvec + c->fused_tile - 1) / c->fused_tile;
+}
+
+hipError_t launch_fused_iterate(grover_ctx *c, uint64_t k, uint64_t timeout_ticks, bool check)
 {
     FusedArgs a;
     a.state = c->state;
@@ -267,10 +378,10 @@ hipError_t launch_fused_iterate(grover_ctx *c, uint64_t k)
     a.sync = c->sync;
     a.iters = k;
     a.gen0 = c->generation;
-    a.timeout_ticks = c->timeout_ticks;
+    a.timeout_ticks = timeout_ticks;
     void *args[] = {&a};
-    const hipError_t e = hipLaunchCooperativeKernel(kernel_for(c->dtype), dim3(c->grid), dim3(c->block), args,
-                                                    0, c->stream);
+    const void *fn = check ? c->fused_check_kernel : c->fused_kernel;
+    const hipError_t e = hipLaunchCooperativeKernel(fn, dim3(c->grid), dim3(c->block), args, 0, c->stream);
     if (e == hipSuccess)
         c->generation += k + 1u;
     return e;

@@ -1,0 +1,232 @@
+// grover_cli — native driver of libgrover through its C ABI (no Python, no torch), for runs and profiling.
+//
+//   grover_cli run  --n 28 --dtype c64 --form fused --hash-seed 0x6A09E667F3BCC910 --hash-bits 25 --m 8
+//                   [--iters K] [--shots 1000000] [--shot-seed 11] [--steps 1]
+//   grover_cli run  --n 10 --dtype f64 --mark 123 ...          (explicit marked indices, repeatable)
+//   grover_cli copy --bytes 2147483648 [--reps 1]              (plain copy kernel of known size)
+//   run ... --calibrate-copy B                                  (also copy B bytes once, before the search)
+//
+// `run` creates a context, then per step: writes the uniform state, runs the iterations (timed with HIP
+// events on the context's stream), takes the norm and samples the shots with device-generated uniforms.
+// It prints one JSON line.  `copy` moves a buffer of known size with a simple streaming kernel; its byte
+// counters calibrate hardware-counter traffic measurements of the iteration kernel.
+#include <hip/hip_runtime.h>
+
+#include <cinttypes>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "grover.h"
+
+namespace {
+
+__global__ __launch_bounds__(256) void copy_kernel(const float4 *src, float4 *dst, uint64_t n)
+{
+    const uint64_t stride = uint64_t(gridDim.x) * blockDim.x;
+    for (uint64_t i = uint64_t(blockIdx.x) * blockDim.x + threadIdx.x; i < n; i += stride)
+        dst[i] = src[i];
+}
+
+int usage()
+{
+    fprintf(stderr,
+            "usage: grover_cli run --n N [--dtype f64|c64|c128] [--form auto|fused|resident|two_pass]\n"
+            "                      [--mark I ... | --hash-seed S --hash-bits B --m M] [--iters K]\n"
+            "                      [--shots S] [--shot-seed U] [--steps T] [--calibrate-copy BYTES]\n"
+            "       grover_cli copy --bytes B [--reps R]\n");
+    return 2;
+}
+
+#define CHECK_HIP(x)                                                                   \
+    do {                                                                               \
+        const hipError_t e_ = (x);                                                     \
+        if (e_ != hipSuccess) {                                                        \
+            fprintf(stderr, "HIP error %s at %s:%d\n", hipGetErrorString(e_), __FILE__, __LINE__); \
+            return 1;                                                                  \
+        }                                                                              \
+    } while (0)
+
+#define CHECK_GROVER(ctx, x)                                                           \
+    do {                                                                               \
+        const int s_ = (x);                                                            \
+        if (s_ != GROVER_OK) {                                                         \
+            fprintf(stderr, "grover error %d (%s): %s\n", s_, grover_status_str(s_),   \
+                    grover_last_error(ctx));                                           \
+            return 1;                                                                  \
+        }                                                                              \
+    } while (0)
+
+int run_copy(int argc, char **argv)
+{
+    uint64_t bytes = uint64_t(1) << 31;
+    int reps = 1;
+    for (int i = 2; i < argc; ++i) {
+        if (!strcmp(argv[i], "--bytes") && i + 1 < argc)
+            bytes = strtoull(argv[++i], nullptr, 0);
+        else if (!strcmp(argv[i], "--reps") && i + 1 < argc)
+            reps = atoi(argv[++i]);
+        else
+            return usage();
+    }
+    const uint64_t n = bytes / 16;
+    float4 *a = nullptr, *b = nullptr;
+    CHECK_HIP(hipMalloc(&a, n * 16));
+    CHECK_HIP(hipMalloc(&b, n * 16));
+    CHECK_HIP(hipMemset(a, 0, n * 16));
+    CHECK_HIP(hipDeviceSynchronize());
+    hipEvent_t e0, e1;
+    CHECK_HIP(hipEventCreate(&e0));
+    CHECK_HIP(hipEventCreate(&e1));
+    CHECK_HIP(hipEventRecord(e0));
+    for (int r = 0; r < reps; ++r)
+        copy_kernel<<<4096, 256>>>(a, b, n);
+    CHECK_HIP(hipGetLastError());
+    CHECK_HIP(hipEventRecord(e1));
+    CHECK_HIP(hipEventSynchronize(e1));
+    float ms = 0;
+    CHECK_HIP(hipEventElapsedTime(&ms, e0, e1));
+    printf("{\"mode\": \"copy\", \"bytes_read\": %" PRIu64 ", \"bytes_written\": %" PRIu64
+           ", \"reps\": %d, \"ms\": %.4f, \"gbs\": %.1f}\n",
+           n * 16, n * 16, reps, ms, 2.0 * n * 16 * reps / (ms / 1e3) / 1e9);
+    CHECK_HIP(hipFree(a));
+    CHECK_HIP(hipFree(b));
+    return 0;
+}
+
+int run_search(int argc, char **argv)
+{
+    grover_config cfg;
+    memset(&cfg, 0, sizeof(cfg));
+    cfg.dtype = GROVER_C64;
+    cfg.form = GROVER_FORM_AUTO;
+    std::vector<uint64_t> marks;
+    uint64_t iters = UINT64_MAX, shots = 0, shot_seed = 1, calib_bytes = 0;
+    int steps = 1;
+    bool hash = false;
+    for (int i = 2; i < argc; ++i) {
+        const std::string k = argv[i];
+        const char *v = i + 1 < argc ? argv[i + 1] : nullptr;
+        if (!v)
+            return usage();
+        ++i;
+        if (k == "--n")
+            cfg.n = uint32_t(atoi(v));
+        else if (k == "--dtype")
+            cfg.dtype = !strcmp(v, "f64") ? GROVER_F64_REAL : !strcmp(v, "c128") ? GROVER_C128 : GROVER_C64;
+        else if (k == "--form")
+            cfg.form = !strcmp(v, "fused")      ? GROVER_FORM_FUSED
+                       : !strcmp(v, "resident") ? GROVER_FORM_RESIDENT
+                       : !strcmp(v, "two_pass") ? GROVER_FORM_TWO_PASS
+                                                : GROVER_FORM_AUTO;
+        else if (k == "--mark")
+            marks.push_back(strtoull(v, nullptr, 0));
+        else if (k == "--hash-seed") {
+            cfg.hash_seed = strtoull(v, nullptr, 0);
+            hash = true;
+        } else if (k == "--hash-bits")
+            cfg.hash_bits = uint32_t(atoi(v));
+        else if (k == "--m")
+            cfg.m = strtoull(v, nullptr, 0);
+        else if (k == "--iters")
+            iters = strtoull(v, nullptr, 0);
+        else if (k == "--shots")
+            shots = strtoull(v, nullptr, 0);
+        else if (k == "--shot-seed")
+            shot_seed = strtoull(v, nullptr, 0);
+        else if (k == "--steps")
+            steps = atoi(v);
+        else if (k == "--calibrate-copy")
+            calib_bytes = strtoull(v, nullptr, 0);
+        else
+            return usage();
+    }
+    if (cfg.n == 0)
+        return usage();
+    if (calib_bytes > 0) {
+        // the plain copy kernel of known size, in the same process, for counter calibration
+        const uint64_t cn = calib_bytes / 16;
+        float4 *ca = nullptr, *cb = nullptr;
+        CHECK_HIP(hipMalloc(&ca, cn * 16));
+        CHECK_HIP(hipMalloc(&cb, cn * 16));
+        CHECK_HIP(hipMemset(ca, 0, cn * 16));
+        copy_kernel<<<4096, 256>>>(ca, cb, cn);
+        CHECK_HIP(hipGetLastError());
+        CHECK_HIP(hipDeviceSynchronize());
+        CHECK_HIP(hipFree(ca));
+        CHECK_HIP(hipFree(cb));
+        fprintf(stderr, "[grover_cli] calibration copy of %" PRIu64 " bytes done\n", cn * 16);
+    }
+    if (hash) {
+        cfg.oracle_kind = GROVER_ORACLE_HASH;
+    } else {
+        cfg.oracle_kind = GROVER_ORACLE_LIST;
+        cfg.marked = marks.data();
+        cfg.m = marks.size();
+    }
+    if (iters == UINT64_MAX)
+        iters = grover_optimal_iterations(cfg.n, cfg.m);
+
+    hipStream_t stream;
+    CHECK_HIP(hipStreamCreate(&stream));
+    grover_ctx *ctx = nullptr;
+    CHECK_GROVER(nullptr, grover_init(&ctx, &cfg, stream, nullptr, 0));
+    int64_t grid = 0, block = 0, form = 0;
+    CHECK_GROVER(ctx, grover_query(ctx, 1, &grid));
+    CHECK_GROVER(ctx, grover_query(ctx, 2, &block));
+    CHECK_GROVER(ctx, grover_query(ctx, 0, &form));
+    uint64_t *shots_dev = nullptr;
+    if (shots > 0)
+        CHECK_HIP(hipMalloc(&shots_dev, shots * sizeof(uint64_t)));
+    hipEvent_t e0, e1, s0, s1;
+    CHECK_HIP(hipEventCreate(&e0));
+    CHECK_HIP(hipEventCreate(&e1));
+    CHECK_HIP(hipEventCreate(&s0));
+    CHECK_HIP(hipEventCreate(&s1));
+    double it_ms_sum = 0, step_ms_sum = 0, norm = 0;
+    for (int s = 0; s < steps; ++s) {
+        CHECK_HIP(hipEventRecord(s0, stream));
+        CHECK_GROVER(ctx, grover_reset(ctx));
+        CHECK_HIP(hipEventRecord(e0, stream));
+        CHECK_GROVER(ctx, grover_iterate(ctx, iters));
+        CHECK_HIP(hipEventRecord(e1, stream));
+        CHECK_GROVER(ctx, grover_norm(ctx, &norm));
+        if (shots > 0)
+            CHECK_GROVER(ctx, grover_sample(ctx, shots, shot_seed, shots_dev, 1));
+        CHECK_HIP(hipEventRecord(s1, stream));
+        CHECK_GROVER(ctx, grover_sync(ctx));
+        float it_ms = 0, step_ms = 0;
+        CHECK_HIP(hipEventElapsedTime(&it_ms, e0, e1));
+        CHECK_HIP(hipEventElapsedTime(&step_ms, s0, s1));
+        it_ms_sum += it_ms;
+        step_ms_sum += step_ms;
+        fprintf(stderr, "[grover_cli] step %d/%d: iterate %.3f ms, step %.3f ms\n", s + 1, steps, it_ms, step_ms);
+    }
+    const double N = double(uint64_t(1) << cfg.n);
+    const double it_ms = it_ms_sum / steps;
+    printf("{\"mode\": \"run\", \"n\": %u, \"dtype\": %u, \"form\": %" PRId64 ", \"m\": %" PRIu64
+           ", \"iterations\": %" PRIu64 ", \"shots\": %" PRIu64 ", \"grid\": %" PRId64 ", \"block\": %" PRId64
+           ", \"steps\": %d, \"iterate_ms\": %.4f, \"step_ms\": %.4f, \"updates_per_s\": %.6e, \"norm\": %.12f}\n",
+           cfg.n, cfg.dtype, form, cfg.m, iters, shots, grid, block, steps, it_ms, step_ms_sum / steps,
+           N * double(iters) / (it_ms / 1e3), norm);
+    if (shots_dev)
+        CHECK_HIP(hipFree(shots_dev));
+    grover_destroy(ctx);
+    CHECK_HIP(hipStreamDestroy(stream));
+    return 0;
+}
+
+}  // namespace
+
+int main(int argc, char **argv)
+{
+    if (argc < 2)
+        return usage();
+    if (!strcmp(argv[1], "copy"))
+        return run_copy(argc, argv);
+    if (!strcmp(argv[1], "run"))
+        return run_search(argc, argv);
+    return usage();
+}

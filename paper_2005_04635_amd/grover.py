@@ -10,6 +10,7 @@ from __future__ import annotations
 
 import ctypes
 import os
+import sys
 import threading
 from typing import Optional
 
@@ -326,11 +327,9 @@ class Grover:
             self.ctx = None
 
     def __del__(self):
-        import sys
-
-        if sys.is_finalizing():  # the HIP runtime may already be torn down
-            return
         try:
+            if sys.is_finalizing():  # the HIP runtime may already be torn down
+                return
             self.close()
-        except Exception:
+        except BaseException:
             pass

@@ -1,0 +1,106 @@
+"""Full-size parity: the n = 28 single-large-instance workload in the launch configuration bench.py times
+(fused persistent form, default grid, complex64 storage, hash predicate with M = 8, 4549 iterations,
+10^6 shots), checked against the oracle where it can compute the outputs (the first iterations element by
+element, the two-class value of every amplitude at the end) and through properties that hold at any size.
+"""
+from __future__ import annotations
+
+import os
+
+import numpy as np
+import pytest
+
+import workloads
+from conftest import GOLDEN
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def G():
+    import torch
+
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2005_04635_amd as pkg
+
+    pkg.load()
+    return pkg
+
+
+def max_abs_err_chunked(got: np.ndarray, want: np.ndarray, chunk: int = 1 << 24) -> float:
+    err = 0.0
+    for s in range(0, got.size, chunk):
+        d = np.abs(got[s:s + chunk].astype(np.complex128) - want[s:s + chunk])
+        err = max(err, float(d.max()))
+    return err
+
+
+def test_n28_hash_workload(G, orc):
+    w = workloads.HASH_N28
+    N = 1 << w.n
+    g = G.Grover(w.n, w.dtype, hash_seed=w.hash_seed, hash_bits=w.hash_bits, m=w.m, form="fused")
+    assert g.query(0) == 1
+    marks = g.marked()
+    with open(os.path.join(GOLDEN, "hash_marks_n28.txt")) as f:
+        golden = [int(x) for x in f if x.strip() and not x.startswith("#")]
+    assert marks.tolist() == golden  # bit-exact device predicate + compaction
+
+    # first 8 iterations, every amplitude against the full binary64 oracle
+    g.iterate(8)
+    want = orc.search(w.n, marks, 8)
+    err8 = max_abs_err_chunked(g.read_state(), want)
+    assert err8 <= 1e-5, err8
+    del want
+
+    # the rest of the optimal run (composition is bitwise, so this equals one 4549-iteration call)
+    g.iterate(w.iterations - 8)
+    got = g.read_state()
+    mask = np.zeros(N, dtype=bool)
+    mask[marks.astype(np.int64)] = True
+    a_gpu, b_gpu = got[int(marks[0])], got[int(np.argmin(mask))]
+    assert np.all(got[mask] == a_gpu)          # every marked amplitude bit-identical
+    assert np.all(got[~mask] == b_gpu)         # every unmarked amplitude bit-identical
+    assert np.all(got.imag == 0)               # standard phases keep the state real
+    a, b = orc.two_class(w.n, w.m, w.iterations)
+    assert abs(complex(a_gpu) - a) <= 1e-5 and abs(complex(b_gpu) - b) <= 1e-5
+    assert abs(g.norm() - 1.0) < 1e-5
+
+    # measurement: bit-exact against the oracle sampler on the same state
+    u = workloads.uniforms_u53(w.shot_seed, w.shots)
+    shots = g.sample(w.shots, u53=u)
+    psi = got.astype(np.complex128)
+    del got
+    assert np.array_equal(shots, orc.sample(psi, u))
+    # end to end against the oracle's own final state (its two-class values): a shot can only differ where
+    # U falls within the CDF difference of the two states, ~2e-5 per marked boundary here
+    psi[mask] = a
+    psi[~mask] = b
+    mism = int(np.sum(shots != orc.sample(psi, u)))
+    assert mism <= 64, mism
+    assert np.isin(shots, marks).all()
+    g.close()
+
+
+def test_large_index_range(G, orc):
+    """n = 31 (2^31 complex64 amplitudes, 16 GiB): indices past 2^31 and marks at the very end of the
+    state; three iterations against the oracle's two-class values."""
+    import torch
+
+    n = 31
+    N = 1 << n
+    marks = np.array([5, (1 << 31) - 2, (1 << 31) - 1], dtype=np.uint64)
+    g = G.Grover(n, "c64", marks=marks, form="fused")
+    g.iterate(3)
+    torch.cuda.synchronize()
+    st = g.state
+    a, b = orc.two_class(n, marks.size, 3)
+    idx = torch.from_numpy(marks.astype(np.int64)).cuda()
+    marked_vals = st[idx]
+    assert torch.all(marked_vals == marked_vals[0]).item()
+    assert abs(complex(marked_vals[0].item()) - a) <= 1e-5
+    unmarked = st[6:N - 2]
+    assert torch.all(unmarked == st[0]).item() and torch.all(st[:5] == st[0]).item()
+    assert abs(complex(st[0].item()) - b) <= 1e-5
+    assert abs(g.norm() - 1.0) < 1e-5
+    g.close()

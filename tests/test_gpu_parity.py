@@ -140,7 +140,7 @@ def test_fused_grid_shapes(G, orc, monkeypatch):
     marks = workloads.distinct_marks(n, 6, seed=8)
     psi0 = start_state(n, dtype, seed=8)
     want = orc.iterate(as_c128(psi0), marks, 9)
-    for grid in ["1", "7", "97", "600"]:
+    for grid in ["1", "7", "97", "250"]:
         monkeypatch.setenv("GROVER_FUSED_GRID", grid)
         g = G.Grover(n, dtype, marks=marks, form="fused")
         assert g.query(1) == int(grid)
