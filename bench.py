@@ -11,18 +11,22 @@ One step is one pass of the whole hot path on inputs already resident in HBM: th
 is written, 4549 fused iterations run (one persistent cooperative kernel), the norm is taken, and 10^6
 shots are sampled with device-resident uniforms.  `value` = N * 4549 / (wall time of one step).
 
+The process talks to the GPU only through libgrover's C ABI and the HIP runtime it links (events, device
+buffers, a stream); no framework is loaded.
+
 Printed JSON line (last line of stdout):
   roofline      the fused iterate kernel: algorithmic bytes per launch (16 B per amplitude-update plus the
                 8 B-per-amplitude prologue read) / its mean duration measured with HIP events on the
                 stream it runs on, against MI355X's 8 TB/s; `traffic` is the counter-measured HBM bytes per
                 launch from the committed rocprofv3 summary (null when the kernel source changed since)
   forms         the plain binary64 comparator (complex128, oracle / sum / update kernels per iteration)
-                and the fused complex128 form, timed on a bounded number of iterations
+                and other forms, timed on a bounded number of iterations
   cpu_baseline  the CPU oracle (single thread, binary64) on a bounded sample of the same workload
 """
 from __future__ import annotations
 
 import argparse
+import ctypes
 import hashlib
 import json
 import os
@@ -63,23 +67,86 @@ def committed_traffic():
     return float(val.group(1))
 
 
-def time_form(pkg, torch, n, dtype, form, marks, iters, bytes_per_update, prologue_bytes):
-    """Iterations/s of one form on a resident state, HIP events on its stream."""
-    g = pkg.Grover(n, dtype, marks=marks, form=form)
-    g.iterate(2)
-    torch.cuda.synchronize()
-    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    e0.record()
-    g.iterate(iters)
-    e1.record()
-    torch.cuda.synchronize()
-    ms = e0.elapsed_time(e1)
+class Hip:
+    """The few HIP runtime calls the benchmark needs (the runtime libgrover itself links)."""
+
+    def __init__(self):
+        self.lib = ctypes.CDLL("libamdhip64.so.7")
+        P = ctypes.c_void_p
+        for name, args in {
+            "hipSetDevice": [ctypes.c_int], "hipDeviceSynchronize": [], "hipStreamCreate": [ctypes.POINTER(P)],
+            "hipStreamSynchronize": [P], "hipEventCreate": [ctypes.POINTER(P)], "hipEventRecord": [P, P],
+            "hipEventSynchronize": [P], "hipEventElapsedTime": [ctypes.POINTER(ctypes.c_float), P, P],
+            "hipMalloc": [ctypes.POINTER(P), ctypes.c_size_t], "hipFree": [P],
+            "hipMemcpy": [P, P, ctypes.c_size_t, ctypes.c_int],
+            "hipMemcpyAsync": [P, P, ctypes.c_size_t, ctypes.c_int, P],
+            "hipDeviceGetName": [ctypes.c_char_p, ctypes.c_int, ctypes.c_int],
+        }.items():
+            fn = getattr(self.lib, name)
+            fn.restype = ctypes.c_int
+            fn.argtypes = args
+
+    def ok(self, rc, what):
+        if rc != 0:
+            raise RuntimeError(f"{what} failed with HIP error {rc}")
+
+    def event(self):
+        e = ctypes.c_void_p()
+        self.ok(self.lib.hipEventCreate(ctypes.byref(e)), "hipEventCreate")
+        return e
+
+    def elapsed_ms(self, e0, e1) -> float:
+        ms = ctypes.c_float()
+        self.ok(self.lib.hipEventSynchronize(e1), "hipEventSynchronize")
+        self.ok(self.lib.hipEventElapsedTime(ctypes.byref(ms), e0, e1), "hipEventElapsedTime")
+        return ms.value
+
+    def malloc(self, nbytes: int):
+        p = ctypes.c_void_p()
+        self.ok(self.lib.hipMalloc(ctypes.byref(p), nbytes), "hipMalloc")
+        return p
+
+    def name(self) -> str:
+        buf = ctypes.create_string_buffer(256)
+        self.lib.hipDeviceGetName(buf, 256, 0)
+        return buf.value.decode(errors="replace")
+
+
+def make_config(pkg, n, dtype, marks=None, hash_seed=None, hash_bits=0, m=0, form="fused"):
+    import numpy as np
+
+    g = pkg.grover
+    cfg = g.grover_config()
+    cfg.n, cfg.dtype, cfg.form, cfg.flags = n, g.DTYPES[dtype], g.FORMS[form], 0
+    keep = None
+    if hash_seed is not None:
+        cfg.oracle_kind, cfg.hash_seed, cfg.hash_bits, cfg.m = g.GROVER_ORACLE_HASH, hash_seed, hash_bits, m
+    else:
+        keep = np.ascontiguousarray(np.asarray(marks, dtype=np.uint64))
+        cfg.oracle_kind, cfg.m = g.GROVER_ORACLE_LIST, keep.size
+        cfg.marked = keep.ctypes.data_as(ctypes.POINTER(ctypes.c_uint64))
+    return cfg, keep
+
+
+def time_form(pkg, hip, stream, n, dtype, form, marks, iters, bytes_per_update, prologue_bytes):
+    """Amplitude-updates/s of one form on a resident state, HIP events on its stream."""
+    cfg, keep = make_config(pkg, n, dtype, marks=marks, form=form)
+    ctx = pkg.grover_init(cfg, stream.value, 0, 0)
+    try:
+        pkg.grover_iterate(ctx, 2)
+        pkg.grover_sync(ctx)
+        e0, e1 = hip.event(), hip.event()
+        hip.lib.hipEventRecord(e0, stream)
+        pkg.grover_iterate(ctx, iters)
+        hip.lib.hipEventRecord(e1, stream)
+        ms = hip.elapsed_ms(e0, e1)
+        pkg.grover_sync(ctx)
+    finally:
+        pkg.grover_destroy(ctx)
     N = 1 << n
-    ups = N * iters / (ms / 1e3)
     gbs = (bytes_per_update * N * iters + prologue_bytes * N) / (ms / 1e3) / 1e9
-    g.close()
     return {"form": form, "storage": dtype, "iterations": iters, "ms": round(ms, 3),
-            "amplitude_updates_per_s": ups, "algorithmic_gbs": round(gbs, 1),
+            "amplitude_updates_per_s": N * iters / (ms / 1e3), "algorithmic_gbs": round(gbs, 1),
             "frac_of_hbm_peak": round(gbs / HBM_PEAK_GBS, 4)}
 
 
@@ -115,50 +182,57 @@ def main() -> int:
         return 2
 
     import numpy as np
-    import torch
 
     import paper_2005_04635_amd as pkg
     import workloads
 
+    pkg.load()
+    hip = Hip()
+    hip.ok(hip.lib.hipSetDevice(0), "hipSetDevice")
+    stream = ctypes.c_void_p()
+    hip.ok(hip.lib.hipStreamCreate(ctypes.byref(stream)), "hipStreamCreate")
     w = workloads.HASH_N28
     N = 1 << w.n
-    torch.cuda.set_device(0)
-    log(f"[bench] device {torch.cuda.get_device_name(0)}; workload {w.name}")
-    g = pkg.Grover(w.n, w.dtype, hash_seed=w.hash_seed, hash_bits=w.hash_bits, m=w.m, form="fused")
-    marks = g.marked()
-    grid, block = g.query(pkg.grover.Q_GRID), g.query(pkg.grover.Q_BLOCK)
-    u_dev = torch.from_numpy(workloads.uniforms_u53(w.shot_seed, w.shots).astype(np.int64)).cuda()
-    out_dev = None
-    e_it0 = [torch.cuda.Event(enable_timing=True) for _ in range(args.steps)]
-    e_it1 = [torch.cuda.Event(enable_timing=True) for _ in range(args.steps)]
+    log(f"[bench] device {hip.name()}; workload {w.name}")
+    cfg, _ = make_config(pkg, w.n, w.dtype, hash_seed=w.hash_seed, hash_bits=w.hash_bits, m=w.m, form="fused")
+    ctx = pkg.grover_init(cfg, stream.value, 0, 0)
+    marks = pkg.grover_marked(ctx, w.m)
+    grid, block = pkg.grover_query(ctx, 1), pkg.grover_query(ctx, 2)
+    # measurement uniforms, resident on the device before timing
+    u = np.ascontiguousarray(workloads.uniforms_u53(w.shot_seed, w.shots))
+    u_dev = hip.malloc(u.nbytes)
+    out_dev = hip.malloc(w.shots * 8)
+    hip.ok(hip.lib.hipMemcpy(u_dev, ctypes.c_void_p(u.ctypes.data), u.nbytes, 1), "hipMemcpy H2D")
+    e_it = [(hip.event(), hip.event()) for _ in range(args.steps)]
     norms = []
 
     def step(i_timed):
-        nonlocal out_dev
-        g.reset()
+        pkg.grover_reset(ctx)
         if i_timed is not None:
-            e_it0[i_timed].record()
-        g.iterate(w.iterations)
+            hip.lib.hipEventRecord(e_it[i_timed][0], stream)
+        pkg.grover_iterate(ctx, w.iterations)
         if i_timed is not None:
-            e_it1[i_timed].record()
-        norms.append(g.norm())
-        out_dev = g.sample(w.shots, u53=u_dev, device_out=True)
+            hip.lib.hipEventRecord(e_it[i_timed][1], stream)
+        norms.append(pkg.grover_norm(ctx))
+        pkg.grover_sample_u53(ctx, u_dev.value, True, w.shots, out_dev.value, True)
 
     for i in range(args.warmup):
         step(None)
-        torch.cuda.synchronize()
+        pkg.grover_sync(ctx)
         log(f"[bench] warmup step {i + 1}/{args.warmup} done")
-    torch.cuda.synchronize()
+    hip.ok(hip.lib.hipDeviceSynchronize(), "hipDeviceSynchronize")
     t0 = time.perf_counter()
     for i in range(args.steps):
         step(i)
         log(f"[bench] step {i + 1}/{args.steps} enqueued")
-    torch.cuda.synchronize()
+    hip.ok(hip.lib.hipDeviceSynchronize(), "hipDeviceSynchronize")
     t1 = time.perf_counter()
+    pkg.grover_sync(ctx)
     ms_per_step = (t1 - t0) * 1e3 / args.steps
-    it_ms = [a.elapsed_time(b) for a, b in zip(e_it0, e_it1)]
+    it_ms = [hip.elapsed_ms(a, b) for a, b in e_it]
     it_ms_mean = sum(it_ms) / len(it_ms)
-    shots = out_dev.cpu().numpy().astype(np.uint64)
+    shots = np.empty(w.shots, dtype=np.uint64)
+    hip.ok(hip.lib.hipMemcpy(ctypes.c_void_p(shots.ctypes.data), out_dev, shots.nbytes, 2), "hipMemcpy D2H")
     marked_frac = float(np.isin(shots, marks).mean())
     log(f"[bench] {ms_per_step:.1f} ms/step, iterate kernel {it_ms_mean:.1f} ms, norm {norms[-1]:.9f}, "
         f"marked shot fraction {marked_frac:.6f}")
@@ -166,31 +240,29 @@ def main() -> int:
     alg_bytes = 16.0 * N * w.iterations + 8.0 * N
     achieved = alg_bytes / (it_ms_mean / 1e3) / 1e9
     traffic = committed_traffic()
-    # practical ceiling: a device-to-device copy of the same 2 GiB (read + write)
-    src = g.state.view(torch.float32)
-    dst = torch.empty_like(src)
-    dst.copy_(src)
-    torch.cuda.synchronize()
-    c0, c1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    c0.record()
+    # the runtime's own device-to-device copy of the same 2 GiB (read + write), for context
+    state_ptr, state_bytes = pkg.grover_state_device(ctx)
+    dst = hip.malloc(state_bytes)
+    c0, c1 = hip.event(), hip.event()
+    hip.lib.hipMemcpyAsync(dst, ctypes.c_void_p(state_ptr), state_bytes, 3, stream)
+    hip.lib.hipEventRecord(c0, stream)
     for _ in range(5):
-        dst.copy_(src)
-    c1.record()
-    torch.cuda.synchronize()
-    copy_gbs = 5 * 2 * src.numel() * 4 / (c0.elapsed_time(c1) / 1e3) / 1e9
-    del dst
-    g.close()
-    del g
+        hip.lib.hipMemcpyAsync(dst, ctypes.c_void_p(state_ptr), state_bytes, 3, stream)
+    hip.lib.hipEventRecord(c1, stream)
+    copy_gbs = 5 * 2 * state_bytes / (hip.elapsed_ms(c0, c1) / 1e3) / 1e9
+    hip.lib.hipFree(dst)
+    hip.lib.hipFree(u_dev)
+    hip.lib.hipFree(out_dev)
+    pkg.grover_destroy(ctx)
 
     forms = None
     if not args.no_forms:
-        log("[bench] timing the plain binary64 comparator and the fused complex128 form")
+        log("[bench] timing the plain binary64 comparator and the other forms")
         forms = [
-            time_form(pkg, torch, w.n, "c128", "two_pass", marks, 200, 48, 0),
-            time_form(pkg, torch, w.n, "c128", "fused", marks, 400, 32, 16),
-            time_form(pkg, torch, w.n, "c64", "two_pass", marks, 400, 24, 0),
+            time_form(pkg, hip, stream, w.n, "c128", "two_pass", marks, 200, 48, 0),
+            time_form(pkg, hip, stream, w.n, "c128", "fused", marks, 400, 32, 16),
+            time_form(pkg, hip, stream, w.n, "c64", "two_pass", marks, 400, 24, 0),
         ]
-        torch.cuda.empty_cache()
 
     cpu = None
     if not args.no_cpu_baseline:
@@ -221,7 +293,7 @@ def main() -> int:
                      "traffic": traffic, "kernel": "fused_iterate_kernel<C64>",
                      "kernel_ms_per_launch": round(it_ms_mean, 3),
                      "algorithmic_bytes_per_launch": alg_bytes},
-        "copy_ceiling_gbs": round(copy_gbs, 1),
+        "runtime_copy_gbs": round(copy_gbs, 1),
         "vs_plain_fp64": (value / plain) if plain else None,
         "forms": forms,
         "cpu_baseline": cpu,
