@@ -2,6 +2,7 @@
 per Grover iteration at n = 28, against the plain binary64 form.
 
     python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu-baseline] [--no-forms]
+    python bench.py --sweep table1      (the paper's Table 1 sizes: proposed vs gate-level, one line each)
 
 Workload (synthetic by construction; the paper uses no dataset): the single large instance, n = 28
 (2^28 complex64 amplitudes, 2 GiB), M = 8 marked indices defined by the hash predicate
@@ -167,6 +168,45 @@ def cpu_baseline(w, marks, iters):
             "host_cpus": os.cpu_count()}
 
 
+PAPER_TABLE1_S = {  # Table 1: seconds on an Intel i3-5005U, one thread (conventional, proposed)
+    10: (0.010, 0.025), 16: (3.768, 0.349), 18: (37.708, 2.579), 20: (357.029, 20.005)}
+
+
+def sweep_table1(pkg, hip, stream) -> None:
+    """The paper's Table 1 on this GPU: a full single-solution search (the optimal number of iterations from
+    the uniform superposition) with the proposed iteration and with the gate-level one, at the paper's
+    sizes; then three gate-level and proposed iterations at n = 28.  One JSON line per size."""
+    import workloads
+
+    for n in (10, 16, 18, 20, 28):
+        mark = [workloads.marked_index_from_seed(n, 1000 + n)]
+        cfg, keep = make_config(pkg, n, "c64", marks=mark, form="auto")
+        ctx = pkg.grover_init(cfg, stream.value, 0, 0)
+        k_full = pkg.grover_optimal_iterations(n, 1)
+        k = k_full if n <= 20 else 3
+        res = {"sweep": "table1", "n": n, "iterations": k, "storage": "c64",
+               "form": ["", "fused", "resident", "two_pass"][pkg.grover_query(ctx, 0)]}
+        for path, fn in (("proposed", pkg.grover_iterate), ("gate_level", pkg.grover_gate_iterate)):
+            pkg.grover_reset(ctx)
+            fn(ctx, 1)  # warm
+            pkg.grover_reset(ctx)
+            pkg.grover_sync(ctx)
+            e0, e1 = hip.event(), hip.event()
+            hip.lib.hipEventRecord(e0, stream)
+            fn(ctx, k)
+            hip.lib.hipEventRecord(e1, stream)
+            ms = hip.elapsed_ms(e0, e1)
+            pkg.grover_sync(ctx)
+            res[path + "_s"] = ms / 1e3
+            res[path + "_amplitude_iterations_per_s"] = (1 << n) * k / (ms / 1e3)
+        res["speedup_proposed_over_gate"] = res["gate_level_s"] / res["proposed_s"]
+        if n in PAPER_TABLE1_S:
+            conv, prop = PAPER_TABLE1_S[n]
+            res["paper_i3_1thread_s"] = {"conventional": conv, "proposed": prop, "speedup": conv / prop}
+        pkg.grover_destroy(ctx)
+        print(json.dumps(res), flush=True)
+
+
 def main() -> int:
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -175,6 +215,8 @@ def main() -> int:
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-forms", action="store_true")
     ap.add_argument("--cpu-iters", type=int, default=8)
+    ap.add_argument("--sweep", choices=["table1"], default=None,
+                    help="instead of the headline line, print one JSON line per point of a sweep")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py runs on exactly one GPU: the Grover iteration's state is not sharded across GPUs in "
@@ -191,6 +233,9 @@ def main() -> int:
     hip.ok(hip.lib.hipSetDevice(0), "hipSetDevice")
     stream = ctypes.c_void_p()
     hip.ok(hip.lib.hipStreamCreate(ctypes.byref(stream)), "hipStreamCreate")
+    if args.sweep == "table1":
+        sweep_table1(pkg, hip, stream)
+        return 0
     w = workloads.HASH_N28
     N = 1 << w.n
     log(f"[bench] device {hip.name()}; workload {w.name}")
