@@ -3,6 +3,7 @@ per Grover iteration at n = 28, against the plain binary64 form.
 
     python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu-baseline] [--no-forms]
     python bench.py --sweep table1      (the paper's Table 1 sizes: proposed vs gate-level, one line each)
+    python bench.py --sweep precision   (storage x accumulator of the mean at n = 26, one line each)
 
 Workload (synthetic by construction; the paper uses no dataset): the single large instance, n = 28
 (2^28 complex64 amplitudes, 2 GiB), M = 8 marked indices defined by the hash predicate
@@ -30,6 +31,7 @@ import argparse
 import ctypes
 import hashlib
 import json
+import math
 import os
 import re
 import sys
@@ -207,6 +209,66 @@ def sweep_table1(pkg, hip, stream) -> None:
         print(json.dumps(res), flush=True)
 
 
+def sweep_precision(pkg, hip, stream) -> None:
+    """Storage {complex128, complex64, complex bfloat16} x accumulator of the mean {binary64, binary32,
+    Kahan binary32} on the precision workload (n = 26, M = 4, 3216 iterations from the uniform state):
+    error of the two amplitude values against the binary64 oracle and against Grover's closed form, time per
+    iteration and its ratio to the plain binary64 form (complex128, separate oracle / sum / update kernels).
+    One JSON line per setting; the state is read back to check the two-class structure."""
+    import numpy as np
+
+    import oracle
+    import workloads
+
+    orc = oracle.default()
+    w = workloads.PRECISION_N26
+    marks = np.array(w.marks, dtype=np.uint64)
+    N = 1 << w.n
+    a_ref, b_ref = orc.two_class(w.n, w.m, w.iterations)
+    theta = math.asin(math.sqrt(w.m / N))
+    a_cf = math.sin((2 * w.iterations + 1) * theta) / math.sqrt(w.m)
+    b_cf = math.cos((2 * w.iterations + 1) * theta) / math.sqrt(N - w.m)
+    plain = time_form(pkg, hip, stream, w.n, "c128", "two_pass", marks, 300, 48, 0)
+    plain_ms = plain["ms"] / plain["iterations"]
+    print(json.dumps({"sweep": "precision", "storage": "c128", "accum": "f64", "form": "two_pass (plain FP64)",
+                      "ms_per_iteration": plain_ms, "amplitude_updates_per_s": plain["amplitude_updates_per_s"],
+                      "algorithmic_gbs": plain["algorithmic_gbs"]}), flush=True)
+    for storage in ("c128", "c64", "cbf16"):
+        eb = pkg.grover.ELEM_BYTES[pkg.grover.DTYPES[storage]]
+        for accum in ("f64", "f32", "f32_kahan"):
+            cfg, keep = make_config(pkg, w.n, storage, marks=marks, form="fused")
+            cfg.accum = pkg.grover.ACCUMS[accum]
+            ctx = pkg.grover_init(cfg, stream.value, 0, 0)
+            e0, e1 = hip.event(), hip.event()
+            hip.lib.hipEventRecord(e0, stream)
+            pkg.grover_iterate(ctx, w.iterations)
+            hip.lib.hipEventRecord(e1, stream)
+            ms = hip.elapsed_ms(e0, e1)
+            pkg.grover_sync(ctx)
+            raw = np.empty(N * eb, dtype=np.uint8)
+            pkg.grover_read_state(ctx, raw.ctypes.data, raw.nbytes)
+            pkg.grover_destroy(ctx)
+            if storage == "cbf16":
+                psi = pkg.grover.bf16_pairs_to_complex(raw.view(np.uint16))
+            else:
+                psi = raw.view(np.complex128 if storage == "c128" else np.complex64)
+            a, b = complex(psi[int(marks[0])]), complex(psi[0 if 0 not in marks else 1])
+            two_class = bool(np.all(psi[marks.astype(np.int64)] == psi[int(marks[0])]))
+            del psi, raw
+            gbs = (2 * eb * N * w.iterations + eb * N) / (ms / 1e3) / 1e9
+            print(json.dumps({
+                "sweep": "precision", "n": w.n, "m": w.m, "iterations": w.iterations, "storage": storage,
+                "accum": accum, "form": "fused",
+                "marked_amplitude": a.real, "unmarked_amplitude": b.real,
+                "p_marked": w.m * abs(a) ** 2,
+                "max_abs_err_vs_fp64_oracle": max(abs(a - a_ref), abs(b - b_ref)),
+                "max_abs_err_vs_closed_form": max(abs(a - a_cf), abs(b - b_cf)),
+                "marked_equal": two_class, "ms_per_iteration": ms / w.iterations,
+                "amplitude_updates_per_s": N * w.iterations / (ms / 1e3), "algorithmic_gbs": round(gbs, 1),
+                "frac_of_hbm_peak": round(gbs / HBM_PEAK_GBS, 4),
+                "speedup_vs_plain_fp64": plain_ms / (ms / w.iterations)}), flush=True)
+
+
 def main() -> int:
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -215,7 +277,7 @@ def main() -> int:
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-forms", action="store_true")
     ap.add_argument("--cpu-iters", type=int, default=8)
-    ap.add_argument("--sweep", choices=["table1"], default=None,
+    ap.add_argument("--sweep", choices=["table1", "precision"], default=None,
                     help="instead of the headline line, print one JSON line per point of a sweep")
     args = ap.parse_args()
     if args.gpus != 1:
@@ -235,6 +297,9 @@ def main() -> int:
     hip.ok(hip.lib.hipStreamCreate(ctypes.byref(stream)), "hipStreamCreate")
     if args.sweep == "table1":
         sweep_table1(pkg, hip, stream)
+        return 0
+    if args.sweep == "precision":
+        sweep_precision(pkg, hip, stream)
         return 0
     w = workloads.HASH_N28
     N = 1 << w.n

@@ -47,8 +47,18 @@ extern "C" {
 typedef enum grover_dtype {
     GROVER_F64_REAL = 0, /* double per amplitude, imaginary parts identically 0 */
     GROVER_C64 = 1,      /* complex64: float re, float im; update computed in binary64, stored rounded */
-    GROVER_C128 = 2      /* complex128: double re, double im */
+    GROVER_C128 = 2,     /* complex128: double re, double im */
+    GROVER_CBF16 = 3     /* complex bfloat16: bf16 re, bf16 im (4 bytes); update in binary64, rounded once
+                            to nearest even; fused form only */
 } grover_dtype;
+
+/* Precision of the sum S = sum_i s_i c_i that the mean is taken from (per-thread accumulation and the
+ * reduction tree above it).  The update c' = 2S/N - s c is always computed in binary64. */
+typedef enum grover_accum {
+    GROVER_ACC_F64 = 0,       /* binary64 (default) */
+    GROVER_ACC_F32 = 1,       /* binary32; fused form only */
+    GROVER_ACC_F32_KAHAN = 2  /* binary32 with Kahan-compensated per-thread sums; fused form only */
+} grover_accum;
 
 typedef enum grover_oracle_kind {
     GROVER_ORACLE_LIST = 0, /* marked set given as an explicit list of indices (Algorithm 3's k[]) */
@@ -56,7 +66,7 @@ typedef enum grover_oracle_kind {
 } grover_oracle_kind;
 
 typedef enum grover_form {
-    GROVER_FORM_AUTO = 0,     /* RESIDENT for n <= 14, FUSED above */
+    GROVER_FORM_AUTO = 0,     /* RESIDENT for n <= 14 with f64/c64/c128 storage and binary64 sums, else FUSED */
     GROVER_FORM_FUSED = 1,    /* one persistent cooperative kernel per grover_iterate call, one grid
                                  barrier per iteration, update fused with the next iteration's sum */
     GROVER_FORM_RESIDENT = 2, /* one workgroup holds the whole state on chip (n <= 14) */
@@ -75,13 +85,16 @@ typedef struct grover_config {
     uint64_t hash_seed;      /* HASH only: SplitMix64 seed of the predicate */
     uint32_t form;           /* grover_form */
     uint32_t flags;          /* reserved, must be 0 */
+    uint32_t accum;          /* grover_accum */
+    uint32_t reserved;       /* must be 0 */
 } grover_config;
 
 typedef struct grover_ctx grover_ctx;
 
 /* grover_init — create a context and prepare the initial state (Algorithm 5: psi = H^n |0>).
  *   out         receives the new context (set to NULL on failure).
- *   cfg         problem description, validated: n range, dtype/form/kind values, flags == 0, marked
+ *   cfg         problem description, validated: n range, dtype/form/kind/accum values, flags == 0,
+ *               reserved == 0, the form supports the dtype and accum (else GROVER_E_UNSUPPORTED), marked
  *               indices distinct and < N, m <= N; for HASH the predicate is evaluated on the device over
  *               all N indices, its hits compacted into the marked list, and GROVER_E_PREDICATE returned
  *               when their number differs from cfg->m.
@@ -108,10 +121,11 @@ int grover_iterate(grover_ctx *ctx, uint64_t k);
 
 /* grover_gate_iterate — k iterations of the conventional gate-level simulator (Algorithm 2's loop body):
  * oracle sign flip, H^n as n single-qubit passes (Algorithm 1 with U = H), the conditional phase shift
- * 2|0><0| - I, H^n again.  Asynchronous. */
+ * 2|0><0| - I, H^n again.  Asynchronous.  GROVER_E_UNSUPPORTED for bfloat16 storage. */
 int grover_gate_iterate(grover_ctx *ctx, uint64_t k);
 
-/* grover_apply_hadamard_all — psi <- H^n psi as n single-qubit passes (Algorithm 1).  Asynchronous. */
+/* grover_apply_hadamard_all — psi <- H^n psi as n single-qubit passes (Algorithm 1).  Asynchronous.
+ * GROVER_E_UNSUPPORTED for bfloat16 storage. */
 int grover_apply_hadamard_all(grover_ctx *ctx);
 
 /* grover_sample — measurement (Background, step 6; the paper gives no procedure, this library defines it):

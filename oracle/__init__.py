@@ -61,6 +61,8 @@ def load(path: str = _LIB):
             "orc_gate_search": (ctypes.c_int, [u32, pu, u64, u64, pd]),
             "orc_norm": (dbl, [u32, pd]),
             "orc_two_class": (None, [u32, u64, u64, pd, pd]),
+            "orc_round_to_bits": (dbl, [dbl, ctypes.c_int]),
+            "orc_two_class_stored": (None, [u32, u64, u64, ctypes.c_int, pd, pd]),
             "orc_sample": (ctypes.c_int, [u32, pd, pu, u64, pu]),
             "orc_uniforms_u53": (None, [u64, u64, pu]),
         }
@@ -180,6 +182,14 @@ class Oracle:
     def two_class(self, n: int, m: int, iters: int):
         a, b = ctypes.c_double(), ctypes.c_double()
         self.lib.orc_two_class(n, m, iters, ctypes.byref(a), ctypes.byref(b))
+        return a.value, b.value
+
+    def round_to_bits(self, x: float, p: int) -> float:
+        return float(self.lib.orc_round_to_bits(float(x), p))
+
+    def two_class_stored(self, n: int, m: int, iters: int, p: int):
+        a, b = ctypes.c_double(), ctypes.c_double()
+        self.lib.orc_two_class_stored(n, m, iters, p, ctypes.byref(a), ctypes.byref(b))
         return a.value, b.value
 
     def sample(self, psi: np.ndarray, u53: np.ndarray) -> np.ndarray:

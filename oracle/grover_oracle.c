@@ -275,6 +275,36 @@ void orc_two_class(uint32_t n, uint64_t m, uint64_t iters, double *a_out, double
     *b_out = b;
 }
 
+/* x rounded to the nearest binary floating-point number with p significand bits, ties to even, exponent
+ * unbounded (p = 53: binary64 itself; p = 24: binary32; p = 8: bfloat16, over their normal ranges). */
+double orc_round_to_bits(double x, int p)
+{
+    if (x == 0.0 || !isfinite(x))
+        return x;
+    int e;
+    const double m = frexp(x, &e); /* x = m 2^e, 0.5 <= |m| < 1 */
+    const double r = nearbyint(ldexp(m, p)); /* default rounding mode: to nearest, ties to even */
+    return ldexp(r, e - p);
+}
+
+/* The two-class form of the iteration with the amplitudes stored at p significand bits: the uniform
+ * amplitude and every updated amplitude are rounded to p bits, the sum and the update are binary64.  This
+ * is what a device that stores amplitudes in that precision and accumulates in binary64 computes when
+ * started from the uniform superposition, up to the summation order of the sum. */
+void orc_two_class_stored(uint32_t n, uint64_t m, uint64_t iters, int p, double *a_out, double *b_out)
+{
+    const double N = ldexp(1.0, (int)n);
+    double a = orc_round_to_bits(orc_uniform_amplitude(n), p), b = a;
+    for (uint64_t it = 0; it < iters; ++it) {
+        const double s = (N - (double)m) * b - (double)m * a;
+        const double mean2 = (s * 2.0) / N;
+        a = orc_round_to_bits(mean2 + a, p);
+        b = orc_round_to_bits(mean2 - b, p);
+    }
+    *a_out = a;
+    *b_out = b;
+}
+
 /* Measurement (Background, step 6) by inverse transform over an integer CDF:
  *   p_i = Re^2 + Im^2 (binary64),  q_i = floor(p_i * 2^62),  Q_i = q_0 + ... + q_i,
  *   t_j = floor(U_j * Q_{N-1} / 2^53) for a 53-bit uniform integer U_j,

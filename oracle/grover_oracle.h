@@ -27,6 +27,8 @@ int orc_gate_iterate(uint32_t n, double *psi, const uint64_t *k, uint64_t m, uin
 int orc_gate_search(uint32_t n, const uint64_t *k, uint64_t m, uint64_t iters, double *psi);
 double orc_norm(uint32_t n, const double *psi);
 void orc_two_class(uint32_t n, uint64_t m, uint64_t iters, double *a_out, double *b_out);
+double orc_round_to_bits(double x, int p);
+void orc_two_class_stored(uint32_t n, uint64_t m, uint64_t iters, int p, double *a_out, double *b_out);
 int orc_sample(uint32_t n, const double *psi, const uint64_t *u53, uint64_t shots, uint64_t *out);
 void orc_uniforms_u53(uint64_t seed, uint64_t shots, uint64_t *out);
 

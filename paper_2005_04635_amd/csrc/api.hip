@@ -166,16 +166,21 @@ int grover_init(grover_ctx **out, const grover_config *cfg, void *hip_stream, vo
     *out = nullptr;
     if (!cfg)
         return GROVER_E_INVAL;
-    if (cfg->n < 1 || cfg->n > kMaxQubits || cfg->dtype > GROVER_C128 || cfg->oracle_kind > GROVER_ORACLE_HASH ||
-        cfg->form > GROVER_FORM_TWO_PASS || cfg->flags != 0 || cfg->hash_bits > 64)
+    if (cfg->n < 1 || cfg->n > kMaxQubits || cfg->dtype > GROVER_CBF16 || cfg->oracle_kind > GROVER_ORACLE_HASH ||
+        cfg->form > GROVER_FORM_TWO_PASS || cfg->flags != 0 || cfg->hash_bits > 64 ||
+        cfg->accum > GROVER_ACC_F32_KAHAN || cfg->reserved != 0)
         return GROVER_E_INVAL;
     const uint64_t N = uint64_t(1) << cfg->n;
     if (cfg->m > N)
         return GROVER_E_INVAL;
+    // bfloat16 storage and binary32 sums exist in the fused form only
+    const bool fused_only = cfg->dtype == GROVER_CBF16 || cfg->accum != GROVER_ACC_F64;
     uint32_t form = cfg->form;
     if (form == GROVER_FORM_AUTO)
-        form = cfg->n <= kResidentMaxQubits ? GROVER_FORM_RESIDENT : GROVER_FORM_FUSED;
+        form = cfg->n <= kResidentMaxQubits && !fused_only ? GROVER_FORM_RESIDENT : GROVER_FORM_FUSED;
     if (form == GROVER_FORM_RESIDENT && cfg->n > kResidentMaxQubits)
+        return GROVER_E_UNSUPPORTED;
+    if (fused_only && form != GROVER_FORM_FUSED)
         return GROVER_E_UNSUPPORTED;
     if (cfg->oracle_kind == GROVER_ORACLE_HASH && cfg->m > kHashMarkCap)
         return GROVER_E_UNSUPPORTED;
@@ -188,6 +193,7 @@ int grover_init(grover_ctx **out, const grover_config *cfg, void *hip_stream, vo
         c->n = cfg->n;
         c->N = N;
         c->dtype = cfg->dtype;
+        c->accum = cfg->accum;
         c->form = form;
         c->kind = cfg->oracle_kind;
         c->stream = static_cast<hipStream_t>(hip_stream);
@@ -363,6 +369,8 @@ int grover_gate_iterate(grover_ctx *ctx, uint64_t k)
 {
     if (check_ctx(ctx))
         return GROVER_E_INVAL;
+    if (ctx->dtype == GROVER_CBF16)
+        return fail(ctx, GROVER_E_UNSUPPORTED, "the gate-level path has no bfloat16 form");
     for (uint64_t it = 0; it < k; ++it) {
         GROVER_HIP(ctx, launch_oracle_flip(ctx), "oracle flip");
         GROVER_HIP(ctx, launch_hadamard_all(ctx), "hadamard passes");
@@ -376,6 +384,8 @@ int grover_apply_hadamard_all(grover_ctx *ctx)
 {
     if (check_ctx(ctx))
         return GROVER_E_INVAL;
+    if (ctx->dtype == GROVER_CBF16)
+        return fail(ctx, GROVER_E_UNSUPPORTED, "the gate-level path has no bfloat16 form");
     GROVER_HIP(ctx, launch_hadamard_all(ctx), "hadamard passes");
     return GROVER_OK;
 }

@@ -20,9 +20,33 @@ constexpr uint32_t kResidentMaxQubits = 14;  // on-chip path: 2^14 amplitudes in
 constexpr int kResidentBlock = 1024;
 constexpr uint64_t kHashMarkCap = uint64_t(1) << 26;  // largest hash-defined marked list kept
 
+// ------------------------------------------------------------------------------------ bfloat16 helpers
+// bfloat16 = the top 16 bits of an IEEE binary32.  Rounding from binary64 is done once, correctly: round
+// to odd into binary32 (truncate, then set the last bit when inexact), then round to nearest even into
+// bfloat16 — the intermediate has 16 more bits than the target, so no double rounding can occur.
+__device__ __host__ inline float bf16_to_float(uint16_t b)
+{
+    const uint32_t u = uint32_t(b) << 16;
+    float f;
+    __builtin_memcpy(&f, &u, 4);
+    return f;
+}
+
+__device__ inline uint16_t double_to_bf16(double d)
+{
+    const float t = __double2float_rz(d);
+    uint32_t u = __float_as_uint(t);
+    if (double(t) != d)
+        u |= 1u;
+    u += 0x7FFFu + ((u >> 16) & 1u);
+    return uint16_t(u >> 16);
+}
+
 // ----------------------------------------------------------------------------------- storage traits
 // Every kernel streams the state in 16-byte vectors.  A vector holds EPV amplitudes:
-//   F64 real: double2 = 2 amplitudes; C64: float4 = 2 amplitudes (re, im, re, im); C128: double2 = 1.
+//   F64 real: double2 = 2 amplitudes; C64: float4 = 2 amplitudes (re, im, re, im); C128: double2 = 1;
+//   CBF16: 8 bfloat16 = 4 amplitudes (re, im, ...).
+// re/im read amplitude e as binary64; set writes amplitude e, rounded to the storage type.
 struct F64Real {
     using vec = double2;
     static constexpr int EPV = 2;
@@ -30,6 +54,13 @@ struct F64Real {
     static constexpr bool kComplex = false;
     __device__ static inline double re(const vec &v, int e) { return e == 0 ? v.x : v.y; }
     __device__ static inline double im(const vec &, int) { return 0.0; }
+    __device__ static inline void set(vec &v, int e, double r, double)
+    {
+        if (e == 0)
+            v.x = r;
+        else
+            v.y = r;
+    }
 };
 struct C64 {
     using vec = float4;
@@ -38,6 +69,16 @@ struct C64 {
     static constexpr bool kComplex = true;
     __device__ static inline double re(const vec &v, int e) { return e == 0 ? double(v.x) : double(v.z); }
     __device__ static inline double im(const vec &v, int e) { return e == 0 ? double(v.y) : double(v.w); }
+    __device__ static inline void set(vec &v, int e, double r, double i)
+    {
+        if (e == 0) {
+            v.x = float(r);
+            v.y = float(i);
+        } else {
+            v.z = float(r);
+            v.w = float(i);
+        }
+    }
 };
 struct C128 {
     using vec = double2;
@@ -46,9 +87,37 @@ struct C128 {
     static constexpr bool kComplex = true;
     __device__ static inline double re(const vec &v, int) { return v.x; }
     __device__ static inline double im(const vec &v, int) { return v.y; }
+    __device__ static inline void set(vec &v, int, double r, double i)
+    {
+        v.x = r;
+        v.y = i;
+    }
+};
+struct bf16x8 {
+    uint16_t h[8];
+};
+struct CBF16 {
+    using vec = bf16x8;
+    static constexpr int EPV = 4;
+    static constexpr int kBytes = 4;
+    static constexpr bool kComplex = true;
+    __device__ static inline double re(const vec &v, int e) { return double(bf16_to_float(v.h[2 * e])); }
+    __device__ static inline double im(const vec &v, int e) { return double(bf16_to_float(v.h[2 * e + 1])); }
+    __device__ static inline void set(vec &v, int e, double r, double i)
+    {
+        v.h[2 * e] = double_to_bf16(r);
+        v.h[2 * e + 1] = double_to_bf16(i);
+    }
 };
 
-inline size_t elem_bytes(uint32_t dtype) { return dtype == GROVER_C128 ? 16 : 8; }
+inline size_t elem_bytes(uint32_t dtype)
+{
+    return dtype == GROVER_C128 ? 16 : dtype == GROVER_CBF16 ? 4 : 8;
+}
+inline uint64_t elems_per_vec(uint32_t dtype)
+{
+    return dtype == GROVER_C128 ? 1 : dtype == GROVER_CBF16 ? 4 : 2;
+}
 
 // 16-byte loads and stores of a storage vector; the nontemporal forms mark the lines as streaming so they
 // do not displace reused data from the caches.
@@ -79,61 +148,77 @@ __device__ inline void store16(const V &v, V *p)
     }
 }
 
+// ---------------------------------------------------------------------------------------- accumulators
+// Per-thread accumulation of the sum S = sum_i s_i c_i.  add() takes binary64 values of stored amplitudes.
+//   AccF64:       binary64 sums (the library's default; the tree above it is binary64 too)
+//   AccF32:       plain binary32 sums (tree in binary32)
+//   AccF32Kahan:  binary32 sums with Kahan's compensation (tree in binary32)
+struct AccF64 {
+    using value = double;
+    double r = 0.0, i = 0.0;
+    __device__ inline void add(double x, double y)
+    {
+        r += x;
+        i += y;
+    }
+    __device__ inline double res_r() const { return r; }
+    __device__ inline double res_i() const { return i; }
+};
+struct AccF32 {
+    using value = float;
+    float r = 0.0f, i = 0.0f;
+    __device__ inline void add(double x, double y)
+    {
+        r += float(x);
+        i += float(y);
+    }
+    __device__ inline float res_r() const { return r; }
+    __device__ inline float res_i() const { return i; }
+};
+struct AccF32Kahan {
+    using value = float;
+    float r = 0.0f, i = 0.0f, cr = 0.0f, ci = 0.0f;  // running sums and their compensations
+    __device__ static inline void kahan(float &s, float &c, float x)
+    {
+        const float y = x - c;
+        const float t = s + y;
+        c = (t - s) - y;
+        s = t;
+    }
+    __device__ inline void add(double x, double y)
+    {
+        kahan(r, cr, float(x));
+        kahan(i, ci, float(y));
+    }
+    __device__ inline float res_r() const { return r - cr; }
+    __device__ inline float res_i() const { return i - ci; }
+};
+
 // ------------------------------------------------------------------------------ update of one vector
 // Inversion about the mean on the oracle-flipped amplitudes: c' = 2S/N - s*c with s = -1 for marked
-// amplitudes (bit e of `marked`), +1 otherwise.  (mr, mi) = 2S/N in binary64.  The value that is stored
-// (rounded to the element type) is also added, times s, to (ar, ai): that is the next iteration's sum.
-template <class T>
-__device__ inline void update_vec(typename T::vec &v, double mr, double mi, unsigned marked, double &ar,
-                                  double &ai);
-
-template <>
-__device__ inline void update_vec<C64>(float4 &v, double mr, double mi, unsigned marked, double &ar,
-                                       double &ai)
-{
-    const double s0 = (marked & 1u) ? -1.0 : 1.0, s1 = (marked & 2u) ? -1.0 : 1.0;
-    const float r0 = float(mr - s0 * double(v.x)), i0 = float(mi - s0 * double(v.y));
-    const float r1 = float(mr - s1 * double(v.z)), i1 = float(mi - s1 * double(v.w));
-    v = make_float4(r0, i0, r1, i1);
-    ar += s0 * double(r0);
-    ai += s0 * double(i0);
-    ar += s1 * double(r1);
-    ai += s1 * double(i1);
-}
-
-template <>
-__device__ inline void update_vec<F64Real>(double2 &v, double mr, double, unsigned marked, double &ar,
-                                           double &)
-{
-    const double s0 = (marked & 1u) ? -1.0 : 1.0, s1 = (marked & 2u) ? -1.0 : 1.0;
-    const double r0 = mr - s0 * v.x, r1 = mr - s1 * v.y;
-    v = make_double2(r0, r1);
-    ar += s0 * r0;
-    ar += s1 * r1;
-}
-
-template <>
-__device__ inline void update_vec<C128>(double2 &v, double mr, double mi, unsigned marked, double &ar,
-                                        double &ai)
-{
-    const double s0 = (marked & 1u) ? -1.0 : 1.0;
-    const double r0 = mr - s0 * v.x, i0 = mi - s0 * v.y;
-    v = make_double2(r0, i0);
-    ar += s0 * r0;
-    ai += s0 * i0;
-}
-
-// Sum of s*c over one vector, in exactly the order update_vec accumulates (so a fresh sum of a stored
-// state equals, bit for bit, the sum the fused update produced while writing it).
-template <class T>
-__device__ inline void accum_vec(const typename T::vec &v, unsigned marked, double &ar, double &ai)
+// amplitudes (bit e of `marked`), +1 otherwise, computed in binary64 from (mr, mi) = 2S/N and rounded to
+// the storage type.  The stored value, times s, is added to the accumulator: that is the next iteration's
+// sum.
+template <class T, class A>
+__device__ inline void update_vec(typename T::vec &v, double mr, double mi, unsigned marked, A &acc)
 {
 #pragma unroll
     for (int e = 0; e < T::EPV; ++e) {
         const double s = (marked >> e) & 1u ? -1.0 : 1.0;
-        ar += s * T::re(v, e);
-        if (T::kComplex)
-            ai += s * T::im(v, e);
+        T::set(v, e, mr - s * T::re(v, e), mi - s * T::im(v, e));
+        acc.add(s * T::re(v, e), s * T::im(v, e));
+    }
+}
+
+// Sum of s*c over one vector, in exactly the order update_vec accumulates (so a fresh sum of a stored
+// state equals, bit for bit, the sum the fused update produced while writing it).
+template <class T, class A>
+__device__ inline void accum_vec(const typename T::vec &v, unsigned marked, A &acc)
+{
+#pragma unroll
+    for (int e = 0; e < T::EPV; ++e) {
+        const double s = (marked >> e) & 1u ? -1.0 : 1.0;
+        acc.add(s * T::re(v, e), s * T::im(v, e));
     }
 }
 
@@ -176,8 +261,10 @@ __device__ inline unsigned marked_bits(const uint64_t *marks, uint64_t lo, uint6
     return bits;
 }
 
-// Wavefront sum of a double; the butterfly order is fixed, so the result is reproducible.
-__device__ inline double wave_sum(double x)
+// Wavefront sum; the butterfly order is fixed and addition is commutative, so every lane ends with the same,
+// reproducible value.
+template <class V>
+__device__ inline V wave_sum(V x)
 {
 #pragma unroll
     for (int off = kWave / 2; off > 0; off >>= 1)
@@ -185,9 +272,10 @@ __device__ inline double wave_sum(double x)
     return x;
 }
 
-// Workgroup sum of (a, b): wave butterflies, then wave 0 adds the per-wave values in wave order.
-// `red` must hold 2 * (blockDim / 64) doubles.  Result valid in thread 0 only.
-__device__ inline void block_sum2(double &a, double &b, double *red)
+// Workgroup sum of (a, b): wave butterflies, then thread 0 adds the per-wave values in wave order.
+// `red` must hold 2 * (blockDim / 64) values.  Result valid in thread 0 only.
+template <class V>
+__device__ inline void block_sum2(V &a, V &b, V *red)
 {
     const int lane = threadIdx.x % kWave, wave = threadIdx.x / kWave, nw = blockDim.x / kWave;
     a = wave_sum(a);
@@ -198,7 +286,7 @@ __device__ inline void block_sum2(double &a, double &b, double *red)
     }
     __syncthreads();
     if (threadIdx.x == 0) {
-        double sa = 0.0, sb = 0.0;
+        V sa = V(0), sb = V(0);
         for (int w = 0; w < nw; ++w) {
             sa += red[2 * w];
             sb += red[2 * w + 1];
@@ -236,6 +324,7 @@ struct grover_ctx {
     uint32_t n = 0;
     uint64_t N = 0;
     uint32_t dtype = 0;
+    uint32_t accum = 0;
     uint32_t form = 0;  // resolved (never AUTO)
     uint32_t kind = 0;
     void *state = nullptr;

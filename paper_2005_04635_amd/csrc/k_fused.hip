@@ -5,8 +5,8 @@
 // iteration is a single streaming pass over it:
 //
 //   read c_i, flip the sign of marked amplitudes (Algorithm 3), write c_i' = 2S/N - s_i c_i (Algorithm 4's
-//   second loop), and add s_i c_i' into a binary64 accumulator — which is Algorithm 4's first loop for the
-//   NEXT iteration, already applied to the next iteration's oracle-flipped state.
+//   second loop), and add s_i c_i' into an accumulator — which is Algorithm 4's first loop for the NEXT
+//   iteration, already applied to the next iteration's oracle-flipped state.
 //
 // The per-workgroup accumulators then meet at a grid barrier: every workgroup publishes its partial, the
 // last one to arrive adds all partials in workgroup order (so the sum is reproducible run to run) and
@@ -15,10 +15,17 @@
 //
 // A prologue pass computes S of the incoming state with the same per-thread order as the fused
 // accumulation, which makes iterate(a); iterate(b) equal iterate(a + b) bit for bit.
+//
+// Template parameters: T = storage type (F64Real, C64, C128, CBF16), A = accumulator of the sum (AccF64,
+// AccF32, AccF32Kahan; the grid tree runs in A's precision).  The update itself is always binary64.
 #include "internal.h"
 
 namespace grover {
 namespace {
+
+constexpr int kBlock = 1024;  // one workgroup per CU: fewest barrier participants, 16 waves per CU
+constexpr int kUnroll = 4;    // 16-byte vectors per thread per tile
+constexpr int kTile = kBlock * kUnroll;
 
 struct FusedArgs {
     void *state;
@@ -33,18 +40,30 @@ struct FusedArgs {
     uint64_t timeout_ticks;
 };
 
-template <int BLOCK>
+template <class V>
 struct Shared {
-    double red[2 * (BLOCK / kWave)];
-    double sum[2];
+    V red[2 * (kBlock / kWave)];
+    V sum[2];
     int last;
     int abort;
 };
 
 __device__ inline uint32_t *arrive_word(GridSync *s, unsigned p) { return p ? &s->arrive1 : &s->arrive0; }
 
-// Grid-wide sum of (xr, xi) for barrier generation `gen`.  Returns false when the wait gave up (timeout,
-// or another workgroup gave up); every thread of the workgroup gets the same answer and the sum in (xr, xi).
+__device__ inline uint64_t load_bits(const uint64_t *p)
+{
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+__device__ inline void store_bits(uint64_t *p, double x)
+{
+    __hip_atomic_store(p, (uint64_t)__double_as_longlong(x), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// Grid-wide sum of (xr, xi) for barrier generation `gen`, in the arithmetic of V (binary64 or binary32;
+// partials travel as binary64, which holds a binary32 exactly).  Returns false when the wait gave up
+// (timeout, or another workgroup gave up); every thread of the workgroup gets the same answer and the sum
+// in (xr, xi).
 //
 // Memory ordering: a workgroup publishes its partial and then increments the arrival counter with release
 // semantics; the workgroup whose increment completes the count acquires, adds the partials in workgroup
@@ -52,16 +71,15 @@ __device__ inline uint32_t *arrive_word(GridSync *s, unsigned p) { return p ? &s
 // acquire once it has advanced.  Acquire/release at agent scope make the data visible across the XCDs'
 // separate L2s.  (Letting every workgroup poll the counter and add the partials itself was measured
 // slower on MI355X: the polls contend with the increments.)
-template <int BLOCK>
-__device__ bool grid_sum(double &xr, double &xi, const FusedArgs &a, uint64_t gen, Shared<BLOCK> &sh)
+template <class V>
+__device__ bool grid_sum(V &xr, V &xi, const FusedArgs &a, uint64_t gen, Shared<V> &sh)
 {
     const unsigned p = unsigned(gen & 1u);
     block_sum2(xr, xi, sh.red);
     if (threadIdx.x == 0) {
         uint64_t *dst = a.partials + (uint64_t(p) * gridDim.x + blockIdx.x) * 2u;
-        __hip_atomic_store(dst, (uint64_t)__double_as_longlong(xr), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        __hip_atomic_store(dst + 1, (uint64_t)__double_as_longlong(xi), __ATOMIC_RELAXED,
-                           __HIP_MEMORY_SCOPE_AGENT);
+        store_bits(dst, double(xr));
+        store_bits(dst + 1, double(xi));
         const unsigned old =
             __hip_atomic_fetch_add(arrive_word(a.sync, p), 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
         sh.last = (old == gridDim.x - 1u);
@@ -71,20 +89,16 @@ __device__ bool grid_sum(double &xr, double &xi, const FusedArgs &a, uint64_t ge
     if (sh.last) {
         // Every partial of this barrier is published.  Add them in workgroup order.
         __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
-        double sr = 0.0, si = 0.0;
-        for (unsigned w = threadIdx.x; w < gridDim.x; w += BLOCK) {
+        V sr = V(0), si = V(0);
+        for (unsigned w = threadIdx.x; w < gridDim.x; w += kBlock) {
             const uint64_t *src = a.partials + (uint64_t(p) * gridDim.x + w) * 2u;
-            sr += __longlong_as_double(
-                (long long)__hip_atomic_load(src, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
-            si += __longlong_as_double(
-                (long long)__hip_atomic_load(src + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
+            sr += V(__longlong_as_double((long long)load_bits(src)));
+            si += V(__longlong_as_double((long long)load_bits(src + 1)));
         }
         block_sum2(sr, si, sh.red);
         if (threadIdx.x == 0) {
-            __hip_atomic_store(&a.sync->sum[p][0], (uint64_t)__double_as_longlong(sr), __ATOMIC_RELAXED,
-                               __HIP_MEMORY_SCOPE_AGENT);
-            __hip_atomic_store(&a.sync->sum[p][1], (uint64_t)__double_as_longlong(si), __ATOMIC_RELAXED,
-                               __HIP_MEMORY_SCOPE_AGENT);
+            store_bits(&a.sync->sum[p][0], double(sr));
+            store_bits(&a.sync->sum[p][1], double(si));
             __hip_atomic_store(arrive_word(a.sync, p), 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
             __hip_atomic_store(&a.sync->flag, gen, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
             sh.sum[0] = sr;
@@ -107,10 +121,8 @@ __device__ bool grid_sum(double &xr, double &xi, const FusedArgs &a, uint64_t ge
         }
         if (ok) {
             __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
-            sh.sum[0] = __longlong_as_double(
-                (long long)__hip_atomic_load(&a.sync->sum[p][0], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
-            sh.sum[1] = __longlong_as_double(
-                (long long)__hip_atomic_load(&a.sync->sum[p][1], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
+            sh.sum[0] = V(__longlong_as_double((long long)load_bits(&a.sync->sum[p][0])));
+            sh.sum[1] = V(__longlong_as_double((long long)load_bits(&a.sync->sum[p][1])));
         } else {
             sh.abort = 1;
         }
@@ -163,12 +175,12 @@ constexpr int kMarkWords = 1024;  // LDS bitmap of this workgroup's tiles that h
 // to start on lines the memory-side cache might still hold, measured no faster on MI355X.)  UPDATE:
 // c' = 2S/N - s c written back and s c' summed; otherwise s c summed.  The per-thread order of the sum is
 // identical in both modes.  `slow_tiles` (when `table`) flags the workgroup's tiles holding marked
-// amplitudes; without a table every tile is checked against the marked list.
-template <class T, bool NT, int BLOCK, int UNROLL, bool UPDATE>
+// amplitudes; without a table every tile is checked against the marked list.  Loads and stores carry the
+// nontemporal hint (+6 % measured on MI355X).
+template <class T, class A, bool UPDATE>
 __device__ inline void chunk_pass(const FusedArgs &a, const uint32_t *slow_tiles, bool table, double mr, double mi,
-                                  double &ar, double &ai)
+                                  A &acc)
 {
-    constexpr int kTile = BLOCK * UNROLL;  // 16-byte vectors per tile
     using V = typename T::vec;
     V *st = static_cast<V *>(a.state);
     const unsigned tid = threadIdx.x;
@@ -181,17 +193,17 @@ __device__ inline void chunk_pass(const FusedArgs &a, const uint32_t *slow_tiles
         const bool full = v0 + kTile <= a.nvec;
         const bool marked = table ? ((slow_tiles[j >> 5] >> (j & 31)) & 1u) != 0u : a.m > 0;
         if (full && !marked) {
-            V x[UNROLL];
+            V x[kUnroll];
 #pragma unroll
-            for (int u = 0; u < UNROLL; ++u)
-                x[u] = load16<NT>(st + v0 + u * BLOCK + tid);
+            for (int u = 0; u < kUnroll; ++u)
+                x[u] = load16<true>(st + v0 + u * kBlock + tid);
 #pragma unroll
-            for (int u = 0; u < UNROLL; ++u) {
+            for (int u = 0; u < kUnroll; ++u) {
                 if (UPDATE) {
-                    update_vec<T>(x[u], mr, mi, 0u, ar, ai);
-                    store16<NT>(x[u], st + v0 + u * BLOCK + tid);
+                    update_vec<T>(x[u], mr, mi, 0u, acc);
+                    store16<true>(x[u], st + v0 + u * kBlock + tid);
                 } else {
-                    accum_vec<T>(x[u], 0u, ar, ai);
+                    accum_vec<T>(x[u], 0u, acc);
                 }
             }
         } else {
@@ -204,24 +216,24 @@ __device__ inline void chunk_pass(const FusedArgs &a, const uint32_t *slow_tiles
 #pragma unroll
             for (int q = 0; q < kTileMarks; ++q)
                 mk[q] = in_regs && mp + q < mq ? a.marks[mp + q] : ~uint64_t(0);
-            V x[UNROLL];
+            V x[kUnroll];
 #pragma unroll
-            for (int u = 0; u < UNROLL; ++u) {
-                const uint64_t v = v0 + u * BLOCK + tid;
+            for (int u = 0; u < kUnroll; ++u) {
+                const uint64_t v = v0 + u * kBlock + tid;
                 if (v < a.nvec)
-                    x[u] = load16<NT>(st + v);
+                    x[u] = load16<true>(st + v);
             }
 #pragma unroll
-            for (int u = 0; u < UNROLL; ++u) {
-                const uint64_t v = v0 + u * BLOCK + tid;
+            for (int u = 0; u < kUnroll; ++u) {
+                const uint64_t v = v0 + u * kBlock + tid;
                 if (v < a.nvec) {
                     const unsigned bits = in_regs ? bits_from_regs<T::EPV>(mk, v * T::EPV)
                                                   : marked_bits<T::EPV>(a.marks, mp, mq, v * T::EPV);
                     if (UPDATE) {
-                        update_vec<T>(x[u], mr, mi, bits, ar, ai);
-                        store16<NT>(x[u], st + v);
+                        update_vec<T>(x[u], mr, mi, bits, acc);
+                        store16<true>(x[u], st + v);
                     } else {
-                        accum_vec<T>(x[u], bits, ar, ai);
+                        accum_vec<T>(x[u], bits, acc);
                     }
                 }
             }
@@ -230,21 +242,23 @@ __device__ inline void chunk_pass(const FusedArgs &a, const uint32_t *slow_tiles
     }
 }
 
-template <class T, bool NT, int BLOCK, int UNROLL, bool CHECK = false>
-__global__ __launch_bounds__(BLOCK) void fused_iterate_kernel(FusedArgs a)
+// CHECK only names a second, code-identical instantiation used for the residency check at context
+// creation, so that profiles list it apart from the iteration launches.
+template <class T, class A, bool CHECK>
+__global__ __launch_bounds__(kBlock) void fused_iterate_kernel(FusedArgs a)
 {
-    constexpr int kTile = BLOCK * UNROLL;
-    __shared__ Shared<BLOCK> sh;
+    using Val = typename A::value;
+    __shared__ Shared<Val> sh;
     __shared__ uint32_t slow_tiles[kMarkWords];
     // Table of this workgroup's tiles that hold marked amplitudes, built once per launch.
     const uint64_t ntiles = (a.nvec + kTile - 1) / kTile;
     const uint64_t cnt = blockIdx.x < ntiles ? (ntiles - blockIdx.x + gridDim.x - 1) / gridDim.x : 0;
-    const bool table = cnt <= uint64_t(kMarkWords) * 32u && a.m <= uint64_t(64) * BLOCK;
+    const bool table = cnt <= uint64_t(kMarkWords) * 32u && a.m <= uint64_t(64) * kBlock;
     if (table) {
-        for (unsigned w = threadIdx.x; w < kMarkWords; w += BLOCK)
+        for (unsigned w = threadIdx.x; w < kMarkWords; w += kBlock)
             slow_tiles[w] = 0u;
         __syncthreads();
-        for (uint64_t q = threadIdx.x; q < a.m; q += BLOCK) {
+        for (uint64_t q = threadIdx.x; q < a.m; q += kBlock) {
             const uint64_t t = a.marks[q] / T::EPV / kTile;
             if (t % gridDim.x == blockIdx.x) {
                 const uint64_t j = t / gridDim.x;
@@ -253,76 +267,41 @@ __global__ __launch_bounds__(BLOCK) void fused_iterate_kernel(FusedArgs a)
         }
         __syncthreads();
     }
-    double sr = 0.0, si = 0.0;
-    chunk_pass<T, NT, BLOCK, UNROLL, false>(a, slow_tiles, table, 0.0, 0.0, sr, si);
-    if (!grid_sum<BLOCK>(sr, si, a, a.gen0 + 1u, sh))
+    A acc0;
+    chunk_pass<T, A, false>(a, slow_tiles, table, 0.0, 0.0, acc0);
+    Val sr = acc0.res_r(), si = acc0.res_i();
+    if (!grid_sum<Val>(sr, si, a, a.gen0 + 1u, sh))
         return;
     for (uint64_t it = 0; it < a.iters; ++it) {
-        const double mr = (sr * 2.0) / a.N, mi = (si * 2.0) / a.N;
-        double ar = 0.0, ai = 0.0;
-        chunk_pass<T, NT, BLOCK, UNROLL, true>(a, slow_tiles, table, mr, mi, ar, ai);
-        if (!grid_sum<BLOCK>(ar, ai, a, a.gen0 + 2u + it, sh))
+        const double mr = (double(sr) * 2.0) / a.N, mi = (double(si) * 2.0) / a.N;
+        A acc;
+        chunk_pass<T, A, true>(a, slow_tiles, table, mr, mi, acc);
+        sr = acc.res_r();
+        si = acc.res_i();
+        if (!grid_sum<Val>(sr, si, a, a.gen0 + 2u + it, sh))
             return;
-        sr = ar;
-        si = ai;
     }
 }
 
-// Launch variant: workgroup size, unroll (16-byte vectors per thread per tile) and the streaming hint.
-// Defaults are set by measurement on MI355X; GROVER_FUSED_BLOCK / _UNROLL / _NT override them.
-struct Variant {
-    int block = 1024;
-    int unroll = 4;
-    bool nt = true;
-};
-
-Variant variant()
+template <class A, bool CHECK>
+const void *pick_storage(uint32_t dtype)
 {
-    Variant v;
-    if (const char *e = getenv("GROVER_FUSED_BLOCK"))
-        v.block = atoi(e);
-    if (const char *e = getenv("GROVER_FUSED_UNROLL"))
-        v.unroll = atoi(e);
-    if (const char *e = getenv("GROVER_FUSED_NT"))
-        v.nt = e[0] != '0';
-    return v;
-}
-
-template <class T, bool NT, int BLOCK, bool CHECK>
-const void *pick_unroll(int unroll)
-{
-    switch (unroll) {
-    case 2: return reinterpret_cast<const void *>(&fused_iterate_kernel<T, NT, BLOCK, 2, CHECK>);
-    case 4: return reinterpret_cast<const void *>(&fused_iterate_kernel<T, NT, BLOCK, 4, CHECK>);
-    case 8: return reinterpret_cast<const void *>(&fused_iterate_kernel<T, NT, BLOCK, 8, CHECK>);
+    switch (dtype) {
+    case GROVER_F64_REAL: return reinterpret_cast<const void *>(&fused_iterate_kernel<F64Real, A, CHECK>);
+    case GROVER_C64: return reinterpret_cast<const void *>(&fused_iterate_kernel<C64, A, CHECK>);
+    case GROVER_C128: return reinterpret_cast<const void *>(&fused_iterate_kernel<C128, A, CHECK>);
+    case GROVER_CBF16: return reinterpret_cast<const void *>(&fused_iterate_kernel<CBF16, A, CHECK>);
     default: return nullptr;
     }
-}
-
-template <class T, bool NT, bool CHECK>
-const void *pick_block(int block, int unroll)
-{
-    switch (block) {
-    case 256: return pick_unroll<T, NT, 256, CHECK>(unroll);
-    case 512: return pick_unroll<T, NT, 512, CHECK>(unroll);
-    case 1024: return pick_unroll<T, NT, 1024, CHECK>(unroll);
-    default: return nullptr;
-    }
-}
-
-template <class T, bool CHECK>
-const void *pick(const Variant &v)
-{
-    return v.nt ? pick_block<T, true, CHECK>(v.block, v.unroll) : pick_block<T, false, CHECK>(v.block, v.unroll);
 }
 
 template <bool CHECK>
-const void *kernel_for(uint32_t dtype, const Variant &v)
+const void *kernel_for(uint32_t dtype, uint32_t accum)
 {
-    switch (dtype) {
-    case GROVER_F64_REAL: return pick<F64Real, CHECK>(v);
-    case GROVER_C64: return pick<C64, CHECK>(v);
-    case GROVER_C128: return pick<C128, CHECK>(v);
+    switch (accum) {
+    case GROVER_ACC_F64: return pick_storage<AccF64, CHECK>(dtype);
+    case GROVER_ACC_F32: return pick_storage<AccF32, CHECK>(dtype);
+    case GROVER_ACC_F32_KAHAN: return pick_storage<AccF32Kahan, CHECK>(dtype);
     default: return nullptr;
     }
 }
@@ -331,23 +310,22 @@ const void *kernel_for(uint32_t dtype, const Variant &v)
 
 hipError_t fused_configure(grover_ctx *c, int *per_cu, int *block, int64_t *forced_grid)
 {
-    const Variant v = variant();
-    const void *k = kernel_for<false>(c->dtype, v);
+    const void *k = kernel_for<false>(c->dtype, c->accum);
     if (!k)
         return hipErrorInvalidValue;
     c->fused_kernel = k;
-    c->fused_check_kernel = kernel_for<true>(c->dtype, v);
-    c->fused_tile = uint64_t(v.block) * v.unroll;
+    c->fused_check_kernel = kernel_for<true>(c->dtype, c->accum);
+    c->fused_tile = kTile;
     int coop = 0;
     hipError_t e = hipDeviceGetAttribute(&coop, hipDeviceAttributeCooperativeLaunch, c->device);
     if (e != hipSuccess)
         return e;
     if (!coop)
         return hipErrorCooperativeLaunchTooLarge;
-    e = hipOccupancyMaxActiveBlocksPerMultiprocessor(per_cu, k, v.block, 0);
+    e = hipOccupancyMaxActiveBlocksPerMultiprocessor(per_cu, k, kBlock, 0);
     if (e != hipSuccess)
         return e;
-    *block = v.block;
+    *block = kBlock;
     *forced_grid = 0;
     if (const char *env = getenv("GROVER_FUSED_GRID")) {
         const long long want = atoll(env);
@@ -362,7 +340,7 @@ hipError_t fused_configure(grover_ctx *c, int *per_cu, int *block, int64_t *forc
 
 uint64_t fused_tiles(const grover_ctx *c)
 {
-    const uint64_t nvec = c->N / (c->dtype == GROVER_C128 ? 1 : 2);
+    const uint64_t nvec = c->N / elems_per_vec(c->dtype);
     return (nvec + c->fused_tile - 1) / c->fused_tile;
 }
 
@@ -370,7 +348,7 @@ hipError_t launch_fused_iterate(grover_ctx *c, uint64_t k, uint64_t timeout_tick
 {
     FusedArgs a;
     a.state = c->state;
-    a.nvec = c->N / (c->dtype == GROVER_C128 ? 1 : 2);
+    a.nvec = c->N / elems_per_vec(c->dtype);
     a.N = double(c->N);
     a.marks = c->marks_dev;
     a.m = c->marks.size();

@@ -2,6 +2,9 @@
 //   - fill: psi = H^n|0> written directly as the uniform superposition, 2^(-n/2) in every amplitude;
 //   - hash predicate: i is marked iff the low `bits` bits of SplitMix64_i(seed) are zero; every index is
 //     tested on the device and the hits are compacted into a list (sorted afterwards by the host).
+#include <cmath>
+#include <cstring>
+
 #include "internal.h"
 
 namespace grover {
@@ -30,6 +33,21 @@ __global__ __launch_bounds__(kBlock) void hash_marks_kernel(uint64_t N, uint64_t
                 out[pos] = i;
         }
     }
+}
+
+// Host twin of double_to_bf16 for the one constant the fill writes: one correct rounding to nearest even
+// (round to odd into binary32, then to nearest even into bfloat16).
+uint16_t host_double_to_bf16(double d)
+{
+    float t = float(d);  // nearest; step one ulp towards zero when that rounded away from zero
+    if (std::fabs(double(t)) > std::fabs(d))
+        t = std::nextafter(t, 0.0f);
+    uint32_t u;
+    std::memcpy(&u, &t, 4);
+    if (double(t) != d)
+        u |= 1u;
+    u += 0x7FFFu + ((u >> 16) & 1u);
+    return uint16_t(u >> 16);
 }
 
 unsigned grid_for(uint64_t work, int cu_count)
@@ -67,6 +85,18 @@ hipError_t launch_fill_uniform(grover_ctx *c)
         double2 v = make_double2(a, 0.0);
         void *args[] = {&state, &nvec, &v};
         return hipLaunchKernel(reinterpret_cast<const void *>(&fill_kernel<C128>),
+                               dim3(grid_for(nvec, c->cu_count)), dim3(kBlock), args, 0, c->stream);
+    }
+    case GROVER_CBF16: {
+        uint64_t nvec = c->N / 4;
+        bf16x8 v;
+        const uint16_t ab = host_double_to_bf16(a);
+        for (int e = 0; e < 4; ++e) {
+            v.h[2 * e] = ab;
+            v.h[2 * e + 1] = 0;
+        }
+        void *args[] = {&state, &nvec, &v};
+        return hipLaunchKernel(reinterpret_cast<const void *>(&fill_kernel<CBF16>),
                                dim3(grid_for(nvec, c->cu_count)), dim3(kBlock), args, 0, c->stream);
     }
     default: return hipErrorInvalidValue;

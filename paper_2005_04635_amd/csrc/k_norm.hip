@@ -44,7 +44,7 @@ __global__ __launch_bounds__(kBlock) void norm_finalize_kernel(const double *par
 
 hipError_t launch_norm(grover_ctx *c, double *dev_out)
 {
-    uint64_t nvec = c->N / (c->dtype == GROVER_C128 ? 1 : 2);
+    uint64_t nvec = c->N / elems_per_vec(c->dtype);
     const uint64_t want = (nvec + kBlock - 1) / kBlock;
     int nb = int(want < uint64_t(kMaxBlocks) ? want : uint64_t(kMaxBlocks));
     const void *state = c->state;
@@ -54,6 +54,7 @@ hipError_t launch_norm(grover_ctx *c, double *dev_out)
     case GROVER_F64_REAL: fn = reinterpret_cast<const void *>(&norm_partials_kernel<F64Real>); break;
     case GROVER_C64: fn = reinterpret_cast<const void *>(&norm_partials_kernel<C64>); break;
     case GROVER_C128: fn = reinterpret_cast<const void *>(&norm_partials_kernel<C128>); break;
+    case GROVER_CBF16: fn = reinterpret_cast<const void *>(&norm_partials_kernel<CBF16>); break;
     default: return hipErrorInvalidValue;
     }
     void *a1[] = {&state, &nvec, &partials};

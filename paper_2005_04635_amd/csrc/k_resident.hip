@@ -39,11 +39,12 @@ __global__ __launch_bounds__(kBlock) void resident_iterate_kernel(ResidentArgs a
             bits[e] = 0u;
         }
     }
-    double sr = 0.0, si = 0.0;
+    AccF64 acc0;
 #pragma unroll
     for (int e = 0; e < E; ++e)
         if (uint64_t(e) * kBlock + tid < a.nvec)
-            accum_vec<T>(x[e], bits[e], sr, si);
+            accum_vec<T>(x[e], bits[e], acc0);
+    double sr = acc0.r, si = acc0.i;
     block_sum2(sr, si, red);
     if (tid == 0) {
         bsum[0] = sr;
@@ -54,11 +55,12 @@ __global__ __launch_bounds__(kBlock) void resident_iterate_kernel(ResidentArgs a
     si = bsum[1];
     for (uint64_t it = 0; it < a.iters; ++it) {
         const double mr = (sr * 2.0) / a.N, mi = (si * 2.0) / a.N;
-        double ar = 0.0, ai = 0.0;
+        AccF64 acc;
 #pragma unroll
         for (int e = 0; e < E; ++e)
             if (uint64_t(e) * kBlock + tid < a.nvec)
-                update_vec<T>(x[e], mr, mi, bits[e], ar, ai);
+                update_vec<T>(x[e], mr, mi, bits[e], acc);
+        double ar = acc.r, ai = acc.i;
         block_sum2(ar, ai, red);
         if (tid == 0) {
             bsum[0] = ar;
@@ -95,7 +97,7 @@ hipError_t launch_resident_iterate(grover_ctx *c, uint64_t k)
 {
     ResidentArgs a;
     a.state = c->state;
-    a.nvec = c->N / (c->dtype == GROVER_C128 ? 1 : 2);
+    a.nvec = c->N / elems_per_vec(c->dtype);
     a.N = double(c->N);
     a.marks = c->marks_dev;
     a.m = c->marks.size();

@@ -33,6 +33,14 @@ __device__ inline uint64_t qval<C128>(const void *state, uint64_t i)
     return (uint64_t)__dmul_rn(p, 0x1p62);
 }
 template <>
+__device__ inline uint64_t qval<CBF16>(const void *state, uint64_t i)
+{
+    const uint16_t *h = static_cast<const uint16_t *>(state) + 2 * i;
+    const double r = bf16_to_float(h[0]), m = bf16_to_float(h[1]);
+    const double p = __dadd_rn(__dmul_rn(r, r), __dmul_rn(m, m));
+    return (uint64_t)__dmul_rn(p, 0x1p62);
+}
+template <>
 __device__ inline uint64_t qval<F64Real>(const void *state, uint64_t i)
 {
     const double r = static_cast<const double *>(state)[i];
@@ -158,6 +166,9 @@ Kernels kernels_for(uint32_t dtype)
     case GROVER_C64:
         return {reinterpret_cast<const void *>(&q_block_total_kernel<C64>),
                 reinterpret_cast<const void *>(&cdf_kernel<C64>)};
+    case GROVER_CBF16:
+        return {reinterpret_cast<const void *>(&q_block_total_kernel<CBF16>),
+                reinterpret_cast<const void *>(&cdf_kernel<CBF16>)};
     default:
         return {reinterpret_cast<const void *>(&q_block_total_kernel<C128>),
                 reinterpret_cast<const void *>(&cdf_kernel<C128>)};

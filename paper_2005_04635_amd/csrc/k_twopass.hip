@@ -43,10 +43,11 @@ __global__ __launch_bounds__(kBlock) void block_sum_kernel(const void *state, ui
 {
     __shared__ double red[2 * (kBlock / kWave)];
     const typename T::vec *st = static_cast<const typename T::vec *>(state);
-    double ar = 0.0, ai = 0.0;
+    AccF64 acc;
     const uint64_t stride = uint64_t(gridDim.x) * kBlock;
     for (uint64_t v = uint64_t(blockIdx.x) * kBlock + threadIdx.x; v < nvec; v += stride)
-        accum_vec<T>(st[v], 0u, ar, ai);
+        accum_vec<T>(st[v], 0u, acc);
+    double ar = acc.r, ai = acc.i;
     block_sum2(ar, ai, red);
     if (threadIdx.x == 0) {
         partials[2 * blockIdx.x] = ar;
@@ -77,10 +78,10 @@ __global__ __launch_bounds__(kBlock) void mean_update_kernel(void *state, uint64
     typename T::vec *st = static_cast<typename T::vec *>(state);
     const double mr = (sum[0] * 2.0) / N, mi = (sum[1] * 2.0) / N;
     const uint64_t stride = uint64_t(gridDim.x) * kBlock;
-    double dr = 0.0, di = 0.0;  // unused accumulation of update_vec
+    AccF64 unused;  // the sum is taken by the next iteration's own pass
     for (uint64_t v = uint64_t(blockIdx.x) * kBlock + threadIdx.x; v < nvec; v += stride) {
         typename T::vec x = st[v];
-        update_vec<T>(x, mr, mi, 0u, dr, di);
+        update_vec<T>(x, mr, mi, 0u, unused);
         st[v] = x;
     }
 }
@@ -110,7 +111,7 @@ Kernels kernels_for(uint32_t dtype)
 
 int twopass_blocks(const grover_ctx *c)
 {
-    const uint64_t nvec = c->N / (c->dtype == GROVER_C128 ? 1 : 2);
+    const uint64_t nvec = c->N / elems_per_vec(c->dtype);
     const uint64_t want = (nvec + kBlock - 1) / kBlock;
     return int(want < uint64_t(kMaxBlocks) ? want : uint64_t(kMaxBlocks));
 }
@@ -134,7 +135,7 @@ hipError_t launch_twopass_iterate(grover_ctx *c, uint64_t iters)
 {
     const Kernels k = kernels_for(c->dtype);
     void *state = c->state;
-    uint64_t nvec = c->N / (c->dtype == GROVER_C128 ? 1 : 2);
+    uint64_t nvec = c->N / elems_per_vec(c->dtype);
     double N = double(c->N);
     const int nb = twopass_blocks(c);
     double *partials = c->red_partials;

@@ -33,7 +33,8 @@ __global__ __launch_bounds__(256) void copy_kernel(const float4 *src, float4 *ds
 int usage()
 {
     fprintf(stderr,
-            "usage: grover_cli run --n N [--dtype f64|c64|c128] [--form auto|fused|resident|two_pass]\n"
+            "usage: grover_cli run --n N [--dtype f64|c64|c128|cbf16] [--accum f64|f32|f32_kahan]\n"
+            "                      [--form auto|fused|resident|two_pass]\n"
             "                      [--mark I ... | --hash-seed S --hash-bits B --m M] [--iters K]\n"
             "                      [--shots S] [--shot-seed U] [--steps T] [--calibrate-copy BYTES]\n"
             "       grover_cli copy --bytes B [--reps R]\n");
@@ -115,7 +116,12 @@ int run_search(int argc, char **argv)
         if (k == "--n")
             cfg.n = uint32_t(atoi(v));
         else if (k == "--dtype")
-            cfg.dtype = !strcmp(v, "f64") ? GROVER_F64_REAL : !strcmp(v, "c128") ? GROVER_C128 : GROVER_C64;
+            cfg.dtype = !strcmp(v, "f64")     ? GROVER_F64_REAL
+                        : !strcmp(v, "c128")  ? GROVER_C128
+                        : !strcmp(v, "cbf16") ? GROVER_CBF16
+                                              : GROVER_C64;
+        else if (k == "--accum")
+            cfg.accum = !strcmp(v, "f32") ? GROVER_ACC_F32 : !strcmp(v, "f32_kahan") ? GROVER_ACC_F32_KAHAN : GROVER_ACC_F64;
         else if (k == "--form")
             cfg.form = !strcmp(v, "fused")      ? GROVER_FORM_FUSED
                        : !strcmp(v, "resident") ? GROVER_FORM_RESIDENT

@@ -28,15 +28,39 @@ GROVER_E_UNSUPPORTED = -5
 GROVER_E_PREDICATE = -6
 GROVER_E_TIMEOUT = -7
 
-GROVER_F64_REAL, GROVER_C64, GROVER_C128 = 0, 1, 2
+GROVER_F64_REAL, GROVER_C64, GROVER_C128, GROVER_CBF16 = 0, 1, 2, 3
+GROVER_ACC_F64, GROVER_ACC_F32, GROVER_ACC_F32_KAHAN = 0, 1, 2
 GROVER_ORACLE_LIST, GROVER_ORACLE_HASH = 0, 1
 GROVER_FORM_AUTO, GROVER_FORM_FUSED, GROVER_FORM_RESIDENT, GROVER_FORM_TWO_PASS = 0, 1, 2, 3
 
-DTYPES = {"f64": GROVER_F64_REAL, "c64": GROVER_C64, "c128": GROVER_C128}
+DTYPES = {"f64": GROVER_F64_REAL, "c64": GROVER_C64, "c128": GROVER_C128, "cbf16": GROVER_CBF16}
+ACCUMS = {"f64": GROVER_ACC_F64, "f32": GROVER_ACC_F32, "f32_kahan": GROVER_ACC_F32_KAHAN}
 FORMS = {"auto": GROVER_FORM_AUTO, "fused": GROVER_FORM_FUSED, "resident": GROVER_FORM_RESIDENT,
          "two_pass": GROVER_FORM_TWO_PASS}
-ELEM_BYTES = {GROVER_F64_REAL: 8, GROVER_C64: 8, GROVER_C128: 16}
+ELEM_BYTES = {GROVER_F64_REAL: 8, GROVER_C64: 8, GROVER_C128: 16, GROVER_CBF16: 4}
 NUMPY_DTYPES = {GROVER_F64_REAL: np.float64, GROVER_C64: np.complex64, GROVER_C128: np.complex128}
+
+
+def bf16_pairs_to_complex(raw: np.ndarray) -> np.ndarray:
+    """Complex bfloat16 storage (uint16 re, im, re, im, ...) -> complex128 (exact)."""
+    u = np.ascontiguousarray(raw, dtype=np.uint16).astype(np.uint32) << np.uint32(16)
+    f = u.view(np.float32).astype(np.float64)
+    return f[0::2] + 1j * f[1::2]
+
+
+def complex_to_bf16_pairs(psi: np.ndarray) -> np.ndarray:
+    """complex -> complex bfloat16 storage, each part rounded once to nearest even: round to odd into
+    binary32 (truncate, set the last bit when inexact), then to nearest even into bfloat16."""
+    parts = np.empty(2 * psi.size, dtype=np.float64)
+    parts[0::2] = np.real(psi)
+    parts[1::2] = np.imag(psi)
+    t = parts.astype(np.float32)
+    away = np.abs(t.astype(np.float64)) > np.abs(parts)
+    t[away] = np.nextafter(t[away], np.float32(0))
+    u = t.view(np.uint32).copy()
+    u[t.astype(np.float64) != parts] |= np.uint32(1)
+    u = u + np.uint32(0x7FFF) + ((u >> np.uint32(16)) & np.uint32(1))
+    return (u >> np.uint32(16)).astype(np.uint16)
 
 # grover_query keys
 Q_FORM, Q_GRID, Q_BLOCK, Q_ELEM_BYTES, Q_N, Q_M = 0, 1, 2, 3, 4, 5
@@ -59,6 +83,8 @@ class grover_config(ctypes.Structure):
         ("hash_seed", ctypes.c_uint64),
         ("form", ctypes.c_uint32),
         ("flags", ctypes.c_uint32),
+        ("accum", ctypes.c_uint32),
+        ("reserved", ctypes.c_uint32),
     ]
 
 
@@ -220,24 +246,28 @@ class Grover:
     """One search instance: a state on the current GPU plus its marked set.
 
     n          qubits (N = 2^n amplitudes)
-    dtype      "f64" (real), "c64" or "c128"
+    dtype      "f64" (real), "c64", "c128" or "cbf16" (complex bfloat16)
     marks      explicit marked indices (oracle list), or None with hash_seed/hash_bits/m for the predicate
     form       "auto", "fused", "resident" or "two_pass"
+    accum      precision of the sum the mean is taken from: "f64", "f32" or "f32_kahan"
     state      optional torch tensor (on the current device) to adopt as the state; otherwise one is made
     The state tensor is `self.state` (torch, 1-D, N elements of the dtype); kernels run on torch's
     current stream at construction.
     """
 
     def __init__(self, n: int, dtype: str = "c64", marks=None, *, hash_seed: Optional[int] = None,
-                 hash_bits: int = 0, m: Optional[int] = None, form: str = "auto", state=None):
+                 hash_bits: int = 0, m: Optional[int] = None, form: str = "auto", accum: str = "f64",
+                 state=None):
         import torch
 
         self.n = n
         self.dtype = DTYPES[dtype]
         N = 1 << n
-        tdt = {GROVER_F64_REAL: torch.float64, GROVER_C64: torch.complex64, GROVER_C128: torch.complex128}[self.dtype]
-        self.state = state if state is not None else torch.empty(N, dtype=tdt, device="cuda")
-        if self.state.dtype != tdt or self.state.numel() != N or not self.state.is_contiguous():
+        tdt = {GROVER_F64_REAL: torch.float64, GROVER_C64: torch.complex64, GROVER_C128: torch.complex128,
+               GROVER_CBF16: torch.bfloat16}[self.dtype]
+        numel = 2 * N if self.dtype == GROVER_CBF16 else N  # bfloat16: interleaved (re, im)
+        self.state = state if state is not None else torch.empty(numel, dtype=tdt, device="cuda")
+        if self.state.dtype != tdt or self.state.numel() != numel or not self.state.is_contiguous():
             raise ValueError("state tensor must be contiguous with N elements of the requested dtype")
         self.stream = torch.cuda.current_stream()
         cfg = grover_config()
@@ -245,6 +275,7 @@ class Grover:
         cfg.dtype = self.dtype
         cfg.form = FORMS[form]
         cfg.flags = 0
+        cfg.accum = ACCUMS[accum]
         if hash_seed is not None:
             cfg.oracle_kind = GROVER_ORACLE_HASH
             cfg.hash_seed = hash_seed & (2**64 - 1)
@@ -303,12 +334,22 @@ class Grover:
         return grover_norm(self.ctx)
 
     def read_state(self) -> np.ndarray:
+        """The state on the host: float64 / complex64 / complex128 arrays, complex128 for bfloat16 storage
+        (exact conversion)."""
+        if self.dtype == GROVER_CBF16:
+            raw = np.empty(2 * self.N, dtype=np.uint16)
+            grover_read_state(self.ctx, raw.ctypes.data, self.nbytes)
+            return bf16_pairs_to_complex(raw)
         out = np.empty(self.N, dtype=NUMPY_DTYPES[self.dtype])
         grover_read_state(self.ctx, out.ctypes.data, self.nbytes)
         return out
 
     def write_state(self, psi: np.ndarray) -> "Grover":
-        a = np.ascontiguousarray(psi, dtype=NUMPY_DTYPES[self.dtype])
+        """Write a host state; values are rounded to the storage type (bfloat16: nearest even)."""
+        if self.dtype == GROVER_CBF16:
+            a = complex_to_bf16_pairs(np.asarray(psi))
+        else:
+            a = np.ascontiguousarray(psi, dtype=NUMPY_DTYPES[self.dtype])
         grover_write_state(self.ctx, a.ctypes.data, self.nbytes)
         return self
 

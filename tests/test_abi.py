@@ -75,8 +75,8 @@ def test_status_strings_and_null_handling(lib):
     lib.grover_destroy(None)
 
 
-@pytest.mark.parametrize("field,value", [("n", 0), ("n", 35), ("dtype", 3), ("oracle_kind", 2), ("form", 4),
-                                         ("flags", 1), ("hash_bits", 65)])
+@pytest.mark.parametrize("field,value", [("n", 0), ("n", 35), ("dtype", 4), ("oracle_kind", 2), ("form", 4),
+                                         ("flags", 1), ("hash_bits", 65), ("accum", 3), ("reserved", 1)])
 def test_init_rejects_invalid_config_before_touching_the_device(lib, field, value):
     from paper_2005_04635_amd.grover import grover_config
 
@@ -120,6 +120,32 @@ def test_resident_form_limit(lib):
     cfg.form = 2  # resident holds at most 2^14 amplitudes
     ctx = ctypes.c_void_p()
     assert lib.grover_init(ctypes.byref(ctx), ctypes.byref(cfg), None, None, 0) == -5
+
+
+@pytest.mark.parametrize("dtype,accum,form", [(3, 0, 2), (3, 0, 3), (1, 1, 2), (1, 2, 3), (2, 1, 3)])
+def test_reduced_precision_needs_the_fused_form(lib, dtype, accum, form):
+    """bfloat16 storage and binary32 sums exist in the fused form only."""
+    from paper_2005_04635_amd.grover import grover_config
+
+    cfg = grover_config()
+    cfg.n, cfg.dtype, cfg.accum, cfg.form = 10, dtype, accum, form
+    ctx = ctypes.c_void_p()
+    assert lib.grover_init(ctypes.byref(ctx), ctypes.byref(cfg), None, None, 0) == -5
+
+
+def test_bf16_host_conversions_round_once_to_nearest_even():
+    import numpy as np
+
+    from paper_2005_04635_amd.grover import bf16_pairs_to_complex, complex_to_bf16_pairs
+
+    x = np.array([1 + 2.0 ** -8, 1 + 3 * 2.0 ** -8, -(1 + 2.0 ** -8) + 0.25j, 1 / 3, 2.0 ** -13])
+    back = bf16_pairs_to_complex(complex_to_bf16_pairs(x))
+    assert back[0] == 1.0 and back[1] == 1 + 2.0 ** -6 and back[2] == -1.0 + 0.25j
+    assert abs(back[3] - 1 / 3) <= 2.0 ** -9 / 3 * 2 and back[4] == 2.0 ** -13
+    # one correct rounding from binary64 even where rounding through binary32 first would differ:
+    # 1 + 2^-8 + 2^-30 lies just above the tie, binary32 would round it onto the tie, then to even
+    y = np.array([1 + 2.0 ** -8 + 2.0 ** -30])
+    assert bf16_pairs_to_complex(complex_to_bf16_pairs(y))[0] == 1 + 2.0 ** -7
 
 
 def test_missing_library_fails_loudly(tmp_path, monkeypatch):

@@ -104,3 +104,39 @@ def test_large_index_range(G, orc):
     assert abs(complex(st[0].item()) - b) <= 1e-5
     assert abs(g.norm() - 1.0) < 1e-5
     g.close()
+
+
+@pytest.mark.parametrize("storage,accum", [(s, a) for s in ("c128", "c64", "cbf16")
+                                           for a in ("f64", "f32", "f32_kahan")])
+def test_n26_precision_sweep(G, orc, storage, accum):
+    """The precision workload (n = 26, M = 4, 3216 iterations) in every storage x accumulator setting:
+    the two-class structure holds exactly; binary64-accumulated settings match the oracle's two-class
+    values (complex128: 1e-12, complex64: 1e-5) and, for bfloat16, its stored-precision iteration; the
+    binary32-accumulated ones stay within the bound derived from the arithmetic (test_gpu_precision.py)
+    where that bound is informative."""
+    from test_gpu_precision import BITS, error_bound
+
+    w = workloads.PRECISION_N26
+    marks = np.array(w.marks, dtype=np.uint64)
+    g = G.Grover(w.n, storage, marks=marks, accum=accum, form="fused")
+    g.iterate(w.iterations)
+    got = g.read_state()
+    mask = np.zeros(1 << w.n, dtype=bool)
+    mask[marks.astype(np.int64)] = True
+    a_gpu, b_gpu = complex(got[int(marks[0])]), complex(got[int(np.argmin(mask))])
+    assert np.all(got[mask] == got[int(marks[0])]) and np.all(got[~mask] == got[int(np.argmin(mask))])
+    assert a_gpu.imag == 0 and b_gpu.imag == 0
+    a, b = orc.two_class(w.n, w.m, w.iterations)
+    err = max(abs(a_gpu - a), abs(b_gpu - b))
+    if accum == "f64" and storage == "c128":
+        assert err <= 1e-12
+    elif accum == "f64" and storage == "c64":
+        assert err <= 1e-5
+    elif accum == "f64":
+        sa, sb = orc.two_class_stored(w.n, w.m, w.iterations, BITS[storage])
+        ulp = 2.0 ** (1 - BITS[storage])
+        assert abs(a_gpu.real - sa) <= 2 * ulp * abs(sa) and abs(b_gpu.real - sb) <= 2 * ulp * abs(sb)
+    bound = error_bound(w.n, w.iterations, storage, accum, g.query(1))
+    if bound < 1.0:
+        assert err <= bound, (err, bound)
+    g.close()

@@ -47,8 +47,11 @@ MUTANTS = [
     ("uniform amplitude off by a factor", "return ldexp(1.0, -(int)(n / 2));", "return ldexp(1.0, -(int)(n / 2) - 1);"),
     ("odd-n amplitude rounded twice", "return ldexp(sqrt(2.0), -(int)((n + 1) / 2));",
      "return 1.0 / sqrt(ldexp(1.0, (int)n));"),
-    ("two-class sum sign", "const double s = (N - (double)m) * b - (double)m * a;",
-     "const double s = (N - (double)m) * b + (double)m * a;"),
+    ("two-class sum sign",
+     "double a = orc_uniform_amplitude(n), b = a;\n    for (uint64_t it = 0; it < iters; ++it) {\n"
+     "        const double s = (N - (double)m) * b - (double)m * a;",
+     "double a = orc_uniform_amplitude(n), b = a;\n    for (uint64_t it = 0; it < iters; ++it) {\n"
+     "        const double s = (N - (double)m) * b + (double)m * a;"),
     ("norm drops the imaginary part",
      "s += psi[2 * i] * psi[2 * i] + psi[2 * i + 1] * psi[2 * i + 1];", "s += psi[2 * i] * psi[2 * i];"),
     ("sampler probability drops the imaginary part",
@@ -61,6 +64,10 @@ MUTANTS = [
     ("splitmix shift changed", "z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;", "z = (z ^ (z >> 31)) * 0xBF58476D1CE4E5B9ull;"),
     ("splitmix counter off by one", "uint64_t z = seed + (j + 1u) *", "uint64_t z = seed + j *"),
     ("hash mask one bit short", "(((uint64_t)1 << bits) - 1u)", "(((uint64_t)1 << (bits - 1)) - 1u)"),
+    ("round_to_bits keeps one bit fewer", "const double r = nearbyint(ldexp(m, p));",
+     "const double r = nearbyint(ldexp(m, p - 1));"),
+    ("round_to_bits truncates", "const double r = nearbyint(ldexp(m, p));", "const double r = trunc(ldexp(m, p));"),
+    ("stored two-class skips rounding b", "b = orc_round_to_bits(mean2 - b, p);", "b = mean2 - b;"),
     ("hash marks listed from index 1", "for (uint64_t i = 0; i < N; ++i) {\n        if ((orc_splitmix64",
      "for (uint64_t i = 1; i < N; ++i) {\n        if ((orc_splitmix64"),
 ]
@@ -92,6 +99,10 @@ def battery(orc) -> None:
     pins.test_sample_uniform_state_closed_form(orc, 4)
     pins.test_sample_inverse_transform_on_a_grid(orc, 3)
     pins.test_sample_point_mass(orc)
+    pins.test_round_to_bits_binary32(orc)
+    pins.test_round_to_bits_bfloat16_brute_force(orc)
+    pins.test_two_class_stored_at_53_bits_is_two_class(orc, 10, 1, 25)
+    pins.test_two_class_stored_binary32_matches_float32_full_state(orc)
 
 
 def test_battery_passes_on_the_committed_oracle(orc):

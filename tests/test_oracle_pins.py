@@ -290,6 +290,59 @@ def test_exact_rational_recurrence(orc):
     assert abs(psi[0].real - float(B) * scale) < 1e-15
 
 
+# ------------------------------------------------------------------------------ storage precisions
+def test_round_to_bits_binary32(orc):
+    """p = 24 is IEEE binary32 round-to-nearest-even (numpy's float32 cast), including ties."""
+    rng = np.random.default_rng(5)
+    xs = np.concatenate([rng.normal(size=2000) * 10.0 ** rng.integers(-30, 30, size=2000),
+                         [1 + 2.0 ** -24, 1 + 3 * 2.0 ** -24, -(1 + 2.0 ** -24), 0.1, 1 / 3, 2.0 ** -126]])
+    for x in xs:
+        assert orc.round_to_bits(float(x), 24) == float(np.float32(x)), x
+    assert orc.round_to_bits(0.1, 53) == 0.1
+
+
+def test_round_to_bits_bfloat16_brute_force(orc):
+    """p = 8 is bfloat16 round-to-nearest-even: the nearest of all finite positive bfloat16 values in the
+    normal range, ties to the even bit pattern."""
+    u = (np.arange(0x0080, 0x7F80, dtype=np.uint32) << 16).view(np.float32).astype(np.float64)  # normals
+    rng = np.random.default_rng(6)
+    xs = np.concatenate([rng.uniform(1e-6, 1.0, 1500), rng.uniform(1.0, 1e6, 500),
+                         (u[1000:1010] + u[1001:1011]) / 2])  # exact ties
+    for x in xs:
+        i = np.searchsorted(u, x)
+        lo, hi = u[i - 1], u[i]
+        if x - lo < hi - x or (x - lo == hi - x and (i - 1) % 2 == 0):
+            want = lo
+        else:
+            want = hi
+        if u[i] == x:
+            want = x
+        assert orc.round_to_bits(float(x), 8) == want, x
+        assert orc.round_to_bits(-float(x), 8) == -want
+
+
+@pytest.mark.parametrize("n,m,k", [(10, 1, 25), (20, 3, 464), (28, 8, 4549)])
+def test_two_class_stored_at_53_bits_is_two_class(orc, n, m, k):
+    assert orc.two_class_stored(n, m, k, 53) == orc.two_class(n, m, k)
+
+
+def test_two_class_stored_binary32_matches_float32_full_state(orc):
+    """At p = 24 the two-class form equals the full iteration with every stored amplitude cast to float32
+    (numpy), at n = 12 where the full state is cheap; the two-class structure itself is exact."""
+    n, m, k = 12, 2, 30
+    marks = workloads.distinct_marks(n, m, seed=2)
+    psi = np.full(1 << n, np.float64(np.float32(orc.uniform_amplitude(n))), dtype=np.complex128)
+    mask = np.zeros(1 << n, dtype=bool)
+    mask[marks.astype(np.int64)] = True
+    for _ in range(k):
+        orc.iterate(psi, marks, 1)
+        psi = psi.real.astype(np.float32).astype(np.float64).astype(np.complex128)
+    a, b = orc.two_class_stored(n, m, k, 24)
+    assert np.all(psi[mask] == psi[mask][0]) and np.all(psi[~mask] == psi[~mask][0])
+    assert abs(psi[mask][0].real - a) <= 2 * 2.0 ** -24 * abs(a)
+    assert abs(psi[~mask][0].real - b) <= 2 * 2.0 ** -24 * abs(b)
+
+
 # ------------------------------------------------------------------------------------ random numbers
 def test_splitmix64_published_vectors(orc):
     with open(os.path.join(GOLDEN, "splitmix64_vectors.txt")) as f:

@@ -138,4 +138,20 @@ HASH_N28 = Workload(
     shot_seed=11,
 )
 
-WORKLOADS = {w.name: w for w in (PLAIN_N10, HASH_N28)}
+# Precision sweep, n = 26, M = 4 marked indices drawn from a seed, floor(pi/4 sqrt(N/M)) = 3216 iterations;
+# the storage type and the accumulator of the mean are the swept settings (dtype here is the reference one).
+PRECISION_N26_SEED = 2600426
+PRECISION_N26 = Workload(
+    name="precision_n26_m4",
+    n=26,
+    dtype="c128",
+    m=4,
+    marks=tuple(int(x) for x in distinct_marks(26, 4, PRECISION_N26_SEED)),
+    hash_seed=None,
+    hash_bits=0,
+    iterations=3216,
+    shots=0,
+    shot_seed=0,
+)
+
+WORKLOADS = {w.name: w for w in (PLAIN_N10, HASH_N28, PRECISION_N26)}
