@@ -184,6 +184,81 @@ void grover_destroy(grover_ctx *ctx);
 const char *grover_status_str(int status);
 const char *grover_last_error(const grover_ctx *ctx);
 
+/* ------------------------------------------------------------------------------------- batches
+ * Many independent searches advanced together (Algorithm 5 per instance, from the uniform superposition of
+ * Algorithm 5's first step, with the oracle of Algorithm 3 and the inversion of Eq. 2 / Algorithm 4), in
+ * one persistent launch.  Instance states are GROVER_C64 (interleaved float re, im; the update and the sums
+ * are computed in binary64 and rounded once per amplitude and iteration, as in the single-state
+ * GROVER_C64 + GROVER_ACC_F64 context).  Instance i has n[i] qubits (1 <= n[i] <= 24), m[i] marked
+ * indices and iterations[i] iterations (k_opt(n[i], m[i]) when `iterations` is NULL).
+ *
+ * How the device divides the work is the tiling: instances with n >= split_n are iterated one at a time by
+ * teams of `team` workgroups each (team = grid size: the whole device per instance); the rest are taken
+ * one per workgroup (held in registers when 2^n <= 16384, else streamed).  The tiling changes the order of
+ * additions in the sums, so results of two tilings agree to rounding, and one tiling's results are
+ * reproducible bit for bit.  grover_batch_tune times the candidates and keeps the fastest. */
+typedef struct grover_batch grover_batch;
+
+typedef struct grover_batch_config {
+    uint64_t count;              /* number of instances, >= 1 */
+    const uint32_t *n;           /* host, count entries */
+    const uint64_t *m;           /* host, count entries; m[i] <= 2^n[i] */
+    const uint64_t *marked;      /* host, sum(m) entries: instance 0's list, then instance 1's, ... (any order
+                                    within a list, no duplicates, each < 2^n[i]); may be NULL when sum(m) = 0 */
+    const uint64_t *iterations;  /* host, count entries, or NULL for k_opt(n[i], m[i]) */
+    uint32_t dtype;              /* GROVER_C64 (other types: GROVER_E_UNSUPPORTED) */
+    uint32_t flags;              /* must be 0 */
+    uint64_t reserved;           /* must be 0 */
+} grover_batch_config;
+
+/* grover_batch_init — validate cfg, copy its arrays, allocate every instance's state (each 256-byte
+ * aligned) and the device work queues, and confirm the persistent grid on the device (one short run, as for
+ * the fused form).  hip_stream: the hipStream_t all batch work goes to (NULL = default stream; graph capture
+ * then unavailable).  Synchronous.  GROVER_E_INVAL for a bad config (before any device work),
+ * GROVER_E_UNSUPPORTED for a dtype other than GROVER_C64, GROVER_E_COOP when no grid is co-resident.
+ * The initial tiling is split_n = 19, team = 4. */
+int grover_batch_init(grover_batch **out, const grover_batch_config *cfg, void *hip_stream);
+
+/* grover_batch_set_tiling — choose the tiling (team in [1, grid size]; team = 1 puts every instance in the
+ * one-per-workgroup queue).  Drops a captured graph.  Synchronous. */
+int grover_batch_set_tiling(grover_batch *b, uint32_t split_n, uint32_t team);
+
+/* grover_batch_tune — run the batch once per candidate tiling (split_n in {18, 19, 20} x team in {2, 4, 8,
+ * 16}, and team = 1), keep the fastest, and report it (any output pointer may be NULL).  Overwrites the
+ * states; synchronous; drops a captured graph. */
+int grover_batch_tune(grover_batch *b, uint32_t *split_n, uint32_t *team, float *best_ms);
+
+/* grover_batch_capture — record one run (queue reset + the persistent launch) into a HIP graph that later
+ * grover_batch_run calls replay.  Needs a non-NULL stream; GROVER_E_UNSUPPORTED when the runtime cannot
+ * capture the launch (runs then stay eager). */
+int grover_batch_capture(grover_batch *b);
+
+/* grover_batch_run — enqueue one run of the whole batch: every instance restarts from the uniform
+ * superposition and performs its iterations.  Asynchronous. */
+int grover_batch_run(grover_batch *b);
+
+/* grover_batch_sync — wait for the stream; GROVER_E_TIMEOUT when a team barrier gave up during the last
+ * run (results of that run undefined). */
+int grover_batch_sync(grover_batch *b);
+
+/* grover_batch_state — device address and size in bytes (2^n[i] * 8) of instance i's state. */
+int grover_batch_state(grover_batch *b, uint64_t i, void **dev_ptr, size_t *bytes);
+
+/* grover_batch_read_state — copy instance i's state to host memory; bytes must equal its size.
+ * Synchronises the stream. */
+int grover_batch_read_state(grover_batch *b, uint64_t i, void *host, size_t bytes);
+
+/* grover_batch_query — key: 0 = count, 1 = persistent grid size, 2 = split_n, 3 = team, 4 = total amplitude
+ * updates per run (sum of 2^n[i] * iterations[i]), 5 = 1 when a captured graph is in use, 6 = bytes of all
+ * states, 7 = instances in the team queue. */
+int grover_batch_query(grover_batch *b, int key, int64_t *value);
+
+/* grover_batch_destroy — wait for the stream and release everything.  NULL is ignored. */
+void grover_batch_destroy(grover_batch *b);
+
+/* grover_batch_last_error — message of the last failure on b (a static message when b is NULL). */
+const char *grover_batch_last_error(const grover_batch *b);
+
 #ifdef __cplusplus
 }
 #endif

@@ -7,8 +7,21 @@ time; the first call that needs the library loads it and fails loudly when it ha
 from .grover import (  # noqa: F401
     EXPORTS,
     Grover,
+    GroverBatch,
     GroverError,
     grover_apply_hadamard_all,
+    grover_batch_capture,
+    grover_batch_config,
+    grover_batch_destroy,
+    grover_batch_init,
+    grover_batch_last_error,
+    grover_batch_query,
+    grover_batch_read_state,
+    grover_batch_run,
+    grover_batch_set_tiling,
+    grover_batch_state,
+    grover_batch_sync,
+    grover_batch_tune,
     grover_config,
     grover_destroy,
     grover_gate_iterate,

@@ -1,0 +1,266 @@
+// Device code shared by the persistent kernels (the fused single-instance kernel and the batched kernel):
+// the team barrier that also reduces the iteration's sum, the marked-tile table, and one streaming pass
+// of a team's share of a state.  A "team" is T workgroups of one launch (rank 0 .. T-1) that iterate one
+// state together; the fused kernel is a single team spanning the whole grid.
+#pragma once
+
+#include "internal.h"
+
+namespace grover {
+
+constexpr int kStreamBlock = 1024;  // one workgroup per CU: fewest barrier participants, 16 waves per CU
+constexpr int kStreamUnroll = 4;    // 16-byte vectors per thread per tile
+constexpr int kStreamTile = kStreamBlock * kStreamUnroll;
+constexpr int kMarkWords = 1024;    // LDS bitmap of a workgroup's tiles that hold marked amplitudes
+constexpr int kTileMarks = 8;       // marks of one tile held in registers
+
+template <class V>
+struct TeamShared {
+    V red[2 * (kStreamBlock / kWave)];
+    V sum[2];
+    int last;
+    int abort;
+};
+
+// Where a team's barrier lives: its barrier words, its partials [2][T][2] (binary64 bit patterns), the
+// number of workgroups T, this workgroup's rank, and the wait limit.
+struct Team {
+    GridSync *sync;
+    uint64_t *partials;
+    unsigned size;
+    unsigned rank;
+    uint64_t timeout_ticks;
+};
+
+__device__ inline uint32_t *arrive_word(GridSync *s, unsigned p) { return p ? &s->arrive1 : &s->arrive0; }
+
+__device__ inline uint64_t load_bits(const uint64_t *p)
+{
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+__device__ inline void store_bits(uint64_t *p, double x)
+{
+    __hip_atomic_store(p, (uint64_t)__double_as_longlong(x), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// Team-wide sum of (xr, xi) at barrier generation `gen` (1, 2, ... per barrier object), in the arithmetic
+// of V (binary64 or binary32; partials travel as binary64, which holds a binary32 exactly).  Returns false
+// when the wait gave up (time limit, or another workgroup gave up); every thread of the workgroup gets the
+// same answer and the sum in (xr, xi).
+//
+// Memory ordering: a workgroup publishes its partial and then increments the arrival counter with release
+// semantics; the workgroup whose increment completes the count acquires, adds the partials in rank order
+// (so the sum is reproducible), stores the sum and releases the generation flag; the others poll the flag
+// with relaxed loads and acquire once it has advanced.  Acquire/release at agent scope make the data
+// visible across the XCDs' separate L2s.  (Letting every workgroup poll the counter and add the partials
+// itself was measured slower on MI355X: the polls contend with the increments.)
+template <class V>
+__device__ bool team_sum(V &xr, V &xi, const Team &tm, uint64_t gen, TeamShared<V> &sh)
+{
+    const unsigned p = unsigned(gen & 1u);
+    block_sum2(xr, xi, sh.red);
+    if (threadIdx.x == 0) {
+        uint64_t *dst = tm.partials + (uint64_t(p) * tm.size + tm.rank) * 2u;
+        store_bits(dst, double(xr));
+        store_bits(dst + 1, double(xi));
+        const unsigned old =
+            __hip_atomic_fetch_add(arrive_word(tm.sync, p), 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+        sh.last = (old == tm.size - 1u);
+        sh.abort = 0;
+    }
+    __syncthreads();
+    if (sh.last) {
+        // Every partial of this barrier is published.  Add them in rank order.
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+        V sr = V(0), si = V(0);
+        for (unsigned w = threadIdx.x; w < tm.size; w += kStreamBlock) {
+            const uint64_t *src = tm.partials + (uint64_t(p) * tm.size + w) * 2u;
+            sr += V(__longlong_as_double((long long)load_bits(src)));
+            si += V(__longlong_as_double((long long)load_bits(src + 1)));
+        }
+        block_sum2(sr, si, sh.red);
+        if (threadIdx.x == 0) {
+            store_bits(&tm.sync->sum[p][0], double(sr));
+            store_bits(&tm.sync->sum[p][1], double(si));
+            __hip_atomic_store(arrive_word(tm.sync, p), 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            __hip_atomic_store(&tm.sync->flag, gen, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+            sh.sum[0] = sr;
+            sh.sum[1] = si;
+        }
+    } else if (threadIdx.x == 0) {
+        const uint64_t t0 = wall_clock64();
+        bool ok = true;
+        while (__hip_atomic_load(&tm.sync->flag, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < gen) {
+            if (__hip_atomic_load(&tm.sync->error, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0u) {
+                ok = false;
+                break;
+            }
+            if (uint64_t(wall_clock64()) - t0 > tm.timeout_ticks) {
+                __hip_atomic_store(&tm.sync->error, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                ok = false;
+                break;
+            }
+            __builtin_amdgcn_s_sleep(2);
+        }
+        if (ok) {
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+            sh.sum[0] = V(__longlong_as_double((long long)load_bits(&tm.sync->sum[p][0])));
+            sh.sum[1] = V(__longlong_as_double((long long)load_bits(&tm.sync->sum[p][1])));
+        } else {
+            sh.abort = 1;
+        }
+    }
+    __syncthreads();
+    const bool ok = sh.abort == 0;
+    xr = sh.sum[0];
+    xi = sh.sum[1];
+    __syncthreads();  // sh is reused by the next barrier
+    return ok;
+}
+
+// First index q >= start with marks[q] >= x in the sorted list marks[0, m), given that every entry before
+// `start` is < x: exponential steps from `start`, then a binary search in the last step.  Tiles are visited
+// in increasing order, so each search starts where the previous tile's ended and costs O(log gap).
+__device__ inline uint64_t gallop_lower_bound(const uint64_t *marks, uint64_t start, uint64_t m, uint64_t x)
+{
+    if (start >= m || marks[start] >= x)
+        return start;
+    uint64_t lo = start, step = 1;  // invariant: marks[lo] < x
+    while (lo + step < m && marks[lo + step] < x) {
+        lo += step;
+        step <<= 1;
+    }
+    const uint64_t hi = lo + step < m ? lo + step : m;
+    return lower_bound_u64(marks, lo + 1, hi, x);
+}
+
+// Marked bits of the EPV amplitudes starting at element i, from up to kTileMarks marks held in registers
+// (padded with ~0, which never equals an amplitude index).
+template <int EPV>
+__device__ inline unsigned bits_from_regs(const uint64_t (&mk)[kTileMarks], uint64_t i)
+{
+    unsigned bits = 0;
+#pragma unroll
+    for (int q = 0; q < kTileMarks; ++q) {
+        const uint64_t d = mk[q] - i;  // wraps to a huge value when mk[q] < i
+        bits |= d < uint64_t(EPV) ? 1u << unsigned(d) : 0u;
+    }
+    return bits;
+}
+
+// One team member's view of a state: its tiles are t = rank + j * size, j = 0, 1, ... (tiles of
+// kStreamTile 16-byte vectors).  At any moment the team streams one contiguous window of the state, spread
+// over all HBM channels, while each tile stays with the same workgroup (hence XCD) in every iteration.
+template <class T>
+struct Share {
+    typename T::vec *st;
+    uint64_t nvec;
+    const uint64_t *marks;  // the state's sorted marked list
+    uint64_t m;
+    uint64_t rank;
+    uint64_t size;
+    __device__ uint64_t ntiles() const { return (nvec + kStreamTile - 1) / kStreamTile; }
+    __device__ uint64_t count() const { return rank < ntiles() ? (ntiles() - rank + size - 1) / size : 0; }
+};
+
+// Table of this workgroup's tiles that hold marked amplitudes (bit j = tile rank + j * size), built by the
+// whole workgroup.  Returns false when it cannot be used (too many tiles, or a marked list so long that
+// scanning it per workgroup costs more than checking every tile); every tile then takes the checked path.
+template <class T>
+__device__ bool build_mark_table(const Share<T> &sh, uint32_t *table)
+{
+    const bool use = sh.count() <= uint64_t(kMarkWords) * 32u && sh.m <= uint64_t(64) * kStreamBlock;
+    if (use) {
+        for (unsigned w = threadIdx.x; w < kMarkWords; w += kStreamBlock)
+            table[w] = 0u;
+        __syncthreads();
+        for (uint64_t q = threadIdx.x; q < sh.m; q += kStreamBlock) {
+            const uint64_t t = sh.marks[q] / T::EPV / kStreamTile;
+            if (t % sh.size == sh.rank) {
+                const uint64_t j = t / sh.size;
+                atomicOr(&table[j >> 5], 1u << (j & 31));
+            }
+        }
+    }
+    __syncthreads();
+    return use;
+}
+
+enum PassMode { kAccumulate, kUpdate, kFill };
+
+// One pass over the workgroup's tiles.  kUpdate: c' = 2S/N - s c written back (nontemporal) and s c' added
+// to the accumulator; kAccumulate: s c added; kFill: `fill` written everywhere and s * fill added.  The
+// per-thread order of the sum is identical in all modes, so a fresh sum of a stored state equals, bit for
+// bit, the sum the pass that wrote it produced.
+template <class T, class A, PassMode MODE>
+__device__ inline void stream_pass(const Share<T> &sh, const uint32_t *table, bool use_table, double mr, double mi,
+                                   const typename T::vec &fill, A &acc)
+{
+    using V = typename T::vec;
+    const unsigned tid = threadIdx.x;
+    const uint64_t cnt = sh.count();
+    uint64_t mp = 0;  // marked entries before this position lie in tiles already visited
+    for (uint64_t j = 0; j < cnt; ++j) {
+        const uint64_t t = sh.rank + j * sh.size;
+        const uint64_t v0 = t * kStreamTile;
+        const bool full = v0 + kStreamTile <= sh.nvec;
+        const bool marked = use_table ? ((table[j >> 5] >> (j & 31)) & 1u) != 0u : sh.m > 0;
+        if (full && !marked) {
+            V x[kStreamUnroll];
+            if (MODE != kFill) {
+#pragma unroll
+                for (int u = 0; u < kStreamUnroll; ++u)
+                    x[u] = load16<true>(sh.st + v0 + u * kStreamBlock + tid);
+            }
+#pragma unroll
+            for (int u = 0; u < kStreamUnroll; ++u) {
+                if (MODE == kUpdate) {
+                    update_vec<T>(x[u], mr, mi, 0u, acc);
+                    store16<true>(x[u], sh.st + v0 + u * kStreamBlock + tid);
+                } else if (MODE == kFill) {
+                    store16<true>(fill, sh.st + v0 + u * kStreamBlock + tid);
+                    accum_vec<T>(fill, 0u, acc);
+                } else {
+                    accum_vec<T>(x[u], 0u, acc);
+                }
+            }
+        } else {
+            // Ragged tail of the state, or a tile that may hold marked amplitudes: each amplitude's sign
+            // comes from the tile's slice [mp, mq) of the sorted marked list.
+            mp = gallop_lower_bound(sh.marks, mp, sh.m, v0 * T::EPV);
+            const uint64_t mq = gallop_lower_bound(sh.marks, mp, sh.m, (v0 + kStreamTile) * T::EPV);
+            const bool in_regs = mq - mp <= uint64_t(kTileMarks);
+            uint64_t mk[kTileMarks];
+#pragma unroll
+            for (int q = 0; q < kTileMarks; ++q)
+                mk[q] = in_regs && mp + q < mq ? sh.marks[mp + q] : ~uint64_t(0);
+            V x[kStreamUnroll];
+#pragma unroll
+            for (int u = 0; u < kStreamUnroll; ++u) {
+                const uint64_t v = v0 + u * kStreamBlock + tid;
+                if (v < sh.nvec)
+                    x[u] = MODE == kFill ? fill : load16<true>(sh.st + v);
+            }
+#pragma unroll
+            for (int u = 0; u < kStreamUnroll; ++u) {
+                const uint64_t v = v0 + u * kStreamBlock + tid;
+                if (v < sh.nvec) {
+                    const unsigned bits = in_regs ? bits_from_regs<T::EPV>(mk, v * T::EPV)
+                                                  : marked_bits<T::EPV>(sh.marks, mp, mq, v * T::EPV);
+                    if (MODE == kUpdate) {
+                        update_vec<T>(x[u], mr, mi, bits, acc);
+                        store16<true>(x[u], sh.st + v);
+                    } else {
+                        if (MODE == kFill)
+                            store16<true>(x[u], sh.st + v);
+                        accum_vec<T>(x[u], bits, acc);
+                    }
+                }
+            }
+            mp = mq;
+        }
+    }
+}
+
+}  // namespace grover

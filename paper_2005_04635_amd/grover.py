@@ -66,6 +66,10 @@ def complex_to_bf16_pairs(psi: np.ndarray) -> np.ndarray:
 Q_FORM, Q_GRID, Q_BLOCK, Q_ELEM_BYTES, Q_N, Q_M = 0, 1, 2, 3, 4, 5
 
 
+# grover_batch_query keys
+BQ_COUNT, BQ_GRID, BQ_SPLIT, BQ_TEAM, BQ_UPDATES, BQ_GRAPH, BQ_BYTES, BQ_N_TEAM = range(8)
+
+
 class GroverError(RuntimeError):
     def __init__(self, status: int, message: str):
         super().__init__(f"{message} (status {status})")
@@ -88,11 +92,27 @@ class grover_config(ctypes.Structure):
     ]
 
 
+class grover_batch_config(ctypes.Structure):
+    _fields_ = [
+        ("count", ctypes.c_uint64),
+        ("n", ctypes.POINTER(ctypes.c_uint32)),
+        ("m", ctypes.POINTER(ctypes.c_uint64)),
+        ("marked", ctypes.POINTER(ctypes.c_uint64)),
+        ("iterations", ctypes.POINTER(ctypes.c_uint64)),
+        ("dtype", ctypes.c_uint32),
+        ("flags", ctypes.c_uint32),
+        ("reserved", ctypes.c_uint64),
+    ]
+
+
 EXPORTS = [
     "grover_init", "grover_reset", "grover_iterate", "grover_gate_iterate", "grover_apply_hadamard_all",
     "grover_sample", "grover_sample_u53", "grover_norm", "grover_read_state", "grover_write_state",
     "grover_state_device", "grover_marked", "grover_sync", "grover_query", "grover_optimal_iterations",
     "grover_destroy", "grover_status_str", "grover_last_error",
+    "grover_batch_init", "grover_batch_set_tiling", "grover_batch_tune", "grover_batch_capture",
+    "grover_batch_run", "grover_batch_sync", "grover_batch_state", "grover_batch_read_state",
+    "grover_batch_query", "grover_batch_destroy", "grover_batch_last_error",
 ]
 
 _lock = threading.Lock()
@@ -134,6 +154,18 @@ def load(path: str = LIB_PATH):
             "grover_destroy": (None, [P]),
             "grover_status_str": (ctypes.c_char_p, [i32]),
             "grover_last_error": (ctypes.c_char_p, [P]),
+            "grover_batch_init": (i32, [ctypes.POINTER(P), ctypes.POINTER(grover_batch_config), P]),
+            "grover_batch_set_tiling": (i32, [P, u32, u32]),
+            "grover_batch_tune": (i32, [P, ctypes.POINTER(u32), ctypes.POINTER(u32),
+                                        ctypes.POINTER(ctypes.c_float)]),
+            "grover_batch_capture": (i32, [P]),
+            "grover_batch_run": (i32, [P]),
+            "grover_batch_sync": (i32, [P]),
+            "grover_batch_state": (i32, [P, u64, ctypes.POINTER(P), ctypes.POINTER(ctypes.c_size_t)]),
+            "grover_batch_read_state": (i32, [P, u64, P, ctypes.c_size_t]),
+            "grover_batch_query": (i32, [P, i32, ctypes.POINTER(ctypes.c_int64)]),
+            "grover_batch_destroy": (None, [P]),
+            "grover_batch_last_error": (ctypes.c_char_p, [P]),
         }
         for name, (res, args) in sig.items():
             fn = getattr(lib, name)
@@ -239,6 +271,68 @@ def grover_status_str(status: int) -> str:
 
 def grover_last_error(ctx) -> str:
     return load().grover_last_error(ctx).decode()
+
+
+def _bcheck(b, status: int) -> None:
+    if status != GROVER_OK:
+        lib = load()
+        msg = lib.grover_batch_last_error(b).decode() if b else ""
+        if not msg:
+            msg = lib.grover_status_str(status).decode()
+        raise GroverError(status, msg)
+
+
+def grover_batch_init(cfg: grover_batch_config, hip_stream: int = 0):
+    b = ctypes.c_void_p()
+    _bcheck(None, load().grover_batch_init(ctypes.byref(b), ctypes.byref(cfg), hip_stream or None))
+    return b
+
+
+def grover_batch_set_tiling(b, split_n: int, team: int) -> None:
+    _bcheck(b, load().grover_batch_set_tiling(b, split_n, team))
+
+
+def grover_batch_tune(b):
+    s, t, ms = ctypes.c_uint32(), ctypes.c_uint32(), ctypes.c_float()
+    _bcheck(b, load().grover_batch_tune(b, ctypes.byref(s), ctypes.byref(t), ctypes.byref(ms)))
+    return s.value, t.value, ms.value
+
+
+def grover_batch_capture(b) -> None:
+    _bcheck(b, load().grover_batch_capture(b))
+
+
+def grover_batch_run(b) -> None:
+    _bcheck(b, load().grover_batch_run(b))
+
+
+def grover_batch_sync(b) -> None:
+    _bcheck(b, load().grover_batch_sync(b))
+
+
+def grover_batch_state(b, i: int):
+    p, n = ctypes.c_void_p(), ctypes.c_size_t()
+    _bcheck(b, load().grover_batch_state(b, i, ctypes.byref(p), ctypes.byref(n)))
+    return p.value, n.value
+
+
+def grover_batch_read_state(b, i: int, host: int, nbytes: int) -> None:
+    _bcheck(b, load().grover_batch_read_state(b, i, host, nbytes))
+
+
+def grover_batch_query(b, key: int) -> int:
+    v = ctypes.c_int64()
+    _bcheck(b, load().grover_batch_query(b, key, ctypes.byref(v)))
+    return v.value
+
+
+def grover_batch_destroy(b) -> None:
+    if b:
+        load().grover_batch_destroy(b)
+
+
+def grover_batch_last_error(b) -> str:
+    return load().grover_batch_last_error(b).decode()
 
 
 # --------------------------------------------------------------------------------- convenience class
@@ -370,6 +464,80 @@ class Grover:
     def __del__(self):
         try:
             if sys.is_finalizing():  # the HIP runtime may already be torn down
+                return
+            self.close()
+        except BaseException:
+            pass
+
+
+class GroverBatch:
+    """Many independent searches (complex64 states) advanced by one persistent launch per run.
+
+    n, m        per-instance qubit counts and marked-list lengths (sequences of equal length)
+    marks       per-instance marked lists (a sequence of sequences), concatenated for the library
+    iterations  per-instance iteration counts, or None for k_opt(n, m)
+    Work goes to torch's current stream at construction.  `run()` restarts every instance from the uniform
+    superposition and performs its iterations; `read_state(i)` returns instance i's state (complex64).
+    """
+
+    def __init__(self, n, m, marks, iterations=None):
+        import torch
+
+        self._n = np.ascontiguousarray(np.asarray(n, dtype=np.uint32))
+        self._m = np.ascontiguousarray(np.asarray(m, dtype=np.uint64))
+        lists = [np.asarray(x, dtype=np.uint64).ravel() for x in marks]
+        if len(lists) != self._n.size or self._m.size != self._n.size:
+            raise ValueError("n, m and marks must have one entry per instance")
+        self._marks = np.ascontiguousarray(np.concatenate(lists) if lists else np.zeros(0, np.uint64))
+        self._iters = None if iterations is None else np.ascontiguousarray(np.asarray(iterations, np.uint64))
+        cfg = grover_batch_config()
+        cfg.count = self._n.size
+        cfg.n = self._n.ctypes.data_as(ctypes.POINTER(ctypes.c_uint32))
+        cfg.m = self._m.ctypes.data_as(ctypes.POINTER(ctypes.c_uint64))
+        if self._marks.size:
+            cfg.marked = self._marks.ctypes.data_as(ctypes.POINTER(ctypes.c_uint64))
+        if self._iters is not None:
+            cfg.iterations = self._iters.ctypes.data_as(ctypes.POINTER(ctypes.c_uint64))
+        cfg.dtype = GROVER_C64
+        self.stream = torch.cuda.current_stream()
+        self.b = grover_batch_init(cfg, self.stream.cuda_stream)
+        self.count = int(self._n.size)
+
+    def set_tiling(self, split_n: int, team: int) -> "GroverBatch":
+        grover_batch_set_tiling(self.b, split_n, team)
+        return self
+
+    def tune(self):
+        """(split_n, team, milliseconds) of the fastest candidate tiling, which stays selected."""
+        return grover_batch_tune(self.b)
+
+    def capture(self) -> "GroverBatch":
+        grover_batch_capture(self.b)
+        return self
+
+    def run(self) -> "GroverBatch":
+        grover_batch_run(self.b)
+        return self
+
+    def sync(self) -> None:
+        grover_batch_sync(self.b)
+
+    def query(self, key: int) -> int:
+        return grover_batch_query(self.b, key)
+
+    def read_state(self, i: int) -> np.ndarray:
+        out = np.empty(1 << int(self._n[i]), dtype=np.complex64)
+        grover_batch_read_state(self.b, i, out.ctypes.data, out.nbytes)
+        return out
+
+    def close(self) -> None:
+        if getattr(self, "b", None):
+            grover_batch_destroy(self.b)
+            self.b = None
+
+    def __del__(self):
+        try:
+            if sys.is_finalizing():
                 return
             self.close()
         except BaseException:

@@ -154,3 +154,79 @@ def test_missing_library_fails_loudly(tmp_path, monkeypatch):
     monkeypatch.setattr(g, "_lib", None)
     with pytest.raises(RuntimeError, match="not built"):
         g.load(str(tmp_path / "nope.so"))
+
+
+def _batch_cfg(n, m, marks, dtype=1):
+    from paper_2005_04635_amd.grover import grover_batch_config
+
+    keep = [(ctypes.c_uint32 * len(n))(*n), (ctypes.c_uint64 * len(m))(*m),
+            (ctypes.c_uint64 * max(len(marks), 1))(*marks)]
+    cfg = grover_batch_config()
+    cfg.count = len(n)
+    cfg.n = ctypes.cast(keep[0], ctypes.POINTER(ctypes.c_uint32))
+    cfg.m = ctypes.cast(keep[1], ctypes.POINTER(ctypes.c_uint64))
+    if marks:
+        cfg.marked = ctypes.cast(keep[2], ctypes.POINTER(ctypes.c_uint64))
+    cfg.dtype = dtype
+    return cfg, keep
+
+
+@pytest.mark.parametrize("n,m,marks,status", [
+    ([4], [1], [16], -1),            # index out of range
+    ([4], [2], [3, 3], -1),          # duplicate
+    ([0], [0], [], -1),              # no qubits
+    ([25], [1], [0], -1),            # above the batch size limit
+    ([3], [9], list(range(9)), -1),  # m > N
+    ([3, 4], [1, 1], [2], -1),       # marks given for fewer than sum(m): passed as a null list
+])
+def test_batch_init_rejects_invalid_configs(lib, n, m, marks, status):
+    cfg, keep = _batch_cfg(n, m, marks)
+    if len(marks) < sum(m):
+        cfg.marked = None
+    b = ctypes.c_void_p()
+    assert lib.grover_batch_init(ctypes.byref(b), ctypes.byref(cfg), None) == status
+    assert not b.value
+
+
+def test_batch_init_rejects_other_fields(lib):
+    b = ctypes.c_void_p()
+    cfg, keep = _batch_cfg([4], [1], [3], dtype=2)
+    assert lib.grover_batch_init(ctypes.byref(b), ctypes.byref(cfg), None) == -5  # complex128 batches
+    cfg, keep = _batch_cfg([4], [1], [3])
+    cfg.flags = 1
+    assert lib.grover_batch_init(ctypes.byref(b), ctypes.byref(cfg), None) == -1
+    cfg.flags, cfg.reserved = 0, 1
+    assert lib.grover_batch_init(ctypes.byref(b), ctypes.byref(cfg), None) == -1
+    cfg.reserved, cfg.count = 0, 0
+    assert lib.grover_batch_init(ctypes.byref(b), ctypes.byref(cfg), None) == -1
+    assert lib.grover_batch_init(None, ctypes.byref(cfg), None) == -1
+    assert lib.grover_batch_init(ctypes.byref(b), None, None) == -1
+    assert not b.value
+
+
+def test_batch_null_handles(lib):
+    assert lib.grover_batch_run(None) == -1
+    assert lib.grover_batch_sync(None) == -1
+    assert lib.grover_batch_capture(None) == -1
+    assert lib.grover_batch_set_tiling(None, 10, 2) == -1
+    assert lib.grover_batch_tune(None, None, None, None) == -1
+    assert lib.grover_batch_last_error(None) == b"no batch"
+    lib.grover_batch_destroy(None)
+
+
+def test_batch_workload_statistics():
+    """The 4096-instance workload: n spans [8, 20], M spans [1, 8], marks distinct and in range."""
+    import math
+
+    import numpy as np
+
+    import workloads
+
+    n, m, marks = workloads.BATCH_4096.instances()
+    assert n.size == 4096 and n.min() == 8 and n.max() == 20 and m.min() == 1 and m.max() == 8
+    for b in range(0, 4096, 97):
+        mk = marks[b]
+        assert mk.size == m[b] and np.unique(mk).size == mk.size and int(mk.max()) < (1 << int(n[b]))
+    N = np.ldexp(1.0, n.astype(int))
+    updates = float(np.sum(N * np.floor(math.pi / 4 * np.sqrt(N / m))))
+    assert 2.2e11 < updates < 2.3e11

@@ -140,3 +140,39 @@ def test_n26_precision_sweep(G, orc, storage, accum):
     if bound < 1.0:
         assert err <= bound, (err, bound)
     g.close()
+
+
+def test_batch4096_workload(G, orc):
+    """The 4096-instance batch at full size, in the configuration the benchmark times (the autotuned tiling,
+    replayed from a captured graph): every amplitude of every instance is checked — each class (marked,
+    unmarked) bitwise constant, and its value within the complex64 bound of the oracle's two-class result."""
+    import torch
+
+    from test_gpu_precision import error_bound
+
+    w = workloads.BATCH_4096
+    n, m, marks = w.instances()
+    stream = torch.cuda.Stream()
+    with torch.cuda.stream(stream):
+        b = G.GroverBatch(n, m, marks)
+        split, team, ms = b.tune()
+        b.capture()
+        b.run()
+        b.sync()
+        print(f"tiling split={split} team={team} tuned {ms:.1f} ms", flush=True)
+        worst = 0.0
+        for i in range(w.count):
+            ni, mi = int(n[i]), int(m[i])
+            k = orc.optimal_iterations(ni, mi)
+            a, u = orc.two_class(ni, mi, k)  # marked, unmarked amplitude (binary64)
+            got = b.read_state(i)
+            mask = np.zeros(1 << ni, dtype=bool)
+            mask[marks[i].astype(np.int64)] = True
+            gm, gu = got[mask], got[~mask]
+            assert np.all(gm.view(np.uint64) == gm.view(np.uint64)[0]), i
+            assert np.all(gu.view(np.uint64) == gu.view(np.uint64)[0]), i
+            err = max(abs(complex(gm[0]) - a), abs(complex(gu[0]) - u))
+            worst = max(worst, err / error_bound(ni, k, "c64", "f64", 1))
+            assert err <= error_bound(ni, k, "c64", "f64", 1), (i, ni, mi, k, err)
+        print(f"worst error / bound = {worst:.3g}", flush=True)
+        b.close()

@@ -155,3 +155,34 @@ PRECISION_N26 = Workload(
 )
 
 WORKLOADS = {w.name: w for w in (PLAIN_N10, HASH_N28, PRECISION_N26)}
+
+
+@dataclasses.dataclass(frozen=True)
+class BatchWorkload:
+    """Many independent searches with uneven sizes.
+
+    Instance b takes x = SplitMix64_{3b}(seed), x' = SplitMix64_{3b+1}(seed) and s = SplitMix64_{3b+2}(seed):
+    n_b = n_min + (x mod n_span), M_b = 1 + (x' mod m_max), and M_b distinct marked indices drawn by
+    `distinct_marks(n_b, M_b, s)`.  Each instance runs its own floor(pi/4 sqrt(N_b / M_b)) iterations from
+    the uniform superposition; states are complex64.
+    """
+
+    name: str
+    count: int
+    n_min: int
+    n_span: int
+    m_max: int
+    seed: int
+
+    def instances(self):
+        """(n, m, marks) arrays: n uint32[count], m uint64[count], marks = list of uint64 arrays."""
+        s = splitmix64(self.seed, 3 * self.count)
+        n = (self.n_min + s[0::3] % np.uint64(self.n_span)).astype(np.uint32)
+        m = (np.uint64(1) + s[1::3] % np.uint64(self.m_max)).astype(np.uint64)
+        marks = [distinct_marks(int(n[b]), int(m[b]), int(s[3 * b + 2])) for b in range(self.count)]
+        return n, m, marks
+
+
+# 4096 searches, n uniform in [8, 20], M uniform in [1, 8].
+BATCH_4096 = BatchWorkload(name="batch4096_n8to20_m1to8_c64", count=4096, n_min=8, n_span=13, m_max=8,
+                           seed=0x4096C3B5)
