@@ -4,6 +4,7 @@ per Grover iteration at n = 28, against the plain binary64 form.
     python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu-baseline] [--no-forms]
     python bench.py --sweep table1      (the paper's Table 1 sizes: proposed vs gate-level, one line each)
     python bench.py --sweep precision   (storage x accumulator of the mean at n = 26, one line each)
+    python bench.py --sweep batch       (4096 independent searches: tilings, the tuned graph, one-by-one)
 
 Workload (synthetic by construction; the paper uses no dataset): the single large instance, n = 28
 (2^28 complex64 amplitudes, 2 GiB), M = 8 marked indices defined by the hash predicate
@@ -42,7 +43,8 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, public datasheet
 TRAFFIC_SUMMARY = os.path.join(ROOT, "profiles", "fused_iterate_n28_c64_traffic.txt")
-KERNEL_SOURCES = [os.path.join(ROOT, "paper_2005_04635_amd", "csrc", f) for f in ("k_fused.hip", "internal.h")]
+KERNEL_SOURCES = [os.path.join(ROOT, "paper_2005_04635_amd", "csrc", f)
+                  for f in ("k_fused.hip", "stream.h", "internal.h")]
 PAPER_CPU_N20_UPDATES_PER_S = 1048576 * 804 / 20.005  # Table 1, proposed simulator, n = 20, i3-5005U 1 thread
 
 
@@ -269,6 +271,115 @@ def sweep_precision(pkg, hip, stream) -> None:
                 "speedup_vs_plain_fp64": plain_ms / (ms / w.iterations)}), flush=True)
 
 
+def batch_config(pkg, n, m, marks):
+    import numpy as np
+
+    g = pkg.grover
+    keep = [np.ascontiguousarray(n, dtype=np.uint32), np.ascontiguousarray(m, dtype=np.uint64),
+            np.ascontiguousarray(np.concatenate(marks), dtype=np.uint64)]
+    cfg = g.grover_batch_config()
+    cfg.count = keep[0].size
+    cfg.n = keep[0].ctypes.data_as(ctypes.POINTER(ctypes.c_uint32))
+    cfg.m = keep[1].ctypes.data_as(ctypes.POINTER(ctypes.c_uint64))
+    cfg.marked = keep[2].ctypes.data_as(ctypes.POINTER(ctypes.c_uint64))
+    cfg.dtype = g.GROVER_C64
+    return cfg, keep
+
+
+def sweep_batch(pkg, hip, stream, runs: int) -> None:
+    """The 4096-instance batch: every candidate tiling timed (one JSON line each), then the fastest replayed
+    from a captured graph `runs` times; against running the instances one by one, with the plain binary64
+    form (complex128, separate oracle / sum / update kernels) and with the best single-instance form
+    (complex64, `auto`), both timed on every 8th instance and scaled by amplitude-updates."""
+    import numpy as np
+
+    import workloads
+
+    g = pkg.grover
+    w = workloads.BATCH_4096
+    n, m, marks = w.instances()
+    cfg, keep = batch_config(pkg, n, m, marks)
+    b = pkg.grover_batch_init(cfg, stream.value)
+    updates = pkg.grover_batch_query(b, g.BQ_UPDATES)
+    state_bytes = pkg.grover_batch_query(b, g.BQ_BYTES)
+    alg_bytes = 16.0 * updates + 8.0 * float(np.sum(np.ldexp(1.0, n.astype(int))))
+    grid = pkg.grover_batch_query(b, g.BQ_GRID)
+    log(f"[bench] batch {w.name}: {w.count} instances, {updates:.4g} updates, {state_bytes / 2**30:.2f} GiB, "
+        f"grid {grid}")
+
+    def timed_run():
+        e0, e1 = hip.event(), hip.event()
+        hip.lib.hipEventRecord(e0, stream)
+        pkg.grover_batch_run(b)
+        hip.lib.hipEventRecord(e1, stream)
+        ms = hip.elapsed_ms(e0, e1)
+        pkg.grover_batch_sync(b)
+        return ms
+
+    cands = [(0, 1)] + [(s, t) for s in (17, 18, 19, 20) for t in (2, 4, 8, 16, 32) if t <= grid]
+    best = None
+    for split, team in cands:
+        pkg.grover_batch_set_tiling(b, split, team)
+        timed_run()  # warm
+        ms = min(timed_run() for _ in range(2))
+        log(f"[bench] tiling split={split} team={team}: {ms:.1f} ms")
+        print(json.dumps({"sweep": "batch_tiling", "split_n": split, "team": team,
+                          "in_team_queue": pkg.grover_batch_query(b, g.BQ_N_TEAM), "ms": round(ms, 3),
+                          "amplitude_updates_per_s": updates / (ms / 1e3)}), flush=True)
+        if best is None or ms < best[2]:
+            best = (split, team, ms)
+    pkg.grover_batch_set_tiling(b, best[0], best[1])
+    pkg.grover_batch_capture(b)
+    pkg.grover_batch_run(b)
+    pkg.grover_batch_sync(b)
+    hip.ok(hip.lib.hipDeviceSynchronize(), "hipDeviceSynchronize")
+    e0, e1 = hip.event(), hip.event()
+    t0 = time.perf_counter()
+    hip.lib.hipEventRecord(e0, stream)
+    for _ in range(runs):
+        pkg.grover_batch_run(b)
+    hip.lib.hipEventRecord(e1, stream)
+    ms = hip.elapsed_ms(e0, e1) / runs
+    pkg.grover_batch_sync(b)
+    wall_ms = (time.perf_counter() - t0) * 1e3 / runs
+    pkg.grover_batch_destroy(b)
+
+    # one by one, on every 8th instance
+    sample = list(range(0, w.count, 8))
+    one_by_one = {}
+    for dtype, form in (("c128", "two_pass"), ("c64", "auto")):
+        t_ms, upd = 0.0, 0.0
+        for i in sample:
+            cfgi, keepi = make_config(pkg, int(n[i]), dtype, marks=marks[i], form=form)
+            ctx = pkg.grover_init(cfgi, stream.value, 0, 0)
+            k = pkg.grover_optimal_iterations(int(n[i]), int(m[i]))
+            pkg.grover_sync(ctx)
+            a0, a1 = hip.event(), hip.event()
+            hip.lib.hipEventRecord(a0, stream)
+            pkg.grover_reset(ctx)
+            pkg.grover_iterate(ctx, k)
+            hip.lib.hipEventRecord(a1, stream)
+            t_ms += hip.elapsed_ms(a0, a1)
+            pkg.grover_sync(ctx)
+            pkg.grover_destroy(ctx)
+            upd += float(1 << int(n[i])) * k
+        one_by_one[f"{dtype}_{form}"] = {"amplitude_updates_per_s": upd / (t_ms / 1e3),
+                                        "sample": f"every 8th instance ({len(sample)}), reset + iterate each, "
+                                                  f"{t_ms:.0f} ms of device time"}
+        log(f"[bench] one by one {dtype} {form}: {upd / (t_ms / 1e3):.4g} updates/s")
+    rate = updates / (ms / 1e3)
+    gbs = alg_bytes / (ms / 1e3) / 1e9
+    print(json.dumps({
+        "sweep": "batch", "workload": w.name, "instances": w.count, "amplitude_updates": updates,
+        "state_bytes": state_bytes, "split_n": best[0], "team": best[1], "graph": True, "runs": runs,
+        "ms_per_run": round(ms, 3), "wall_ms_per_run": round(wall_ms, 3), "amplitude_updates_per_s": rate,
+        "algorithmic_gbs": round(gbs, 1), "frac_of_hbm_peak": round(gbs / HBM_PEAK_GBS, 4),
+        "one_by_one": one_by_one,
+        "speedup_vs_plain_fp64_one_by_one": rate / one_by_one["c128_two_pass"]["amplitude_updates_per_s"],
+        "speedup_vs_best_single_form_one_by_one": rate / one_by_one["c64_auto"]["amplitude_updates_per_s"],
+    }), flush=True)
+
+
 def main() -> int:
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -277,7 +388,7 @@ def main() -> int:
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-forms", action="store_true")
     ap.add_argument("--cpu-iters", type=int, default=8)
-    ap.add_argument("--sweep", choices=["table1", "precision"], default=None,
+    ap.add_argument("--sweep", choices=["table1", "precision", "batch"], default=None,
                     help="instead of the headline line, print one JSON line per point of a sweep")
     args = ap.parse_args()
     if args.gpus != 1:
@@ -300,6 +411,9 @@ def main() -> int:
         return 0
     if args.sweep == "precision":
         sweep_precision(pkg, hip, stream)
+        return 0
+    if args.sweep == "batch":
+        sweep_batch(pkg, hip, stream, max(args.steps, 1))
         return 0
     w = workloads.HASH_N28
     N = 1 << w.n

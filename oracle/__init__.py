@@ -65,6 +65,12 @@ def load(path: str = _LIB):
             "orc_two_class_stored": (None, [u32, u64, u64, ctypes.c_int, pd, pd]),
             "orc_sample": (ctypes.c_int, [u32, pd, pu, u64, pu]),
             "orc_uniforms_u53": (None, [u64, u64, pu]),
+            "orc_phase_oracle": (None, [pd, pu, u64, dbl]),
+            "orc_phase_diffusion": (None, [u32, pd, dbl]),
+            "orc_phase_search": (None, [u32, pu, u64, u64, pd, pd, pd]),
+            "orc_phase_loss": (dbl, [pd, pu, u64]),
+            "orc_phase_grad_tangent": (ctypes.c_int, [u32, pu, u64, u64, pd, pd, pd, pd]),
+            "orc_phase_grad_adjoint": (ctypes.c_int, [u32, pu, u64, u64, pd, pd, pd, pd]),
         }
         for name, (res, args) in sig.items():
             fn = getattr(lib, name)
@@ -91,6 +97,14 @@ def _state(psi: np.ndarray) -> np.ndarray:
 
 def _marks(k) -> np.ndarray:
     return np.ascontiguousarray(np.asarray(k, dtype=np.uint64).reshape(-1))
+
+
+def _params(phi, theta):
+    ph = np.ascontiguousarray(np.asarray(phi, dtype=np.float64).reshape(-1))
+    th = np.ascontiguousarray(np.asarray(theta, dtype=np.float64).reshape(-1))
+    if ph.size != th.size:
+        raise ValueError("phi and theta need one entry per iteration")
+    return ph, th
 
 
 def _n_of(psi: np.ndarray) -> int:
@@ -201,6 +215,43 @@ class Oracle:
         if rc != 0:
             raise MemoryError("oracle CDF allocation failed")
         return out
+
+    # -- generalized iteration with per-iteration phases (phi_j on the marked entries, theta_j in the
+    #    diffusion); phi = theta = pi is Algorithm 3 + Eq. 2
+    def phase_oracle(self, psi: np.ndarray, marks, phi: float) -> np.ndarray:
+        k = _marks(marks)
+        self.lib.orc_phase_oracle(_pd(_state(psi)), _pu(k), k.size, float(phi))
+        return psi
+
+    def phase_diffusion(self, psi: np.ndarray, theta: float) -> np.ndarray:
+        self.lib.orc_phase_diffusion(_n_of(psi), _pd(_state(psi)), float(theta))
+        return psi
+
+    def phase_search(self, n: int, marks, phi, theta) -> np.ndarray:
+        k = _marks(marks)
+        ph, th = _params(phi, theta)
+        psi = np.empty(1 << n, dtype=np.complex128)
+        self.lib.orc_phase_search(n, _pu(k), k.size, ph.size, _pd(ph), _pd(th), _pd(psi))
+        return psi
+
+    def phase_loss(self, psi: np.ndarray, marks) -> float:
+        k = _marks(marks)
+        return float(self.lib.orc_phase_loss(_pd(_state(psi)), _pu(k), k.size))
+
+    def phase_grad_tangent(self, n: int, marks, phi, theta):
+        return self._phase_grad(self.lib.orc_phase_grad_tangent, n, marks, phi, theta)
+
+    def phase_grad_adjoint(self, n: int, marks, phi, theta):
+        return self._phase_grad(self.lib.orc_phase_grad_adjoint, n, marks, phi, theta)
+
+    @staticmethod
+    def _phase_grad(fn, n, marks, phi, theta):
+        k = _marks(marks)
+        ph, th = _params(phi, theta)
+        dphi, dtheta = np.empty(ph.size), np.empty(ph.size)
+        if fn(n, _pu(k), k.size, ph.size, _pd(ph), _pd(th), _pd(dphi), _pd(dtheta)) != 0:
+            raise MemoryError("oracle gradient allocation failed")
+        return dphi, dtheta
 
     def uniforms_u53(self, seed: int, shots: int) -> np.ndarray:
         out = np.empty(shots, dtype=np.uint64)

@@ -349,3 +349,215 @@ void orc_uniforms_u53(uint64_t seed, uint64_t shots, uint64_t *out)
     for (uint64_t j = 0; j < shots; ++j)
         out[j] = orc_splitmix64(seed, j) >> 11;
 }
+
+/* ------------------------------------------------------------------------------------------------ */
+/* Generalized iteration with per-iteration phases.  The paper fixes both phases at pi (the oracle of
+ * Algorithm 3 negates, Eq. 2 inverts about the mean); this is the usual phase-matched generalization, a
+ * convention of this project:
+ *   O(phi):   c_i <- e^{i phi} c_i for every marked i;
+ *   D(theta): c <- ((1 - e^{i theta}) |psi><psi| - I) c with |psi> the uniform superposition, i.e.
+ *             c_i <- (1 - e^{i theta}) * mean(c) - c_i with mean(c) = (sum_j c_j) / N.
+ * At phi = theta = pi these are Algorithm 3 and Eq. 2.  Iteration j applies D(theta_j) O(phi_j), from the
+ * uniform superposition, for j = 1 .. K.  The loss is L = 1 - sum over marked i of |c_i|^2. */
+
+typedef struct {
+    double re, im;
+} orc_c;
+
+static orc_c c_mul(orc_c a, orc_c b)
+{
+    orc_c r = {a.re * b.re - a.im * b.im, a.re * b.im + a.im * b.re};
+    return r;
+}
+
+static orc_c c_expi(double x)
+{
+    orc_c r = {cos(x), sin(x)};
+    return r;
+}
+
+static orc_c c_at(const double *psi, uint64_t i)
+{
+    orc_c r = {psi[2 * i], psi[2 * i + 1]};
+    return r;
+}
+
+static void c_put(double *psi, uint64_t i, orc_c v)
+{
+    psi[2 * i] = v.re;
+    psi[2 * i + 1] = v.im;
+}
+
+void orc_phase_oracle(double *psi, const uint64_t *k, uint64_t m, double phi)
+{
+    const orc_c e = c_expi(phi);
+    for (uint64_t q = 0; q < m; ++q)
+        c_put(psi, k[q], c_mul(e, c_at(psi, k[q])));
+}
+
+void orc_phase_diffusion(uint32_t n, double *psi, double theta)
+{
+    const uint64_t N = (uint64_t)1 << n;
+    double re, im;
+    pairwise_sum(psi, 0, N, &re, &im);
+    const orc_c mean = {re / ldexp(1.0, (int)n), im / ldexp(1.0, (int)n)};
+    const orc_c e = c_expi(theta);
+    const orc_c one_minus_e = {1.0 - e.re, -e.im};
+    const orc_c f = c_mul(one_minus_e, mean);
+    for (uint64_t i = 0; i < N; ++i) {
+        psi[2 * i] = f.re - psi[2 * i];
+        psi[2 * i + 1] = f.im - psi[2 * i + 1];
+    }
+}
+
+void orc_phase_search(uint32_t n, const uint64_t *k, uint64_t m, uint64_t K, const double *phi,
+                      const double *theta, double *psi)
+{
+    orc_init_uniform(n, psi);
+    for (uint64_t j = 0; j < K; ++j) {
+        orc_phase_oracle(psi, k, m, phi[j]);
+        orc_phase_diffusion(n, psi, theta[j]);
+    }
+}
+
+double orc_phase_loss(const double *psi, const uint64_t *k, uint64_t m)
+{
+    double p = 0.0;
+    for (uint64_t q = 0; q < m; ++q)
+        p += psi[2 * k[q]] * psi[2 * k[q]] + psi[2 * k[q] + 1] * psi[2 * k[q] + 1];
+    return 1.0 - p;
+}
+
+/* dL/dp = -2 Re sum over marked i of conj(c_i) t_i, t = dc/dp at the end of the run. */
+static double loss_derivative(const double *psi, const double *t, const uint64_t *k, uint64_t m)
+{
+    double s = 0.0;
+    for (uint64_t q = 0; q < m; ++q)
+        s += psi[2 * k[q]] * t[2 * k[q]] + psi[2 * k[q] + 1] * t[2 * k[q] + 1];
+    return -2.0 * s;
+}
+
+/* Gradient of the loss by forward-mode differentiation: for each parameter p the tangent t = dc/dp is
+ * carried beside c.  Iteration j maps (c, t) to (D O c, D O t + dD/dp O c + D dO/dp c), where the only
+ * nonzero parameter derivatives are, for p = phi_j, dO/dphi = i e^{i phi} on the marked entries, and for
+ * p = theta_j, dD/dtheta c = -i e^{i theta} mean(c) 1 (D is affine in |psi><psi|).  Both operators are
+ * linear, so the tangent obeys the same step.  Cost O(K^2 N); returns -1 when memory is short. */
+int orc_phase_grad_tangent(uint32_t n, const uint64_t *k, uint64_t m, uint64_t K, const double *phi,
+                           const double *theta, double *dphi, double *dtheta)
+{
+    const uint64_t N = (uint64_t)1 << n;
+    double *c = malloc(2 * N * sizeof(double)), *t = malloc(2 * N * sizeof(double));
+    double *w = malloc(2 * N * sizeof(double));
+    if (!c || !t || !w) {
+        free(c);
+        free(t);
+        free(w);
+        return -1;
+    }
+    for (uint64_t p = 0; p < 2 * K; ++p) {
+        const uint64_t jp = p % K;     /* iteration the parameter belongs to */
+        const int is_theta = p >= K;   /* parameters 0..K-1 are phi, K..2K-1 theta */
+        orc_init_uniform(n, c);
+        memset(t, 0, 2 * N * sizeof(double));
+        for (uint64_t j = 0; j < K; ++j) {
+            if (j != jp) {
+                orc_phase_oracle(c, k, m, phi[j]);
+                orc_phase_diffusion(n, c, theta[j]);
+                orc_phase_oracle(t, k, m, phi[j]);
+                orc_phase_diffusion(n, t, theta[j]);
+                continue;
+            }
+            if (!is_theta) {
+                /* d/dphi of D O c = D (i e^{i phi} P_M c): w = i e^{i phi} c on marked, 0 elsewhere */
+                memset(w, 0, 2 * N * sizeof(double));
+                const orc_c ie = c_mul((orc_c){0.0, 1.0}, c_expi(phi[j]));
+                for (uint64_t q = 0; q < m; ++q)
+                    c_put(w, k[q], c_mul(ie, c_at(c, k[q])));
+                /* D applied to w: D w = (1 - e^{i theta}) mean(w) - w */
+                orc_phase_diffusion(n, w, theta[j]);
+                orc_phase_oracle(t, k, m, phi[j]);
+                orc_phase_diffusion(n, t, theta[j]);
+                for (uint64_t i = 0; i < 2 * N; ++i)
+                    t[i] += w[i];
+                orc_phase_oracle(c, k, m, phi[j]);
+                orc_phase_diffusion(n, c, theta[j]);
+            } else {
+                /* d/dtheta of D y with y = O c: -i e^{i theta} mean(y) in every entry */
+                orc_phase_oracle(c, k, m, phi[j]);
+                double re, im;
+                pairwise_sum(c, 0, N, &re, &im);
+                const orc_c mean = {re / ldexp(1.0, (int)n), im / ldexp(1.0, (int)n)};
+                const orc_c g = c_mul(c_mul((orc_c){0.0, -1.0}, c_expi(theta[j])), mean);
+                orc_phase_diffusion(n, c, theta[j]);
+                orc_phase_oracle(t, k, m, phi[j]);
+                orc_phase_diffusion(n, t, theta[j]);
+                for (uint64_t i = 0; i < N; ++i) {
+                    t[2 * i] += g.re;
+                    t[2 * i + 1] += g.im;
+                }
+            }
+        }
+        (is_theta ? dtheta : dphi)[jp] = loss_derivative(c, t, k, m);
+    }
+    free(c);
+    free(t);
+    free(w);
+    return 0;
+}
+
+/* Gradient of the loss by reverse-mode differentiation with every intermediate state stored (memory
+ * (K + 1) N complex values).  With lambda = dL/d(conj c) (lambda = -c on the marked entries after the last
+ * iteration, 0 elsewhere) and y_j = O(phi_j) c_{j-1}:
+ *   dL/dtheta_j = 2 Re( conj(sum lambda_j) * (-i e^{i theta_j}) * mean(y_j) ),
+ *   nu_j = D(theta_j)^H lambda_j,   dL/dphi_j = 2 Re( sum over marked of conj(nu_j) * i * y_j ),
+ *   lambda_{j-1} = O(phi_j)^H nu_j,
+ * where D^H = D(-theta) and O^H = O(-phi).  Returns -1 when memory is short. */
+int orc_phase_grad_adjoint(uint32_t n, const uint64_t *k, uint64_t m, uint64_t K, const double *phi,
+                           const double *theta, double *dphi, double *dtheta)
+{
+    const uint64_t N = (uint64_t)1 << n;
+    double *states = malloc((K + 1) * 2 * N * sizeof(double));
+    double *lam = malloc(2 * N * sizeof(double)), *y = malloc(2 * N * sizeof(double));
+    if (!states || !lam || !y) {
+        free(states);
+        free(lam);
+        free(y);
+        return -1;
+    }
+    orc_init_uniform(n, states);
+    for (uint64_t j = 0; j < K; ++j) {
+        double *next = states + (j + 1) * 2 * N;
+        memcpy(next, states + j * 2 * N, 2 * N * sizeof(double));
+        orc_phase_oracle(next, k, m, phi[j]);
+        orc_phase_diffusion(n, next, theta[j]);
+    }
+    memset(lam, 0, 2 * N * sizeof(double));
+    const double *last = states + K * 2 * N;
+    for (uint64_t q = 0; q < m; ++q)
+        c_put(lam, k[q], (orc_c){-last[2 * k[q]], -last[2 * k[q] + 1]});
+    for (uint64_t jj = K; jj-- > 0;) {
+        memcpy(y, states + jj * 2 * N, 2 * N * sizeof(double));
+        orc_phase_oracle(y, k, m, phi[jj]);
+        double yr, yi, lr, li;
+        pairwise_sum(y, 0, N, &yr, &yi);
+        pairwise_sum(lam, 0, N, &lr, &li);
+        const orc_c mean_y = {yr / ldexp(1.0, (int)n), yi / ldexp(1.0, (int)n)};
+        const orc_c conj_sum_lam = {lr, -li};
+        const orc_c g = c_mul(c_mul(conj_sum_lam, c_mul((orc_c){0.0, -1.0}, c_expi(theta[jj]))), mean_y);
+        dtheta[jj] = 2.0 * g.re;
+        orc_phase_diffusion(n, lam, -theta[jj]); /* nu = D(-theta) lambda */
+        double s = 0.0;
+        for (uint64_t q = 0; q < m; ++q) {
+            const orc_c nu = c_at(lam, k[q]);
+            const orc_c conj_nu = {nu.re, -nu.im};
+            const orc_c t = c_mul(conj_nu, c_mul((orc_c){0.0, 1.0}, c_at(y, k[q])));
+            s += t.re;
+        }
+        dphi[jj] = 2.0 * s;
+        orc_phase_oracle(lam, k, m, -phi[jj]); /* lambda_{j-1} = O(-phi) nu */
+    }
+    free(states);
+    free(lam);
+    free(y);
+    return 0;
+}

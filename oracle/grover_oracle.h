@@ -31,6 +31,15 @@ double orc_round_to_bits(double x, int p);
 void orc_two_class_stored(uint32_t n, uint64_t m, uint64_t iters, int p, double *a_out, double *b_out);
 int orc_sample(uint32_t n, const double *psi, const uint64_t *u53, uint64_t shots, uint64_t *out);
 void orc_uniforms_u53(uint64_t seed, uint64_t shots, uint64_t *out);
+void orc_phase_oracle(double *psi, const uint64_t *k, uint64_t m, double phi);
+void orc_phase_diffusion(uint32_t n, double *psi, double theta);
+void orc_phase_search(uint32_t n, const uint64_t *k, uint64_t m, uint64_t K, const double *phi,
+                      const double *theta, double *psi);
+double orc_phase_loss(const double *psi, const uint64_t *k, uint64_t m);
+int orc_phase_grad_tangent(uint32_t n, const uint64_t *k, uint64_t m, uint64_t K, const double *phi,
+                           const double *theta, double *dphi, double *dtheta);
+int orc_phase_grad_adjoint(uint32_t n, const uint64_t *k, uint64_t m, uint64_t K, const double *phi,
+                           const double *theta, double *dphi, double *dtheta);
 
 #ifdef __cplusplus
 }

@@ -4,6 +4,8 @@
 //                   [--iters K] [--shots 1000000] [--shot-seed 11] [--steps 1]
 //   grover_cli run  --n 10 --dtype f64 --mark 123 ...          (explicit marked indices, repeatable)
 //   grover_cli copy --bytes 2147483648 [--reps 1]              (plain copy kernel of known size)
+//   grover_cli batch --instances FILE [--split S --team T | --tune] [--graph] [--runs R]
+//                   (many searches in one launch; FILE holds one instance per line: n m mark_1 ... mark_m)
 //   run ... --calibrate-copy B                                  (also copy B bytes once, before the search)
 //
 // `run` creates a context, then per step: writes the uniform state, runs the iterations (timed with HIP
@@ -37,7 +39,8 @@ int usage()
             "                      [--form auto|fused|resident|two_pass]\n"
             "                      [--mark I ... | --hash-seed S --hash-bits B --m M] [--iters K]\n"
             "                      [--shots S] [--shot-seed U] [--steps T] [--calibrate-copy BYTES]\n"
-            "       grover_cli copy --bytes B [--reps R]\n");
+            "       grover_cli copy --bytes B [--reps R]\n"
+            "       grover_cli batch --instances FILE [--split S --team T | --tune] [--graph] [--runs R]\n");
     return 2;
 }
 
@@ -224,6 +227,117 @@ int run_search(int argc, char **argv)
     return 0;
 }
 
+#define CHECK_BATCH(b, x)                                                              \
+    do {                                                                               \
+        const int s_ = (x);                                                            \
+        if (s_ != GROVER_OK) {                                                         \
+            fprintf(stderr, "grover batch error %d (%s): %s\n", s_, grover_status_str(s_), \
+                    grover_batch_last_error(b));                                       \
+            return 1;                                                                  \
+        }                                                                              \
+    } while (0)
+
+int run_batch(int argc, char **argv)
+{
+    const char *path = nullptr;
+    long split = -1, team = -1;
+    int runs = 3;
+    bool tune = false, graph = false;
+    for (int i = 2; i < argc; ++i) {
+        if (!strcmp(argv[i], "--instances") && i + 1 < argc)
+            path = argv[++i];
+        else if (!strcmp(argv[i], "--split") && i + 1 < argc)
+            split = strtol(argv[++i], nullptr, 0);
+        else if (!strcmp(argv[i], "--team") && i + 1 < argc)
+            team = strtol(argv[++i], nullptr, 0);
+        else if (!strcmp(argv[i], "--runs") && i + 1 < argc)
+            runs = atoi(argv[++i]);
+        else if (!strcmp(argv[i], "--tune"))
+            tune = true;
+        else if (!strcmp(argv[i], "--graph"))
+            graph = true;
+        else
+            return usage();
+    }
+    if (!path || runs < 1 || (split >= 0) != (team >= 0))
+        return usage();
+    FILE *f = fopen(path, "r");
+    if (!f) {
+        fprintf(stderr, "cannot open %s\n", path);
+        return 1;
+    }
+    std::vector<uint32_t> ns;
+    std::vector<uint64_t> ms, marks;
+    unsigned n = 0;
+    unsigned long long m = 0;
+    while (fscanf(f, "%u %llu", &n, &m) == 2) {
+        ns.push_back(n);
+        ms.push_back(m);
+        for (unsigned long long j = 0; j < m; ++j) {
+            unsigned long long x = 0;
+            if (fscanf(f, "%llu", &x) != 1) {
+                fclose(f);
+                fprintf(stderr, "%s: instance %zu lists fewer than %llu marks\n", path, ns.size() - 1, m);
+                return 1;
+            }
+            marks.push_back(x);
+        }
+    }
+    fclose(f);
+    if (ns.empty()) {
+        fprintf(stderr, "%s: no instances\n", path);
+        return 1;
+    }
+    grover_batch_config cfg{};
+    cfg.count = ns.size();
+    cfg.n = ns.data();
+    cfg.m = ms.data();
+    cfg.marked = marks.empty() ? nullptr : marks.data();
+    cfg.dtype = GROVER_C64;
+    hipStream_t stream;
+    CHECK_HIP(hipStreamCreate(&stream));
+    grover_batch *b = nullptr;
+    CHECK_BATCH(nullptr, grover_batch_init(&b, &cfg, stream));
+    if (split >= 0)
+        CHECK_BATCH(b, grover_batch_set_tiling(b, uint32_t(split), uint32_t(team)));
+    if (tune) {
+        uint32_t s = 0, t = 0;
+        float ms_best = 0;
+        CHECK_BATCH(b, grover_batch_tune(b, &s, &t, &ms_best));
+        fprintf(stderr, "[grover_cli] tuned tiling split=%u team=%u (%.3f ms)\n", s, t, ms_best);
+    }
+    if (graph)
+        CHECK_BATCH(b, grover_batch_capture(b));
+    int64_t updates = 0, grid = 0, sp = 0, tm = 0;
+    CHECK_BATCH(b, grover_batch_query(b, 4, &updates));
+    CHECK_BATCH(b, grover_batch_query(b, 1, &grid));
+    CHECK_BATCH(b, grover_batch_query(b, 2, &sp));
+    CHECK_BATCH(b, grover_batch_query(b, 3, &tm));
+    hipEvent_t e0, e1;
+    CHECK_HIP(hipEventCreate(&e0));
+    CHECK_HIP(hipEventCreate(&e1));
+    double ms_sum = 0;
+    for (int r = 0; r < runs; ++r) {
+        CHECK_HIP(hipEventRecord(e0, stream));
+        CHECK_BATCH(b, grover_batch_run(b));
+        CHECK_HIP(hipEventRecord(e1, stream));
+        CHECK_BATCH(b, grover_batch_sync(b));
+        float ms = 0;
+        CHECK_HIP(hipEventElapsedTime(&ms, e0, e1));
+        ms_sum += ms;
+        fprintf(stderr, "[grover_cli] batch run %d/%d: %.3f ms\n", r + 1, runs, ms);
+    }
+    const double run_ms = ms_sum / runs;
+    printf("{\"mode\": \"batch\", \"instances\": %zu, \"amplitude_updates\": %" PRId64 ", \"grid\": %" PRId64
+           ", \"split_n\": %" PRId64 ", \"team\": %" PRId64 ", \"graph\": %s, \"runs\": %d, \"ms_per_run\": %.4f"
+           ", \"updates_per_s\": %.6e}\n",
+           ns.size(), updates, grid, sp, tm, graph ? "true" : "false", runs, run_ms,
+           double(updates) / (run_ms / 1e3));
+    grover_batch_destroy(b);
+    CHECK_HIP(hipStreamDestroy(stream));
+    return 0;
+}
+
 }  // namespace
 
 int main(int argc, char **argv)
@@ -234,5 +348,7 @@ int main(int argc, char **argv)
         return run_copy(argc, argv);
     if (!strcmp(argv[1], "run"))
         return run_search(argc, argv);
+    if (!strcmp(argv[1], "batch"))
+        return run_batch(argc, argv);
     return usage();
 }

@@ -12,6 +12,7 @@ import shutil
 import pytest
 
 import oracle
+import test_oracle_phase as phase
 import test_oracle_pins as pins
 
 SRC = os.path.join(os.path.dirname(oracle.__file__), "grover_oracle.c")
@@ -68,6 +69,21 @@ MUTANTS = [
      "const double r = nearbyint(ldexp(m, p - 1));"),
     ("round_to_bits truncates", "const double r = nearbyint(ldexp(m, p));", "const double r = trunc(ldexp(m, p));"),
     ("stored two-class skips rounding b", "b = orc_round_to_bits(mean2 - b, p);", "b = mean2 - b;"),
+    ("phase diffusion conjugates its phase", "const orc_c e = c_expi(theta);", "const orc_c e = c_expi(-theta);"),
+    ("phase oracle conjugates its phase", "const orc_c e = c_expi(phi);", "const orc_c e = c_expi(-phi);"),
+    ("phase diffusion mean over N/2", "const orc_c mean = {re / ldexp(1.0, (int)n), im / ldexp(1.0, (int)n)};\n    const orc_c e",
+     "const orc_c mean = {re / ldexp(1.0, (int)n - 1), im / ldexp(1.0, (int)n)};\n    const orc_c e"),
+    ("adjoint theta gradient sign", "dtheta[jj] = 2.0 * g.re;", "dtheta[jj] = -2.0 * g.re;"),
+    ("adjoint forgets to undo the oracle", "orc_phase_oracle(lam, k, m, -phi[jj]);", "orc_phase_oracle(lam, k, m, phi[jj]);"),
+    ("adjoint applies D instead of its inverse", "orc_phase_diffusion(n, lam, -theta[jj]);",
+     "orc_phase_diffusion(n, lam, theta[jj]);"),
+    ("adjoint phi gradient takes the real product", "s += t.re;", "s += t.im;"),
+    ("tangent theta term conjugated", "t[2 * i + 1] += g.im;", "t[2 * i + 1] -= g.im;"),
+    ("tangent phi term skips the diffusion", "        orc_phase_diffusion(n, w, theta[j]);\n", "\n"),
+    ("loss derivative sign", "return -2.0 * s;", "return 2.0 * s;"),
+    ("phase loss drops the imaginary part",
+     "p += psi[2 * k[q]] * psi[2 * k[q]] + psi[2 * k[q] + 1] * psi[2 * k[q] + 1];",
+     "p += psi[2 * k[q]] * psi[2 * k[q]];"),
     ("hash marks listed from index 1", "for (uint64_t i = 0; i < N; ++i) {\n        if ((orc_splitmix64",
      "for (uint64_t i = 1; i < N; ++i) {\n        if ((orc_splitmix64"),
 ]
@@ -103,6 +119,12 @@ def battery(orc) -> None:
     pins.test_round_to_bits_bfloat16_brute_force(orc)
     pins.test_two_class_stored_at_53_bits_is_two_class(orc, 10, 1, 25)
     pins.test_two_class_stored_binary32_matches_float32_full_state(orc)
+    phase.test_phases_at_pi_are_the_standard_iteration(orc)
+    phase.test_fig2_through_the_generalized_iteration(orc)
+    phase.test_dense_matrices_and_torch_autograd(orc, 5, [1, 30], 5, 2)
+    phase.test_two_amplitude_reduction_in_50_digits(orc)
+    phase.test_inverses_and_unitarity(orc)
+    phase.test_tangent_and_adjoint_agree(orc)
 
 
 def test_battery_passes_on_the_committed_oracle(orc):

@@ -182,7 +182,56 @@ class BatchWorkload:
         marks = [distinct_marks(int(n[b]), int(m[b]), int(s[3 * b + 2])) for b in range(self.count)]
         return n, m, marks
 
+    def write_instances(self, path: str) -> None:
+        """One line per instance, "n m mark_1 ... mark_m" (the native driver's batch input format)."""
+        n, m, marks = self.instances()
+        with open(path, "w") as f:
+            for b in range(self.count):
+                f.write(" ".join([str(int(n[b])), str(int(m[b]))] + [str(int(x)) for x in marks[b]]) + "\n")
+
 
 # 4096 searches, n uniform in [8, 20], M uniform in [1, 8].
 BATCH_4096 = BatchWorkload(name="batch4096_n8to20_m1to8_c64", count=4096, n_min=8, n_span=13, m_max=8,
                            seed=0x4096C3B5)
+
+
+def normal_pairs(seed: int, count: int) -> np.ndarray:
+    """`count` standard normal variates: Box-Muller on consecutive pairs of 53-bit uniforms of SplitMix64."""
+    pairs = (count + 1) // 2
+    u = (splitmix64(seed, 2 * pairs) >> np.uint64(11)).astype(np.float64) * 2.0 ** -53
+    u1, u2 = u[0::2], u[1::2]
+    r = np.sqrt(-2.0 * np.log1p(-u1))
+    z = np.empty(2 * pairs)
+    z[0::2] = r * np.cos(2.0 * np.pi * u2)
+    z[1::2] = r * np.sin(2.0 * np.pi * u2)
+    return z[:count]
+
+
+def phase_schedule(K: int, seed: int, spread: float = 0.1, batch: int = 1):
+    """Per-iteration phases phi, theta ~ N(pi, spread^2), shape (batch, K) each (float64)."""
+    z = normal_pairs(seed, 2 * batch * K).reshape(batch, 2, K)
+    return np.pi + spread * z[:, 0, :], np.pi + spread * z[:, 1, :]
+
+
+@dataclasses.dataclass(frozen=True)
+class PhaseWorkload:
+    """A batch of phase schedules for the generalized iteration: n qubits, m marked indices drawn from
+    `seed`, K iterations, `batch` schedules with phi, theta ~ N(pi, spread^2) drawn from `seed + 1`."""
+
+    name: str
+    n: int
+    m: int
+    K: int
+    batch: int
+    spread: float
+    seed: int
+
+    def marks(self) -> np.ndarray:
+        return distinct_marks(self.n, self.m, self.seed)
+
+    def schedules(self):
+        return phase_schedule(self.K, self.seed + 1, self.spread, self.batch)
+
+
+# Differentiable generalized search: n = 20, M = 3, K = 64 iterations, 64 schedules, phases N(pi, 0.1).
+PHASE_N20 = PhaseWorkload(name="phase_n20_m3_k64_b64", n=20, m=3, K=64, batch=64, spread=0.1, seed=0x5EED2005)
