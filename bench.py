@@ -5,6 +5,7 @@ per Grover iteration at n = 28, against the plain binary64 form.
     python bench.py --sweep table1      (the paper's Table 1 sizes: proposed vs gate-level, one line each)
     python bench.py --sweep precision   (storage x accumulator of the mean at n = 26, one line each)
     python bench.py --sweep batch       (4096 independent searches: tilings, the tuned graph, one-by-one)
+    python bench.py --sweep adjoint     (generalized iteration with phases: forward + adjoint gradient)
 
 Workload (synthetic by construction; the paper uses no dataset): the single large instance, n = 28
 (2^28 complex64 amplitudes, 2 GiB), M = 8 marked indices defined by the hash predicate
@@ -43,8 +44,7 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, public datasheet
 TRAFFIC_SUMMARY = os.path.join(ROOT, "profiles", "fused_iterate_n28_c64_traffic.txt")
-KERNEL_SOURCES = [os.path.join(ROOT, "paper_2005_04635_amd", "csrc", f)
-                  for f in ("k_fused.hip", "stream.h", "internal.h")]
+KERNEL_SOURCES = [os.path.join(ROOT, "paper_2005_04635_amd", "csrc", f) for f in ("k_fused.hip", "internal.h")]
 PAPER_CPU_N20_UPDATES_PER_S = 1048576 * 804 / 20.005  # Table 1, proposed simulator, n = 20, i3-5005U 1 thread
 
 
@@ -380,6 +380,101 @@ def sweep_batch(pkg, hip, stream, runs: int) -> None:
     }), flush=True)
 
 
+def sweep_adjoint(pkg, hip, stream, runs: int) -> None:
+    """The differentiable workload (n = 20, M = 3, K = 64 iterations, 64 phase schedules ~ N(pi, 0.1)):
+    forward runs (loss) and adjoint runs (gradient) timed with HIP events on the context's stream, their
+    amplitude rates and algorithmic HBM bandwidth, accuracy against the binary64 oracle on two schedules,
+    and the plain binary64 GPU form (standard iteration, complex128, separate kernels) at the same n for
+    comparison.  One JSON line."""
+    import numpy as np
+
+    import oracle
+    import workloads
+
+    g = pkg.grover
+    w = workloads.PHASE_N20
+    marks = np.ascontiguousarray(w.marks(), dtype=np.uint64)
+    phi, theta = w.schedules()
+    cfg = g.grover_phase_config()
+    cfg.n, cfg.batch, cfg.iterations, cfg.dtype = w.n, w.batch, w.K, g.GROVER_C64
+    cfg.m = marks.size
+    cfg.marked = marks.ctypes.data_as(ctypes.POINTER(ctypes.c_uint64))
+    p = pkg.grover_phase_init(cfg, stream.value)
+    every, nck = pkg.grover_phase_query(p, g.PQ_EVERY), pkg.grover_phase_query(p, g.PQ_CHECKPOINTS)
+    team, grid = pkg.grover_phase_query(p, g.PQ_TEAM), pkg.grover_phase_query(p, g.PQ_GRID)
+    B, K, N = w.batch, w.K, 1 << w.n
+    nbytes = B * K * 8
+    bufs = {name: hip.malloc(size) for name, size in
+            (("phi", nbytes), ("theta", nbytes), ("loss", B * 8), ("dloss", B * 8), ("dphi", nbytes),
+             ("dtheta", nbytes))}
+    ones = np.ones(B)
+    for name, arr in (("phi", phi), ("theta", theta), ("dloss", ones)):
+        a = np.ascontiguousarray(arr, dtype=np.float64)
+        hip.ok(hip.lib.hipMemcpy(bufs[name], ctypes.c_void_p(a.ctypes.data), a.nbytes, 1), "hipMemcpy H2D")
+
+    def fwd():
+        pkg.grover_phase_forward(p, bufs["phi"].value, bufs["theta"].value, bufs["loss"].value)
+
+    def bwd():
+        pkg.grover_phase_backward(p, bufs["dloss"].value, bufs["dphi"].value, bufs["dtheta"].value)
+
+    fwd()
+    bwd()
+    pkg.grover_phase_sync(p)
+    f_ms, b_ms = [], []
+    for _ in range(runs):
+        e = [hip.event() for _ in range(3)]
+        hip.lib.hipEventRecord(e[0], stream)
+        fwd()
+        hip.lib.hipEventRecord(e[1], stream)
+        bwd()
+        hip.lib.hipEventRecord(e[2], stream)
+        f_ms.append(hip.elapsed_ms(e[0], e[1]))
+        b_ms.append(hip.elapsed_ms(e[1], e[2]))
+        pkg.grover_phase_sync(p)
+    fm, bm = sorted(f_ms)[len(f_ms) // 2], sorted(b_ms)[len(b_ms) // 2]
+    # results of the last timed pair
+    fwd()
+    pkg.grover_phase_sync(p)
+    loss = np.empty(B)
+    hip.ok(hip.lib.hipMemcpy(ctypes.c_void_p(loss.ctypes.data), bufs["loss"], B * 8, 2), "hipMemcpy D2H")
+    bwd()
+    pkg.grover_phase_sync(p)
+    dphi, dtheta = np.empty((B, K)), np.empty((B, K))
+    hip.ok(hip.lib.hipMemcpy(ctypes.c_void_p(dphi.ctypes.data), bufs["dphi"], nbytes, 2), "hipMemcpy D2H")
+    hip.ok(hip.lib.hipMemcpy(ctypes.c_void_p(dtheta.ctypes.data), bufs["dtheta"], nbytes, 2), "hipMemcpy D2H")
+    pkg.grover_phase_destroy(p)
+    for b_ in bufs.values():
+        hip.lib.hipFree(b_)
+    orc = oracle.default()
+    acc = []
+    for b in (0, B - 1):
+        want_loss = orc.phase_loss(orc.phase_search(w.n, marks, phi[b], theta[b]), marks)
+        wphi, wtheta = orc.phase_grad_adjoint(w.n, marks, phi[b], theta[b])
+        acc.append({"schedule": b, "loss": loss[b], "loss_abs_err": abs(loss[b] - want_loss),
+                    "grad_max_abs_err": float(max(np.max(np.abs(dphi[b] - wphi)), np.max(np.abs(dtheta[b] - wtheta)))),
+                    "grad_max_abs": float(max(np.max(np.abs(wphi)), np.max(np.abs(wtheta))))})
+    plain = time_form(pkg, hip, stream, w.n, "c128", "two_pass", marks, 300, 48, 0)
+    fwd_bytes = B * (8.0 * N + 16.0 * N * K + 8.0 * N * nck)
+    bwd_bytes = B * (8.0 * N + 32.0 * N * K)
+    updates = float(B) * K * N
+    print(json.dumps({
+        "sweep": "adjoint", "workload": w.name, "n": w.n, "m": w.m, "K": K, "batch": B, "storage": "complex64",
+        "arithmetic": "f64", "checkpoint_every": every, "checkpoints_per_schedule": nck, "team": team, "grid": grid,
+        "forward_ms": round(fm, 3), "adjoint_ms": round(bm, 3),
+        "forward_amplitude_updates_per_s": updates / (fm / 1e3),
+        "adjoint_amplitude_steps_per_s": updates / (bm / 1e3),
+        "forward_algorithmic_gbs": round(fwd_bytes / (fm / 1e3) / 1e9, 1),
+        "adjoint_algorithmic_gbs": round(bwd_bytes / (bm / 1e3) / 1e9, 1),
+        "forward_frac_of_hbm_peak": round(fwd_bytes / (fm / 1e3) / 1e9 / HBM_PEAK_GBS, 4),
+        "adjoint_frac_of_hbm_peak": round(bwd_bytes / (bm / 1e3) / 1e9 / HBM_PEAK_GBS, 4),
+        "plain_fp64_amplitude_updates_per_s": plain["amplitude_updates_per_s"],
+        "forward_vs_plain_fp64": (updates / (fm / 1e3)) / plain["amplitude_updates_per_s"],
+        "forward_plus_adjoint_vs_plain_fp64_forward_only":
+            (updates / ((fm + bm) / 1e3)) / plain["amplitude_updates_per_s"],
+        "accuracy_vs_fp64_oracle": acc, "runs": runs}), flush=True)
+
+
 def main() -> int:
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -388,7 +483,7 @@ def main() -> int:
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-forms", action="store_true")
     ap.add_argument("--cpu-iters", type=int, default=8)
-    ap.add_argument("--sweep", choices=["table1", "precision", "batch"], default=None,
+    ap.add_argument("--sweep", choices=["table1", "precision", "batch", "adjoint"], default=None,
                     help="instead of the headline line, print one JSON line per point of a sweep")
     args = ap.parse_args()
     if args.gpus != 1:
@@ -414,6 +509,9 @@ def main() -> int:
         return 0
     if args.sweep == "batch":
         sweep_batch(pkg, hip, stream, max(args.steps, 1))
+        return 0
+    if args.sweep == "adjoint":
+        sweep_adjoint(pkg, hip, stream, max(args.steps, 1))
         return 0
     w = workloads.HASH_N28
     N = 1 << w.n

@@ -259,6 +259,69 @@ void grover_batch_destroy(grover_batch *b);
 /* grover_batch_last_error — message of the last failure on b (a static message when b is NULL). */
 const char *grover_batch_last_error(const grover_batch *b);
 
+/* ------------------------------------------------------------ generalized iteration and its adjoint
+ * A generalization of Algorithm 5 with a phase per iteration (a convention of this library; at
+ * phi = theta = pi it is the paper's iteration): iteration j = 1 .. K applies
+ *   O(phi_j):   c_i <- e^{i phi_j} c_i on the marked indices (Algorithm 3 at phi = pi), then
+ *   D(theta_j): c_i <- (1 - e^{i theta_j}) S / N - c_i, S = sum_i c_i  (Eq. 2 at theta = pi),
+ * from the uniform superposition, and the loss is L = 1 - sum over marked i of |c_i|^2.  A context runs
+ * B schedules (phi, theta of shape [B][K]) over the same marked set, each on its own complex64 state
+ * (binary64 phases, sums and element arithmetic).
+ * The gradient dL/dphi, dL/dtheta comes from a reverse sweep that rebuilds each earlier state with the
+ * inverse steps D(-theta), O(-phi) while carrying the adjoint state back, and re-reads the state from a
+ * checkpoint every `checkpoint_every` iterations (stored by the forward run), so memory is
+ * (2 + floor((K - 1) / checkpoint_every)) states per schedule rather than K + 1. */
+typedef struct grover_phase grover_phase;
+
+typedef struct grover_phase_config {
+    uint32_t n;                /* qubits, 1 <= n <= 30 */
+    uint32_t batch;            /* schedules B >= 1 */
+    uint32_t iterations;       /* K >= 1 */
+    uint32_t checkpoint_every; /* checkpoint interval s >= 1; 0 = round(sqrt(K)) */
+    const uint64_t *marked;    /* host, m distinct indices < 2^n (any order); NULL when m = 0 */
+    uint64_t m;
+    uint32_t dtype;            /* GROVER_C64 (other types: GROVER_E_UNSUPPORTED) */
+    uint32_t flags;            /* must be 0 */
+} grover_phase_config;
+
+/* grover_phase_init — validate cfg (GROVER_E_INVAL before any device work), allocate the states, adjoint
+ * states and checkpoints, and confirm the persistent grid on the device.  All work goes to hip_stream
+ * (NULL = default stream).  Synchronous. */
+int grover_phase_init(grover_phase **out, const grover_phase_config *cfg, void *hip_stream);
+
+/* grover_phase_set_team — workgroups per schedule (1 .. grid size; default: grid / B, at most the number of
+ * 64 KiB tiles of one state).  Changes the order of additions in the sums, not the results' meaning. */
+int grover_phase_set_team(grover_phase *p, uint32_t team);
+
+/* grover_phase_forward — run all B schedules.  phi, theta: device, binary64 [B][K] row-major (copied on
+ * the stream before the run, so the caller may reuse them afterwards); loss: device, binary64 [B], written.
+ * Leaves each schedule's final state in the context (grover_phase_state) with its checkpoints.
+ * Asynchronous. */
+int grover_phase_forward(grover_phase *p, const double *phi, const double *theta, double *loss);
+
+/* grover_phase_backward — the gradient of sum_b dloss[b] * L_b at the phases of the last forward run:
+ * dloss: device binary64 [B]; dphi, dtheta: device binary64 [B][K], written.  Needs a forward run since
+ * the last backward (GROVER_E_INVAL otherwise): the sweep overwrites the states, which afterwards hold the
+ * uniform superposition.  Asynchronous. */
+int grover_phase_backward(grover_phase *p, const double *dloss, double *dphi, double *dtheta);
+
+/* grover_phase_sync — wait for the stream; GROVER_E_TIMEOUT when a team barrier gave up. */
+int grover_phase_sync(grover_phase *p);
+
+/* grover_phase_state / grover_phase_read_state — device address and size (2^n * 8 bytes) of schedule
+ * b's state; copy it to host memory (synchronises the stream; bytes must equal the size). */
+int grover_phase_state(grover_phase *p, uint32_t b, void **dev_ptr, size_t *bytes);
+int grover_phase_read_state(grover_phase *p, uint32_t b, void *host, size_t bytes);
+
+/* grover_phase_query — key: 0 = B, 1 = persistent grid size, 2 = workgroups per schedule, 3 = checkpoint
+ * interval, 4 = stored checkpoints per schedule, 5 = device bytes held. */
+int grover_phase_query(grover_phase *p, int key, int64_t *value);
+
+/* grover_phase_destroy — wait for the stream and release everything (NULL is ignored);
+ * grover_phase_last_error — the last failure message (a static message when p is NULL). */
+void grover_phase_destroy(grover_phase *p);
+const char *grover_phase_last_error(const grover_phase *p);
+
 #ifdef __cplusplus
 }
 #endif

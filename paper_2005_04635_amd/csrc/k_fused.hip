@@ -17,13 +17,15 @@
 // accumulation, which makes iterate(a); iterate(b) equal iterate(a + b) bit for bit.
 //
 // Template parameters: T = storage type (F64Real, C64, C128, CBF16), A = accumulator of the sum (AccF64,
-// AccF32, AccF32Kahan; the grid tree runs in A's precision).  The update itself is always binary64.  The
-// streaming pass and the barrier are shared with the batched kernel (stream.h); here the whole grid is
-// one team.
-#include "stream.h"
+// AccF32, AccF32Kahan; the grid tree runs in A's precision).  The update itself is always binary64.
+#include "internal.h"
 
 namespace grover {
 namespace {
+
+constexpr int kBlock = 1024;  // one workgroup per CU: fewest barrier participants, 16 waves per CU
+constexpr int kUnroll = 4;    // 16-byte vectors per thread per tile
+constexpr int kTile = kBlock * kUnroll;
 
 struct FusedArgs {
     void *state;
@@ -38,30 +40,245 @@ struct FusedArgs {
     uint64_t timeout_ticks;
 };
 
+template <class V>
+struct Shared {
+    V red[2 * (kBlock / kWave)];
+    V sum[2];
+    int last;
+    int abort;
+};
+
+__device__ inline uint32_t *arrive_word(GridSync *s, unsigned p) { return p ? &s->arrive1 : &s->arrive0; }
+
+__device__ inline uint64_t load_bits(const uint64_t *p)
+{
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+__device__ inline void store_bits(uint64_t *p, double x)
+{
+    __hip_atomic_store(p, (uint64_t)__double_as_longlong(x), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// Grid-wide sum of (xr, xi) for barrier generation `gen`, in the arithmetic of V (binary64 or binary32;
+// partials travel as binary64, which holds a binary32 exactly).  Returns false when the wait gave up
+// (timeout, or another workgroup gave up); every thread of the workgroup gets the same answer and the sum
+// in (xr, xi).
+//
+// Memory ordering: a workgroup publishes its partial and then increments the arrival counter with release
+// semantics; the workgroup whose increment completes the count acquires, adds the partials in workgroup
+// order, stores the sum and releases the generation flag; the others poll the flag with relaxed loads and
+// acquire once it has advanced.  Acquire/release at agent scope make the data visible across the XCDs'
+// separate L2s.  (Letting every workgroup poll the counter and add the partials itself was measured
+// slower on MI355X: the polls contend with the increments.)
+template <class V>
+__device__ bool grid_sum(V &xr, V &xi, const FusedArgs &a, uint64_t gen, Shared<V> &sh)
+{
+    const unsigned p = unsigned(gen & 1u);
+    block_sum2(xr, xi, sh.red);
+    if (threadIdx.x == 0) {
+        uint64_t *dst = a.partials + (uint64_t(p) * gridDim.x + blockIdx.x) * 2u;
+        store_bits(dst, double(xr));
+        store_bits(dst + 1, double(xi));
+        const unsigned old =
+            __hip_atomic_fetch_add(arrive_word(a.sync, p), 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+        sh.last = (old == gridDim.x - 1u);
+        sh.abort = 0;
+    }
+    __syncthreads();
+    if (sh.last) {
+        // Every partial of this barrier is published.  Add them in workgroup order.
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+        V sr = V(0), si = V(0);
+        for (unsigned w = threadIdx.x; w < gridDim.x; w += kBlock) {
+            const uint64_t *src = a.partials + (uint64_t(p) * gridDim.x + w) * 2u;
+            sr += V(__longlong_as_double((long long)load_bits(src)));
+            si += V(__longlong_as_double((long long)load_bits(src + 1)));
+        }
+        block_sum2(sr, si, sh.red);
+        if (threadIdx.x == 0) {
+            store_bits(&a.sync->sum[p][0], double(sr));
+            store_bits(&a.sync->sum[p][1], double(si));
+            __hip_atomic_store(arrive_word(a.sync, p), 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            __hip_atomic_store(&a.sync->flag, gen, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+            sh.sum[0] = sr;
+            sh.sum[1] = si;
+        }
+    } else if (threadIdx.x == 0) {
+        const uint64_t t0 = wall_clock64();
+        bool ok = true;
+        while (__hip_atomic_load(&a.sync->flag, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < gen) {
+            if (__hip_atomic_load(&a.sync->error, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0u) {
+                ok = false;
+                break;
+            }
+            if (uint64_t(wall_clock64()) - t0 > a.timeout_ticks) {
+                __hip_atomic_store(&a.sync->error, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                ok = false;
+                break;
+            }
+            __builtin_amdgcn_s_sleep(2);
+        }
+        if (ok) {
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+            sh.sum[0] = V(__longlong_as_double((long long)load_bits(&a.sync->sum[p][0])));
+            sh.sum[1] = V(__longlong_as_double((long long)load_bits(&a.sync->sum[p][1])));
+        } else {
+            sh.abort = 1;
+        }
+    }
+    __syncthreads();
+    const bool ok = sh.abort == 0;
+    xr = sh.sum[0];
+    xi = sh.sum[1];
+    __syncthreads();  // sh is reused by the next barrier
+    return ok;
+}
+
+// First index q >= start with marks[q] >= x in the sorted list marks[0, m), given that every entry before
+// `start` is < x: exponential steps from `start`, then a binary search in the last step.  Tiles are visited
+// in increasing order, so each search starts where the previous tile's ended and costs O(log gap).
+__device__ inline uint64_t gallop_lower_bound(const uint64_t *marks, uint64_t start, uint64_t m, uint64_t x)
+{
+    if (start >= m || marks[start] >= x)
+        return start;
+    uint64_t lo = start, step = 1;  // invariant: marks[lo] < x
+    while (lo + step < m && marks[lo + step] < x) {
+        lo += step;
+        step <<= 1;
+    }
+    const uint64_t hi = lo + step < m ? lo + step : m;
+    return lower_bound_u64(marks, lo + 1, hi, x);
+}
+
+// Marks of one tile held in registers: up to kTileMarks entries of the sorted slice marks[lo, hi), padded
+// with ~0 (never equal to an amplitude index).  Longer slices fall back to a binary search per vector.
+constexpr int kTileMarks = 8;
+
+template <int EPV>
+__device__ inline unsigned bits_from_regs(const uint64_t (&mk)[kTileMarks], uint64_t i)
+{
+    unsigned bits = 0;
+#pragma unroll
+    for (int q = 0; q < kTileMarks; ++q) {
+        const uint64_t d = mk[q] - i;  // wraps to a huge value when mk[q] < i
+        bits |= d < uint64_t(EPV) ? 1u << unsigned(d) : 0u;
+    }
+    return bits;
+}
+
+constexpr int kMarkWords = 1024;  // LDS bitmap of this workgroup's tiles that hold marked amplitudes
+
+// One pass over this workgroup's tiles t = blockIdx.x + j G, j = 0, 1, ... (G = gridDim.x).  At any moment
+// the grid streams one contiguous window of the state, spread over all HBM channels, while each tile still
+// belongs to the same workgroup (hence XCD) in every iteration.  (Alternating the direction between passes,
+// to start on lines the memory-side cache might still hold, measured no faster on MI355X.)  UPDATE:
+// c' = 2S/N - s c written back and s c' summed; otherwise s c summed.  The per-thread order of the sum is
+// identical in both modes.  `slow_tiles` (when `table`) flags the workgroup's tiles holding marked
+// amplitudes; without a table every tile is checked against the marked list.  Loads and stores carry the
+// nontemporal hint (+6 % measured on MI355X).
+template <class T, class A, bool UPDATE>
+__device__ inline void chunk_pass(const FusedArgs &a, const uint32_t *slow_tiles, bool table, double mr, double mi,
+                                  A &acc)
+{
+    using V = typename T::vec;
+    V *st = static_cast<V *>(a.state);
+    const unsigned tid = threadIdx.x;
+    const uint64_t ntiles = (a.nvec + kTile - 1) / kTile;
+    const uint64_t cnt = blockIdx.x < ntiles ? (ntiles - blockIdx.x + gridDim.x - 1) / gridDim.x : 0;
+    uint64_t mp = 0;  // marked entries before this position lie in tiles already visited
+    for (uint64_t j = 0; j < cnt; ++j) {
+        const uint64_t t = blockIdx.x + j * gridDim.x;
+        const uint64_t v0 = t * kTile;
+        const bool full = v0 + kTile <= a.nvec;
+        const bool marked = table ? ((slow_tiles[j >> 5] >> (j & 31)) & 1u) != 0u : a.m > 0;
+        if (full && !marked) {
+            V x[kUnroll];
+#pragma unroll
+            for (int u = 0; u < kUnroll; ++u)
+                x[u] = load16<true>(st + v0 + u * kBlock + tid);
+#pragma unroll
+            for (int u = 0; u < kUnroll; ++u) {
+                if (UPDATE) {
+                    update_vec<T>(x[u], mr, mi, 0u, acc);
+                    store16<true>(x[u], st + v0 + u * kBlock + tid);
+                } else {
+                    accum_vec<T>(x[u], 0u, acc);
+                }
+            }
+        } else {
+            // Ragged tail of the state, or a tile that may hold marked amplitudes: the same vector loads,
+            // then each amplitude's sign from the tile's slice [mp, mq) of the sorted marked list.
+            mp = gallop_lower_bound(a.marks, mp, a.m, v0 * T::EPV);
+            const uint64_t mq = gallop_lower_bound(a.marks, mp, a.m, (v0 + kTile) * T::EPV);
+            const bool in_regs = mq - mp <= uint64_t(kTileMarks);
+            uint64_t mk[kTileMarks];
+#pragma unroll
+            for (int q = 0; q < kTileMarks; ++q)
+                mk[q] = in_regs && mp + q < mq ? a.marks[mp + q] : ~uint64_t(0);
+            V x[kUnroll];
+#pragma unroll
+            for (int u = 0; u < kUnroll; ++u) {
+                const uint64_t v = v0 + u * kBlock + tid;
+                if (v < a.nvec)
+                    x[u] = load16<true>(st + v);
+            }
+#pragma unroll
+            for (int u = 0; u < kUnroll; ++u) {
+                const uint64_t v = v0 + u * kBlock + tid;
+                if (v < a.nvec) {
+                    const unsigned bits = in_regs ? bits_from_regs<T::EPV>(mk, v * T::EPV)
+                                                  : marked_bits<T::EPV>(a.marks, mp, mq, v * T::EPV);
+                    if (UPDATE) {
+                        update_vec<T>(x[u], mr, mi, bits, acc);
+                        store16<true>(x[u], st + v);
+                    } else {
+                        accum_vec<T>(x[u], bits, acc);
+                    }
+                }
+            }
+            mp = mq;
+        }
+    }
+}
+
 // CHECK only names a second, code-identical instantiation used for the residency check at context
 // creation, so that profiles list it apart from the iteration launches.
 template <class T, class A, bool CHECK>
-__global__ __launch_bounds__(kStreamBlock) void fused_iterate_kernel(FusedArgs a)
+__global__ __launch_bounds__(kBlock) void fused_iterate_kernel(FusedArgs a)
 {
     using Val = typename A::value;
-    __shared__ TeamShared<Val> sh;
-    __shared__ uint32_t table[kMarkWords];
-    const Team team{a.sync, a.partials, gridDim.x, blockIdx.x, a.timeout_ticks};
-    const Share<T> share{static_cast<typename T::vec *>(a.state), a.nvec, a.marks, a.m, blockIdx.x, gridDim.x};
-    const bool use_table = build_mark_table(share, table);
-    const typename T::vec none{};
+    __shared__ Shared<Val> sh;
+    __shared__ uint32_t slow_tiles[kMarkWords];
+    // Table of this workgroup's tiles that hold marked amplitudes, built once per launch.
+    const uint64_t ntiles = (a.nvec + kTile - 1) / kTile;
+    const uint64_t cnt = blockIdx.x < ntiles ? (ntiles - blockIdx.x + gridDim.x - 1) / gridDim.x : 0;
+    const bool table = cnt <= uint64_t(kMarkWords) * 32u && a.m <= uint64_t(64) * kBlock;
+    if (table) {
+        for (unsigned w = threadIdx.x; w < kMarkWords; w += kBlock)
+            slow_tiles[w] = 0u;
+        __syncthreads();
+        for (uint64_t q = threadIdx.x; q < a.m; q += kBlock) {
+            const uint64_t t = a.marks[q] / T::EPV / kTile;
+            if (t % gridDim.x == blockIdx.x) {
+                const uint64_t j = t / gridDim.x;
+                atomicOr(&slow_tiles[j >> 5], 1u << (j & 31));
+            }
+        }
+        __syncthreads();
+    }
     A acc0;
-    stream_pass<T, A, kAccumulate>(share, table, use_table, 0.0, 0.0, none, acc0);
+    chunk_pass<T, A, false>(a, slow_tiles, table, 0.0, 0.0, acc0);
     Val sr = acc0.res_r(), si = acc0.res_i();
-    if (!team_sum<Val>(sr, si, team, a.gen0 + 1u, sh))
+    if (!grid_sum<Val>(sr, si, a, a.gen0 + 1u, sh))
         return;
     for (uint64_t it = 0; it < a.iters; ++it) {
         const double mr = (double(sr) * 2.0) / a.N, mi = (double(si) * 2.0) / a.N;
         A acc;
-        stream_pass<T, A, kUpdate>(share, table, use_table, mr, mi, none, acc);
+        chunk_pass<T, A, true>(a, slow_tiles, table, mr, mi, acc);
         sr = acc.res_r();
         si = acc.res_i();
-        if (!team_sum<Val>(sr, si, team, a.gen0 + 2u + it, sh))
+        if (!grid_sum<Val>(sr, si, a, a.gen0 + 2u + it, sh))
             return;
     }
 }
@@ -98,17 +315,17 @@ hipError_t fused_configure(grover_ctx *c, int *per_cu, int *block, int64_t *forc
         return hipErrorInvalidValue;
     c->fused_kernel = k;
     c->fused_check_kernel = kernel_for<true>(c->dtype, c->accum);
-    c->fused_tile = kStreamTile;
+    c->fused_tile = kTile;
     int coop = 0;
     hipError_t e = hipDeviceGetAttribute(&coop, hipDeviceAttributeCooperativeLaunch, c->device);
     if (e != hipSuccess)
         return e;
     if (!coop)
         return hipErrorCooperativeLaunchTooLarge;
-    e = hipOccupancyMaxActiveBlocksPerMultiprocessor(per_cu, k, kStreamBlock, 0);
+    e = hipOccupancyMaxActiveBlocksPerMultiprocessor(per_cu, k, kBlock, 0);
     if (e != hipSuccess)
         return e;
-    *block = kStreamBlock;
+    *block = kBlock;
     *forced_grid = 0;
     if (const char *env = getenv("GROVER_FUSED_GRID")) {
         const long long want = atoll(env);

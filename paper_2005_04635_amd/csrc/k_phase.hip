@@ -1,0 +1,509 @@
+// Generalized iteration with per-iteration phases, and its adjoint (reverse sweep) for the gradient.
+//
+// Iteration j (1 .. K) of schedule b applies O(phi_j) then D(theta_j), with
+//   O(phi):   c_i <- e^{i phi} c_i on the marked indices (Algorithm 3 is phi = pi),
+//   D(theta): c_i <- (1 - e^{i theta}) S / N - c_i with S the sum of the state (Eq. 2 is theta = pi),
+// from the uniform superposition; the loss is L = 1 - sum over marked i of |c_i|^2.
+//
+// Forward: one pass per iteration, fused as in the plain kernel: the pass that writes c' = alpha - O c also
+// accumulates the sum T of c' and the sum Mk of its marked entries, so the next iteration's
+// S = sum O(phi') c' = T + (e^{i phi'} - 1) Mk needs no extra pass.  Every `every`-th state is also written
+// to a checkpoint buffer.
+//
+// Adjoint: lambda = dL/d(conj c) starts as -g c on the marked entries (g = upstream gradient of L) and is
+// carried back through the inverses of the unitary steps, D(theta)^-1 = D(-theta) and O(phi)^-1 = O(-phi),
+// while the state is rebuilt backwards with the same inverses.  Step j needs the sums of c_j and
+// lambda_j and yields, with y = O(phi_j) c_{j-1} = D(-theta_j) c_j and nu = D(-theta_j) lambda_j,
+//   dL/dtheta_j = -2 Im( conj(sum lambda_j) * sum c_j ) / N,
+//   dL/dphi_j   = -2 Im( sum over marked of conj(nu) * y ),
+//   c_{j-1} = O(-phi_j) y,  lambda_{j-1} = O(-phi_j) nu,
+// all in one pass that also accumulates the sums for step j - 1.  Where j - 1 is a checkpoint the state is
+// re-read from it (the uniform state for j - 1 = 0) instead of being rebuilt, which bounds the drift of the
+// rebuilt state to `every` steps.
+//
+// Storage is complex64 (float re, im); phases, sums and the element arithmetic are binary64.  A team of
+// `team_size` workgroups iterates one schedule at a time, with one team barrier per iteration that also
+// reduces six binary64 values; teams take schedules b = team, team + teams, ...
+#include "phase.h"
+#include "stream.h"
+
+namespace grover {
+namespace {
+
+constexpr int kPV = 6;  // values a barrier reduces
+
+struct C2 {
+    double re, im;
+};
+
+__device__ inline C2 cmul(C2 a, C2 b) { return {a.re * b.re - a.im * b.im, a.re * b.im + a.im * b.re}; }
+
+struct PhaseShared {
+    double red[kPV * (kStreamBlock / kWave)];
+    double sum[kPV];
+    int last;
+    int abort;
+};
+
+struct PhaseTeam {
+    PhaseSync *sync;
+    uint64_t *partials;  // [2][size][8] binary64 bit patterns
+    unsigned size;
+    unsigned rank;
+    uint64_t timeout_ticks;
+};
+
+// Workgroup sum of v[0 .. kPV): wave butterflies, then thread 0 adds the wave values in wave order.
+__device__ inline void block_sum_n(double (&v)[kPV], PhaseShared &sh)
+{
+    const int lane = threadIdx.x % kWave, wave = threadIdx.x / kWave, nw = blockDim.x / kWave;
+#pragma unroll
+    for (int q = 0; q < kPV; ++q)
+        v[q] = wave_sum(v[q]);
+    if (lane == 0) {
+#pragma unroll
+        for (int q = 0; q < kPV; ++q)
+            sh.red[q * (kStreamBlock / kWave) + wave] = v[q];
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+#pragma unroll
+        for (int q = 0; q < kPV; ++q) {
+            double s = 0.0;
+            for (int w = 0; w < nw; ++w)
+                s += sh.red[q * (kStreamBlock / kWave) + w];
+            v[q] = s;
+        }
+    }
+    __syncthreads();
+}
+
+// Team-wide sum of v, with the memory ordering of the single-state barrier (publish, release-increment,
+// the completing workgroup acquires, adds in rank order and releases a generation flag; the others poll
+// with relaxed loads under a wall-clock limit).  Every thread gets the sums; false when the wait gave up.
+__device__ bool team_sum_n(double (&v)[kPV], const PhaseTeam &tm, uint64_t gen, PhaseShared &sh)
+{
+    const unsigned p = unsigned(gen & 1u);
+    block_sum_n(v, sh);
+    if (threadIdx.x == 0) {
+        uint64_t *dst = tm.partials + (uint64_t(p) * tm.size + tm.rank) * 8u;
+#pragma unroll
+        for (int q = 0; q < kPV; ++q)
+            store_bits(dst + q, v[q]);
+        uint32_t *arrive = p ? &tm.sync->arrive1 : &tm.sync->arrive0;
+        const unsigned old = __hip_atomic_fetch_add(arrive, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+        sh.last = (old == tm.size - 1u);
+        sh.abort = 0;
+    }
+    __syncthreads();
+    if (sh.last) {
+        if (threadIdx.x == 0) {
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+            double s[kPV] = {};
+            for (unsigned w = 0; w < tm.size; ++w) {
+                const uint64_t *src = tm.partials + (uint64_t(p) * tm.size + w) * 8u;
+#pragma unroll
+                for (int q = 0; q < kPV; ++q)
+                    s[q] += __longlong_as_double((long long)load_bits(src + q));
+            }
+#pragma unroll
+            for (int q = 0; q < kPV; ++q) {
+                store_bits(&tm.sync->sum[p][q], s[q]);
+                sh.sum[q] = s[q];
+            }
+            uint32_t *arrive = p ? &tm.sync->arrive1 : &tm.sync->arrive0;
+            __hip_atomic_store(arrive, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            __hip_atomic_store(&tm.sync->flag, gen, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+        }
+    } else if (threadIdx.x == 0) {
+        const uint64_t t0 = wall_clock64();
+        bool ok = true;
+        while (__hip_atomic_load(&tm.sync->flag, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < gen) {
+            if (__hip_atomic_load(&tm.sync->error, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0u) {
+                ok = false;
+                break;
+            }
+            if (uint64_t(wall_clock64()) - t0 > tm.timeout_ticks) {
+                __hip_atomic_store(&tm.sync->error, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                ok = false;
+                break;
+            }
+            __builtin_amdgcn_s_sleep(2);
+        }
+        if (ok) {
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+#pragma unroll
+            for (int q = 0; q < kPV; ++q)
+                sh.sum[q] = __longlong_as_double((long long)load_bits(&tm.sync->sum[p][q]));
+        } else {
+            sh.abort = 1;
+        }
+    }
+    __syncthreads();
+    const bool ok = sh.abort == 0;
+#pragma unroll
+    for (int q = 0; q < kPV; ++q)
+        v[q] = sh.sum[q];
+    __syncthreads();
+    return ok;
+}
+
+struct PhaseArgs {
+    float4 *state;   // [B][nvec]
+    float4 *lambda;  // [B][nvec]
+    float4 *ckpt;    // [B][nck][nvec]
+    const uint64_t *marks;
+    uint64_t m;
+    uint64_t nvec;
+    double N;
+    float amp;  // uniform amplitude rounded to binary32
+    uint32_t B, K, every, nck;
+    const double *phi, *theta;  // [B][K]
+    double *loss;               // [B]
+    double *aux;                // [B][2] sum of the final state (forward -> adjoint)
+    const double *dloss;        // [B]
+    double *dphi, *dtheta;      // [B][K]
+    PhaseSync *sync;            // one per team
+    uint64_t *partials;         // [teams][2][T][8]
+    uint32_t team_size;
+    uint32_t probe;  // 1: only meet once at a barrier of the whole grid (residency check)
+    uint64_t timeout_ticks;
+};
+
+// Marked entries of one tile: the slice [mp, mq) of the sorted list, held in registers when short.
+struct TileMarks {
+    uint64_t mp, mq;
+    bool in_regs;
+    uint64_t mk[kTileMarks];
+    __device__ void load(const uint64_t *marks, uint64_t m, uint64_t v0)
+    {
+        mp = gallop_lower_bound(marks, mp, m, v0 * 2u);
+        mq = gallop_lower_bound(marks, mp, m, (v0 + kStreamTile) * 2u);
+        in_regs = mq - mp <= uint64_t(kTileMarks);
+#pragma unroll
+        for (int q = 0; q < kTileMarks; ++q)
+            mk[q] = in_regs && mp + q < mq ? marks[mp + q] : ~uint64_t(0);
+    }
+    __device__ unsigned bits(const uint64_t *marks, uint64_t v) const
+    {
+        return in_regs ? bits_from_regs<2>(mk, v * 2u) : marked_bits<2>(marks, mp, mq, v * 2u);
+    }
+};
+
+__device__ inline C2 lo(const float4 &x) { return {double(x.x), double(x.y)}; }
+__device__ inline C2 hi(const float4 &x) { return {double(x.z), double(x.w)}; }
+__device__ inline float4 pack(C2 a, C2 b) { return make_float4(float(a.re), float(a.im), float(b.re), float(b.im)); }
+
+// The team-rank-th share of one state: tiles t = rank + j * size (kStreamTile vectors each).
+__device__ inline uint64_t share_tiles(uint64_t nvec, unsigned rank, unsigned size)
+{
+    const uint64_t nt = (nvec + kStreamTile - 1) / kStreamTile;
+    return rank < nt ? (nt - rank + size - 1) / size : 0;
+}
+
+// Forward pass over a team's share.  mode 0: write the uniform state; mode 1: c' = alpha - O(phi) c.
+// Accumulates v = {sum re, sum im, marked sum re, marked sum im, marked |c|^2, 0} of the values stored.
+__device__ void forward_pass(const PhaseArgs &a, float4 *st, float4 *ck, const PhaseTeam &tm, int mode, C2 alpha,
+                             C2 ephi, double (&v)[kPV])
+{
+    const unsigned tid = threadIdx.x;
+    const uint64_t cnt = share_tiles(a.nvec, tm.rank, tm.size);
+    TileMarks tmk;
+    tmk.mp = 0;
+    for (uint64_t j = 0; j < cnt; ++j) {
+        const uint64_t v0 = (tm.rank + j * tm.size) * uint64_t(kStreamTile);
+        tmk.load(a.marks, a.m, v0);
+        const bool fast = tmk.mq == tmk.mp && v0 + kStreamTile <= a.nvec;
+        float4 x[kStreamUnroll];
+#pragma unroll
+        for (int u = 0; u < kStreamUnroll; ++u) {
+            const uint64_t vi = v0 + u * kStreamBlock + tid;
+            if (fast || vi < a.nvec)
+                x[u] = mode == 0 ? make_float4(a.amp, 0.0f, a.amp, 0.0f) : load16<true>(st + vi);
+        }
+#pragma unroll
+        for (int u = 0; u < kStreamUnroll; ++u) {
+            const uint64_t vi = v0 + u * kStreamBlock + tid;
+            if (!fast && vi >= a.nvec)
+                continue;
+            const unsigned bits = fast ? 0u : tmk.bits(a.marks, vi);
+            float4 out;
+            if (mode == 0) {
+                out = x[u];
+            } else {
+                C2 c0 = lo(x[u]), c1 = hi(x[u]);
+                if (bits & 1u)
+                    c0 = cmul(ephi, c0);
+                if (bits & 2u)
+                    c1 = cmul(ephi, c1);
+                out = pack({alpha.re - c0.re, alpha.im - c0.im}, {alpha.re - c1.re, alpha.im - c1.im});
+            }
+            store16<true>(out, st + vi);
+            if (ck)
+                store16<true>(out, ck + vi);
+            const C2 r0 = lo(out), r1 = hi(out);
+            v[0] += r0.re + r1.re;
+            v[1] += r0.im + r1.im;
+            if (bits & 1u) {
+                v[2] += r0.re;
+                v[3] += r0.im;
+                v[4] += r0.re * r0.re + r0.im * r0.im;
+            }
+            if (bits & 2u) {
+                v[2] += r1.re;
+                v[3] += r1.im;
+                v[4] += r1.re * r1.re + r1.im * r1.im;
+            }
+        }
+        tmk.mp = tmk.mq;
+    }
+}
+
+__global__ __launch_bounds__(kStreamBlock) void phase_forward_kernel(PhaseArgs a)
+{
+    __shared__ PhaseShared sh;
+    const unsigned T = a.team_size, teams = gridDim.x / T, team_id = blockIdx.x / T;
+    if (team_id >= teams)
+        return;
+    const PhaseTeam tm{a.sync + team_id, a.partials + uint64_t(team_id) * 16u * T, T, blockIdx.x % T,
+                       a.timeout_ticks};
+    uint64_t gen = 0;
+    if (a.probe) {
+        double v[kPV] = {};
+        (void)team_sum_n(v, tm, ++gen, sh);
+        return;
+    }
+    for (uint32_t b = team_id; b < a.B; b += teams) {
+        float4 *st = a.state + uint64_t(b) * a.nvec;
+        double v[kPV] = {};
+        forward_pass(a, st, nullptr, tm, 0, {0.0, 0.0}, {1.0, 0.0}, v);
+        if (!team_sum_n(v, tm, ++gen, sh))
+            return;
+        for (uint32_t k = 1; k <= a.K; ++k) {
+            const double ph = a.phi[uint64_t(b) * a.K + k - 1], th = a.theta[uint64_t(b) * a.K + k - 1];
+            const C2 ephi{cos(ph), sin(ph)}, eth{cos(th), sin(th)};
+            // S = sum of O(phi) c = T + (e^{i phi} - 1) Mk;  alpha = (1 - e^{i theta}) S / N
+            const C2 S = {v[0] + (ephi.re - 1.0) * v[2] - ephi.im * v[3], v[1] + (ephi.re - 1.0) * v[3] + ephi.im * v[2]};
+            const C2 f = cmul({1.0 - eth.re, -eth.im}, S);
+            const C2 alpha{f.re / a.N, f.im / a.N};
+            float4 *ck = (k % a.every == 0 && k < a.K)
+                             ? a.ckpt + (uint64_t(b) * a.nck + (k / a.every - 1u)) * a.nvec
+                             : nullptr;
+            double w[kPV] = {};
+            forward_pass(a, st, ck, tm, 1, alpha, ephi, w);
+            if (!team_sum_n(w, tm, ++gen, sh))
+                return;
+#pragma unroll
+            for (int q = 0; q < kPV; ++q)
+                v[q] = w[q];
+        }
+        if (tm.rank == 0 && threadIdx.x == 0) {
+            a.loss[b] = 1.0 - v[4];
+            a.aux[2u * b] = v[0];
+            a.aux[2u * b + 1u] = v[1];
+        }
+    }
+}
+
+// Adjoint seed: lambda = -g c on the marked entries, 0 elsewhere; accumulates its sum into v[2], v[3].
+__device__ void lambda_seed_pass(const PhaseArgs &a, const float4 *st, float4 *lam, const PhaseTeam &tm, double g,
+                                 double (&v)[kPV])
+{
+    const unsigned tid = threadIdx.x;
+    const uint64_t cnt = share_tiles(a.nvec, tm.rank, tm.size);
+    TileMarks tmk;
+    tmk.mp = 0;
+    for (uint64_t j = 0; j < cnt; ++j) {
+        const uint64_t v0 = (tm.rank + j * tm.size) * uint64_t(kStreamTile);
+        tmk.load(a.marks, a.m, v0);
+#pragma unroll
+        for (int u = 0; u < kStreamUnroll; ++u) {
+            const uint64_t vi = v0 + u * kStreamBlock + tid;
+            if (vi >= a.nvec)
+                continue;
+            const unsigned bits = tmk.mq == tmk.mp ? 0u : tmk.bits(a.marks, vi);
+            float4 out = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+            if (bits) {
+                const float4 x = st[vi];
+                const C2 c0 = lo(x), c1 = hi(x);
+                const C2 l0 = (bits & 1u) ? C2{-g * c0.re, -g * c0.im} : C2{0.0, 0.0};
+                const C2 l1 = (bits & 2u) ? C2{-g * c1.re, -g * c1.im} : C2{0.0, 0.0};
+                out = pack(l0, l1);
+                const C2 r0 = lo(out), r1 = hi(out);
+                v[2] += r0.re + r1.re;
+                v[3] += r0.im + r1.im;
+            }
+            store16<true>(out, lam + vi);
+        }
+        tmk.mp = tmk.mq;
+    }
+}
+
+// One reverse step over a team's share (see the file comment).  src: the checkpoint to re-read c_{j-1}
+// from, or null with anchor set for the uniform state, or anchor clear to rebuild from the state.
+// Accumulates v = {sum c_{j-1}, sum lambda_{j-1}, sum over marked of conj(nu) y}.
+__device__ void reverse_pass(const PhaseArgs &a, float4 *st, float4 *lam, const float4 *src, bool anchor,
+                             const PhaseTeam &tm, C2 beta_c, C2 beta_l, C2 ephi, double (&v)[kPV])
+{
+    const unsigned tid = threadIdx.x;
+    const uint64_t cnt = share_tiles(a.nvec, tm.rank, tm.size);
+    const C2 emphi{ephi.re, -ephi.im};
+    TileMarks tmk;
+    tmk.mp = 0;
+    for (uint64_t j = 0; j < cnt; ++j) {
+        const uint64_t v0 = (tm.rank + j * tm.size) * uint64_t(kStreamTile);
+        tmk.load(a.marks, a.m, v0);
+        const bool fast = tmk.mq == tmk.mp && v0 + kStreamTile <= a.nvec;
+        float4 xc[kStreamUnroll], xl[kStreamUnroll];
+#pragma unroll
+        for (int u = 0; u < kStreamUnroll; ++u) {
+            const uint64_t vi = v0 + u * kStreamBlock + tid;
+            if (fast || vi < a.nvec) {
+                if (!anchor)
+                    xc[u] = load16<true>(st + vi);
+                else
+                    xc[u] = src ? load16<true>(src + vi) : make_float4(a.amp, 0.0f, a.amp, 0.0f);
+                xl[u] = load16<true>(lam + vi);
+            }
+        }
+#pragma unroll
+        for (int u = 0; u < kStreamUnroll; ++u) {
+            const uint64_t vi = v0 + u * kStreamBlock + tid;
+            if (!fast && vi >= a.nvec)
+                continue;
+            const unsigned bits = fast ? 0u : tmk.bits(a.marks, vi);
+            C2 cp[2], lp[2];
+            const C2 cin[2] = {lo(xc[u]), hi(xc[u])}, lin[2] = {lo(xl[u]), hi(xl[u])};
+#pragma unroll
+            for (int e = 0; e < 2; ++e) {
+                const bool mk = (bits >> e) & 1u;
+                C2 y;
+                if (anchor) {
+                    cp[e] = cin[e];
+                    y = mk ? cmul(ephi, cin[e]) : cin[e];
+                } else {
+                    y = {beta_c.re - cin[e].re, beta_c.im - cin[e].im};
+                    cp[e] = mk ? cmul(emphi, y) : y;
+                }
+                const C2 nu{beta_l.re - lin[e].re, beta_l.im - lin[e].im};
+                lp[e] = mk ? cmul(emphi, nu) : nu;
+                if (mk) {
+                    // conj(nu) * y
+                    v[4] += nu.re * y.re + nu.im * y.im;
+                    v[5] += nu.re * y.im - nu.im * y.re;
+                }
+            }
+            const float4 oc = pack(cp[0], cp[1]), ol = pack(lp[0], lp[1]);
+            store16<true>(oc, st + vi);
+            store16<true>(ol, lam + vi);
+            v[0] += double(oc.x) + double(oc.z);
+            v[1] += double(oc.y) + double(oc.w);
+            v[2] += double(ol.x) + double(ol.z);
+            v[3] += double(ol.y) + double(ol.w);
+        }
+        tmk.mp = tmk.mq;
+    }
+}
+
+__global__ __launch_bounds__(kStreamBlock) void phase_adjoint_kernel(PhaseArgs a)
+{
+    __shared__ PhaseShared sh;
+    const unsigned T = a.team_size, teams = gridDim.x / T, team_id = blockIdx.x / T;
+    if (team_id >= teams)
+        return;
+    const PhaseTeam tm{a.sync + team_id, a.partials + uint64_t(team_id) * 16u * T, T, blockIdx.x % T,
+                       a.timeout_ticks};
+    uint64_t gen = 0;
+    if (a.probe) {
+        double v[kPV] = {};
+        (void)team_sum_n(v, tm, ++gen, sh);
+        return;
+    }
+    const bool leader = tm.rank == 0 && threadIdx.x == 0;
+    for (uint32_t b = team_id; b < a.B; b += teams) {
+        float4 *st = a.state + uint64_t(b) * a.nvec;
+        float4 *lam = a.lambda + uint64_t(b) * a.nvec;
+        double v[kPV] = {};
+        lambda_seed_pass(a, st, lam, tm, a.dloss[b], v);
+        if (!team_sum_n(v, tm, ++gen, sh))
+            return;
+        C2 sc{a.aux[2u * b], a.aux[2u * b + 1u]}, sl{v[2], v[3]};
+        for (uint32_t k = a.K; k >= 1; --k) {
+            const uint64_t pk = uint64_t(b) * a.K + k - 1;
+            const double ph = a.phi[pk], th = a.theta[pk];
+            if (leader)  // -2 Im(conj(sum lambda) * sum c) / N
+                a.dtheta[pk] = -2.0 * (sl.re * sc.im - sl.im * sc.re) / a.N;
+            const C2 emth{cos(th), -sin(th)};
+            const C2 om{1.0 - emth.re, -emth.im};
+            const C2 fc = cmul(om, sc), fl = cmul(om, sl);
+            const C2 beta_c{fc.re / a.N, fc.im / a.N}, beta_l{fl.re / a.N, fl.im / a.N};
+            const bool anchor = (k - 1u) % a.every == 0u;
+            const float4 *src = (anchor && k - 1u > 0u)
+                                    ? a.ckpt + (uint64_t(b) * a.nck + ((k - 1u) / a.every - 1u)) * a.nvec
+                                    : nullptr;
+            double w[kPV] = {};
+            reverse_pass(a, st, lam, src, anchor, tm, beta_c, beta_l, {cos(ph), sin(ph)}, w);
+            if (!team_sum_n(w, tm, ++gen, sh))
+                return;
+            if (leader)  // -2 Im(sum over marked of conj(nu) y)
+                a.dphi[pk] = -2.0 * w[5];
+            sc = {w[0], w[1]};
+            sl = {w[2], w[3]};
+        }
+    }
+}
+
+// Zeroes the team barriers before a launch (a kernel, so that launches can be captured and replayed).
+__global__ void phase_reset_kernel(uint64_t *words, uint64_t nwords)
+{
+    for (uint64_t w = uint64_t(blockIdx.x) * blockDim.x + threadIdx.x; w < nwords; w += uint64_t(gridDim.x) * blockDim.x)
+        words[w] = 0u;
+}
+
+}  // namespace
+
+const void *phase_kernel_fn(bool adjoint)
+{
+    return adjoint ? reinterpret_cast<const void *>(&phase_adjoint_kernel)
+                   : reinterpret_cast<const void *>(&phase_forward_kernel);
+}
+
+hipError_t launch_phase(const PhaseLaunch &L, bool adjoint)
+{
+    PhaseArgs a;
+    a.state = static_cast<float4 *>(L.state);
+    a.lambda = static_cast<float4 *>(L.lambda);
+    a.ckpt = static_cast<float4 *>(L.ckpt);
+    a.marks = L.marks;
+    a.m = L.m;
+    a.nvec = L.nvec;
+    a.N = L.N;
+    a.amp = L.amp;
+    a.B = L.B;
+    a.K = L.K;
+    a.every = L.every;
+    a.nck = L.nck;
+    a.phi = L.phi;
+    a.theta = L.theta;
+    a.loss = L.loss;
+    a.aux = L.aux;
+    a.dloss = L.dloss;
+    a.dphi = L.dphi;
+    a.dtheta = L.dtheta;
+    a.sync = L.sync;
+    a.partials = L.partials;
+    a.team_size = L.team_size;
+    a.probe = L.probe;
+    a.timeout_ticks = L.timeout_ticks;
+    uint64_t *words = reinterpret_cast<uint64_t *>(L.sync);
+    uint64_t nwords = uint64_t(L.teams_alloc) * sizeof(PhaseSync) / sizeof(uint64_t);
+    void *ra[] = {&words, &nwords};
+    hipError_t e = hipLaunchKernel(reinterpret_cast<const void *>(&phase_reset_kernel), dim3(64), dim3(256), ra, 0,
+                                   L.stream);
+    if (e != hipSuccess)
+        return e;
+    void *args[] = {&a};
+    return hipLaunchCooperativeKernel(phase_kernel_fn(adjoint), dim3(L.grid), dim3(kStreamBlock), args, 0, L.stream);
+}
+
+}  // namespace grover

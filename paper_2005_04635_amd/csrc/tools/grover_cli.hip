@@ -6,6 +6,9 @@
 //   grover_cli copy --bytes 2147483648 [--reps 1]              (plain copy kernel of known size)
 //   grover_cli batch --instances FILE [--split S --team T | --tune] [--graph] [--runs R]
 //                   (many searches in one launch; FILE holds one instance per line: n m mark_1 ... mark_m)
+//   grover_cli phase --schedules FILE [--every S] [--team T] [--runs R]
+//                   (generalized iteration: forward runs and adjoint runs; FILE holds "n m K B", the m marks,
+//                    then B rows of K phases phi and B rows of K phases theta)
 //   run ... --calibrate-copy B                                  (also copy B bytes once, before the search)
 //
 // `run` creates a context, then per step: writes the uniform state, runs the iterations (timed with HIP
@@ -40,7 +43,8 @@ int usage()
             "                      [--mark I ... | --hash-seed S --hash-bits B --m M] [--iters K]\n"
             "                      [--shots S] [--shot-seed U] [--steps T] [--calibrate-copy BYTES]\n"
             "       grover_cli copy --bytes B [--reps R]\n"
-            "       grover_cli batch --instances FILE [--split S --team T | --tune] [--graph] [--runs R]\n");
+            "       grover_cli batch --instances FILE [--split S --team T | --tune] [--graph] [--runs R]\n"
+            "       grover_cli phase --schedules FILE [--every S] [--team T] [--runs R]\n");
     return 2;
 }
 
@@ -220,6 +224,7 @@ int run_search(int argc, char **argv)
            ", \"steps\": %d, \"iterate_ms\": %.4f, \"step_ms\": %.4f, \"updates_per_s\": %.6e, \"norm\": %.12f}\n",
            cfg.n, cfg.dtype, form, cfg.m, iters, shots, grid, block, steps, it_ms, step_ms_sum / steps,
            N * double(iters) / (it_ms / 1e3), norm);
+    fflush(stdout);
     if (shots_dev)
         CHECK_HIP(hipFree(shots_dev));
     grover_destroy(ctx);
@@ -333,7 +338,122 @@ int run_batch(int argc, char **argv)
            ", \"updates_per_s\": %.6e}\n",
            ns.size(), updates, grid, sp, tm, graph ? "true" : "false", runs, run_ms,
            double(updates) / (run_ms / 1e3));
+    fflush(stdout);
     grover_batch_destroy(b);
+    CHECK_HIP(hipStreamDestroy(stream));
+    return 0;
+}
+
+#define CHECK_PHASE(p, x)                                                              \
+    do {                                                                               \
+        const int s_ = (x);                                                            \
+        if (s_ != GROVER_OK) {                                                         \
+            fprintf(stderr, "grover phase error %d (%s): %s\n", s_, grover_status_str(s_), \
+                    grover_phase_last_error(p));                                       \
+            return 1;                                                                  \
+        }                                                                              \
+    } while (0)
+
+int run_phase(int argc, char **argv)
+{
+    const char *path = nullptr;
+    unsigned every = 0, team = 0;
+    int runs = 3;
+    for (int i = 2; i < argc; ++i) {
+        if (!strcmp(argv[i], "--schedules") && i + 1 < argc)
+            path = argv[++i];
+        else if (!strcmp(argv[i], "--every") && i + 1 < argc)
+            every = unsigned(atoi(argv[++i]));
+        else if (!strcmp(argv[i], "--team") && i + 1 < argc)
+            team = unsigned(atoi(argv[++i]));
+        else if (!strcmp(argv[i], "--runs") && i + 1 < argc)
+            runs = atoi(argv[++i]);
+        else
+            return usage();
+    }
+    if (!path || runs < 1)
+        return usage();
+    FILE *f = fopen(path, "r");
+    if (!f) {
+        fprintf(stderr, "cannot open %s\n", path);
+        return 1;
+    }
+    unsigned n = 0, K = 0, B = 0;
+    unsigned long long m = 0;
+    bool ok = fscanf(f, "%u %llu %u %u", &n, &m, &K, &B) == 4 && K > 0 && B > 0 && m < (1ull << 20);
+    std::vector<uint64_t> marks(ok ? m : 0);
+    for (auto &x : marks) {
+        unsigned long long v = 0;
+        ok = ok && fscanf(f, "%llu", &v) == 1;
+        x = v;
+    }
+    std::vector<double> params(ok ? size_t(2) * B * K : 0);
+    for (auto &x : params)
+        ok = ok && fscanf(f, "%lf", &x) == 1;
+    fclose(f);
+    if (!ok) {
+        fprintf(stderr, "%s: malformed schedule file\n", path);
+        return 1;
+    }
+    grover_phase_config cfg{};
+    cfg.n = n;
+    cfg.batch = B;
+    cfg.iterations = K;
+    cfg.checkpoint_every = every;
+    cfg.marked = marks.empty() ? nullptr : marks.data();
+    cfg.m = marks.size();
+    cfg.dtype = GROVER_C64;
+    hipStream_t stream;
+    CHECK_HIP(hipStreamCreate(&stream));
+    grover_phase *p = nullptr;
+    CHECK_PHASE(nullptr, grover_phase_init(&p, &cfg, stream));
+    if (team)
+        CHECK_PHASE(p, grover_phase_set_team(p, team));
+    const size_t pb = size_t(B) * K * sizeof(double);
+    double *d_par = nullptr, *d_loss = nullptr, *d_dloss = nullptr, *d_grad = nullptr;
+    CHECK_HIP(hipMalloc(&d_par, 2 * pb));
+    CHECK_HIP(hipMalloc(&d_loss, B * sizeof(double)));
+    CHECK_HIP(hipMalloc(&d_dloss, B * sizeof(double)));
+    CHECK_HIP(hipMalloc(&d_grad, 2 * pb));
+    CHECK_HIP(hipMemcpy(d_par, params.data(), 2 * pb, hipMemcpyHostToDevice));
+    std::vector<double> ones(B, 1.0);
+    CHECK_HIP(hipMemcpy(d_dloss, ones.data(), B * sizeof(double), hipMemcpyHostToDevice));
+    hipEvent_t e0, e1, e2;
+    CHECK_HIP(hipEventCreate(&e0));
+    CHECK_HIP(hipEventCreate(&e1));
+    CHECK_HIP(hipEventCreate(&e2));
+    double fsum = 0, bsum = 0;
+    for (int r = 0; r < runs; ++r) {
+        CHECK_HIP(hipEventRecord(e0, stream));
+        CHECK_PHASE(p, grover_phase_forward(p, d_par, d_par + size_t(B) * K, d_loss));
+        CHECK_HIP(hipEventRecord(e1, stream));
+        CHECK_PHASE(p, grover_phase_backward(p, d_dloss, d_grad, d_grad + size_t(B) * K));
+        CHECK_HIP(hipEventRecord(e2, stream));
+        CHECK_PHASE(p, grover_phase_sync(p));
+        float fm = 0, bm = 0;
+        CHECK_HIP(hipEventElapsedTime(&fm, e0, e1));
+        CHECK_HIP(hipEventElapsedTime(&bm, e1, e2));
+        fsum += fm;
+        bsum += bm;
+        fprintf(stderr, "[grover_cli] phase run %d/%d: forward %.3f ms, adjoint %.3f ms\n", r + 1, runs, fm, bm);
+    }
+    double loss0 = 0;
+    CHECK_HIP(hipMemcpy(&loss0, d_loss, sizeof(double), hipMemcpyDeviceToHost));
+    int64_t grid = 0, tm = 0, ev = 0;
+    CHECK_PHASE(p, grover_phase_query(p, 1, &grid));
+    CHECK_PHASE(p, grover_phase_query(p, 2, &tm));
+    CHECK_PHASE(p, grover_phase_query(p, 3, &ev));
+    const double upd = double(B) * K * double(uint64_t(1) << n);
+    printf("{\"mode\": \"phase\", \"n\": %u, \"m\": %zu, \"K\": %u, \"batch\": %u, \"grid\": %" PRId64
+           ", \"team\": %" PRId64 ", \"every\": %" PRId64 ", \"runs\": %d, \"forward_ms\": %.4f, \"adjoint_ms\": %.4f"
+           ", \"forward_updates_per_s\": %.6e, \"loss0\": %.12f}\n",
+           n, marks.size(), K, B, grid, tm, ev, runs, fsum / runs, bsum / runs, upd / (fsum / runs / 1e3), loss0);
+    fflush(stdout);
+    CHECK_HIP(hipFree(d_par));
+    CHECK_HIP(hipFree(d_loss));
+    CHECK_HIP(hipFree(d_dloss));
+    CHECK_HIP(hipFree(d_grad));
+    grover_phase_destroy(p);
     CHECK_HIP(hipStreamDestroy(stream));
     return 0;
 }
@@ -350,5 +470,7 @@ int main(int argc, char **argv)
         return run_search(argc, argv);
     if (!strcmp(argv[1], "batch"))
         return run_batch(argc, argv);
+    if (!strcmp(argv[1], "phase"))
+        return run_phase(argc, argv);
     return usage();
 }

@@ -70,6 +70,10 @@ Q_FORM, Q_GRID, Q_BLOCK, Q_ELEM_BYTES, Q_N, Q_M = 0, 1, 2, 3, 4, 5
 BQ_COUNT, BQ_GRID, BQ_SPLIT, BQ_TEAM, BQ_UPDATES, BQ_GRAPH, BQ_BYTES, BQ_N_TEAM = range(8)
 
 
+# grover_phase_query keys
+PQ_BATCH, PQ_GRID, PQ_TEAM, PQ_EVERY, PQ_CHECKPOINTS, PQ_BYTES = range(6)
+
+
 class GroverError(RuntimeError):
     def __init__(self, status: int, message: str):
         super().__init__(f"{message} (status {status})")
@@ -89,6 +93,19 @@ class grover_config(ctypes.Structure):
         ("flags", ctypes.c_uint32),
         ("accum", ctypes.c_uint32),
         ("reserved", ctypes.c_uint32),
+    ]
+
+
+class grover_phase_config(ctypes.Structure):
+    _fields_ = [
+        ("n", ctypes.c_uint32),
+        ("batch", ctypes.c_uint32),
+        ("iterations", ctypes.c_uint32),
+        ("checkpoint_every", ctypes.c_uint32),
+        ("marked", ctypes.POINTER(ctypes.c_uint64)),
+        ("m", ctypes.c_uint64),
+        ("dtype", ctypes.c_uint32),
+        ("flags", ctypes.c_uint32),
     ]
 
 
@@ -113,6 +130,9 @@ EXPORTS = [
     "grover_batch_init", "grover_batch_set_tiling", "grover_batch_tune", "grover_batch_capture",
     "grover_batch_run", "grover_batch_sync", "grover_batch_state", "grover_batch_read_state",
     "grover_batch_query", "grover_batch_destroy", "grover_batch_last_error",
+    "grover_phase_init", "grover_phase_set_team", "grover_phase_forward", "grover_phase_backward",
+    "grover_phase_sync", "grover_phase_state", "grover_phase_read_state", "grover_phase_query",
+    "grover_phase_destroy", "grover_phase_last_error",
 ]
 
 _lock = threading.Lock()
@@ -166,6 +186,16 @@ def load(path: str = LIB_PATH):
             "grover_batch_query": (i32, [P, i32, ctypes.POINTER(ctypes.c_int64)]),
             "grover_batch_destroy": (None, [P]),
             "grover_batch_last_error": (ctypes.c_char_p, [P]),
+            "grover_phase_init": (i32, [ctypes.POINTER(P), ctypes.POINTER(grover_phase_config), P]),
+            "grover_phase_set_team": (i32, [P, u32]),
+            "grover_phase_forward": (i32, [P, P, P, P]),
+            "grover_phase_backward": (i32, [P, P, P, P]),
+            "grover_phase_sync": (i32, [P]),
+            "grover_phase_state": (i32, [P, u32, ctypes.POINTER(P), ctypes.POINTER(ctypes.c_size_t)]),
+            "grover_phase_read_state": (i32, [P, u32, P, ctypes.c_size_t]),
+            "grover_phase_query": (i32, [P, i32, ctypes.POINTER(ctypes.c_int64)]),
+            "grover_phase_destroy": (None, [P]),
+            "grover_phase_last_error": (ctypes.c_char_p, [P]),
         }
         for name, (res, args) in sig.items():
             fn = getattr(lib, name)
@@ -333,6 +363,62 @@ def grover_batch_destroy(b) -> None:
 
 def grover_batch_last_error(b) -> str:
     return load().grover_batch_last_error(b).decode()
+
+
+def _pcheck(p, status: int) -> None:
+    if status != GROVER_OK:
+        lib = load()
+        msg = lib.grover_phase_last_error(p).decode() if p else ""
+        if not msg:
+            msg = lib.grover_status_str(status).decode()
+        raise GroverError(status, msg)
+
+
+def grover_phase_init(cfg: grover_phase_config, hip_stream: int = 0):
+    p = ctypes.c_void_p()
+    _pcheck(None, load().grover_phase_init(ctypes.byref(p), ctypes.byref(cfg), hip_stream or None))
+    return p
+
+
+def grover_phase_set_team(p, team: int) -> None:
+    _pcheck(p, load().grover_phase_set_team(p, team))
+
+
+def grover_phase_forward(p, phi: int, theta: int, loss: int) -> None:
+    _pcheck(p, load().grover_phase_forward(p, phi or None, theta or None, loss or None))
+
+
+def grover_phase_backward(p, dloss: int, dphi: int, dtheta: int) -> None:
+    _pcheck(p, load().grover_phase_backward(p, dloss or None, dphi or None, dtheta or None))
+
+
+def grover_phase_sync(p) -> None:
+    _pcheck(p, load().grover_phase_sync(p))
+
+
+def grover_phase_state(p, b: int):
+    ptr, n = ctypes.c_void_p(), ctypes.c_size_t()
+    _pcheck(p, load().grover_phase_state(p, b, ctypes.byref(ptr), ctypes.byref(n)))
+    return ptr.value, n.value
+
+
+def grover_phase_read_state(p, b: int, host: int, nbytes: int) -> None:
+    _pcheck(p, load().grover_phase_read_state(p, b, host, nbytes))
+
+
+def grover_phase_query(p, key: int) -> int:
+    v = ctypes.c_int64()
+    _pcheck(p, load().grover_phase_query(p, key, ctypes.byref(v)))
+    return v.value
+
+
+def grover_phase_destroy(p) -> None:
+    if p:
+        load().grover_phase_destroy(p)
+
+
+def grover_phase_last_error(p) -> str:
+    return load().grover_phase_last_error(p).decode()
 
 
 # --------------------------------------------------------------------------------- convenience class
@@ -542,3 +628,138 @@ class GroverBatch:
             self.close()
         except BaseException:
             pass
+
+
+class GroverPhase:
+    """B schedules of the generalized iteration (phases phi_j on the marked amplitudes, theta_j in the
+    diffusion) over one marked set, with the adjoint gradient; complex64 states on the current GPU.
+
+    n, marks, K, batch   problem shape; checkpoint_every = 0 picks round(sqrt(K))
+    `loss(phi, theta)` is differentiable with torch autograd: phi, theta are CUDA float64 tensors of shape
+    (batch, K); the result has shape (batch,).  Each forward run must be followed by at most one backward
+    run before the next forward (the adjoint sweep reuses the forward run's checkpoints).
+    """
+
+    def __init__(self, n: int, marks, K: int, batch: int = 1, checkpoint_every: int = 0):
+        import torch
+
+        self._marks = np.ascontiguousarray(np.asarray(marks, dtype=np.uint64).reshape(-1))
+        cfg = grover_phase_config()
+        cfg.n, cfg.batch, cfg.iterations, cfg.checkpoint_every = n, batch, K, checkpoint_every
+        cfg.m = self._marks.size
+        if self._marks.size:
+            cfg.marked = self._marks.ctypes.data_as(ctypes.POINTER(ctypes.c_uint64))
+        cfg.dtype = GROVER_C64
+        self.stream = torch.cuda.current_stream()
+        self.p = grover_phase_init(cfg, self.stream.cuda_stream)
+        self.n, self.K, self.batch = n, K, batch
+        self.generation = 0
+
+    def _enter(self):
+        import torch
+
+        cur = torch.cuda.current_stream()
+        if cur.cuda_stream != self.stream.cuda_stream:
+            self.stream.wait_stream(cur)
+        return cur
+
+    def _leave(self, cur):
+        if cur.cuda_stream != self.stream.cuda_stream:
+            cur.wait_stream(self.stream)
+
+    def forward(self, phi, theta):
+        """Loss per schedule (torch float64, shape (batch,)) without autograd."""
+        import torch
+
+        phi = phi.detach().to(torch.float64).contiguous()
+        theta = theta.detach().to(torch.float64).contiguous()
+        if phi.shape != (self.batch, self.K) or theta.shape != (self.batch, self.K) or not phi.is_cuda:
+            raise ValueError(f"phi and theta must be CUDA tensors of shape ({self.batch}, {self.K})")
+        loss = torch.empty(self.batch, dtype=torch.float64, device=phi.device)
+        cur = self._enter()
+        grover_phase_forward(self.p, phi.data_ptr(), theta.data_ptr(), loss.data_ptr())
+        for t in (phi, theta, loss):
+            t.record_stream(self.stream)
+        self._leave(cur)
+        self.generation += 1
+        return loss
+
+    def backward(self, dloss):
+        """(dphi, dtheta) of sum_b dloss[b] * L_b at the last forward run's phases."""
+        import torch
+
+        dloss = dloss.detach().to(torch.float64).contiguous()
+        dphi = torch.empty(self.batch, self.K, dtype=torch.float64, device=dloss.device)
+        dtheta = torch.empty_like(dphi)
+        cur = self._enter()
+        grover_phase_backward(self.p, dloss.data_ptr(), dphi.data_ptr(), dtheta.data_ptr())
+        for t in (dloss, dphi, dtheta):
+            t.record_stream(self.stream)
+        self._leave(cur)
+        return dphi, dtheta
+
+    def loss(self, phi, theta):
+        """Differentiable loss: torch.autograd calls the adjoint kernel for the gradient."""
+        return _PhaseLoss.apply(phi, theta, self)
+
+    def sync(self) -> None:
+        grover_phase_sync(self.p)
+
+    def query(self, key: int) -> int:
+        return grover_phase_query(self.p, key)
+
+    def read_state(self, b: int) -> np.ndarray:
+        out = np.empty(1 << self.n, dtype=np.complex64)
+        grover_phase_read_state(self.p, b, out.ctypes.data, out.nbytes)
+        return out
+
+    def close(self) -> None:
+        if getattr(self, "p", None):
+            grover_phase_destroy(self.p)
+            self.p = None
+
+    def __del__(self):
+        try:
+            if sys.is_finalizing():
+                return
+            self.close()
+        except BaseException:
+            pass
+
+
+def _phase_loss_function():
+    import torch
+
+    class PhaseLoss(torch.autograd.Function):
+        """L_b(phi_b, theta_b) through libgrover: forward kernel for the value, adjoint kernel for the
+        gradient (no intermediate state is kept by torch)."""
+
+        @staticmethod
+        def forward(ctx, phi, theta, engine):
+            loss = engine.forward(phi, theta)
+            ctx.engine = engine
+            ctx.generation = engine.generation
+            return loss
+
+        @staticmethod
+        def backward(ctx, grad_loss):
+            engine = ctx.engine
+            if engine.generation != ctx.generation:
+                raise RuntimeError("another forward run replaced the checkpoints this backward needs")
+            dphi, dtheta = engine.backward(grad_loss)
+            return dphi, dtheta, None
+
+    return PhaseLoss
+
+
+class _LazyPhaseLoss:
+    _fn = None
+
+    @classmethod
+    def apply(cls, *args):
+        if cls._fn is None:
+            cls._fn = _phase_loss_function()
+        return cls._fn.apply(*args)
+
+
+_PhaseLoss = _LazyPhaseLoss

@@ -230,3 +230,43 @@ def test_batch_workload_statistics():
     N = np.ldexp(1.0, n.astype(int))
     updates = float(np.sum(N * np.floor(math.pi / 4 * np.sqrt(N / m))))
     assert 2.2e11 < updates < 2.3e11
+
+
+def _phase_cfg(**kw):
+    from paper_2005_04635_amd.grover import grover_phase_config
+
+    cfg = grover_phase_config()
+    cfg.n, cfg.batch, cfg.iterations, cfg.dtype = 6, 2, 8, 1
+    keep = (ctypes.c_uint64 * 3)(3, 17, 40)
+    cfg.marked = ctypes.cast(keep, ctypes.POINTER(ctypes.c_uint64))
+    cfg.m = 3
+    for k, v in kw.items():
+        setattr(cfg, k, v)
+    return cfg, keep
+
+
+@pytest.mark.parametrize("field,value,status", [("n", 0, -1), ("n", 31, -1), ("batch", 0, -1),
+                                                ("iterations", 0, -1), ("flags", 1, -1), ("m", 65, -1),
+                                                ("dtype", 2, -5), ("dtype", 0, -5)])
+def test_phase_init_rejects_invalid_configs(lib, field, value, status):
+    cfg, keep = _phase_cfg(**{field: value})
+    p = ctypes.c_void_p()
+    assert lib.grover_phase_init(ctypes.byref(p), ctypes.byref(cfg), None) == status
+    assert not p.value
+
+
+def test_phase_init_rejects_bad_marks_and_nulls(lib):
+    p = ctypes.c_void_p()
+    for marks in ([3, 3], [64]):
+        arr = (ctypes.c_uint64 * len(marks))(*marks)
+        cfg, keep = _phase_cfg(m=len(marks), marked=ctypes.cast(arr, ctypes.POINTER(ctypes.c_uint64)))
+        assert lib.grover_phase_init(ctypes.byref(p), ctypes.byref(cfg), None) == -1
+    cfg, keep = _phase_cfg(marked=None)
+    assert lib.grover_phase_init(ctypes.byref(p), ctypes.byref(cfg), None) == -1
+    assert lib.grover_phase_init(None, ctypes.byref(cfg), None) == -1
+    assert lib.grover_phase_init(ctypes.byref(p), None, None) == -1
+    assert lib.grover_phase_forward(None, None, None, None) == -1
+    assert lib.grover_phase_backward(None, None, None, None) == -1
+    assert lib.grover_phase_sync(None) == -1
+    assert lib.grover_phase_last_error(None) == b"no phase context"
+    lib.grover_phase_destroy(None)

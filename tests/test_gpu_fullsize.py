@@ -176,3 +176,45 @@ def test_batch4096_workload(G, orc):
             assert err <= error_bound(ni, k, "c64", "f64", 1), (i, ni, mi, k, err)
         print(f"worst error / bound = {worst:.3g}", flush=True)
         b.close()
+
+
+def test_phase_n20_workload(G, orc):
+    """The differentiable workload at full size (n = 20, M = 3, K = 64, 64 schedules, phases N(pi, 0.1)), in
+    the configuration the benchmark times: losses of 8 schedules and the final states' two-class structure
+    against the oracle, gradients of 2 schedules against the oracle's stored-state adjoint."""
+    import torch
+
+    from test_gpu_phase import forward_bound, grad_bound, loss_bound
+
+    w = workloads.PHASE_N20
+    marks = w.marks()
+    phi, theta = w.schedules()
+    eng = G.GroverPhase(w.n, marks, w.K, batch=w.batch)
+    every = eng.query(G.grover.PQ_EVERY)
+    assert every == 8 and eng.query(G.grover.PQ_CHECKPOINTS) == 7
+    ph = torch.tensor(phi, dtype=torch.float64, device="cuda")
+    th = torch.tensor(theta, dtype=torch.float64, device="cuda")
+    loss = eng.forward(ph, th)
+    eng.sync()
+    loss = loss.cpu().numpy()
+    mask = np.zeros(1 << w.n, dtype=bool)
+    mask[marks.astype(np.int64)] = True
+    for b in range(0, w.batch, 9):
+        got = eng.read_state(b)
+        gm, gu = got[mask], got[~mask]
+        assert np.all(gm.view(np.uint64) == gm.view(np.uint64)[0]) and np.all(gu.view(np.uint64) == gu.view(np.uint64)[0])
+        want = orc.phase_search(w.n, marks, phi[b], theta[b])
+        assert np.max(np.abs(got.astype(np.complex128) - want)) <= forward_bound(w.K), b
+        assert abs(loss[b] - orc.phase_loss(want, marks)) <= loss_bound(w.K), b
+    g = np.linspace(1.0, 2.0, w.batch)
+    dphi, dtheta = eng.backward(torch.tensor(g, dtype=torch.float64, device="cuda"))
+    eng.sync()
+    dphi, dtheta = dphi.cpu().numpy(), dtheta.cpu().numpy()
+    for b in (0, w.batch - 1):
+        wphi, wtheta = orc.phase_grad_adjoint(w.n, marks, phi[b], theta[b])
+        tol = grad_bound(w.K, every, g[b])
+        err = max(np.max(np.abs(dphi[b] - g[b] * wphi)), np.max(np.abs(dtheta[b] - g[b] * wtheta)))
+        print(f"schedule {b}: max gradient error {err:.3g} (bound {tol:.3g}), |grad| max "
+              f"{max(np.max(np.abs(wphi)), np.max(np.abs(wtheta))):.3g}", flush=True)
+        assert err <= tol, b
+    eng.close()

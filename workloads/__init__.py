@@ -232,6 +232,16 @@ class PhaseWorkload:
     def schedules(self):
         return phase_schedule(self.K, self.seed + 1, self.spread, self.batch)
 
+    def write_file(self, path: str) -> None:
+        """"n m K B", the marks, B rows of phi, B rows of theta (the native driver's input format)."""
+        phi, theta = self.schedules()
+        with open(path, "w") as f:
+            f.write(f"{self.n} {self.m} {self.K} {self.batch}\n")
+            f.write(" ".join(str(int(x)) for x in self.marks()) + "\n")
+            for rows in (phi, theta):
+                for r in rows:
+                    f.write(" ".join(repr(float(x)) for x in r) + "\n")
+
 
 # Differentiable generalized search: n = 20, M = 3, K = 64 iterations, 64 schedules, phases N(pi, 0.1).
 PHASE_N20 = PhaseWorkload(name="phase_n20_m3_k64_b64", n=20, m=3, K=64, batch=64, spread=0.1, seed=0x5EED2005)
