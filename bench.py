@@ -482,7 +482,7 @@ def main() -> int:
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-forms", action="store_true")
-    ap.add_argument("--cpu-iters", type=int, default=8)
+    ap.add_argument("--cpu-iters", type=int, default=40)
     ap.add_argument("--sweep", choices=["table1", "precision", "batch", "adjoint"], default=None,
                     help="instead of the headline line, print one JSON line per point of a sweep")
     args = ap.parse_args()
