@@ -201,10 +201,25 @@ __device__ inline uint64_t share_tiles(uint64_t nvec, unsigned rank, unsigned si
     return rank < nt ? (nt - rank + size - 1) / size : 0;
 }
 
+// Does local tile j of this workgroup's share hold a marked amplitude?  From the LDS table when it could be
+// built, otherwise assume it may (the tile then finds its marks by search).
+__device__ inline bool tile_marked(const PhaseArgs &a, const uint32_t *table, bool use_table, uint64_t j)
+{
+    return use_table ? ((table[j >> 5] >> (j & 31)) & 1u) != 0u : a.m > 0;
+}
+
+// The table of this workgroup's tiles that hold marked amplitudes; every schedule shares the marked set and
+// the tile assignment, so it is built once per launch.
+__device__ inline bool build_phase_table(const PhaseArgs &a, const PhaseTeam &tm, uint32_t *table)
+{
+    const Share<C64> share{nullptr, a.nvec, a.marks, a.m, tm.rank, tm.size};
+    return build_mark_table(share, table);
+}
+
 // Forward pass over a team's share.  mode 0: write the uniform state; mode 1: c' = alpha - O(phi) c.
 // Accumulates v = {sum re, sum im, marked sum re, marked sum im, marked |c|^2, 0} of the values stored.
-__device__ void forward_pass(const PhaseArgs &a, float4 *st, float4 *ck, const PhaseTeam &tm, int mode, C2 alpha,
-                             C2 ephi, double (&v)[kPV])
+__device__ void forward_pass(const PhaseArgs &a, float4 *st, float4 *ck, const PhaseTeam &tm, const uint32_t *table,
+                             bool use_table, int mode, C2 alpha, C2 ephi, double (&v)[kPV])
 {
     const unsigned tid = threadIdx.x;
     const uint64_t cnt = share_tiles(a.nvec, tm.rank, tm.size);
@@ -212,8 +227,9 @@ __device__ void forward_pass(const PhaseArgs &a, float4 *st, float4 *ck, const P
     tmk.mp = 0;
     for (uint64_t j = 0; j < cnt; ++j) {
         const uint64_t v0 = (tm.rank + j * tm.size) * uint64_t(kStreamTile);
-        tmk.load(a.marks, a.m, v0);
-        const bool fast = tmk.mq == tmk.mp && v0 + kStreamTile <= a.nvec;
+        const bool fast = !tile_marked(a, table, use_table, j) && v0 + kStreamTile <= a.nvec;
+        if (!fast)
+            tmk.load(a.marks, a.m, v0);
         float4 x[kStreamUnroll];
 #pragma unroll
         for (int u = 0; u < kStreamUnroll; ++u) {
@@ -255,13 +271,15 @@ __device__ void forward_pass(const PhaseArgs &a, float4 *st, float4 *ck, const P
                 v[4] += r1.re * r1.re + r1.im * r1.im;
             }
         }
-        tmk.mp = tmk.mq;
+        if (!fast)
+            tmk.mp = tmk.mq;
     }
 }
 
 __global__ __launch_bounds__(kStreamBlock) void phase_forward_kernel(PhaseArgs a)
 {
     __shared__ PhaseShared sh;
+    __shared__ uint32_t table[kMarkWords];
     const unsigned T = a.team_size, teams = gridDim.x / T, team_id = blockIdx.x / T;
     if (team_id >= teams)
         return;
@@ -273,10 +291,11 @@ __global__ __launch_bounds__(kStreamBlock) void phase_forward_kernel(PhaseArgs a
         (void)team_sum_n(v, tm, ++gen, sh);
         return;
     }
+    const bool use_table = build_phase_table(a, tm, table);
     for (uint32_t b = team_id; b < a.B; b += teams) {
         float4 *st = a.state + uint64_t(b) * a.nvec;
         double v[kPV] = {};
-        forward_pass(a, st, nullptr, tm, 0, {0.0, 0.0}, {1.0, 0.0}, v);
+        forward_pass(a, st, nullptr, tm, table, use_table, 0, {0.0, 0.0}, {1.0, 0.0}, v);
         if (!team_sum_n(v, tm, ++gen, sh))
             return;
         for (uint32_t k = 1; k <= a.K; ++k) {
@@ -290,7 +309,7 @@ __global__ __launch_bounds__(kStreamBlock) void phase_forward_kernel(PhaseArgs a
                              ? a.ckpt + (uint64_t(b) * a.nck + (k / a.every - 1u)) * a.nvec
                              : nullptr;
             double w[kPV] = {};
-            forward_pass(a, st, ck, tm, 1, alpha, ephi, w);
+            forward_pass(a, st, ck, tm, table, use_table, 1, alpha, ephi, w);
             if (!team_sum_n(w, tm, ++gen, sh))
                 return;
 #pragma unroll
@@ -306,8 +325,8 @@ __global__ __launch_bounds__(kStreamBlock) void phase_forward_kernel(PhaseArgs a
 }
 
 // Adjoint seed: lambda = -g c on the marked entries, 0 elsewhere; accumulates its sum into v[2], v[3].
-__device__ void lambda_seed_pass(const PhaseArgs &a, const float4 *st, float4 *lam, const PhaseTeam &tm, double g,
-                                 double (&v)[kPV])
+__device__ void lambda_seed_pass(const PhaseArgs &a, const float4 *st, float4 *lam, const PhaseTeam &tm,
+                                 const uint32_t *table, bool use_table, double g, double (&v)[kPV])
 {
     const unsigned tid = threadIdx.x;
     const uint64_t cnt = share_tiles(a.nvec, tm.rank, tm.size);
@@ -315,13 +334,15 @@ __device__ void lambda_seed_pass(const PhaseArgs &a, const float4 *st, float4 *l
     tmk.mp = 0;
     for (uint64_t j = 0; j < cnt; ++j) {
         const uint64_t v0 = (tm.rank + j * tm.size) * uint64_t(kStreamTile);
-        tmk.load(a.marks, a.m, v0);
+        const bool marked = tile_marked(a, table, use_table, j);
+        if (marked)
+            tmk.load(a.marks, a.m, v0);
 #pragma unroll
         for (int u = 0; u < kStreamUnroll; ++u) {
             const uint64_t vi = v0 + u * kStreamBlock + tid;
             if (vi >= a.nvec)
                 continue;
-            const unsigned bits = tmk.mq == tmk.mp ? 0u : tmk.bits(a.marks, vi);
+            const unsigned bits = !marked || tmk.mq == tmk.mp ? 0u : tmk.bits(a.marks, vi);
             float4 out = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
             if (bits) {
                 const float4 x = st[vi];
@@ -335,7 +356,8 @@ __device__ void lambda_seed_pass(const PhaseArgs &a, const float4 *st, float4 *l
             }
             store16<true>(out, lam + vi);
         }
-        tmk.mp = tmk.mq;
+        if (marked)
+            tmk.mp = tmk.mq;
     }
 }
 
@@ -343,7 +365,8 @@ __device__ void lambda_seed_pass(const PhaseArgs &a, const float4 *st, float4 *l
 // from, or null with anchor set for the uniform state, or anchor clear to rebuild from the state.
 // Accumulates v = {sum c_{j-1}, sum lambda_{j-1}, sum over marked of conj(nu) y}.
 __device__ void reverse_pass(const PhaseArgs &a, float4 *st, float4 *lam, const float4 *src, bool anchor,
-                             const PhaseTeam &tm, C2 beta_c, C2 beta_l, C2 ephi, double (&v)[kPV])
+                             const PhaseTeam &tm, const uint32_t *table, bool use_table, C2 beta_c, C2 beta_l,
+                             C2 ephi, double (&v)[kPV])
 {
     const unsigned tid = threadIdx.x;
     const uint64_t cnt = share_tiles(a.nvec, tm.rank, tm.size);
@@ -352,8 +375,9 @@ __device__ void reverse_pass(const PhaseArgs &a, float4 *st, float4 *lam, const 
     tmk.mp = 0;
     for (uint64_t j = 0; j < cnt; ++j) {
         const uint64_t v0 = (tm.rank + j * tm.size) * uint64_t(kStreamTile);
-        tmk.load(a.marks, a.m, v0);
-        const bool fast = tmk.mq == tmk.mp && v0 + kStreamTile <= a.nvec;
+        const bool fast = !tile_marked(a, table, use_table, j) && v0 + kStreamTile <= a.nvec;
+        if (!fast)
+            tmk.load(a.marks, a.m, v0);
         float4 xc[kStreamUnroll], xl[kStreamUnroll];
 #pragma unroll
         for (int u = 0; u < kStreamUnroll; ++u) {
@@ -401,13 +425,15 @@ __device__ void reverse_pass(const PhaseArgs &a, float4 *st, float4 *lam, const 
             v[2] += double(ol.x) + double(ol.z);
             v[3] += double(ol.y) + double(ol.w);
         }
-        tmk.mp = tmk.mq;
+        if (!fast)
+            tmk.mp = tmk.mq;
     }
 }
 
 __global__ __launch_bounds__(kStreamBlock) void phase_adjoint_kernel(PhaseArgs a)
 {
     __shared__ PhaseShared sh;
+    __shared__ uint32_t table[kMarkWords];
     const unsigned T = a.team_size, teams = gridDim.x / T, team_id = blockIdx.x / T;
     if (team_id >= teams)
         return;
@@ -420,11 +446,12 @@ __global__ __launch_bounds__(kStreamBlock) void phase_adjoint_kernel(PhaseArgs a
         return;
     }
     const bool leader = tm.rank == 0 && threadIdx.x == 0;
+    const bool use_table = build_phase_table(a, tm, table);
     for (uint32_t b = team_id; b < a.B; b += teams) {
         float4 *st = a.state + uint64_t(b) * a.nvec;
         float4 *lam = a.lambda + uint64_t(b) * a.nvec;
         double v[kPV] = {};
-        lambda_seed_pass(a, st, lam, tm, a.dloss[b], v);
+        lambda_seed_pass(a, st, lam, tm, table, use_table, a.dloss[b], v);
         if (!team_sum_n(v, tm, ++gen, sh))
             return;
         C2 sc{a.aux[2u * b], a.aux[2u * b + 1u]}, sl{v[2], v[3]};
@@ -442,7 +469,7 @@ __global__ __launch_bounds__(kStreamBlock) void phase_adjoint_kernel(PhaseArgs a
                                     ? a.ckpt + (uint64_t(b) * a.nck + ((k - 1u) / a.every - 1u)) * a.nvec
                                     : nullptr;
             double w[kPV] = {};
-            reverse_pass(a, st, lam, src, anchor, tm, beta_c, beta_l, {cos(ph), sin(ph)}, w);
+            reverse_pass(a, st, lam, src, anchor, tm, table, use_table, beta_c, beta_l, {cos(ph), sin(ph)}, w);
             if (!team_sum_n(w, tm, ++gen, sh))
                 return;
             if (leader)  // -2 Im(sum over marked of conj(nu) y)
