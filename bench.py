@@ -178,8 +178,9 @@ PAPER_TABLE1_S = {  # Table 1: seconds on an Intel i3-5005U, one thread (convent
 
 def sweep_table1(pkg, hip, stream) -> None:
     """The paper's Table 1 on this GPU: a full single-solution search (the optimal number of iterations from
-    the uniform superposition) with the proposed iteration and with the gate-level one, at the paper's
-    sizes; then three gate-level and proposed iterations at n = 28.  One JSON line per size."""
+    the uniform superposition) with the proposed iteration and with the gate-level one (H^n as n single-qubit
+    passes, and as the blocked Walsh-Hadamard transform), at the paper's sizes; then three iterations of
+    each at n = 28.  One JSON line per size."""
     import workloads
 
     for n in (10, 16, 18, 20, 28):
@@ -190,7 +191,8 @@ def sweep_table1(pkg, hip, stream) -> None:
         k = k_full if n <= 20 else 3
         res = {"sweep": "table1", "n": n, "iterations": k, "storage": "c64",
                "form": ["", "fused", "resident", "two_pass"][pkg.grover_query(ctx, 0)]}
-        for path, fn in (("proposed", pkg.grover_iterate), ("gate_level", pkg.grover_gate_iterate)):
+        for path, fn in (("proposed", pkg.grover_iterate), ("gate_level", pkg.grover_gate_iterate),
+                         ("gate_level_blocked", pkg.grover_gate_iterate_blocked)):
             pkg.grover_reset(ctx)
             fn(ctx, 1)  # warm
             pkg.grover_reset(ctx)
@@ -204,6 +206,7 @@ def sweep_table1(pkg, hip, stream) -> None:
             res[path + "_s"] = ms / 1e3
             res[path + "_amplitude_iterations_per_s"] = (1 << n) * k / (ms / 1e3)
         res["speedup_proposed_over_gate"] = res["gate_level_s"] / res["proposed_s"]
+        res["speedup_proposed_over_blocked_gate"] = res["gate_level_blocked_s"] / res["proposed_s"]
         if n in PAPER_TABLE1_S:
             conv, prop = PAPER_TABLE1_S[n]
             res["paper_i3_1thread_s"] = {"conventional": conv, "proposed": prop, "speedup": conv / prop}

@@ -128,6 +128,17 @@ int grover_gate_iterate(grover_ctx *ctx, uint64_t k);
  * GROVER_E_UNSUPPORTED for bfloat16 storage. */
 int grover_apply_hadamard_all(grover_ctx *ctx);
 
+/* grover_gate_iterate_blocked / grover_apply_hadamard_all_blocked — the same operators (Algorithm 2's
+ * iteration; H^n) with H^n computed as a blocked Walsh-Hadamard transform: qubits are transformed in
+ * groups held in LDS (12 or 13 low qubits per pass, then 8 or 9 per pass), with unnormalised butterflies in
+ * binary64 and the normalisation applied once (2^(-n/2) for H^n; for the iteration the exact 2^(-n) of
+ * both transforms, with the conditional phase shift fused into the first transform's last pass).  At
+ * n = 28 an H^n is 3 passes instead of 28.  Results equal the single-qubit path's up to rounding (one
+ * rounding to the storage type per pass instead of per qubit).  Asynchronous; GROVER_E_UNSUPPORTED for
+ * bfloat16 storage. */
+int grover_gate_iterate_blocked(grover_ctx *ctx, uint64_t k);
+int grover_apply_hadamard_all_blocked(grover_ctx *ctx);
+
 /* grover_sample — measurement (Background, step 6; the paper gives no procedure, this library defines it):
  *   p_i = re_i^2 + im_i^2 in binary64 (no fused multiply-add), q_i = floor(p_i * 2^62) as uint64,
  *   Q_i = q_0 + ... + q_i (exact integer prefix sum), and for shot j with 53-bit uniform U_j:

@@ -7,6 +7,7 @@
 #include <new>
 
 #include "internal.h"
+#include "wht.h"
 
 using namespace grover;
 
@@ -377,6 +378,29 @@ int grover_gate_iterate(grover_ctx *ctx, uint64_t k)
         GROVER_HIP(ctx, launch_conditional_phase_shift(ctx), "conditional phase shift");
         GROVER_HIP(ctx, launch_hadamard_all(ctx), "hadamard passes");
     }
+    return GROVER_OK;
+}
+
+int grover_gate_iterate_blocked(grover_ctx *ctx, uint64_t k)
+{
+    if (check_ctx(ctx))
+        return GROVER_E_INVAL;
+    if (ctx->dtype == GROVER_CBF16)
+        return fail(ctx, GROVER_E_UNSUPPORTED, "the gate-level path has no bfloat16 form");
+    for (uint64_t it = 0; it < k; ++it) {
+        GROVER_HIP(ctx, launch_oracle_flip(ctx), "oracle flip");
+        GROVER_HIP(ctx, launch_gate_diffusion_blocked(ctx), "blocked Walsh-Hadamard passes");
+    }
+    return GROVER_OK;
+}
+
+int grover_apply_hadamard_all_blocked(grover_ctx *ctx)
+{
+    if (check_ctx(ctx))
+        return GROVER_E_INVAL;
+    if (ctx->dtype == GROVER_CBF16)
+        return fail(ctx, GROVER_E_UNSUPPORTED, "the gate-level path has no bfloat16 form");
+    GROVER_HIP(ctx, launch_hadamard_all_blocked(ctx), "blocked Walsh-Hadamard passes");
     return GROVER_OK;
 }
 

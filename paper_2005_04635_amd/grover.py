@@ -127,6 +127,7 @@ EXPORTS = [
     "grover_sample", "grover_sample_u53", "grover_norm", "grover_read_state", "grover_write_state",
     "grover_state_device", "grover_marked", "grover_sync", "grover_query", "grover_optimal_iterations",
     "grover_destroy", "grover_status_str", "grover_last_error",
+    "grover_gate_iterate_blocked", "grover_apply_hadamard_all_blocked",
     "grover_batch_init", "grover_batch_set_tiling", "grover_batch_tune", "grover_batch_capture",
     "grover_batch_run", "grover_batch_sync", "grover_batch_state", "grover_batch_read_state",
     "grover_batch_query", "grover_batch_destroy", "grover_batch_last_error",
@@ -161,6 +162,8 @@ def load(path: str = LIB_PATH):
             "grover_iterate": (i32, [P, u64]),
             "grover_gate_iterate": (i32, [P, u64]),
             "grover_apply_hadamard_all": (i32, [P]),
+            "grover_gate_iterate_blocked": (i32, [P, u64]),
+            "grover_apply_hadamard_all_blocked": (i32, [P]),
             "grover_sample": (i32, [P, u64, u64, P, i32]),
             "grover_sample_u53": (i32, [P, P, i32, u64, P, i32]),
             "grover_norm": (i32, [P, ctypes.POINTER(ctypes.c_double)]),
@@ -237,6 +240,14 @@ def grover_gate_iterate(ctx, k: int) -> None:
 
 def grover_apply_hadamard_all(ctx) -> None:
     _check(ctx, load().grover_apply_hadamard_all(ctx))
+
+
+def grover_gate_iterate_blocked(ctx, k: int) -> None:
+    _check(ctx, load().grover_gate_iterate_blocked(ctx, k))
+
+
+def grover_apply_hadamard_all_blocked(ctx) -> None:
+    _check(ctx, load().grover_apply_hadamard_all_blocked(ctx))
 
 
 def grover_sample(ctx, shots: int, seed: int, out: int, out_is_device: bool) -> None:
@@ -485,8 +496,12 @@ class Grover:
         grover_gate_iterate(self.ctx, k)
         return self
 
-    def hadamard_all(self) -> "Grover":
-        grover_apply_hadamard_all(self.ctx)
+    def hadamard_all(self, blocked: bool = False) -> "Grover":
+        (grover_apply_hadamard_all_blocked if blocked else grover_apply_hadamard_all)(self.ctx)
+        return self
+
+    def gate_iterate_blocked(self, k: int) -> "Grover":
+        grover_gate_iterate_blocked(self.ctx, k)
         return self
 
     def sample(self, shots: int, seed: Optional[int] = None, u53=None, device_out: bool = False):

@@ -71,6 +71,8 @@ def test_status_strings_and_null_handling(lib):
     assert lib.grover_status_str(-99) == b"unknown status"
     assert lib.grover_last_error(None) == b"no context"
     assert lib.grover_iterate(None, 5) == -1
+    assert lib.grover_gate_iterate_blocked(None, 1) == -1
+    assert lib.grover_apply_hadamard_all_blocked(None) == -1
     assert lib.grover_sync(None) == -1
     lib.grover_destroy(None)
 

@@ -218,3 +218,21 @@ def test_phase_n20_workload(G, orc):
               f"{max(np.max(np.abs(wphi)), np.max(np.abs(wtheta))):.3g}", flush=True)
         assert err <= tol, b
     eng.close()
+
+
+def test_n28_blocked_gate_iterations(G, orc):
+    """The blocked Walsh-Hadamard gate path at n = 28 (3 passes per H^n): three conventional iterations of
+    the hash workload from the uniform state against the oracle's two-class values."""
+    w = workloads.HASH_N28
+    g = G.Grover(w.n, w.dtype, hash_seed=w.hash_seed, hash_bits=w.hash_bits, m=w.m, form="fused")
+    marks = g.marked()
+    g.reset().gate_iterate_blocked(3)
+    got = g.read_state()
+    mask = np.zeros(1 << w.n, dtype=bool)
+    mask[marks.astype(np.int64)] = True
+    a, b = orc.two_class(w.n, w.m, 3)
+    assert np.max(np.abs(got[mask].astype(np.complex128) - a)) <= 1e-5
+    un = got[~mask]
+    for s in range(0, un.size, 1 << 24):
+        assert np.max(np.abs(un[s:s + (1 << 24)].astype(np.complex128) - b)) <= 1e-5
+    g.close()
