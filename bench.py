@@ -319,19 +319,21 @@ def sweep_batch(pkg, hip, stream, runs: int) -> None:
         pkg.grover_batch_sync(b)
         return ms
 
-    cands = [(0, 1)] + [(s, t) for s in (17, 18, 19, 20) for t in (2, 4, 8, 16, 32) if t <= grid]
+    cands = [(0, 1, 0)] + [(s, t, 0) for s in (18, 19, 20) for t in (2, 4, 8) if t <= grid]
+    cands += [(19, 2, r) for r in (8, 4, 2, 1)]
     best = None
-    for split, team in cands:
-        pkg.grover_batch_set_tiling(b, split, team)
+    for split, team, res in cands:
+        pkg.grover_batch_set_tiling(b, split, team, res)
         timed_run()  # warm
         ms = min(timed_run() for _ in range(2))
-        log(f"[bench] tiling split={split} team={team}: {ms:.1f} ms")
-        print(json.dumps({"sweep": "batch_tiling", "split_n": split, "team": team,
-                          "in_team_queue": pkg.grover_batch_query(b, g.BQ_N_TEAM), "ms": round(ms, 3),
+        log(f"[bench] tiling split={split} team={team} resident={res}: {ms:.1f} ms")
+        print(json.dumps({"sweep": "batch_tiling", "split_n": split, "team": team, "resident": res,
+                          "in_teams": pkg.grover_batch_query(b, g.BQ_N_TEAM),
+                          "phases": pkg.grover_batch_query(b, g.BQ_PHASES), "ms": round(ms, 3),
                           "amplitude_updates_per_s": updates / (ms / 1e3)}), flush=True)
-        if best is None or ms < best[2]:
-            best = (split, team, ms)
-    pkg.grover_batch_set_tiling(b, best[0], best[1])
+        if best is None or ms < best[3]:
+            best = (split, team, res, ms)
+    pkg.grover_batch_set_tiling(b, best[0], best[1], best[2])
     pkg.grover_batch_capture(b)
     pkg.grover_batch_run(b)
     pkg.grover_batch_sync(b)
@@ -374,7 +376,8 @@ def sweep_batch(pkg, hip, stream, runs: int) -> None:
     gbs = alg_bytes / (ms / 1e3) / 1e9
     print(json.dumps({
         "sweep": "batch", "workload": w.name, "instances": w.count, "amplitude_updates": updates,
-        "state_bytes": state_bytes, "split_n": best[0], "team": best[1], "graph": True, "runs": runs,
+        "state_bytes": state_bytes, "split_n": best[0], "team": best[1], "resident": best[2], "graph": True,
+        "runs": runs,
         "ms_per_run": round(ms, 3), "wall_ms_per_run": round(wall_ms, 3), "amplitude_updates_per_s": rate,
         "algorithmic_gbs": round(gbs, 1), "frac_of_hbm_peak": round(gbs / HBM_PEAK_GBS, 4),
         "one_by_one": one_by_one,

@@ -203,11 +203,16 @@ const char *grover_last_error(const grover_ctx *ctx);
  * GROVER_C64 + GROVER_ACC_F64 context).  Instance i has n[i] qubits (1 <= n[i] <= 24), m[i] marked
  * indices and iterations[i] iterations (k_opt(n[i], m[i]) when `iterations` is NULL).
  *
- * How the device divides the work is the tiling: instances with n >= split_n are iterated one at a time by
- * teams of `team` workgroups each (team = grid size: the whole device per instance); the rest are taken
- * one per workgroup (held in registers when 2^n <= 16384, else streamed).  The tiling changes the order of
- * additions in the sums, so results of two tilings agree to rounding, and one tiling's results are
- * reproducible bit for bit.  grover_batch_tune times the candidates and keeps the fastest. */
+ * How the device divides the work is the tiling (split_n, team, resident):
+ *   - states of 2^n <= 16384 amplitudes are iterated by one workgroup each, held in its registers;
+ *   - with resident = r in {1, 2, 4, 8}, a larger state is held in the registers of a team of T
+ *     workgroups, T the power of two >= 2^n / (2048 r) (r 16-byte vectors per thread), when T does not
+ *     exceed the grid: one team barrier per iteration and no memory traffic until the final write;
+ *   - the remaining states stream from memory every iteration: those with n >= split_n by teams of `team`
+ *     workgroups each (team = grid size: the whole device per instance), the others one per workgroup.
+ * The tiling changes the order of additions in the sums, so results of two tilings agree to rounding, and
+ * one tiling's results are reproducible bit for bit.  grover_batch_tune times candidates and keeps the
+ * fastest. */
 typedef struct grover_batch grover_batch;
 
 typedef struct grover_batch_config {
@@ -227,17 +232,20 @@ typedef struct grover_batch_config {
  * the fused form).  hip_stream: the hipStream_t all batch work goes to (NULL = default stream; graph capture
  * then unavailable).  Synchronous.  GROVER_E_INVAL for a bad config (before any device work),
  * GROVER_E_UNSUPPORTED for a dtype other than GROVER_C64, GROVER_E_COOP when no grid is co-resident.
- * The initial tiling is split_n = 19, team = 4. */
+ * The initial tiling is split_n = 19, team = 2, resident = 8. */
 int grover_batch_init(grover_batch **out, const grover_batch_config *cfg, void *hip_stream);
 
-/* grover_batch_set_tiling — choose the tiling (team in [1, grid size]; team = 1 puts every instance in the
- * one-per-workgroup queue).  Drops a captured graph.  Synchronous. */
-int grover_batch_set_tiling(grover_batch *b, uint32_t split_n, uint32_t team);
+/* grover_batch_set_tiling — choose the tiling: team in [1, grid size] (team = 1: no streamed teams),
+ * resident in {0, 1, 2, 4, 8} (0: no register-resident teams).  GROVER_E_INVAL outside those ranges,
+ * GROVER_E_UNSUPPORTED when a streamed team size does not divide the resident teams' sizes.  Drops a
+ * captured graph.  Synchronous. */
+int grover_batch_set_tiling(grover_batch *b, uint32_t split_n, uint32_t team, uint32_t resident);
 
-/* grover_batch_tune — run the batch once per candidate tiling (split_n in {18, 19, 20} x team in {2, 4, 8,
- * 16}, and team = 1), keep the fastest, and report it (any output pointer may be NULL).  Overwrites the
- * states; synchronous; drops a captured graph. */
-int grover_batch_tune(grover_batch *b, uint32_t *split_n, uint32_t *team, float *best_ms);
+/* grover_batch_tune — run the batch once per candidate tiling (streamed: team = 1, and split_n in
+ * {18, 19, 20} x team in {2, 4, 8}; register-resident: resident in {8, 4, 2} with split_n = 19, team = 2),
+ * keep the fastest, and report it (any output pointer may be NULL).  Overwrites the states; synchronous;
+ * drops a captured graph. */
+int grover_batch_tune(grover_batch *b, uint32_t *split_n, uint32_t *team, uint32_t *resident, float *best_ms);
 
 /* grover_batch_capture — record one run (queue reset + the persistent launch) into a HIP graph that later
  * grover_batch_run calls replay.  Needs a non-NULL stream; GROVER_E_UNSUPPORTED when the runtime cannot
@@ -261,7 +269,7 @@ int grover_batch_read_state(grover_batch *b, uint64_t i, void *host, size_t byte
 
 /* grover_batch_query — key: 0 = count, 1 = persistent grid size, 2 = split_n, 3 = team, 4 = total amplitude
  * updates per run (sum of 2^n[i] * iterations[i]), 5 = 1 when a captured graph is in use, 6 = bytes of all
- * states, 7 = instances in the team queue. */
+ * states, 7 = instances iterated by multi-workgroup teams, 8 = resident, 9 = phases of the tiling. */
 int grover_batch_query(grover_batch *b, int key, int64_t *value);
 
 /* grover_batch_destroy — wait for the stream and release everything.  NULL is ignored. */

@@ -7,7 +7,7 @@
 #include <new>
 #include <numeric>
 
-#include "internal.h"
+#include "batch.h"
 
 using namespace grover;
 
@@ -24,13 +24,16 @@ struct grover_batch {
     void *state = nullptr;
     uint64_t *marks_dev = nullptr;
     BatchInstance *inst_dev = nullptr;
-    uint32_t *queue_team = nullptr, *queue_single = nullptr;
+    uint32_t *queue = nullptr;
     unsigned long long *heads = nullptr;
     GridSync *team_sync = nullptr;
     uint64_t *team_partials = nullptr, *team_mail = nullptr;
     int grid = 0;
-    uint32_t split_n = 0, team_size = 1;
-    uint64_t n_team = 0, n_single = 0;
+    uint32_t split_n = 0, team_size = 1, resident = 0;
+    uint64_t n_team = 0;  // instances in multi-workgroup phases
+    uint32_t nphases = 0;
+    uint64_t qoff[kBatchMaxPhases + 1] = {};
+    uint32_t phase_team[kBatchMaxPhases] = {}, phase_resident[kBatchMaxPhases] = {};
     uint64_t timeout_ticks = 0;
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
@@ -83,9 +86,8 @@ void release(grover_batch *b)
         (void)hipGraphExecDestroy(b->exec);
     if (b->graph)
         (void)hipGraphDestroy(b->graph);
-    for (void *p : {b->state, (void *)b->marks_dev, (void *)b->inst_dev, (void *)b->queue_team,
-                    (void *)b->queue_single, (void *)b->heads, (void *)b->team_sync, (void *)b->team_partials,
-                    (void *)b->team_mail})
+    for (void *p : {b->state, (void *)b->marks_dev, (void *)b->inst_dev, (void *)b->queue, (void *)b->heads,
+                    (void *)b->team_sync, (void *)b->team_partials, (void *)b->team_mail})
         if (p)
             (void)hipFree(p);
     delete b;
@@ -93,20 +95,22 @@ void release(grover_batch *b)
 
 BatchLaunch launch_of(const grover_batch *b, uint64_t timeout_ticks)
 {
-    BatchLaunch L;
+    BatchLaunch L{};
     L.state = b->state;
     L.marks = b->marks_dev;
     L.inst = b->inst_dev;
-    L.queue_team = b->queue_team;
-    L.n_team = b->n_team;
-    L.queue_single = b->queue_single;
-    L.n_single = b->n_single;
+    L.queue = b->queue;
+    for (int p = 0; p <= kBatchMaxPhases; ++p)
+        L.qoff[p] = b->qoff[p];
+    for (int p = 0; p < kBatchMaxPhases; ++p) {
+        L.team[p] = b->phase_team[p];
+        L.resident[p] = b->phase_resident[p];
+    }
+    L.nphases = b->nphases;
     L.heads = b->heads;
-    L.team_sync = b->team_sync;
-    L.team_partials = b->team_partials;
-    L.team_mail = b->team_mail;
-    L.team_size = b->team_size;
-    L.teams_alloc = uint32_t(b->grid);
+    L.sync = b->team_sync;
+    L.partials = b->team_partials;
+    L.mail = b->team_mail;
     L.grid = b->grid;
     L.timeout_ticks = timeout_ticks;
     L.stream = b->stream;
@@ -117,7 +121,7 @@ BatchLaunch launch_of(const grover_batch *b, uint64_t timeout_ticks)
 int check_barriers(grover_batch *b)
 {
     BATCH_HIP(b, hipStreamSynchronize(b->stream), "stream synchronise");
-    std::vector<GridSync> gs(size_t(b->grid));
+    std::vector<GridSync> gs(size_t(b->grid) * kBatchMaxPhases);
     BATCH_HIP(b, hipMemcpy(gs.data(), b->team_sync, gs.size() * sizeof(GridSync), hipMemcpyDeviceToHost),
               "barrier status download");
     for (const GridSync &g : gs)
@@ -126,27 +130,90 @@ int check_barriers(grover_batch *b)
     return GROVER_OK;
 }
 
-// Queues of a tiling: instances with n >= split_n go to the team queue when team_size > 1, the rest to the
-// single queue; both ordered by decreasing work N * k (ties by index, for a reproducible order).
-int apply_tiling(grover_batch *b, uint32_t split_n, uint32_t team_size)
+uint32_t next_pow2(uint64_t x)
+{
+    uint32_t p = 1;
+    while (p < x)
+        p <<= 1;
+    return p;
+}
+
+// Phases of a tiling.  With resident vectors r > 0, an instance whose state fits the registers of a team of
+// T = the power of two >= nvec / (r * 1024) workgroups (T no larger than the largest power of two <= grid)
+// runs in the resident phase of that T; states of <= 8192 vectors (n <= 14) run alone in registers.
+// Every other instance streams: with n >= split_n and team > 1 in a streamed phase of teams of `team`
+// workgroups, else alone.  Phases are ordered by decreasing team size (streamed before resident at equal
+// size), each queue by decreasing work N * k (ties by index, for a reproducible order).
+int apply_tiling(grover_batch *b, uint32_t split_n, uint32_t team_size, uint32_t resident)
 {
     if (team_size < 1 || team_size > uint32_t(b->grid))
         return bfail(b, GROVER_E_INVAL, "team size must lie in [1, grid size]");
+    if (resident > uint32_t(kBatchResE) || (resident & (resident - 1u)) != 0u)
+        return bfail(b, GROVER_E_INVAL, "resident vectors per thread must be 0, 1, 2, 4 or 8");
+    const uint32_t max_team = next_pow2(uint64_t(b->grid) + 1) / 2;  // largest power of two <= grid
     std::vector<uint32_t> order(b->count);
     std::iota(order.begin(), order.end(), 0u);
     auto work = [&](uint32_t i) { return double(b->nvec[i]) * double(b->iters[i] + 1); };
     std::stable_sort(order.begin(), order.end(), [&](uint32_t x, uint32_t y) { return work(x) > work(y); });
-    std::vector<uint32_t> qt, qs;
-    for (uint32_t i : order)
-        (team_size > 1 && b->n[i] >= split_n ? qt : qs).push_back(i);
-    if (!qt.empty())
-        BATCH_HIP(b, hipMemcpy(b->queue_team, qt.data(), qt.size() * 4, hipMemcpyHostToDevice), "queue upload");
-    if (!qs.empty())
-        BATCH_HIP(b, hipMemcpy(b->queue_single, qs.data(), qs.size() * 4, hipMemcpyHostToDevice), "queue upload");
-    b->n_team = qt.size();
-    b->n_single = qs.size();
+    // phase key: team size, and streamed (1) before resident (0) at equal size
+    std::vector<std::pair<std::pair<uint32_t, uint32_t>, std::vector<uint32_t>>> phases;
+    auto phase_of = [&](uint32_t t, uint32_t streamed) -> std::vector<uint32_t> & {
+        for (auto &ph : phases)
+            if (ph.first == std::make_pair(t, streamed))
+                return ph.second;
+        phases.push_back({{t, streamed}, {}});
+        return phases.back().second;
+    };
+    uint64_t n_team = 0;
+    for (uint32_t i : order) {
+        const uint64_t nvec = b->nvec[i];
+        if (nvec <= uint64_t(kBatchResE) * 1024u) {
+            phase_of(1, 0).push_back(i);
+            continue;
+        }
+        if (resident > 0) {
+            const uint32_t t = next_pow2((nvec + uint64_t(resident) * 1024u - 1) / (uint64_t(resident) * 1024u));
+            if (t <= max_team) {
+                phase_of(t, 0).push_back(i);
+                ++n_team;
+                continue;
+            }
+        }
+        if (team_size > 1 && b->n[i] >= split_n) {
+            phase_of(team_size, 1).push_back(i);
+            ++n_team;
+        } else {
+            phase_of(1, 0).push_back(i);
+        }
+    }
+    std::stable_sort(phases.begin(), phases.end(), [](const auto &x, const auto &y) {
+        return x.first.first != y.first.first ? x.first.first > y.first.first : x.first.second > y.first.second;
+    });
+    // each team size must divide the previous one (all are powers of two except a streamed `team`)
+    for (size_t p = 1; p < phases.size(); ++p)
+        if (phases[p - 1].first.first % phases[p].first.first != 0u)
+            return bfail(b, GROVER_E_UNSUPPORTED,
+                         "the streamed team size must be a power of two when resident teams are used");
+    if (phases.size() > size_t(kBatchMaxPhases))
+        return bfail(b, GROVER_E_UNSUPPORTED, "too many phases");
+    std::vector<uint32_t> q;
+    q.reserve(b->count);
+    b->nphases = uint32_t(phases.size());
+    for (int p = 0; p <= kBatchMaxPhases; ++p)
+        b->qoff[p] = 0;
+    for (size_t p = 0; p < phases.size(); ++p) {
+        b->qoff[p] = q.size();
+        b->phase_team[p] = phases[p].first.first;
+        b->phase_resident[p] = phases[p].first.second ? 0u : (phases[p].first.first > 1 ? resident : 1u);
+        q.insert(q.end(), phases[p].second.begin(), phases[p].second.end());
+    }
+    for (size_t p = phases.size(); p <= size_t(kBatchMaxPhases); ++p)
+        b->qoff[p] = q.size();
+    BATCH_HIP(b, hipMemcpy(b->queue, q.data(), q.size() * 4, hipMemcpyHostToDevice), "queue upload");
+    b->n_team = n_team;
     b->split_n = split_n;
     b->team_size = team_size;
+    b->resident = resident;
     if (b->exec) {  // a captured graph holds the old tiling's arguments
         (void)hipGraphExecDestroy(b->exec);
         (void)hipGraphDestroy(b->graph);
@@ -164,17 +231,16 @@ int select_grid(grover_batch *b, int clock_khz)
     int per_cu = 0;
     BATCH_HIP(b, hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, batch_kernel_fn(), 1024, 0), "occupancy");
     const int max_grid = std::max(1, per_cu) * b->cu_count;
-    BATCH_HIP(b, balloc(&b->team_sync, size_t(max_grid) * sizeof(GridSync)), "batch allocation");
-    BATCH_HIP(b, balloc(&b->team_partials, size_t(max_grid) * 4 * sizeof(uint64_t)), "batch allocation");
-    BATCH_HIP(b, balloc(&b->team_mail, size_t(max_grid) * 32 * sizeof(uint64_t)), "batch allocation");
+    BATCH_HIP(b, balloc(&b->team_sync, size_t(max_grid) * kBatchMaxPhases * sizeof(GridSync)), "batch allocation");
+    BATCH_HIP(b, balloc(&b->team_partials, size_t(max_grid) * kBatchMaxPhases * 8 * sizeof(uint64_t)),
+              "batch allocation");
+    BATCH_HIP(b, balloc(&b->team_mail, size_t(max_grid) * kBatchMaxPhases * 32 * sizeof(uint64_t)),
+              "batch allocation");
     const uint64_t probe_ticks = uint64_t(clock_khz > 0 ? clock_khz : 100000) * 250;  // 0.25 s
     for (int pc = per_cu > 1 ? per_cu - 1 : 1; pc >= 1; --pc) {
         b->grid = pc * b->cu_count;
         BatchLaunch L = launch_of(b, probe_ticks);
-        L.n_team = 0;
-        L.n_single = 0;
-        L.team_size = uint32_t(b->grid);
-        L.teams_alloc = uint32_t(b->grid);
+        L.probe = 1;
         BATCH_HIP(b, launch_batch(L), "batch grid check");
         BATCH_HIP(b, hipStreamSynchronize(b->stream), "batch grid check");
         if (check_barriers(b) == GROVER_OK)
@@ -318,11 +384,9 @@ int grover_batch_init(grover_batch **out, const grover_batch_config *cfg, void *
         if (e == hipSuccess)
             e = balloc(&b->inst_dev, b->count * sizeof(BatchInstance));
         if (e == hipSuccess)
-            e = balloc(&b->queue_team, b->count * 4);
+            e = balloc(&b->queue, b->count * 4);
         if (e == hipSuccess)
-            e = balloc(&b->queue_single, b->count * 4);
-        if (e == hipSuccess)
-            e = balloc(&b->heads, 2 * sizeof(unsigned long long));
+            e = balloc(&b->heads, kBatchMaxPhases * sizeof(unsigned long long));
         if (e == hipSuccess && total_m > 0)
             e = hipMemcpy(b->marks_dev, b->marks.data(), total_m * sizeof(uint64_t), hipMemcpyHostToDevice);
         if (e == hipSuccess)
@@ -334,8 +398,9 @@ int grover_batch_init(grover_batch **out, const grover_batch_config *cfg, void *
         status = select_grid(b, clock_khz);
         if (status != GROVER_OK)
             throw status;
-        // default tiling until tuned: teams of 4 for the largest instances (n >= 19), the rest alone
-        status = apply_tiling(b, 19, b->grid >= 4 ? 4u : 1u);
+        // default tiling until tuned: states in the registers of teams sized to hold 8 vectors per thread;
+        // states too large for that stream with teams of 2
+        status = apply_tiling(b, 19, b->grid >= 2 ? 2u : 1u, uint32_t(kBatchResE));
         if (status != GROVER_OK)
             throw status;
     } catch (int) {
@@ -349,11 +414,11 @@ int grover_batch_init(grover_batch **out, const grover_batch_config *cfg, void *
     return GROVER_OK;
 }
 
-int grover_batch_set_tiling(grover_batch *b, uint32_t split_n, uint32_t team_size)
+int grover_batch_set_tiling(grover_batch *b, uint32_t split_n, uint32_t team_size, uint32_t resident)
 {
     if (!b)
         return GROVER_E_INVAL;
-    return apply_tiling(b, split_n, team_size);
+    return apply_tiling(b, split_n, team_size, resident);
 }
 
 int grover_batch_run(grover_batch *b)
@@ -375,18 +440,20 @@ int grover_batch_sync(grover_batch *b)
     return check_barriers(b);
 }
 
-int grover_batch_tune(grover_batch *b, uint32_t *split_n, uint32_t *team_size, float *best_ms)
+int grover_batch_tune(grover_batch *b, uint32_t *split_n, uint32_t *team_size, uint32_t *resident, float *best_ms)
 {
     if (!b)
         return GROVER_E_INVAL;
     struct Cand {
-        uint32_t split, team;
+        uint32_t split, team, resident;
     };
-    std::vector<Cand> cands = {{0, 1}};
+    std::vector<Cand> cands = {{0, 1, 0}};
     for (uint32_t split : {18u, 19u, 20u})
-        for (uint32_t t : {2u, 4u, 8u, 16u})
+        for (uint32_t t : {2u, 4u, 8u})
             if (t <= uint32_t(b->grid))
-                cands.push_back({split, t});
+                cands.push_back({split, t, 0});
+    for (uint32_t r : {8u, 4u, 2u})
+        cands.push_back({19, 2, r});
     hipEvent_t e0, e1;
     BATCH_HIP(b, hipEventCreate(&e0), "event");
     BATCH_HIP(b, hipEventCreate(&e1), "event");
@@ -394,7 +461,7 @@ int grover_batch_tune(grover_batch *b, uint32_t *split_n, uint32_t *team_size, f
     Cand pick = cands[0];
     int status = GROVER_OK;
     for (const Cand &c : cands) {
-        status = apply_tiling(b, c.split, c.team);
+        status = apply_tiling(b, c.split, c.team, c.resident);
         if (status != GROVER_OK)
             break;
         hipError_t e = hipEventRecord(e0, b->stream);
@@ -423,13 +490,15 @@ int grover_batch_tune(grover_batch *b, uint32_t *split_n, uint32_t *team_size, f
     (void)hipEventDestroy(e1);
     if (status != GROVER_OK)
         return status;
-    status = apply_tiling(b, pick.split, pick.team);
+    status = apply_tiling(b, pick.split, pick.team, pick.resident);
     if (status != GROVER_OK)
         return status;
     if (split_n)
         *split_n = pick.split;
     if (team_size)
         *team_size = pick.team;
+    if (resident)
+        *resident = pick.resident;
     if (best_ms)
         *best_ms = best;
     return GROVER_OK;
@@ -513,6 +582,8 @@ int grover_batch_query(grover_batch *b, int key, int64_t *value)
     case 5: *value = b->exec ? 1 : 0; break;
     case 6: *value = int64_t(b->total_vecs * 16); break;
     case 7: *value = int64_t(b->n_team); break;
+    case 8: *value = b->resident; break;
+    case 9: *value = b->nphases; break;
     default: return bfail(b, GROVER_E_INVAL, "unknown query key");
     }
     return GROVER_OK;

@@ -315,17 +315,6 @@ struct GridSync {
 };
 static_assert(sizeof(GridSync) == 1024, "barrier words on separate lines");
 
-// One instance of a batch (device table, written by the host).
-struct BatchInstance {
-    uint64_t state_off;  // first 16-byte vector of the instance's state in the batch buffer
-    uint64_t nvec;       // N / 2 (complex64: two amplitudes per vector)
-    uint64_t marks_off;  // first entry of its sorted marked list in the concatenated marks
-    uint64_t m;
-    uint64_t iters;
-    double N;
-    double amp;  // 2^(-n/2) in binary64 (rounded to the storage type by the fill)
-};
-
 // ------------------------------------------------------------------------------------------ context
 }  // namespace grover
 
@@ -396,28 +385,6 @@ hipError_t launch_norm(grover_ctx *c, double *dev_out);
 hipError_t launch_sample(grover_ctx *c, const uint64_t *u53_dev, uint64_t seed, bool device_uniforms,
                          uint64_t shots, uint64_t *out_dev);
 size_t sample_block_count(uint64_t N);
-
-// Batched searches: everything one launch needs (device pointers from the batch context).
-struct BatchLaunch {
-    void *state;
-    const uint64_t *marks;
-    const BatchInstance *inst;
-    const uint32_t *queue_team;
-    uint64_t n_team;
-    const uint32_t *queue_single;
-    uint64_t n_single;
-    unsigned long long *heads;
-    GridSync *team_sync;
-    uint64_t *team_partials;
-    uint64_t *team_mail;
-    uint32_t team_size;
-    uint32_t teams_alloc;  // team barrier objects allocated (zeroed before every run)
-    int grid;
-    uint64_t timeout_ticks;
-    hipStream_t stream;
-};
-const void *batch_kernel_fn();
-hipError_t launch_batch(const BatchLaunch &L);
 
 hipError_t launch_oracle_flip(grover_ctx *c);
 hipError_t launch_hadamard_all(grover_ctx *c);

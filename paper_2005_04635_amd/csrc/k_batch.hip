@@ -1,34 +1,40 @@
 // Batched searches in one persistent launch (many independent instances of Algorithm 5, complex64 states,
-// binary64 sums).  The grid (one workgroup per CU, all co-resident) works through two queues, each ordered
-// by decreasing work N * k:
-//   1. team queue: the grid is split into teams of T consecutive workgroups; a team takes one instance at a
-//      time and iterates it exactly as the fused single-instance kernel does, with a team barrier per
-//      iteration (T = grid size is grid-per-instance);
-//   2. single queue: once the team queue is empty, every workgroup takes instances alone — held in
-//      registers for the whole run when the state fits (n <= 14), otherwise streamed with workgroup-level
-//      sums only (workgroup-per-instance).
-// Which instances go to the team queue (n >= split) and T are the tiling the host's autotuner chooses.
-// Each instance starts from the uniform superposition, written by the instance's own first pass.
+// binary64 update and sums).  The grid (one workgroup per CU, all co-resident) works through a sequence of
+// phases, each with its own queue ordered by decreasing work N * k and its own team size T:
+//   - in a phase with T > 1 the grid is split into teams of T consecutive workgroups; a team's leader takes
+//     the next instance and publishes it through the team barrier, and the team iterates it with one team
+//     barrier per iteration (which also reduces the sum).  The state is either held in the team's
+//     registers for all iterations (resident phases: the instance fits T * 1024 threads * the phase's
+//     vectors per thread) or streamed from memory every iteration, exactly as the fused single-instance
+//     kernel does;
+//   - in a phase with T = 1 every workgroup takes instances alone: held in registers when the state fits
+//     (n <= 14), otherwise streamed with workgroup-level sums only.
+// Team sizes do not increase from one phase to the next and each divides the previous one, so the members
+// of a team always come from one team of the previous phase (they finish it together) and no grid-wide
+// barrier is needed between phases.  Which phases exist and their parameters is the tiling the host
+// chooses; each instance starts from the uniform superposition.
+#include "batch.h"
 #include "stream.h"
 
 namespace grover {
 namespace {
 
-constexpr int kResE = 8;  // 16-byte vectors per thread for a register-held state: N <= 2 * 8 * 1024
+constexpr int kResE = kBatchResE;
 
 struct BatchArgs {
     float4 *state;
     const uint64_t *marks;
     const BatchInstance *inst;
-    const uint32_t *queue_team;
-    uint64_t n_team;
-    const uint32_t *queue_single;
-    uint64_t n_single;
-    unsigned long long *heads;  // [0] next team-queue entry, [1] next single-queue entry
-    GridSync *team_sync;        // one per team
-    uint64_t *team_partials;    // [teams][2][T][2]
-    uint64_t *team_mail;        // one 256-byte line per team: the instance its leader took
-    uint32_t team_size;
+    const uint32_t *queue;
+    uint64_t qoff[kBatchMaxPhases + 1];
+    uint32_t team[kBatchMaxPhases];
+    uint32_t resident[kBatchMaxPhases];
+    uint32_t nphases;
+    uint32_t probe;
+    unsigned long long *heads;
+    GridSync *sync;
+    uint64_t *partials;
+    uint64_t *mail;
     uint64_t timeout_ticks;
 };
 
@@ -51,8 +57,8 @@ __device__ inline float4 uniform_vec(double amp)
     return make_float4(af, 0.0f, af, 0.0f);
 }
 
-// One instance iterated by the T workgroups of a team.  Returns false when a barrier gave up.
-__device__ bool run_team_instance(const BatchArgs &a, const BatchInstance &I, const Team &tm, uint64_t &gen,
+// One instance streamed by the T workgroups of a team.  Returns false when a barrier gave up.
+__device__ bool run_team_streamed(const BatchArgs &a, const BatchInstance &I, const Team &tm, uint64_t &gen,
                                   TeamShared<double> &sh, uint32_t *table)
 {
     const Share<C64> share{a.state + I.state_off, I.nvec, a.marks + I.marks_off, I.m, tm.rank, tm.size};
@@ -71,6 +77,55 @@ __device__ bool run_team_instance(const BatchArgs &a, const BatchInstance &I, co
         si = acc.i;
         if (!team_sum<double>(sr, si, tm, ++gen, sh))
             return false;
+    }
+    return true;
+}
+
+// One instance held in the registers of the T workgroups of a team for all its iterations: member `rank`
+// owns the contiguous vectors [rank * per, (rank + 1) * per), per = nvec / T <= kResE * 1024, thread `tid`
+// the vectors rank * per + e * 1024 + tid.  The state is written to memory once, at the end.
+__device__ bool run_team_resident(const BatchArgs &a, const BatchInstance &I, const Team &tm, uint64_t &gen,
+                                  TeamShared<double> &sh)
+{
+    const uint64_t per = I.nvec / tm.size;
+    const uint64_t base = uint64_t(tm.rank) * per;
+    float4 *st = a.state + I.state_off + base;
+    const uint64_t *marks = a.marks + I.marks_off;
+    const unsigned tid = threadIdx.x;
+    float4 x[kResE];
+    unsigned bits[kResE];
+    const float4 fill = uniform_vec(I.amp);
+    AccF64 acc0;
+#pragma unroll
+    for (int e = 0; e < kResE; ++e) {
+        const uint64_t v = uint64_t(e) * kStreamBlock + tid;
+        bits[e] = 0u;
+        if (v < per) {
+            x[e] = fill;
+            bits[e] = marked_bits<2>(marks, 0, I.m, (base + v) * 2u);
+            accum_vec<C64>(x[e], bits[e], acc0);
+        }
+    }
+    double sr = acc0.r, si = acc0.i;
+    if (!team_sum<double>(sr, si, tm, ++gen, sh))
+        return false;
+    for (uint64_t it = 0; it < I.iters; ++it) {
+        const double mr = (sr * 2.0) / I.N, mi = (si * 2.0) / I.N;
+        AccF64 acc;
+#pragma unroll
+        for (int e = 0; e < kResE; ++e)
+            if (uint64_t(e) * kStreamBlock + tid < per)
+                update_vec<C64>(x[e], mr, mi, bits[e], acc);
+        sr = acc.r;
+        si = acc.i;
+        if (!team_sum<double>(sr, si, tm, ++gen, sh))
+            return false;
+    }
+#pragma unroll
+    for (int e = 0; e < kResE; ++e) {
+        const uint64_t v = uint64_t(e) * kStreamBlock + tid;
+        if (v < per)
+            st[v] = x[e];
     }
     return true;
 }
@@ -142,19 +197,45 @@ __global__ __launch_bounds__(kStreamBlock) void batch_kernel(BatchArgs a)
     __shared__ TeamShared<double> sh;
     __shared__ uint32_t table[kMarkWords];
     __shared__ uint64_t taken;
-    // 1. team queue
-    const unsigned T = a.team_size;
-    const unsigned teams = T > 1 ? gridDim.x / T : 0u;
-    const unsigned team_id = blockIdx.x / (T > 0 ? T : 1u);
-    if (team_id < teams) {
-        const Team tm{a.team_sync + team_id, a.team_partials + uint64_t(team_id) * 4u * T, T, blockIdx.x % T,
+    const uint32_t grid = gridDim.x;
+    if (a.probe) {
+        const Team tm{a.sync, a.partials, grid, blockIdx.x, a.timeout_ticks};
+        double zr = 0.0, zi = 0.0;
+        (void)team_sum<double>(zr, zi, tm, 1u, sh);
+        return;
+    }
+    for (uint32_t p = 0; p < a.nphases; ++p) {
+        const uint64_t q0 = a.qoff[p], count = a.qoff[p + 1] - q0;
+        const unsigned T = a.team[p];
+        const unsigned teams = grid / T, team_id = blockIdx.x / T;
+        if (count == 0 || team_id >= teams)
+            continue;
+        if (T == 1) {
+            for (;;) {
+                if (threadIdx.x == 0)
+                    taken = atomicAdd(&a.heads[p], 1ull);
+                __syncthreads();
+                const uint64_t q = taken;
+                __syncthreads();
+                if (q >= count)
+                    break;
+                const BatchInstance I = a.inst[a.queue[q0 + q]];
+                if (I.nvec <= uint64_t(kResE) * kStreamBlock)
+                    run_single_resident(a, I, sh);
+                else
+                    run_single_streamed(a, I, sh, table);
+            }
+            continue;
+        }
+        const Team tm{a.sync + uint64_t(p) * grid + team_id,
+                      a.partials + uint64_t(p) * 8u * grid + uint64_t(team_id) * 8u * T, T, blockIdx.x % T,
                       a.timeout_ticks};
-        uint64_t *mail = a.team_mail + uint64_t(team_id) * 32u;
+        uint64_t *mail = a.mail + (uint64_t(p) * grid + team_id) * 32u;
         uint64_t gen = 0;
         for (;;) {
             // the leader takes the next instance; the barrier that follows publishes it to the team
             if (tm.rank == 0 && threadIdx.x == 0)
-                __hip_atomic_store(mail, uint64_t(atomicAdd(&a.heads[0], 1ull)), __ATOMIC_RELAXED,
+                __hip_atomic_store(mail, uint64_t(atomicAdd(&a.heads[p], 1ull)), __ATOMIC_RELAXED,
                                    __HIP_MEMORY_SCOPE_AGENT);
             double zr = 0.0, zi = 0.0;
             if (!team_sum<double>(zr, zi, tm, ++gen, sh))
@@ -164,38 +245,30 @@ __global__ __launch_bounds__(kStreamBlock) void batch_kernel(BatchArgs a)
             __syncthreads();
             const uint64_t q = taken;
             __syncthreads();
-            if (q >= a.n_team)
+            if (q >= count)
                 break;
-            if (!run_team_instance(a, a.inst[a.queue_team[q]], tm, gen, sh, table))
+            const BatchInstance I = a.inst[a.queue[q0 + q]];
+            const bool ok = a.resident[p] ? run_team_resident(a, I, tm, gen, sh) : run_team_streamed(a, I, tm, gen, sh, table);
+            if (!ok)
                 return;
         }
     }
-    // 2. single queue
-    for (;;) {
-        if (threadIdx.x == 0)
-            taken = atomicAdd(&a.heads[1], 1ull);
-        __syncthreads();
-        const uint64_t q = taken;
-        __syncthreads();
-        if (q >= a.n_single)
-            break;
-        const BatchInstance I = a.inst[a.queue_single[q]];
-        if (I.nvec <= uint64_t(kResE) * kStreamBlock)
-            run_single_resident(a, I, sh);
-        else
-            run_single_streamed(a, I, sh, table);
-    }
 }
 
-// Zeroes the queue heads and the team barriers before a run (a kernel, not a memset, so that the pair of
-// launches can be captured into a graph and replayed).
-__global__ void batch_reset_kernel(unsigned long long *heads, uint64_t *sync_words, uint64_t nwords)
+// Zeroes the phase heads, the team barriers and the member slots (whose generation tags the barriers
+// compare against) before a run — a kernel, not a memset, so that the pair of launches can be captured into
+// a graph and replayed.
+__global__ void batch_reset_kernel(unsigned long long *heads, uint64_t nheads, uint64_t *sync_words, uint64_t nwords,
+                                   uint64_t *slots, uint64_t nslots)
 {
     const uint64_t i = uint64_t(blockIdx.x) * blockDim.x + threadIdx.x;
-    if (i < 2)
+    const uint64_t stride = uint64_t(gridDim.x) * blockDim.x;
+    if (i < nheads)
         heads[i] = 0ull;
-    for (uint64_t w = i; w < nwords; w += uint64_t(gridDim.x) * blockDim.x)
+    for (uint64_t w = i; w < nwords; w += stride)
         sync_words[w] = 0u;
+    for (uint64_t w = i; w < nslots; w += stride)
+        slots[w] = 0u;
 }
 
 }  // namespace
@@ -208,21 +281,28 @@ hipError_t launch_batch(const BatchLaunch &L)
     a.state = static_cast<float4 *>(L.state);
     a.marks = L.marks;
     a.inst = L.inst;
-    a.queue_team = L.queue_team;
-    a.n_team = L.n_team;
-    a.queue_single = L.queue_single;
-    a.n_single = L.n_single;
+    a.queue = L.queue;
+    for (int p = 0; p <= kBatchMaxPhases; ++p)
+        a.qoff[p] = L.qoff[p];
+    for (int p = 0; p < kBatchMaxPhases; ++p) {
+        a.team[p] = L.team[p];
+        a.resident[p] = L.resident[p];
+    }
+    a.nphases = L.nphases;
+    a.probe = L.probe;
     a.heads = L.heads;
-    a.team_sync = L.team_sync;
-    a.team_partials = L.team_partials;
-    a.team_mail = L.team_mail;
-    a.team_size = L.team_size;
+    a.sync = L.sync;
+    a.partials = L.partials;
+    a.mail = L.mail;
     a.timeout_ticks = L.timeout_ticks;
     unsigned long long *heads = L.heads;
-    uint64_t *words = reinterpret_cast<uint64_t *>(L.team_sync);
-    uint64_t nwords = uint64_t(L.teams_alloc) * sizeof(GridSync) / sizeof(uint64_t);
-    void *ra[] = {&heads, &words, &nwords};
-    hipError_t e = hipLaunchKernel(reinterpret_cast<const void *>(&batch_reset_kernel), dim3(64), dim3(256), ra, 0,
+    uint64_t nheads = kBatchMaxPhases;
+    uint64_t *words = reinterpret_cast<uint64_t *>(L.sync);
+    uint64_t nwords = uint64_t(kBatchMaxPhases) * uint64_t(L.grid) * sizeof(GridSync) / sizeof(uint64_t);
+    uint64_t *slots = L.partials;
+    uint64_t nslots = uint64_t(kBatchMaxPhases) * uint64_t(L.grid) * 8u;
+    void *ra[] = {&heads, &nheads, &words, &nwords, &slots, &nslots};
+    hipError_t e = hipLaunchKernel(reinterpret_cast<const void *>(&batch_reset_kernel), dim3(256), dim3(256), ra, 0,
                                    L.stream);
     if (e != hipSuccess)
         return e;

@@ -41,13 +41,11 @@ __device__ inline C2 cmul(C2 a, C2 b) { return {a.re * b.re - a.im * b.im, a.re 
 struct PhaseShared {
     double red[kPV * (kStreamBlock / kWave)];
     double sum[kPV];
-    int last;
-    int abort;
 };
 
 struct PhaseTeam {
     PhaseSync *sync;
-    uint64_t *partials;  // [2][size][8] binary64 bit patterns
+    uint64_t *partials;  // [2][size][8]: kPV binary64 bit patterns, then (slot 7) the generation
     unsigned size;
     unsigned rank;
     uint64_t timeout_ticks;
@@ -78,74 +76,63 @@ __device__ inline void block_sum_n(double (&v)[kPV], PhaseShared &sh)
     __syncthreads();
 }
 
-// Team-wide sum of v, with the memory ordering of the single-state barrier (publish, release-increment,
-// the completing workgroup acquires, adds in rank order and releases a generation flag; the others poll
-// with relaxed loads under a wall-clock limit).  Every thread gets the sums; false when the wait gave up.
+__device__ inline bool wait_gen(const uint64_t *word, uint64_t gen, const PhaseTeam &tm)
+{
+    const uint64_t t0 = wall_clock64();
+    while (__hip_atomic_load(word, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < gen) {
+        if (__hip_atomic_load(&tm.sync->error, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0u)
+            return false;
+        if (uint64_t(wall_clock64()) - t0 > tm.timeout_ticks) {
+            __hip_atomic_store(&tm.sync->error, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            return false;
+        }
+        __builtin_amdgcn_s_sleep(2);
+    }
+    return true;
+}
+
+// Team-wide sum of v, an all-gather as in the batched kernels' barrier: every member stores its partials in
+// its slot [parity][rank][0 .. kPV) and then the generation in [parity][rank][7] with release semantics;
+// in every member thread w waits for member w and the partials are added by a fixed tree, so all members
+// compute identical sums.  Slots are double-buffered by the generation's parity (a slot is rewritten two
+// generations later, after every member has read it).  Every thread gets the sums; false when the wait
+// gave up.
 __device__ bool team_sum_n(double (&v)[kPV], const PhaseTeam &tm, uint64_t gen, PhaseShared &sh)
 {
-    const unsigned p = unsigned(gen & 1u);
+    uint64_t *slots = tm.partials + uint64_t(gen & 1u) * tm.size * 8u;
     block_sum_n(v, sh);
     if (threadIdx.x == 0) {
-        uint64_t *dst = tm.partials + (uint64_t(p) * tm.size + tm.rank) * 8u;
+        uint64_t *slot = slots + uint64_t(tm.rank) * 8u;
 #pragma unroll
         for (int q = 0; q < kPV; ++q)
-            store_bits(dst + q, v[q]);
-        uint32_t *arrive = p ? &tm.sync->arrive1 : &tm.sync->arrive0;
-        const unsigned old = __hip_atomic_fetch_add(arrive, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
-        sh.last = (old == tm.size - 1u);
-        sh.abort = 0;
+            store_bits(slot + q, v[q]);
+        __hip_atomic_store(slot + 7, gen, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
     }
-    __syncthreads();
-    if (sh.last) {
-        if (threadIdx.x == 0) {
-            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
-            double s[kPV] = {};
-            for (unsigned w = 0; w < tm.size; ++w) {
-                const uint64_t *src = tm.partials + (uint64_t(p) * tm.size + w) * 8u;
-#pragma unroll
-                for (int q = 0; q < kPV; ++q)
-                    s[q] += __longlong_as_double((long long)load_bits(src + q));
-            }
-#pragma unroll
-            for (int q = 0; q < kPV; ++q) {
-                store_bits(&tm.sync->sum[p][q], s[q]);
-                sh.sum[q] = s[q];
-            }
-            uint32_t *arrive = p ? &tm.sync->arrive1 : &tm.sync->arrive0;
-            __hip_atomic_store(arrive, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            __hip_atomic_store(&tm.sync->flag, gen, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
-        }
-    } else if (threadIdx.x == 0) {
-        const uint64_t t0 = wall_clock64();
-        bool ok = true;
-        while (__hip_atomic_load(&tm.sync->flag, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < gen) {
-            if (__hip_atomic_load(&tm.sync->error, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0u) {
-                ok = false;
-                break;
-            }
-            if (uint64_t(wall_clock64()) - t0 > tm.timeout_ticks) {
-                __hip_atomic_store(&tm.sync->error, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                ok = false;
-                break;
-            }
-            __builtin_amdgcn_s_sleep(2);
-        }
+    double w[kPV] = {};
+    bool ok = true;
+    for (unsigned r = threadIdx.x; r < tm.size; r += kStreamBlock) {
+        const uint64_t *slot = slots + uint64_t(r) * 8u;
+        ok = ok && wait_gen(slot + 7, gen, tm);
         if (ok) {
             __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
 #pragma unroll
             for (int q = 0; q < kPV; ++q)
-                sh.sum[q] = __longlong_as_double((long long)load_bits(&tm.sync->sum[p][q]));
-        } else {
-            sh.abort = 1;
+                w[q] += __longlong_as_double((long long)load_bits(slot + q));
         }
     }
+    const bool failed = __syncthreads_or(!ok) != 0;
+    block_sum_n(w, sh);
+    if (threadIdx.x == 0) {
+#pragma unroll
+        for (int q = 0; q < kPV; ++q)
+            sh.sum[q] = w[q];
+    }
     __syncthreads();
-    const bool ok = sh.abort == 0;
 #pragma unroll
     for (int q = 0; q < kPV; ++q)
         v[q] = sh.sum[q];
     __syncthreads();
-    return ok;
+    return !failed;
 }
 
 struct PhaseArgs {
@@ -480,11 +467,15 @@ __global__ __launch_bounds__(kStreamBlock) void phase_adjoint_kernel(PhaseArgs a
     }
 }
 
-// Zeroes the team barriers before a launch (a kernel, so that launches can be captured and replayed).
-__global__ void phase_reset_kernel(uint64_t *words, uint64_t nwords)
+// Zeroes the team barriers and the member slots (whose generation tags the barriers compare against)
+// before a launch — a kernel, so that launches can be captured and replayed.
+__global__ void phase_reset_kernel(uint64_t *words, uint64_t nwords, uint64_t *slots, uint64_t nslots)
 {
-    for (uint64_t w = uint64_t(blockIdx.x) * blockDim.x + threadIdx.x; w < nwords; w += uint64_t(gridDim.x) * blockDim.x)
+    const uint64_t stride = uint64_t(gridDim.x) * blockDim.x;
+    for (uint64_t w = uint64_t(blockIdx.x) * blockDim.x + threadIdx.x; w < nwords; w += stride)
         words[w] = 0u;
+    for (uint64_t w = uint64_t(blockIdx.x) * blockDim.x + threadIdx.x; w < nslots; w += stride)
+        slots[w] = 0u;
 }
 
 }  // namespace
@@ -524,7 +515,9 @@ hipError_t launch_phase(const PhaseLaunch &L, bool adjoint)
     a.timeout_ticks = L.timeout_ticks;
     uint64_t *words = reinterpret_cast<uint64_t *>(L.sync);
     uint64_t nwords = uint64_t(L.teams_alloc) * sizeof(PhaseSync) / sizeof(uint64_t);
-    void *ra[] = {&words, &nwords};
+    uint64_t *slots = L.partials;
+    uint64_t nslots = uint64_t(L.grid) * 16u;
+    void *ra[] = {&words, &nwords, &slots, &nslots};
     hipError_t e = hipLaunchKernel(reinterpret_cast<const void *>(&phase_reset_kernel), dim3(64), dim3(256), ra, 0,
                                    L.stream);
     if (e != hipSuccess)

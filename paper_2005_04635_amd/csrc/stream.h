@@ -20,12 +20,11 @@ template <class V>
 struct TeamShared {
     V red[2 * (kStreamBlock / kWave)];
     V sum[2];
-    int last;
-    int abort;
 };
 
-// Where a team's barrier lives: its barrier words, its partials [2][T][2] (binary64 bit patterns), the
-// number of workgroups T, this workgroup's rank, and the wait limit.
+// Where a team's barrier lives: its error word (GridSync), its member slots [2][T][4] (binary64 bit
+// patterns of the member's partial sum, then the generation it belongs to; double-buffered by the
+// generation's parity), the number of workgroups T, this workgroup's rank, and the wait limit.
 struct Team {
     GridSync *sync;
     uint64_t *partials;
@@ -33,8 +32,6 @@ struct Team {
     unsigned rank;
     uint64_t timeout_ticks;
 };
-
-__device__ inline uint32_t *arrive_word(GridSync *s, unsigned p) { return p ? &s->arrive1 : &s->arrive0; }
 
 __device__ inline uint64_t load_bits(const uint64_t *p)
 {
@@ -46,79 +43,70 @@ __device__ inline void store_bits(uint64_t *p, double x)
     __hip_atomic_store(p, (uint64_t)__double_as_longlong(x), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
-// Team-wide sum of (xr, xi) at barrier generation `gen` (1, 2, ... per barrier object), in the arithmetic
-// of V (binary64 or binary32; partials travel as binary64, which holds a binary32 exactly).  Returns false
-// when the wait gave up (time limit, or another workgroup gave up); every thread of the workgroup gets the
-// same answer and the sum in (xr, xi).
+// Bounded wait until *word >= gen (relaxed polls, sleeping between them), giving up when the team's error
+// word is set or the wall-clock limit passes (then setting the error word).  Returns true on success.
+__device__ inline bool wait_at_least(const uint64_t *word, uint64_t gen, const Team &tm)
+{
+    const uint64_t t0 = wall_clock64();
+    while (__hip_atomic_load(word, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < gen) {
+        if (__hip_atomic_load(&tm.sync->error, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0u)
+            return false;
+        if (uint64_t(wall_clock64()) - t0 > tm.timeout_ticks) {
+            __hip_atomic_store(&tm.sync->error, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            return false;
+        }
+        __builtin_amdgcn_s_sleep(2);
+    }
+    return true;
+}
+
+// Team-wide sum of (xr, xi) at barrier generation `gen` (1, 2, ... per barrier object; slots zeroed before
+// the launch), in the arithmetic of V (binary64 or binary32; partials travel as binary64, which holds a
+// binary32 exactly).  Returns false when the wait gave up (time limit, or another workgroup gave up); every
+// thread of the workgroup gets the same answer and the sum in (xr, xi).
 //
-// Memory ordering: a workgroup publishes its partial and then increments the arrival counter with release
-// semantics; the workgroup whose increment completes the count acquires, adds the partials in rank order
-// (so the sum is reproducible), stores the sum and releases the generation flag; the others poll the flag
-// with relaxed loads and acquire once it has advanced.  Acquire/release at agent scope make the data
-// visible across the XCDs' separate L2s.  (Letting every workgroup poll the counter and add the partials
-// itself was measured slower on MI355X: the polls contend with the increments.)
+// An all-gather: every member stores its partial in its own slot of the generation's parity and then the
+// generation, with release semantics; then, in every member, thread w waits for member w's generation
+// (all members awaited in parallel) and the partials are added by a fixed tree, so every member computes
+// the same sum bit for bit without a second round trip through memory.  A member rewrites a slot of
+// parity p only at generation g + 2, which it reaches only after every member has arrived at g + 1, i.e.
+// has finished reading generation g.  (Arrivals counted with one atomic per member serialise at the
+// counter's address, and a gather to one member followed by a broadcast costs two memory round trips.)
+// Acquire/release at agent scope make the data visible across the XCDs' separate L2s.
 template <class V>
 __device__ bool team_sum(V &xr, V &xi, const Team &tm, uint64_t gen, TeamShared<V> &sh)
 {
     const unsigned p = unsigned(gen & 1u);
+    uint64_t *slots = tm.partials + uint64_t(p) * tm.size * 4u;
     block_sum2(xr, xi, sh.red);
     if (threadIdx.x == 0) {
-        uint64_t *dst = tm.partials + (uint64_t(p) * tm.size + tm.rank) * 2u;
-        store_bits(dst, double(xr));
-        store_bits(dst + 1, double(xi));
-        const unsigned old =
-            __hip_atomic_fetch_add(arrive_word(tm.sync, p), 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
-        sh.last = (old == tm.size - 1u);
-        sh.abort = 0;
+        uint64_t *slot = slots + uint64_t(tm.rank) * 4u;
+        store_bits(slot, double(xr));
+        store_bits(slot + 1, double(xi));
+        __hip_atomic_store(slot + 2, gen, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
     }
-    __syncthreads();
-    if (sh.last) {
-        // Every partial of this barrier is published.  Add them in rank order.
-        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
-        V sr = V(0), si = V(0);
-        for (unsigned w = threadIdx.x; w < tm.size; w += kStreamBlock) {
-            const uint64_t *src = tm.partials + (uint64_t(p) * tm.size + w) * 2u;
-            sr += V(__longlong_as_double((long long)load_bits(src)));
-            si += V(__longlong_as_double((long long)load_bits(src + 1)));
-        }
-        block_sum2(sr, si, sh.red);
-        if (threadIdx.x == 0) {
-            store_bits(&tm.sync->sum[p][0], double(sr));
-            store_bits(&tm.sync->sum[p][1], double(si));
-            __hip_atomic_store(arrive_word(tm.sync, p), 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            __hip_atomic_store(&tm.sync->flag, gen, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
-            sh.sum[0] = sr;
-            sh.sum[1] = si;
-        }
-    } else if (threadIdx.x == 0) {
-        const uint64_t t0 = wall_clock64();
-        bool ok = true;
-        while (__hip_atomic_load(&tm.sync->flag, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < gen) {
-            if (__hip_atomic_load(&tm.sync->error, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0u) {
-                ok = false;
-                break;
-            }
-            if (uint64_t(wall_clock64()) - t0 > tm.timeout_ticks) {
-                __hip_atomic_store(&tm.sync->error, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                ok = false;
-                break;
-            }
-            __builtin_amdgcn_s_sleep(2);
-        }
+    V pr = V(0), pi = V(0);
+    bool ok = true;
+    for (unsigned w = threadIdx.x; w < tm.size; w += kStreamBlock) {
+        const uint64_t *slot = slots + uint64_t(w) * 4u;
+        ok = ok && wait_at_least(slot + 2, gen, tm);
         if (ok) {
             __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
-            sh.sum[0] = V(__longlong_as_double((long long)load_bits(&tm.sync->sum[p][0])));
-            sh.sum[1] = V(__longlong_as_double((long long)load_bits(&tm.sync->sum[p][1])));
-        } else {
-            sh.abort = 1;
+            pr += V(__longlong_as_double((long long)load_bits(slot)));
+            pi += V(__longlong_as_double((long long)load_bits(slot + 1)));
         }
     }
+    const bool failed = __syncthreads_or(!ok) != 0;
+    block_sum2(pr, pi, sh.red);
+    if (threadIdx.x == 0) {
+        sh.sum[0] = pr;
+        sh.sum[1] = pi;
+    }
     __syncthreads();
-    const bool ok = sh.abort == 0;
     xr = sh.sum[0];
     xi = sh.sum[1];
     __syncthreads();  // sh is reused by the next barrier
-    return ok;
+    return !failed;
 }
 
 // First index q >= start with marks[q] >= x in the sorted list marks[0, m), given that every entry before

@@ -4,7 +4,7 @@
 //                   [--iters K] [--shots 1000000] [--shot-seed 11] [--steps 1]
 //   grover_cli run  --n 10 --dtype f64 --mark 123 ...          (explicit marked indices, repeatable)
 //   grover_cli copy --bytes 2147483648 [--reps 1]              (plain copy kernel of known size)
-//   grover_cli batch --instances FILE [--split S --team T | --tune] [--graph] [--runs R]
+//   grover_cli batch --instances FILE [--split S --team T [--resident V] | --tune] [--graph] [--runs R]
 //                   (many searches in one launch; FILE holds one instance per line: n m mark_1 ... mark_m)
 //   grover_cli phase --schedules FILE [--every S] [--team T] [--runs R]
 //                   (generalized iteration: forward runs and adjoint runs; FILE holds "n m K B", the m marks,
@@ -43,7 +43,7 @@ int usage()
             "                      [--mark I ... | --hash-seed S --hash-bits B --m M] [--iters K]\n"
             "                      [--shots S] [--shot-seed U] [--steps T] [--calibrate-copy BYTES]\n"
             "       grover_cli copy --bytes B [--reps R]\n"
-            "       grover_cli batch --instances FILE [--split S --team T | --tune] [--graph] [--runs R]\n"
+            "       grover_cli batch --instances FILE [--split S --team T [--resident V] | --tune] [--graph] [--runs R]\n"
             "       grover_cli phase --schedules FILE [--every S] [--team T] [--runs R]\n");
     return 2;
 }
@@ -245,7 +245,7 @@ int run_search(int argc, char **argv)
 int run_batch(int argc, char **argv)
 {
     const char *path = nullptr;
-    long split = -1, team = -1;
+    long split = -1, team = -1, resident = 0;
     int runs = 3;
     bool tune = false, graph = false;
     for (int i = 2; i < argc; ++i) {
@@ -255,6 +255,8 @@ int run_batch(int argc, char **argv)
             split = strtol(argv[++i], nullptr, 0);
         else if (!strcmp(argv[i], "--team") && i + 1 < argc)
             team = strtol(argv[++i], nullptr, 0);
+        else if (!strcmp(argv[i], "--resident") && i + 1 < argc)
+            resident = strtol(argv[++i], nullptr, 0);
         else if (!strcmp(argv[i], "--runs") && i + 1 < argc)
             runs = atoi(argv[++i]);
         else if (!strcmp(argv[i], "--tune"))
@@ -304,12 +306,12 @@ int run_batch(int argc, char **argv)
     grover_batch *b = nullptr;
     CHECK_BATCH(nullptr, grover_batch_init(&b, &cfg, stream));
     if (split >= 0)
-        CHECK_BATCH(b, grover_batch_set_tiling(b, uint32_t(split), uint32_t(team)));
+        CHECK_BATCH(b, grover_batch_set_tiling(b, uint32_t(split), uint32_t(team), uint32_t(resident)));
     if (tune) {
-        uint32_t s = 0, t = 0;
+        uint32_t s = 0, t = 0, r = 0;
         float ms_best = 0;
-        CHECK_BATCH(b, grover_batch_tune(b, &s, &t, &ms_best));
-        fprintf(stderr, "[grover_cli] tuned tiling split=%u team=%u (%.3f ms)\n", s, t, ms_best);
+        CHECK_BATCH(b, grover_batch_tune(b, &s, &t, &r, &ms_best));
+        fprintf(stderr, "[grover_cli] tuned tiling split=%u team=%u resident=%u (%.3f ms)\n", s, t, r, ms_best);
     }
     if (graph)
         CHECK_BATCH(b, grover_batch_capture(b));

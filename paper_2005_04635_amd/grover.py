@@ -67,7 +67,7 @@ Q_FORM, Q_GRID, Q_BLOCK, Q_ELEM_BYTES, Q_N, Q_M = 0, 1, 2, 3, 4, 5
 
 
 # grover_batch_query keys
-BQ_COUNT, BQ_GRID, BQ_SPLIT, BQ_TEAM, BQ_UPDATES, BQ_GRAPH, BQ_BYTES, BQ_N_TEAM = range(8)
+BQ_COUNT, BQ_GRID, BQ_SPLIT, BQ_TEAM, BQ_UPDATES, BQ_GRAPH, BQ_BYTES, BQ_N_TEAM, BQ_RESIDENT, BQ_PHASES = range(10)
 
 
 # grover_phase_query keys
@@ -178,8 +178,8 @@ def load(path: str = LIB_PATH):
             "grover_status_str": (ctypes.c_char_p, [i32]),
             "grover_last_error": (ctypes.c_char_p, [P]),
             "grover_batch_init": (i32, [ctypes.POINTER(P), ctypes.POINTER(grover_batch_config), P]),
-            "grover_batch_set_tiling": (i32, [P, u32, u32]),
-            "grover_batch_tune": (i32, [P, ctypes.POINTER(u32), ctypes.POINTER(u32),
+            "grover_batch_set_tiling": (i32, [P, u32, u32, u32]),
+            "grover_batch_tune": (i32, [P, ctypes.POINTER(u32), ctypes.POINTER(u32), ctypes.POINTER(u32),
                                         ctypes.POINTER(ctypes.c_float)]),
             "grover_batch_capture": (i32, [P]),
             "grover_batch_run": (i32, [P]),
@@ -329,14 +329,14 @@ def grover_batch_init(cfg: grover_batch_config, hip_stream: int = 0):
     return b
 
 
-def grover_batch_set_tiling(b, split_n: int, team: int) -> None:
-    _bcheck(b, load().grover_batch_set_tiling(b, split_n, team))
+def grover_batch_set_tiling(b, split_n: int, team: int, resident: int = 0) -> None:
+    _bcheck(b, load().grover_batch_set_tiling(b, split_n, team, resident))
 
 
 def grover_batch_tune(b):
-    s, t, ms = ctypes.c_uint32(), ctypes.c_uint32(), ctypes.c_float()
-    _bcheck(b, load().grover_batch_tune(b, ctypes.byref(s), ctypes.byref(t), ctypes.byref(ms)))
-    return s.value, t.value, ms.value
+    s, t, r, ms = ctypes.c_uint32(), ctypes.c_uint32(), ctypes.c_uint32(), ctypes.c_float()
+    _bcheck(b, load().grover_batch_tune(b, ctypes.byref(s), ctypes.byref(t), ctypes.byref(r), ctypes.byref(ms)))
+    return s.value, t.value, r.value, ms.value
 
 
 def grover_batch_capture(b) -> None:
@@ -604,12 +604,12 @@ class GroverBatch:
         self.b = grover_batch_init(cfg, self.stream.cuda_stream)
         self.count = int(self._n.size)
 
-    def set_tiling(self, split_n: int, team: int) -> "GroverBatch":
-        grover_batch_set_tiling(self.b, split_n, team)
+    def set_tiling(self, split_n: int, team: int, resident: int = 0) -> "GroverBatch":
+        grover_batch_set_tiling(self.b, split_n, team, resident)
         return self
 
     def tune(self):
-        """(split_n, team, milliseconds) of the fastest candidate tiling, which stays selected."""
+        """(split_n, team, resident, milliseconds) of the fastest candidate tiling, which stays selected."""
         return grover_batch_tune(self.b)
 
     def capture(self) -> "GroverBatch":

@@ -210,8 +210,8 @@ def test_batch_null_handles(lib):
     assert lib.grover_batch_run(None) == -1
     assert lib.grover_batch_sync(None) == -1
     assert lib.grover_batch_capture(None) == -1
-    assert lib.grover_batch_set_tiling(None, 10, 2) == -1
-    assert lib.grover_batch_tune(None, None, None, None) == -1
+    assert lib.grover_batch_set_tiling(None, 10, 2, 0) == -1
+    assert lib.grover_batch_tune(None, None, None, None, None) == -1
     assert lib.grover_batch_last_error(None) == b"no batch"
     lib.grover_batch_destroy(None)
 

@@ -71,16 +71,21 @@ def check_against(orc_states, ks, rows, read, team):
         assert err <= error_bound(n, max(k, 1), "c64", "f64", 1), (i, n, len(mk), k, team, err)
 
 
-@pytest.mark.parametrize("split,team", [(0, 1), (12, 2), (10, 4), (0, 4), (14, 0)])
-def test_small_batch_matches_oracle(G, expected, split, team):
+@pytest.mark.parametrize("split,team,resident", [(0, 1, 0), (12, 2, 0), (10, 4, 0), (0, 4, 0), (14, 0, 0),
+                                                 (19, 2, 8), (0, 1, 4), (10, 2, 2), (15, 4, 1), (0, 0, 8)])
+def test_small_batch_matches_oracle(G, expected, split, team, resident):
+    """Streamed tilings (resident = 0) and register-resident teams (resident vectors per thread r: a state of
+    nvec vectors is held by the power of two >= nvec / (1024 r) workgroups); team 0 here means the whole
+    grid per streamed instance."""
     rows = small_batch()
     b = make(G, rows)
     grid = b.query(G.grover.BQ_GRID)
-    b.set_tiling(split, team if team else grid)  # team 0 here: the whole grid per instance
+    b.set_tiling(split, team if team else grid, resident)
     assert b.query(G.grover.BQ_TEAM) == (team if team else grid)
+    assert b.query(G.grover.BQ_RESIDENT) == resident
     b.run()
     b.sync()
-    check_against(*expected, rows, b.read_state, team)
+    check_against(*expected, rows, b.read_state, (team, resident))
     b.close()
 
 
@@ -91,7 +96,7 @@ def test_batch_runs_are_bitwise_reproducible_and_graph_replays_match(G):
     stream = torch.cuda.Stream()
     with torch.cuda.stream(stream):
         b = make(G, rows)
-        b.set_tiling(12, 2)
+        b.set_tiling(12, 2, 4)
         b.run()
         b.sync()
         first = [b.read_state(i) for i in range(b.count)]
@@ -148,9 +153,11 @@ def test_graph_replay_rewrites_the_states(G):
 def test_batch_tune_selects_a_candidate_and_stays_correct(G, expected):
     rows = small_batch()
     b = make(G, rows)
-    split, team, ms = b.tune()
-    assert ms > 0.0 and (team == 1 or (split in (18, 19, 20) and team in (2, 4, 8, 16)))
-    assert (b.query(G.grover.BQ_SPLIT), b.query(G.grover.BQ_TEAM)) == (split, team)
+    split, team, resident, ms = b.tune()
+    assert ms > 0.0 and (team == 1 or (split in (18, 19, 20) and team in (2, 4, 8)))
+    assert resident in (0, 2, 4, 8)
+    assert (b.query(G.grover.BQ_SPLIT), b.query(G.grover.BQ_TEAM), b.query(G.grover.BQ_RESIDENT)) == (split, team,
+                                                                                                     resident)
     b.run()
     b.sync()
     check_against(*expected, rows, b.read_state, team)
@@ -169,8 +176,19 @@ def test_batch_queries_and_tiling_limits(G, orc):
         b.set_tiling(10, 0)
     with pytest.raises(G.GroverError):
         b.set_tiling(10, grid + 1)
+    with pytest.raises(G.GroverError):
+        b.set_tiling(10, 2, 3)  # resident vectors must be a power of two <= 8
+    # a streamed team of 3 could not nest inside resident teams of 2, 4, ...; here every state fits the
+    # registers of a resident team (n <= 18), so no streamed phase exists and the tiling is accepted
+    b.set_tiling(10, 3, 8)
+    assert b.query(G.grover.BQ_PHASES) == 1 + len({n for n, _, _ in rows if n >= 15})
     b.set_tiling(15, 2)
     assert b.query(G.grover.BQ_N_TEAM) == sum(1 for n, _, _ in rows if n >= 15)
+    assert b.query(G.grover.BQ_PHASES) == 2
+    # resident teams of 2^k workgroups for n = 15 .. 18 (8 vectors per thread), nothing streamed
+    b.set_tiling(15, 2, 8)
+    assert b.query(G.grover.BQ_N_TEAM) == sum(1 for n, _, _ in rows if n >= 15)
+    assert b.query(G.grover.BQ_PHASES) == 1 + len({n for n, _, _ in rows if n >= 15})
     ptr, nbytes = G.grover_batch_state(b.b, 3)
     assert ptr % 256 == 0 and nbytes == (1 << rows[3][0]) * 8
     with pytest.raises(G.GroverError):
@@ -186,7 +204,7 @@ def test_batch_barrier_timeout_is_reported(G, expected, monkeypatch):
     monkeypatch.setenv("GROVER_BARRIER_TIMEOUT_MS", "0")
     rows = small_batch()
     b = make(G, rows)
-    b.set_tiling(10, 8)
+    b.set_tiling(10, 8, 2)
     b.run()
     with pytest.raises(G.GroverError) as e:
         b.sync()
@@ -194,7 +212,7 @@ def test_batch_barrier_timeout_is_reported(G, expected, monkeypatch):
     b.close()
     monkeypatch.delenv("GROVER_BARRIER_TIMEOUT_MS")
     b = make(G, rows)
-    b.set_tiling(10, 8)
+    b.set_tiling(10, 8, 2)
     b.run()
     b.sync()
     check_against(*expected, rows, b.read_state, 8)

@@ -155,11 +155,11 @@ def test_batch4096_workload(G, orc):
     stream = torch.cuda.Stream()
     with torch.cuda.stream(stream):
         b = G.GroverBatch(n, m, marks)
-        split, team, ms = b.tune()
+        split, team, resident, ms = b.tune()
         b.capture()
         b.run()
         b.sync()
-        print(f"tiling split={split} team={team} tuned {ms:.1f} ms", flush=True)
+        print(f"tiling split={split} team={team} resident={resident} tuned {ms:.1f} ms", flush=True)
         worst = 0.0
         for i in range(w.count):
             ni, mi = int(n[i]), int(m[i])
