@@ -179,7 +179,8 @@ int grover_sync(grover_ctx *ctx);
 
 /* grover_query — launch facts for diagnostics.  key: 0 = resolved form, 1 = persistent grid size
  * (workgroups), 2 = workgroup size, 3 = element size in bytes, 4 = N, 5 = number of marked indices,
- * 6 = grid-barrier wait limit in device wall-clock ticks. */
+ * 6 = grid-barrier wait limit in device wall-clock ticks, 7 = workgroups per CU of the fused kernel as the
+ * runtime's occupancy calculator reports them (the grid actually used is confirmed on the device). */
 int grover_query(grover_ctx *ctx, int key, int64_t *value);
 
 /* grover_optimal_iterations — floor(pi/4 * sqrt(2^n / m)) (Algorithm 5's iteration count with m
@@ -191,7 +192,8 @@ uint64_t grover_optimal_iterations(uint32_t n, uint64_t m);
 void grover_destroy(grover_ctx *ctx);
 
 /* grover_status_str — static text for a status code.  grover_last_error — the last failure message on ctx
- * (empty string when none; a static message when ctx is NULL). */
+ * (empty string when none); with ctx NULL, the message of the last grover_init failure on the calling
+ * thread that got past validation, else a static message. */
 const char *grover_status_str(int status);
 const char *grover_last_error(const grover_ctx *ctx);
 

@@ -67,10 +67,16 @@ void release(grover_ctx *c)
 
 int check_ctx(const grover_ctx *c) { return c ? GROVER_OK : GROVER_E_INVAL; }
 
-// Clear the grid-barrier state after a wait gave up (the device grid has exited by then).
+// Bytes of the fused kernel's barrier slots: [2][grid][4] member slots and the [2][4] published sum.
+size_t barrier_slot_bytes(int64_t grid) { return size_t(8 * grid + 8) * sizeof(uint64_t); }
+
+// Clear the grid-barrier state (after a wait gave up, the device grid has exited by then; or before the
+// generation tags would wrap).
 hipError_t reset_barrier(grover_ctx *c)
 {
     hipError_t e = hipMemsetAsync(c->sync, 0, sizeof(GridSync), c->stream);
+    if (e == hipSuccess && c->partials && c->partials_grid > 0)
+        e = hipMemsetAsync(c->partials, 0, barrier_slot_bytes(c->partials_grid), c->stream);
     if (e == hipSuccess)
         e = hipStreamSynchronize(c->stream);
     c->generation = 0;
@@ -88,10 +94,15 @@ int select_persistent_grid(grover_ctx *c, int clock_khz)
     int per_cu = 0, block = 0;
     int64_t forced = 0;
     GROVER_HIP(c, fused_configure(c, &per_cu, &block, &forced), "persistent grid configuration");
+    c->per_cu_reported = per_cu;
+    if (per_cu < 1)
+        per_cu = 1;  // the runtime may report 0 workgroups per CU; the device check below decides
     const int64_t max_grid = forced > 0 ? forced : int64_t(per_cu) * c->cu_count;
-    GROVER_HIP(c, dev_alloc(&c->partials, size_t(2) * max_grid * 2 * sizeof(double)), "barrier allocation");
+    GROVER_HIP(c, dev_alloc(&c->partials, barrier_slot_bytes(max_grid)), "barrier allocation");
+    GROVER_HIP(c, hipMemset(c->partials, 0, barrier_slot_bytes(max_grid)), "barrier allocation");
+    c->partials_grid = max_grid;
     GROVER_HIP(c, dev_alloc(&c->sync, sizeof(GridSync)), "barrier allocation");
-    GROVER_HIP(c, reset_barrier(c), "barrier reset");
+    GROVER_HIP(c, reset_barrier(c), "barrier reset before the grid check");
     const uint64_t probe_ticks = uint64_t(clock_khz > 0 ? clock_khz : 100000) * 250;  // 0.25 s
     const uint64_t tiles = fused_tiles(c);
     c->block = block;
@@ -99,6 +110,8 @@ int select_persistent_grid(grover_ctx *c, int clock_khz)
         int64_t g = forced > 0 ? forced : int64_t(pc) * c->cu_count;
         if (forced == 0 && uint64_t(g) > tiles)
             g = int64_t(tiles > 0 ? tiles : 1);
+        if (g > max_grid)
+            return fail(c, GROVER_E_COOP, "persistent grid larger than its barrier allocation");
         c->grid = int(g);
         GROVER_HIP(c, launch_fused_iterate(c, 0, probe_ticks, true), "persistent grid check");
         GROVER_HIP(c, hipStreamSynchronize(c->stream), "persistent grid check");
@@ -106,7 +119,7 @@ int select_persistent_grid(grover_ctx *c, int clock_khz)
         GROVER_HIP(c, hipMemcpy(&gs, c->sync, sizeof(gs), hipMemcpyDeviceToHost), "persistent grid check");
         if (!gs.error)
             return GROVER_OK;
-        GROVER_HIP(c, reset_barrier(c), "barrier reset");
+        GROVER_HIP(c, reset_barrier(c), "barrier reset after a failed grid check");
         if (forced > 0)
             break;
     }
@@ -119,6 +132,9 @@ int run_iterations(grover_ctx *c, uint64_t k)
         return GROVER_OK;
     switch (c->form) {
     case GROVER_FORM_FUSED:
+        // barrier generations are tagged modulo 2^32: start again from clear slots before they would wrap
+        if (c->generation + k + 2u >= (uint64_t(1) << 32))
+            GROVER_HIP(c, reset_barrier(c), "barrier reset");
         GROVER_HIP(c, launch_fused_iterate(c, k, c->timeout_ticks), "fused iterate launch");
         break;
     case GROVER_FORM_RESIDENT: GROVER_HIP(c, launch_resident_iterate(c, k), "resident iterate launch"); break;
@@ -155,9 +171,14 @@ const char *grover_status_str(int status)
     }
 }
 
+// The message of the last grover_init failure on this thread (its context is gone by then).
+thread_local std::string init_error;
+
 const char *grover_last_error(const grover_ctx *ctx)
 {
-    return ctx ? ctx->last_error.c_str() : "no context";
+    if (ctx)
+        return ctx->last_error.c_str();
+    return init_error.empty() ? "no context" : init_error.c_str();
 }
 
 int grover_init(grover_ctx **out, const grover_config *cfg, void *hip_stream, void *state_dev, size_t state_bytes)
@@ -341,9 +362,11 @@ int grover_init(grover_ctx **out, const grover_config *cfg, void *hip_stream, vo
                 throw status;
         }
     } catch (int) {
+        init_error = c->last_error;
         release(c);
         return status;
     } catch (...) {
+        init_error = "host allocation failed";
         release(c);
         return GROVER_E_NOMEM;
     }
@@ -550,9 +573,7 @@ int grover_sync(grover_ctx *ctx)
         GridSync gs;
         GROVER_HIP(ctx, hipMemcpy(&gs, ctx->sync, sizeof(gs), hipMemcpyDeviceToHost), "barrier status download");
         if (gs.error) {
-            GROVER_HIP(ctx, hipMemset(ctx->sync, 0, sizeof(GridSync)), "barrier reset");
-            GROVER_HIP(ctx, hipDeviceSynchronize(), "barrier reset");
-            ctx->generation = 0;
+            GROVER_HIP(ctx, reset_barrier(ctx), "barrier reset");
             return fail(ctx, GROVER_E_TIMEOUT, "a grid barrier wait exceeded its limit; state undefined");
         }
     }
@@ -571,6 +592,7 @@ int grover_query(grover_ctx *ctx, int key, int64_t *value)
     case 4: *value = int64_t(ctx->N); break;
     case 5: *value = int64_t(ctx->marks.size()); break;
     case 6: *value = int64_t(ctx->timeout_ticks); break;
+    case 7: *value = ctx->per_cu_reported; break;
     default: return fail(ctx, GROVER_E_INVAL, "unknown query key");
     }
     return GROVER_OK;

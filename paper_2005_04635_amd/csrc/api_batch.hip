@@ -27,7 +27,7 @@ struct grover_batch {
     uint32_t *queue = nullptr;
     unsigned long long *heads = nullptr;
     GridSync *team_sync = nullptr;
-    uint64_t *team_partials = nullptr, *team_mail = nullptr;
+    uint64_t *team_partials = nullptr;
     int grid = 0;
     uint32_t split_n = 0, team_size = 1, resident = 0;
     uint64_t n_team = 0;  // instances in multi-workgroup phases
@@ -87,7 +87,7 @@ void release(grover_batch *b)
     if (b->graph)
         (void)hipGraphDestroy(b->graph);
     for (void *p : {b->state, (void *)b->marks_dev, (void *)b->inst_dev, (void *)b->queue, (void *)b->heads,
-                    (void *)b->team_sync, (void *)b->team_partials, (void *)b->team_mail})
+                    (void *)b->team_sync, (void *)b->team_partials})
         if (p)
             (void)hipFree(p);
     delete b;
@@ -110,7 +110,6 @@ BatchLaunch launch_of(const grover_batch *b, uint64_t timeout_ticks)
     L.heads = b->heads;
     L.sync = b->team_sync;
     L.partials = b->team_partials;
-    L.mail = b->team_mail;
     L.grid = b->grid;
     L.timeout_ticks = timeout_ticks;
     L.stream = b->stream;
@@ -233,8 +232,6 @@ int select_grid(grover_batch *b, int clock_khz)
     const int max_grid = std::max(1, per_cu) * b->cu_count;
     BATCH_HIP(b, balloc(&b->team_sync, size_t(max_grid) * kBatchMaxPhases * sizeof(GridSync)), "batch allocation");
     BATCH_HIP(b, balloc(&b->team_partials, size_t(max_grid) * kBatchMaxPhases * 8 * sizeof(uint64_t)),
-              "batch allocation");
-    BATCH_HIP(b, balloc(&b->team_mail, size_t(max_grid) * kBatchMaxPhases * 32 * sizeof(uint64_t)),
               "batch allocation");
     const uint64_t probe_ticks = uint64_t(clock_khz > 0 ? clock_khz : 100000) * 250;  // 0.25 s
     for (int pc = per_cu > 1 ? per_cu - 1 : 1; pc >= 1; --pc) {

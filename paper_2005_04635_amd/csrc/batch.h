@@ -38,7 +38,6 @@ struct BatchLaunch {
     unsigned long long *heads;   // one per phase
     GridSync *sync;              // [phase][grid]
     uint64_t *partials;          // [phase][grid * 8]: team slots [2][T][4]
-    uint64_t *mail;              // [phase][grid * 32]
     int grid;
     uint64_t timeout_ticks;
     hipStream_t stream;

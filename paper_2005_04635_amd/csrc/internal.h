@@ -335,7 +335,9 @@ struct grover_ctx {
     // fused form
     int grid = 0;
     int block = 0;
-    double *partials = nullptr;  // 2 * grid * 2 doubles
+    uint64_t *partials = nullptr;  // fused barrier: slots [2][grid][4] and the published sum [2][4]
+    int64_t partials_grid = 0;     // the largest grid those slots were allocated for
+    int per_cu_reported = 0;       // workgroups per CU of the fused kernel according to the runtime
     grover::GridSync *sync = nullptr;
     const void *fused_kernel = nullptr;        // the fused kernel variant chosen at creation
     const void *fused_check_kernel = nullptr;  // its code-identical twin for the residency check

@@ -34,7 +34,6 @@ struct BatchArgs {
     unsigned long long *heads;
     GridSync *sync;
     uint64_t *partials;
-    uint64_t *mail;
     uint64_t timeout_ticks;
 };
 
@@ -230,21 +229,16 @@ __global__ __launch_bounds__(kStreamBlock) void batch_kernel(BatchArgs a)
         const Team tm{a.sync + uint64_t(p) * grid + team_id,
                       a.partials + uint64_t(p) * 8u * grid + uint64_t(team_id) * 8u * T, T, blockIdx.x % T,
                       a.timeout_ticks};
-        uint64_t *mail = a.mail + (uint64_t(p) * grid + team_id) * 32u;
         uint64_t gen = 0;
         for (;;) {
-            // the leader takes the next instance; the barrier that follows publishes it to the team
-            if (tm.rank == 0 && threadIdx.x == 0)
-                __hip_atomic_store(mail, uint64_t(atomicAdd(&a.heads[p], 1ull)), __ATOMIC_RELAXED,
-                                   __HIP_MEMORY_SCOPE_AGENT);
+            // the leader takes the next instance and contributes its index to a team sum (exact in binary64:
+            // one integer below 2^53 plus zeros), which hands it to every member
             double zr = 0.0, zi = 0.0;
+            if (tm.rank == 0 && threadIdx.x == 0)
+                zr = double(atomicAdd(&a.heads[p], 1ull));
             if (!team_sum<double>(zr, zi, tm, ++gen, sh))
                 return;
-            if (threadIdx.x == 0)
-                taken = __hip_atomic_load(mail, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            __syncthreads();
-            const uint64_t q = taken;
-            __syncthreads();
+            const uint64_t q = uint64_t(zr);
             if (q >= count)
                 break;
             const BatchInstance I = a.inst[a.queue[q0 + q]];
@@ -293,7 +287,6 @@ hipError_t launch_batch(const BatchLaunch &L)
     a.heads = L.heads;
     a.sync = L.sync;
     a.partials = L.partials;
-    a.mail = L.mail;
     a.timeout_ticks = L.timeout_ticks;
     unsigned long long *heads = L.heads;
     uint64_t nheads = kBatchMaxPhases;

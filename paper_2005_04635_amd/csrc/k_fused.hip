@@ -8,9 +8,9 @@
 //   second loop), and add s_i c_i' into an accumulator — which is Algorithm 4's first loop for the NEXT
 //   iteration, already applied to the next iteration's oracle-flipped state.
 //
-// The per-workgroup accumulators then meet at a grid barrier: every workgroup publishes its partial, the
-// last one to arrive adds all partials in workgroup order (so the sum is reproducible run to run) and
-// releases the others with the new S.  One read and one write of the state per iteration is the minimum:
+// The per-workgroup accumulators then meet at a grid barrier: every workgroup publishes its partial,
+// workgroup 0 gathers all of them and adds them in a fixed order (so the sum is reproducible run to run)
+// and publishes the new S to the others.  One read and one write of the state per iteration is the minimum:
 // S depends on every amplitude, so no amplitude can be updated twice before all have been read once.
 //
 // A prologue pass computes S of the incoming state with the same per-thread order as the fused
@@ -33,7 +33,7 @@ struct FusedArgs {
     double N;
     const uint64_t *marks;
     uint64_t m;
-    uint64_t *partials;  // [2][grid][2] binary64 bit patterns
+    uint64_t *partials;  // slots [2][grid][4], then the published sum [2][4] (tagged words)
     GridSync *sync;
     uint64_t iters;
     uint64_t gen0;
@@ -44,85 +44,93 @@ template <class V>
 struct Shared {
     V red[2 * (kBlock / kWave)];
     V sum[2];
-    int last;
     int abort;
 };
 
-__device__ inline uint32_t *arrive_word(GridSync *s, unsigned p) { return p ? &s->arrive1 : &s->arrive0; }
-
-__device__ inline uint64_t load_bits(const uint64_t *p)
+// A binary64 value published as two self-validating 64-bit words: each carries 32 bits of the value in its
+// high half and the barrier generation (mod 2^32) in its low half.  Each word is one atomic access, so a
+// reader that sees the current generation in both words has both halves of this generation's value, and
+// the barrier needs no memory fence (on this GPU a release writes back, and an acquire invalidates, a whole
+// L2; the workgroups share nothing but these values within a launch).  The host keeps generations below
+// 2^32 by clearing the slots before they would wrap.
+__device__ inline void put_tagged(uint64_t *w, double x, uint32_t tag)
 {
-    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    const uint64_t b = (uint64_t)__double_as_longlong(x);
+    __hip_atomic_store(w, (b & 0xFFFFFFFF00000000ull) | tag, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    __hip_atomic_store(w + 1, (b << 32) | tag, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
-__device__ inline void store_bits(uint64_t *p, double x)
+// Bounded wait until the two values at w[0 .. 3] carry generation `tag`; gives up when the error word is
+// set or the wall-clock limit passes (then setting the error word).
+__device__ inline bool wait_pair(const uint64_t *w, uint32_t tag, const FusedArgs &a, double &x, double &y)
 {
-    __hip_atomic_store(p, (uint64_t)__double_as_longlong(x), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    const uint64_t t0 = wall_clock64();
+    for (;;) {
+        const uint64_t h0 = __hip_atomic_load(w, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        const uint64_t l0 = __hip_atomic_load(w + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        const uint64_t h1 = __hip_atomic_load(w + 2, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        const uint64_t l1 = __hip_atomic_load(w + 3, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        if (uint32_t(h0) == tag && uint32_t(l0) == tag && uint32_t(h1) == tag && uint32_t(l1) == tag) {
+            x = __longlong_as_double((long long)((h0 & 0xFFFFFFFF00000000ull) | (l0 >> 32)));
+            y = __longlong_as_double((long long)((h1 & 0xFFFFFFFF00000000ull) | (l1 >> 32)));
+            return true;
+        }
+        if (__hip_atomic_load(&a.sync->error, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0u)
+            return false;
+        if (uint64_t(wall_clock64()) - t0 > a.timeout_ticks) {
+            __hip_atomic_store(&a.sync->error, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            return false;
+        }
+        __builtin_amdgcn_s_sleep(1);
+    }
 }
 
-// Grid-wide sum of (xr, xi) for barrier generation `gen`, in the arithmetic of V (binary64 or binary32;
-// partials travel as binary64, which holds a binary32 exactly).  Returns false when the wait gave up
-// (timeout, or another workgroup gave up); every thread of the workgroup gets the same answer and the sum
-// in (xr, xi).
-//
-// Memory ordering: a workgroup publishes its partial and then increments the arrival counter with release
-// semantics; the workgroup whose increment completes the count acquires, adds the partials in workgroup
-// order, stores the sum and releases the generation flag; the others poll the flag with relaxed loads and
-// acquire once it has advanced.  Acquire/release at agent scope make the data visible across the XCDs'
-// separate L2s.  (Letting every workgroup poll the counter and add the partials itself was measured
-// slower on MI355X: the polls contend with the increments.)
+// Grid-wide sum of (xr, xi) at generation `gen`: every workgroup publishes its partial as tagged words in
+// its slot of the generation's parity; in workgroup 0, thread w waits for workgroup w's slot (all awaited
+// in parallel), the partials are added by a fixed tree (so the sum is reproducible run to run), and the sum
+// is published as tagged words, which the other workgroups poll.  A slot of parity p is rewritten two
+// generations later, after workgroup 0 has read it and every workgroup has read the sum in between; the
+// sum is double-buffered the same way.  Returns false when a wait gave up.
 template <class V>
 __device__ bool grid_sum(V &xr, V &xi, const FusedArgs &a, uint64_t gen, Shared<V> &sh)
 {
+    const uint32_t tag = uint32_t(gen);
     const unsigned p = unsigned(gen & 1u);
+    uint64_t *slots = a.partials + uint64_t(p) * gridDim.x * 4u;
+    uint64_t *bcast = a.partials + uint64_t(2) * gridDim.x * 4u + uint64_t(p) * 4u;
     block_sum2(xr, xi, sh.red);
     if (threadIdx.x == 0) {
-        uint64_t *dst = a.partials + (uint64_t(p) * gridDim.x + blockIdx.x) * 2u;
-        store_bits(dst, double(xr));
-        store_bits(dst + 1, double(xi));
-        const unsigned old =
-            __hip_atomic_fetch_add(arrive_word(a.sync, p), 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
-        sh.last = (old == gridDim.x - 1u);
+        uint64_t *slot = slots + uint64_t(blockIdx.x) * 4u;
+        put_tagged(slot, double(xr), tag);
+        put_tagged(slot + 2, double(xi), tag);
         sh.abort = 0;
     }
-    __syncthreads();
-    if (sh.last) {
-        // Every partial of this barrier is published.  Add them in workgroup order.
-        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
-        V sr = V(0), si = V(0);
-        for (unsigned w = threadIdx.x; w < gridDim.x; w += kBlock) {
-            const uint64_t *src = a.partials + (uint64_t(p) * gridDim.x + w) * 2u;
-            sr += V(__longlong_as_double((long long)load_bits(src)));
-            si += V(__longlong_as_double((long long)load_bits(src + 1)));
+    if (blockIdx.x == 0) {
+        V pr = V(0), pi = V(0);
+        bool ok = true;
+        for (unsigned w = threadIdx.x; w < gridDim.x && ok; w += kBlock) {
+            double x = 0.0, y = 0.0;
+            ok = wait_pair(slots + uint64_t(w) * 4u, tag, a, x, y);
+            pr += V(x);
+            pi += V(y);
         }
-        block_sum2(sr, si, sh.red);
+        const bool failed = __syncthreads_or(!ok) != 0;
+        block_sum2(pr, pi, sh.red);
         if (threadIdx.x == 0) {
-            store_bits(&a.sync->sum[p][0], double(sr));
-            store_bits(&a.sync->sum[p][1], double(si));
-            __hip_atomic_store(arrive_word(a.sync, p), 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            __hip_atomic_store(&a.sync->flag, gen, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
-            sh.sum[0] = sr;
-            sh.sum[1] = si;
+            if (failed) {
+                sh.abort = 1;
+            } else {
+                put_tagged(bcast, double(pr), tag);
+                put_tagged(bcast + 2, double(pi), tag);
+                sh.sum[0] = pr;
+                sh.sum[1] = pi;
+            }
         }
     } else if (threadIdx.x == 0) {
-        const uint64_t t0 = wall_clock64();
-        bool ok = true;
-        while (__hip_atomic_load(&a.sync->flag, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < gen) {
-            if (__hip_atomic_load(&a.sync->error, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0u) {
-                ok = false;
-                break;
-            }
-            if (uint64_t(wall_clock64()) - t0 > a.timeout_ticks) {
-                __hip_atomic_store(&a.sync->error, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                ok = false;
-                break;
-            }
-            __builtin_amdgcn_s_sleep(2);
-        }
-        if (ok) {
-            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
-            sh.sum[0] = V(__longlong_as_double((long long)load_bits(&a.sync->sum[p][0])));
-            sh.sum[1] = V(__longlong_as_double((long long)load_bits(&a.sync->sum[p][1])));
+        double x = 0.0, y = 0.0;
+        if (wait_pair(bcast, tag, a, x, y)) {
+            sh.sum[0] = V(x);
+            sh.sum[1] = V(y);
         } else {
             sh.abort = 1;
         }
@@ -135,9 +143,6 @@ __device__ bool grid_sum(V &xr, V &xi, const FusedArgs &a, uint64_t gen, Shared<
     return ok;
 }
 
-// First index q >= start with marks[q] >= x in the sorted list marks[0, m), given that every entry before
-// `start` is < x: exponential steps from `start`, then a binary search in the last step.  Tiles are visited
-// in increasing order, so each search starts where the previous tile's ended and costs O(log gap).
 __device__ inline uint64_t gallop_lower_bound(const uint64_t *marks, uint64_t start, uint64_t m, uint64_t x)
 {
     if (start >= m || marks[start] >= x)

@@ -45,7 +45,7 @@ struct PhaseShared {
 
 struct PhaseTeam {
     PhaseSync *sync;
-    uint64_t *partials;  // [2][size][8]: kPV binary64 bit patterns, then (slot 7) the generation
+    uint64_t *partials;  // [2][size][16]: kPV values as tagged word pairs
     unsigned size;
     unsigned rank;
     uint64_t timeout_ticks;
@@ -76,48 +76,51 @@ __device__ inline void block_sum_n(double (&v)[kPV], PhaseShared &sh)
     __syncthreads();
 }
 
-__device__ inline bool wait_gen(const uint64_t *word, uint64_t gen, const PhaseTeam &tm)
-{
-    const uint64_t t0 = wall_clock64();
-    while (__hip_atomic_load(word, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < gen) {
-        if (__hip_atomic_load(&tm.sync->error, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0u)
-            return false;
-        if (uint64_t(wall_clock64()) - t0 > tm.timeout_ticks) {
-            __hip_atomic_store(&tm.sync->error, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            return false;
-        }
-        __builtin_amdgcn_s_sleep(2);
-    }
-    return true;
-}
-
-// Team-wide sum of v, an all-gather as in the batched kernels' barrier: every member stores its partials in
-// its slot [parity][rank][0 .. kPV) and then the generation in [parity][rank][7] with release semantics;
-// in every member thread w waits for member w and the partials are added by a fixed tree, so all members
-// compute identical sums.  Slots are double-buffered by the generation's parity (a slot is rewritten two
-// generations later, after every member has read it).  Every thread gets the sums; false when the wait
-// gave up.
+// Team-wide sum of v, an all-gather as in the batched kernels' barrier: every member publishes its kPV
+// partials in its slot of the generation's parity as tagged words (two per value, each carrying the
+// generation; see put_tagged); in every member thread w waits until all of member w's words carry this
+// generation, and the partials are added by a fixed tree, so all members compute identical sums.  Slots
+// are double-buffered by parity (a slot is rewritten two generations later, after every member has read
+// it).  Every thread gets the sums; false when the wait gave up.
 __device__ bool team_sum_n(double (&v)[kPV], const PhaseTeam &tm, uint64_t gen, PhaseShared &sh)
 {
-    uint64_t *slots = tm.partials + uint64_t(gen & 1u) * tm.size * 8u;
+    const uint32_t tag = uint32_t(gen);
+    uint64_t *slots = tm.partials + uint64_t(gen & 1u) * tm.size * 16u;
     block_sum_n(v, sh);
     if (threadIdx.x == 0) {
-        uint64_t *slot = slots + uint64_t(tm.rank) * 8u;
+        uint64_t *slot = slots + uint64_t(tm.rank) * 16u;
 #pragma unroll
         for (int q = 0; q < kPV; ++q)
-            store_bits(slot + q, v[q]);
-        __hip_atomic_store(slot + 7, gen, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+            put_tagged(slot + 2 * q, v[q], tag);
     }
     double w[kPV] = {};
     bool ok = true;
-    for (unsigned r = threadIdx.x; r < tm.size; r += kStreamBlock) {
-        const uint64_t *slot = slots + uint64_t(r) * 8u;
-        ok = ok && wait_gen(slot + 7, gen, tm);
-        if (ok) {
-            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+    for (unsigned r = threadIdx.x; r < tm.size && ok; r += kStreamBlock) {
+        const uint64_t *slot = slots + uint64_t(r) * 16u;
+        const uint64_t t0 = wall_clock64();
+        uint64_t hi[kPV], lo[kPV];
+        for (;;) {
+            bool ready = true;
 #pragma unroll
             for (int q = 0; q < kPV; ++q)
-                w[q] += __longlong_as_double((long long)load_bits(slot + q));
+                ready = tagged_ready(slot + 2 * q, tag, hi[q], lo[q]) && ready;
+            if (ready)
+                break;
+            if (__hip_atomic_load(&tm.sync->error, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0u) {
+                ok = false;
+                break;
+            }
+            if (uint64_t(wall_clock64()) - t0 > tm.timeout_ticks) {
+                __hip_atomic_store(&tm.sync->error, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                ok = false;
+                break;
+            }
+            __builtin_amdgcn_s_sleep(1);
+        }
+        if (ok) {
+#pragma unroll
+            for (int q = 0; q < kPV; ++q)
+                w[q] += tagged_value(hi[q], lo[q]);
         }
     }
     const bool failed = __syncthreads_or(!ok) != 0;
@@ -270,7 +273,7 @@ __global__ __launch_bounds__(kStreamBlock) void phase_forward_kernel(PhaseArgs a
     const unsigned T = a.team_size, teams = gridDim.x / T, team_id = blockIdx.x / T;
     if (team_id >= teams)
         return;
-    const PhaseTeam tm{a.sync + team_id, a.partials + uint64_t(team_id) * 16u * T, T, blockIdx.x % T,
+    const PhaseTeam tm{a.sync + team_id, a.partials + uint64_t(team_id) * 32u * T, T, blockIdx.x % T,
                        a.timeout_ticks};
     uint64_t gen = 0;
     if (a.probe) {
@@ -424,7 +427,7 @@ __global__ __launch_bounds__(kStreamBlock) void phase_adjoint_kernel(PhaseArgs a
     const unsigned T = a.team_size, teams = gridDim.x / T, team_id = blockIdx.x / T;
     if (team_id >= teams)
         return;
-    const PhaseTeam tm{a.sync + team_id, a.partials + uint64_t(team_id) * 16u * T, T, blockIdx.x % T,
+    const PhaseTeam tm{a.sync + team_id, a.partials + uint64_t(team_id) * 32u * T, T, blockIdx.x % T,
                        a.timeout_ticks};
     uint64_t gen = 0;
     if (a.probe) {
@@ -516,7 +519,7 @@ hipError_t launch_phase(const PhaseLaunch &L, bool adjoint)
     uint64_t *words = reinterpret_cast<uint64_t *>(L.sync);
     uint64_t nwords = uint64_t(L.teams_alloc) * sizeof(PhaseSync) / sizeof(uint64_t);
     uint64_t *slots = L.partials;
-    uint64_t nslots = uint64_t(L.grid) * 16u;
+    uint64_t nslots = uint64_t(L.grid) * 32u;
     void *ra[] = {&words, &nwords, &slots, &nslots};
     hipError_t e = hipLaunchKernel(reinterpret_cast<const void *>(&phase_reset_kernel), dim3(64), dim3(256), ra, 0,
                                    L.stream);

@@ -22,9 +22,9 @@ struct TeamShared {
     V sum[2];
 };
 
-// Where a team's barrier lives: its error word (GridSync), its member slots [2][T][4] (binary64 bit
-// patterns of the member's partial sum, then the generation it belongs to; double-buffered by the
-// generation's parity), the number of workgroups T, this workgroup's rank, and the wait limit.
+// Where a team's barrier lives: its error word (GridSync), its member slots [2][T][4] (the member's partial
+// sum as tagged words, see put_tagged; double-buffered by the generation's parity), the number of
+// workgroups T, this workgroup's rank, and the wait limit.
 struct Team {
     GridSync *sync;
     uint64_t *partials;
@@ -43,20 +43,51 @@ __device__ inline void store_bits(uint64_t *p, double x)
     __hip_atomic_store(p, (uint64_t)__double_as_longlong(x), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
-// Bounded wait until *word >= gen (relaxed polls, sleeping between them), giving up when the team's error
-// word is set or the wall-clock limit passes (then setting the error word).  Returns true on success.
-__device__ inline bool wait_at_least(const uint64_t *word, uint64_t gen, const Team &tm)
+// A binary64 value published as two self-validating 64-bit words: each carries 32 bits of the value in its
+// high half and the barrier generation (mod 2^32) in its low half.  Each word is stored and loaded as one
+// atomic access, so a reader that sees the current tag in both words has both halves of this generation's
+// value, and no memory fence (which on this GPU writes back or invalidates a whole L2) is needed to order
+// the value against a separate flag.  Slots are zeroed before a launch and generations start at 1.
+__device__ inline void put_tagged(uint64_t *w, double x, uint32_t tag)
+{
+    const uint64_t b = (uint64_t)__double_as_longlong(x);
+    __hip_atomic_store(w, (b & 0xFFFFFFFF00000000ull) | tag, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    __hip_atomic_store(w + 1, (b << 32) | tag, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+__device__ inline bool tagged_ready(const uint64_t *w, uint32_t tag, uint64_t &hi, uint64_t &lo)
+{
+    hi = __hip_atomic_load(w, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    lo = __hip_atomic_load(w + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    return uint32_t(hi) == tag && uint32_t(lo) == tag;
+}
+
+__device__ inline double tagged_value(uint64_t hi, uint64_t lo)
+{
+    return __longlong_as_double((long long)((hi & 0xFFFFFFFF00000000ull) | (lo >> 32)));
+}
+
+// Bounded wait for the two values (tagged words w[0..3]) of generation `tag`, giving up when the team's
+// error word is set or the wall-clock limit passes (then setting the error word).
+__device__ inline bool wait_pair(const uint64_t *w, uint32_t tag, const Team &tm, double &a, double &b)
 {
     const uint64_t t0 = wall_clock64();
-    while (__hip_atomic_load(word, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < gen) {
+    uint64_t h0, l0, h1, l1;
+    for (;;) {
+        const bool ra = tagged_ready(w, tag, h0, l0);
+        const bool rb = tagged_ready(w + 2, tag, h1, l1);
+        if (ra && rb)
+            break;
         if (__hip_atomic_load(&tm.sync->error, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0u)
             return false;
         if (uint64_t(wall_clock64()) - t0 > tm.timeout_ticks) {
             __hip_atomic_store(&tm.sync->error, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
             return false;
         }
-        __builtin_amdgcn_s_sleep(2);
+        __builtin_amdgcn_s_sleep(1);
     }
+    a = tagged_value(h0, l0);
+    b = tagged_value(h1, l1);
     return true;
 }
 
@@ -65,36 +96,33 @@ __device__ inline bool wait_at_least(const uint64_t *word, uint64_t gen, const T
 // binary32 exactly).  Returns false when the wait gave up (time limit, or another workgroup gave up); every
 // thread of the workgroup gets the same answer and the sum in (xr, xi).
 //
-// An all-gather: every member stores its partial in its own slot of the generation's parity and then the
-// generation, with release semantics; then, in every member, thread w waits for member w's generation
-// (all members awaited in parallel) and the partials are added by a fixed tree, so every member computes
-// the same sum bit for bit without a second round trip through memory.  A member rewrites a slot of
-// parity p only at generation g + 2, which it reaches only after every member has arrived at g + 1, i.e.
-// has finished reading generation g.  (Arrivals counted with one atomic per member serialise at the
-// counter's address, and a gather to one member followed by a broadcast costs two memory round trips.)
-// Acquire/release at agent scope make the data visible across the XCDs' separate L2s.
+// An all-gather: every member publishes its partial in its own slot of the generation's parity as tagged
+// words; then, in every member, thread w waits for member w's words of this generation (all members
+// awaited in parallel) and the partials are added by a fixed tree, so every member computes the same sum
+// bit for bit after one memory round trip.  A member rewrites a slot of parity p only at generation g + 2:
+// its partial for g + 1 depends on the sum of g, so its reads of generation g have returned before it
+// publishes g + 1, and g + 2 follows only after every member's g + 1 has been seen.  (Arrivals counted
+// with one atomic per member serialise at the counter's address, and a gather to one member followed by a
+// broadcast costs two round trips.)  The team's workgroups share no other memory within a launch, so the
+// barrier orders nothing but these values.
 template <class V>
 __device__ bool team_sum(V &xr, V &xi, const Team &tm, uint64_t gen, TeamShared<V> &sh)
 {
-    const unsigned p = unsigned(gen & 1u);
-    uint64_t *slots = tm.partials + uint64_t(p) * tm.size * 4u;
+    const uint32_t tag = uint32_t(gen);
+    uint64_t *slots = tm.partials + uint64_t(gen & 1u) * tm.size * 4u;
     block_sum2(xr, xi, sh.red);
     if (threadIdx.x == 0) {
         uint64_t *slot = slots + uint64_t(tm.rank) * 4u;
-        store_bits(slot, double(xr));
-        store_bits(slot + 1, double(xi));
-        __hip_atomic_store(slot + 2, gen, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+        put_tagged(slot, double(xr), tag);
+        put_tagged(slot + 2, double(xi), tag);
     }
     V pr = V(0), pi = V(0);
     bool ok = true;
     for (unsigned w = threadIdx.x; w < tm.size; w += kStreamBlock) {
-        const uint64_t *slot = slots + uint64_t(w) * 4u;
-        ok = ok && wait_at_least(slot + 2, gen, tm);
-        if (ok) {
-            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
-            pr += V(__longlong_as_double((long long)load_bits(slot)));
-            pi += V(__longlong_as_double((long long)load_bits(slot + 1)));
-        }
+        double a = 0.0, b = 0.0;
+        ok = ok && wait_pair(slots + uint64_t(w) * 4u, tag, tm, a, b);
+        pr += V(a);
+        pi += V(b);
     }
     const bool failed = __syncthreads_or(!ok) != 0;
     block_sum2(pr, pi, sh.red);

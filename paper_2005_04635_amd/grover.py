@@ -211,8 +211,8 @@ def load(path: str = LIB_PATH):
 def _check(ctx, status: int) -> None:
     if status != GROVER_OK:
         lib = load()
-        msg = lib.grover_last_error(ctx).decode() if ctx else ""
-        if not msg:
+        msg = lib.grover_last_error(ctx).decode()
+        if not msg or msg == "no context":
             msg = lib.grover_status_str(status).decode()
         raise GroverError(status, msg)
 
