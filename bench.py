@@ -320,7 +320,7 @@ def sweep_batch(pkg, hip, stream, runs: int) -> None:
         return ms
 
     cands = [(0, 1, 0)] + [(s, t, 0) for s in (18, 19, 20) for t in (2, 4, 8) if t <= grid]
-    cands += [(19, 2, r) for r in (8, 4, 2, 1)]
+    cands += [(19, 2, r) for r in (16, 8, 4, 2)]
     best = None
     for split, team, res in cands:
         pkg.grover_batch_set_tiling(b, split, team, res)

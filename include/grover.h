@@ -206,10 +206,12 @@ const char *grover_last_error(const grover_ctx *ctx);
  * indices and iterations[i] iterations (k_opt(n[i], m[i]) when `iterations` is NULL).
  *
  * How the device divides the work is the tiling (split_n, team, resident):
- *   - states of 2^n <= 16384 amplitudes are iterated by one workgroup each, held in its registers;
- *   - with resident = r in {1, 2, 4, 8}, a larger state is held in the registers of a team of T
- *     workgroups, T the power of two >= 2^n / (2048 r) (r 16-byte vectors per thread), when T does not
- *     exceed the grid: one team barrier per iteration and no memory traffic until the final write;
+ *   - states of 2^n <= 32768 amplitudes are iterated by one workgroup each, held on chip (16 16-byte
+ *     vectors per thread: 8 in registers, 8 in LDS);
+ *   - with resident = r in {1, 2, 4, 8, 16}, a larger state is held on chip by a team of T workgroups,
+ *     T the power of two >= 2^n / (2048 r) (r 16-byte vectors per thread, the first 8 in registers, the
+ *     rest in LDS), when T does not exceed the grid: one team barrier per iteration and no memory traffic
+ *     until the final write;
  *   - the remaining states stream from memory every iteration: those with n >= split_n by teams of `team`
  *     workgroups each (team = grid size: the whole device per instance), the others one per workgroup.
  * The tiling changes the order of additions in the sums, so results of two tilings agree to rounding, and
@@ -234,17 +236,17 @@ typedef struct grover_batch_config {
  * the fused form).  hip_stream: the hipStream_t all batch work goes to (NULL = default stream; graph capture
  * then unavailable).  Synchronous.  GROVER_E_INVAL for a bad config (before any device work),
  * GROVER_E_UNSUPPORTED for a dtype other than GROVER_C64, GROVER_E_COOP when no grid is co-resident.
- * The initial tiling is split_n = 19, team = 2, resident = 8. */
+ * The initial tiling is split_n = 19, team = 2, resident = 16. */
 int grover_batch_init(grover_batch **out, const grover_batch_config *cfg, void *hip_stream);
 
 /* grover_batch_set_tiling — choose the tiling: team in [1, grid size] (team = 1: no streamed teams),
- * resident in {0, 1, 2, 4, 8} (0: no register-resident teams).  GROVER_E_INVAL outside those ranges,
+ * resident in {0, 1, 2, 4, 8, 16} (0: no teams that hold a state on chip).  GROVER_E_INVAL outside those ranges,
  * GROVER_E_UNSUPPORTED when a streamed team size does not divide the resident teams' sizes.  Drops a
  * captured graph.  Synchronous. */
 int grover_batch_set_tiling(grover_batch *b, uint32_t split_n, uint32_t team, uint32_t resident);
 
 /* grover_batch_tune — run the batch once per candidate tiling (streamed: team = 1, and split_n in
- * {18, 19, 20} x team in {2, 4, 8}; register-resident: resident in {8, 4, 2} with split_n = 19, team = 2),
+ * {18, 19, 20} x team in {2, 4, 8}; held on chip: resident in {16, 8, 4} with split_n = 19, team = 2),
  * keep the fastest, and report it (any output pointer may be NULL).  Overwrites the states; synchronous;
  * drops a captured graph. */
 int grover_batch_tune(grover_batch *b, uint32_t *split_n, uint32_t *team, uint32_t *resident, float *best_ms);

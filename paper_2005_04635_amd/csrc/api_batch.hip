@@ -137,9 +137,9 @@ uint32_t next_pow2(uint64_t x)
     return p;
 }
 
-// Phases of a tiling.  With resident vectors r > 0, an instance whose state fits the registers of a team of
+// Phases of a tiling.  With resident vectors r > 0, an instance whose state fits on chip in a team of
 // T = the power of two >= nvec / (r * 1024) workgroups (T no larger than the largest power of two <= grid)
-// runs in the resident phase of that T; states of <= 8192 vectors (n <= 14) run alone in registers.
+// runs in the resident phase of that T; states of <= 16384 vectors (n <= 15) run alone on chip.
 // Every other instance streams: with n >= split_n and team > 1 in a streamed phase of teams of `team`
 // workgroups, else alone.  Phases are ordered by decreasing team size (streamed before resident at equal
 // size), each queue by decreasing work N * k (ties by index, for a reproducible order).
@@ -147,8 +147,8 @@ int apply_tiling(grover_batch *b, uint32_t split_n, uint32_t team_size, uint32_t
 {
     if (team_size < 1 || team_size > uint32_t(b->grid))
         return bfail(b, GROVER_E_INVAL, "team size must lie in [1, grid size]");
-    if (resident > uint32_t(kBatchResE) || (resident & (resident - 1u)) != 0u)
-        return bfail(b, GROVER_E_INVAL, "resident vectors per thread must be 0, 1, 2, 4 or 8");
+    if (resident > uint32_t(kBatchHoldE) || (resident & (resident - 1u)) != 0u)
+        return bfail(b, GROVER_E_INVAL, "resident vectors per thread must be 0, 1, 2, 4, 8 or 16");
     const uint32_t max_team = next_pow2(uint64_t(b->grid) + 1) / 2;  // largest power of two <= grid
     std::vector<uint32_t> order(b->count);
     std::iota(order.begin(), order.end(), 0u);
@@ -166,7 +166,7 @@ int apply_tiling(grover_batch *b, uint32_t split_n, uint32_t team_size, uint32_t
     uint64_t n_team = 0;
     for (uint32_t i : order) {
         const uint64_t nvec = b->nvec[i];
-        if (nvec <= uint64_t(kBatchResE) * 1024u) {
+        if (nvec <= uint64_t(kBatchHoldE) * 1024u) {
             phase_of(1, 0).push_back(i);
             continue;
         }
@@ -395,9 +395,9 @@ int grover_batch_init(grover_batch **out, const grover_batch_config *cfg, void *
         status = select_grid(b, clock_khz);
         if (status != GROVER_OK)
             throw status;
-        // default tiling until tuned: states in the registers of teams sized to hold 8 vectors per thread;
-        // states too large for that stream with teams of 2
-        status = apply_tiling(b, 19, b->grid >= 2 ? 2u : 1u, uint32_t(kBatchResE));
+        // default tiling until tuned: states held on chip by teams sized for 16 vectors per thread (8 in
+        // registers, 8 in LDS); states too large for that stream with teams of 2
+        status = apply_tiling(b, 19, b->grid >= 2 ? 2u : 1u, uint32_t(kBatchHoldE));
         if (status != GROVER_OK)
             throw status;
     } catch (int) {
@@ -449,7 +449,7 @@ int grover_batch_tune(grover_batch *b, uint32_t *split_n, uint32_t *team_size, u
         for (uint32_t t : {2u, 4u, 8u})
             if (t <= uint32_t(b->grid))
                 cands.push_back({split, t, 0});
-    for (uint32_t r : {8u, 4u, 2u})
+    for (uint32_t r : {16u, 8u, 4u})
         cands.push_back({19, 2, r});
     hipEvent_t e0, e1;
     BATCH_HIP(b, hipEventCreate(&e0), "event");

@@ -6,7 +6,9 @@
 namespace grover {
 
 constexpr int kBatchMaxPhases = 12;
-constexpr int kBatchResE = 8;  // 16-byte vectors a thread can hold in registers (complex64: 16 amplitudes)
+constexpr int kBatchRegE = 8;                         // 16-byte vectors a thread holds in registers
+constexpr int kBatchLdsE = 8;                         // ... and in its own slots of LDS (128 KiB per workgroup)
+constexpr int kBatchHoldE = kBatchRegE + kBatchLdsE;  // 16 vectors = 32 complex64 amplitudes per thread
 
 // One instance of a batch (device table, written by the host).
 struct BatchInstance {
@@ -22,9 +24,9 @@ struct BatchInstance {
 // A run is a sequence of phases.  Phase p has a queue of instances (ordered by decreasing work), a team
 // size team[p] (workgroups per instance; non-increasing from one phase to the next, each a divisor of the
 // previous one, so a team of phase p + 1 lies inside one team of phase p) and a mode: resident[p] > 0 holds
-// each instance's state in the team's registers (at most that many 16-byte vectors per thread), 0 streams
-// it from memory every iteration.  Team size 1 is one workgroup per instance (registers when the state fits
-// kBatchResE vectors per thread, else streamed).
+// each instance's state on chip in the team's workgroups (at most that many 16-byte vectors per thread, the
+// first kBatchRegE in registers, the rest in LDS), 0 streams it from memory every iteration.  Team size 1 is
+// one workgroup per instance (on chip when the state fits kBatchHoldE vectors per thread, else streamed).
 struct BatchLaunch {
     void *state;
     const uint64_t *marks;

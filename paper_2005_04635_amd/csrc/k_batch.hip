@@ -3,12 +3,12 @@
 // phases, each with its own queue ordered by decreasing work N * k and its own team size T:
 //   - in a phase with T > 1 the grid is split into teams of T consecutive workgroups; a team's leader takes
 //     the next instance and publishes it through the team barrier, and the team iterates it with one team
-//     barrier per iteration (which also reduces the sum).  The state is either held in the team's
-//     registers for all iterations (resident phases: the instance fits T * 1024 threads * the phase's
-//     vectors per thread) or streamed from memory every iteration, exactly as the fused single-instance
-//     kernel does;
-//   - in a phase with T = 1 every workgroup takes instances alone: held in registers when the state fits
-//     (n <= 14), otherwise streamed with workgroup-level sums only.
+//     barrier per iteration (which also reduces the sum).  The state is either held on chip by the team
+//     for all iterations (resident phases: the instance fits T * 1024 threads * the phase's vectors per
+//     thread, up to 8 in registers and 8 more in LDS) or streamed from memory every iteration, exactly as
+//     the fused single-instance kernel does;
+//   - in a phase with T = 1 every workgroup takes instances alone: held on chip (registers and LDS) when
+//     the state fits (n <= 15), otherwise streamed with workgroup-level sums only.
 // Team sizes do not increase from one phase to the next and each divides the previous one, so the members
 // of a team always come from one team of the previous phase (they finish it together) and no grid-wide
 // barrier is needed between phases.  Which phases exist and their parameters is the tiling the host
@@ -19,7 +19,9 @@
 namespace grover {
 namespace {
 
-constexpr int kResE = kBatchResE;
+constexpr int kRegE = kBatchRegE;
+constexpr int kLdsE = kBatchLdsE;
+constexpr int kHoldE = kBatchHoldE;
 
 struct BatchArgs {
     float4 *state;
@@ -37,17 +39,29 @@ struct BatchArgs {
     uint64_t timeout_ticks;
 };
 
-__device__ inline void block_allsum(double &a, double &b, TeamShared<double> &sh)
+// Workgroup sum of (a, b) for every thread with one workgroup barrier: wave butterflies, then every thread
+// adds the wave values in wave order (the same bits everywhere).  The wave values alternate between two
+// buffers by `parity`: a buffer is rewritten two calls later, after the next call's barrier, which every
+// thread reaches only after reading it.
+__device__ inline void block_allsum(double &a, double &b, unsigned parity, TeamShared<double> &sh)
 {
-    block_sum2(a, b, sh.red);
-    if (threadIdx.x == 0) {
-        sh.sum[0] = a;
-        sh.sum[1] = b;
+    const unsigned lane = threadIdx.x % kWave, wave = threadIdx.x / kWave;
+    double *red = sh.red[parity & 1u];
+    a = wave_sum(a);
+    b = wave_sum(b);
+    if (lane == 0) {
+        red[2 * wave] = a;
+        red[2 * wave + 1] = b;
     }
     __syncthreads();
-    a = sh.sum[0];
-    b = sh.sum[1];
-    __syncthreads();
+    double sa = 0.0, sb = 0.0;
+#pragma unroll
+    for (unsigned w = 0; w < kStreamBlock / kWave; ++w) {
+        sa += red[2 * w];
+        sb += red[2 * w + 1];
+    }
+    a = sa;
+    b = sb;
 }
 
 __device__ inline float4 uniform_vec(double amp)
@@ -80,51 +94,65 @@ __device__ bool run_team_streamed(const BatchArgs &a, const BatchInstance &I, co
     return true;
 }
 
-// One instance held in the registers of the T workgroups of a team for all its iterations: member `rank`
-// owns the contiguous vectors [rank * per, (rank + 1) * per), per = nvec / T <= kResE * 1024, thread `tid`
-// the vectors rank * per + e * 1024 + tid.  The state is written to memory once, at the end.
-__device__ bool run_team_resident(const BatchArgs &a, const BatchInstance &I, const Team &tm, uint64_t &gen,
-                                  TeamShared<double> &sh)
+// One instance held on chip by a team for all its iterations: member `rank` owns the contiguous vectors
+// [rank * per, (rank + 1) * per), per = nvec / T <= kHoldE * 1024, thread `tid` the vectors
+// rank * per + e * 1024 + tid, e < kHoldE: the first kRegE in registers, the others in the thread's own
+// slots of LDS (held[(e - kRegE) * 1024 + tid]; no other thread touches them, so no workgroup barrier is
+// needed around them).  Marked bits travel packed, two per vector.  `reduce` is the team's (or the
+// workgroup's) sum; the state is written to memory once, at the end.  Returns false when a barrier gave up.
+template <class Reduce>
+__device__ bool run_held(const BatchArgs &a, const BatchInstance &I, uint64_t base, uint64_t per, float4 *held,
+                         TeamShared<double> &sh, Reduce reduce)
 {
-    const uint64_t per = I.nvec / tm.size;
-    const uint64_t base = uint64_t(tm.rank) * per;
     float4 *st = a.state + I.state_off + base;
     const uint64_t *marks = a.marks + I.marks_off;
     const unsigned tid = threadIdx.x;
-    float4 x[kResE];
-    unsigned bits[kResE];
     const float4 fill = uniform_vec(I.amp);
+    uint32_t mask = 0u;
     AccF64 acc0;
-#pragma unroll
-    for (int e = 0; e < kResE; ++e) {
+#pragma unroll 1
+    for (int e = 0; e < kHoldE; ++e) {
         const uint64_t v = uint64_t(e) * kStreamBlock + tid;
-        bits[e] = 0u;
         if (v < per) {
-            x[e] = fill;
-            bits[e] = marked_bits<2>(marks, 0, I.m, (base + v) * 2u);
-            accum_vec<C64>(x[e], bits[e], acc0);
+            const unsigned bits = marked_bits<2>(marks, 0, I.m, (base + v) * 2u);
+            mask |= uint32_t(bits) << (2 * e);
+            accum_vec<C64>(fill, bits, acc0);
+            if (e >= kRegE)
+                held[(e - kRegE) * kStreamBlock + tid] = fill;
         }
     }
+    float4 x[kRegE];
+#pragma unroll
+    for (int e = 0; e < kRegE; ++e)
+        x[e] = fill;
     double sr = acc0.r, si = acc0.i;
-    if (!team_sum<double>(sr, si, tm, ++gen, sh))
+    if (!reduce(sr, si))
         return false;
     for (uint64_t it = 0; it < I.iters; ++it) {
         const double mr = (sr * 2.0) / I.N, mi = (si * 2.0) / I.N;
         AccF64 acc;
 #pragma unroll
-        for (int e = 0; e < kResE; ++e)
+        for (int e = 0; e < kRegE; ++e)
             if (uint64_t(e) * kStreamBlock + tid < per)
-                update_vec<C64>(x[e], mr, mi, bits[e], acc);
+                update_vec<C64>(x[e], mr, mi, (mask >> (2 * e)) & 3u, acc);
+#pragma unroll 2
+        for (int e = kRegE; e < kHoldE; ++e) {
+            if (uint64_t(e) * kStreamBlock + tid >= per)
+                break;
+            float4 y = held[(e - kRegE) * kStreamBlock + tid];
+            update_vec<C64>(y, mr, mi, (mask >> (2 * e)) & 3u, acc);
+            held[(e - kRegE) * kStreamBlock + tid] = y;
+        }
         sr = acc.r;
         si = acc.i;
-        if (!team_sum<double>(sr, si, tm, ++gen, sh))
+        if (!reduce(sr, si))
             return false;
     }
 #pragma unroll
-    for (int e = 0; e < kResE; ++e) {
+    for (int e = 0; e < kHoldE; ++e) {
         const uint64_t v = uint64_t(e) * kStreamBlock + tid;
         if (v < per)
-            st[v] = x[e];
+            st[v] = e < kRegE ? x[e] : held[(e - kRegE) * kStreamBlock + tid];
     }
     return true;
 }
@@ -138,7 +166,8 @@ __device__ void run_single_streamed(const BatchArgs &a, const BatchInstance &I, 
     AccF64 acc0;
     stream_pass<C64, AccF64, kFill>(share, table, use_table, 0.0, 0.0, uniform_vec(I.amp), acc0);
     double sr = acc0.r, si = acc0.i;
-    block_allsum(sr, si, sh);
+    unsigned parity = 0;
+    block_allsum(sr, si, parity++, sh);
     const float4 none{};
     for (uint64_t it = 0; it < I.iters; ++it) {
         const double mr = (sr * 2.0) / I.N, mi = (si * 2.0) / I.N;
@@ -146,48 +175,7 @@ __device__ void run_single_streamed(const BatchArgs &a, const BatchInstance &I, 
         stream_pass<C64, AccF64, kUpdate>(share, table, use_table, mr, mi, none, acc);
         sr = acc.r;
         si = acc.i;
-        block_allsum(sr, si, sh);
-    }
-}
-
-// One instance held in the registers of one workgroup for all its iterations (vector v = e * block + tid).
-__device__ void run_single_resident(const BatchArgs &a, const BatchInstance &I, TeamShared<double> &sh)
-{
-    float4 *st = a.state + I.state_off;
-    const uint64_t *marks = a.marks + I.marks_off;
-    const unsigned tid = threadIdx.x;
-    float4 x[kResE];
-    unsigned bits[kResE];
-    const float4 fill = uniform_vec(I.amp);
-    AccF64 acc0;
-#pragma unroll
-    for (int e = 0; e < kResE; ++e) {
-        const uint64_t v = uint64_t(e) * kStreamBlock + tid;
-        bits[e] = 0u;
-        if (v < I.nvec) {
-            x[e] = fill;
-            bits[e] = marked_bits<2>(marks, 0, I.m, v * 2u);
-            accum_vec<C64>(x[e], bits[e], acc0);
-        }
-    }
-    double sr = acc0.r, si = acc0.i;
-    block_allsum(sr, si, sh);
-    for (uint64_t it = 0; it < I.iters; ++it) {
-        const double mr = (sr * 2.0) / I.N, mi = (si * 2.0) / I.N;
-        AccF64 acc;
-#pragma unroll
-        for (int e = 0; e < kResE; ++e)
-            if (uint64_t(e) * kStreamBlock + tid < I.nvec)
-                update_vec<C64>(x[e], mr, mi, bits[e], acc);
-        sr = acc.r;
-        si = acc.i;
-        block_allsum(sr, si, sh);
-    }
-#pragma unroll
-    for (int e = 0; e < kResE; ++e) {
-        const uint64_t v = uint64_t(e) * kStreamBlock + tid;
-        if (v < I.nvec)
-            st[v] = x[e];
+        block_allsum(sr, si, parity++, sh);
     }
 }
 
@@ -196,6 +184,7 @@ __global__ __launch_bounds__(kStreamBlock) void batch_kernel(BatchArgs a)
     __shared__ TeamShared<double> sh;
     __shared__ uint32_t table[kMarkWords];
     __shared__ uint64_t taken;
+    __shared__ float4 held[kLdsE * kStreamBlock];  // on-chip state beyond the registers (128 KiB)
     const uint32_t grid = gridDim.x;
     if (a.probe) {
         const Team tm{a.sync, a.partials, grid, blockIdx.x, a.timeout_ticks};
@@ -219,8 +208,12 @@ __global__ __launch_bounds__(kStreamBlock) void batch_kernel(BatchArgs a)
                 if (q >= count)
                     break;
                 const BatchInstance I = a.inst[a.queue[q0 + q]];
-                if (I.nvec <= uint64_t(kResE) * kStreamBlock)
-                    run_single_resident(a, I, sh);
+                unsigned parity = 0;
+                if (I.nvec <= uint64_t(kHoldE) * kStreamBlock)
+                    (void)run_held(a, I, 0, I.nvec, held, sh, [&](double &r, double &i) {
+                        block_allsum(r, i, parity++, sh);
+                        return true;
+                    });
                 else
                     run_single_streamed(a, I, sh, table);
             }
@@ -242,7 +235,14 @@ __global__ __launch_bounds__(kStreamBlock) void batch_kernel(BatchArgs a)
             if (q >= count)
                 break;
             const BatchInstance I = a.inst[a.queue[q0 + q]];
-            const bool ok = a.resident[p] ? run_team_resident(a, I, tm, gen, sh) : run_team_streamed(a, I, tm, gen, sh, table);
+            bool ok;
+            if (a.resident[p]) {
+                const uint64_t per = I.nvec / T;
+                ok = run_held(a, I, uint64_t(tm.rank) * per, per, held, sh,
+                              [&](double &r, double &i) { return team_sum<double>(r, i, tm, ++gen, sh); });
+            } else {
+                ok = run_team_streamed(a, I, tm, gen, sh, table);
+            }
             if (!ok)
                 return;
         }

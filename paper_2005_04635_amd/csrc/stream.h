@@ -18,8 +18,9 @@ constexpr int kTileMarks = 8;       // marks of one tile held in registers
 
 template <class V>
 struct TeamShared {
-    V red[2 * (kStreamBlock / kWave)];
+    V red[2][2 * (kStreamBlock / kWave)];  // per-wave partials, double-buffered (see block_allsum)
     V sum[2];
+    int failed;
 };
 
 // Where a team's barrier lives: its error word (GridSync), its member slots [2][T][4] (the member's partial
@@ -110,11 +111,47 @@ __device__ bool team_sum(V &xr, V &xi, const Team &tm, uint64_t gen, TeamShared<
 {
     const uint32_t tag = uint32_t(gen);
     uint64_t *slots = tm.partials + uint64_t(gen & 1u) * tm.size * 4u;
-    block_sum2(xr, xi, sh.red);
+    const unsigned lane = threadIdx.x % kWave, wave = threadIdx.x / kWave;
+    // this member's partial: wave butterflies, then thread 0 adds the wave values in wave order and publishes
+    // it.  sh.red[0] is read by thread 0 only before the workgroup barrier below; a wave writes it again
+    // only in the next call, after that barrier, so no barrier is needed behind the read.
+    xr = wave_sum(xr);
+    xi = wave_sum(xi);
+    if (lane == 0) {
+        sh.red[0][2 * wave] = xr;
+        sh.red[0][2 * wave + 1] = xi;
+    }
+    __syncthreads();
     if (threadIdx.x == 0) {
+        V sr = V(0), si = V(0);
+        for (unsigned w = 0; w < kStreamBlock / kWave; ++w) {
+            sr += sh.red[0][2 * w];
+            si += sh.red[0][2 * w + 1];
+        }
         uint64_t *slot = slots + uint64_t(tm.rank) * 4u;
-        put_tagged(slot, double(xr), tag);
-        put_tagged(slot + 2, double(xi), tag);
+        put_tagged(slot, double(sr), tag);
+        put_tagged(slot + 2, double(si), tag);
+    }
+    if (tm.size <= kWave) {
+        // every member's partial fits one wave: wave 0 gathers them (lane w waits for member w) and adds them
+        // by butterflies, which leave the same bits in every lane and in every member; one workgroup barrier
+        // hands the sum on.  sh.sum and sh.failed are written again only after the first barrier of the next
+        // call, which every thread reaches after reading them here.
+        if (wave == 0) {
+            double a = 0.0, b = 0.0;
+            const bool ok = lane < tm.size ? wait_pair(slots + uint64_t(lane) * 4u, tag, tm, a, b) : true;
+            const V pr = wave_sum(V(a)), pi = wave_sum(V(b));
+            const bool failed = __any(!ok);
+            if (lane == 0) {
+                sh.sum[0] = pr;
+                sh.sum[1] = pi;
+                sh.failed = failed;
+            }
+        }
+        __syncthreads();
+        xr = sh.sum[0];
+        xi = sh.sum[1];
+        return !sh.failed;
     }
     V pr = V(0), pi = V(0);
     bool ok = true;
@@ -125,7 +162,7 @@ __device__ bool team_sum(V &xr, V &xi, const Team &tm, uint64_t gen, TeamShared<
         pi += V(b);
     }
     const bool failed = __syncthreads_or(!ok) != 0;
-    block_sum2(pr, pi, sh.red);
+    block_sum2(pr, pi, sh.red[1]);
     if (threadIdx.x == 0) {
         sh.sum[0] = pr;
         sh.sum[1] = pi;
@@ -133,7 +170,7 @@ __device__ bool team_sum(V &xr, V &xi, const Team &tm, uint64_t gen, TeamShared<
     __syncthreads();
     xr = sh.sum[0];
     xi = sh.sum[1];
-    __syncthreads();  // sh is reused by the next barrier
+    __syncthreads();  // sh.sum is rewritten by the next call before its first barrier on this path
     return !failed;
 }
 

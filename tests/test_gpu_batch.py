@@ -31,8 +31,8 @@ def G():
 
 
 def small_batch():
-    """(n, marks, iterations or None) per instance: sizes that span the register-held form (n <= 14), the
-    streamed one, several tiles and ragged tiles, marked lists dense within one tile and degenerate sets."""
+    """(n, marks, iterations or None) per instance: sizes that span the form one workgroup holds on chip
+    (n <= 15), the team-held and streamed ones, several tiles and ragged tiles, marked lists dense within one tile and degenerate sets."""
     rows = [
         (1, [0], None), (2, [3], None), (3, [5], None), (3, [1, 6], 3), (4, [], None), (4, list(range(16)), None),
         (5, [0, 31], 3), (6, [17], 0), (8, [1, 2, 200], None), (9, [511], None), (10, [5], None),
@@ -72,11 +72,12 @@ def check_against(orc_states, ks, rows, read, team):
 
 
 @pytest.mark.parametrize("split,team,resident", [(0, 1, 0), (12, 2, 0), (10, 4, 0), (0, 4, 0), (14, 0, 0),
-                                                 (19, 2, 8), (0, 1, 4), (10, 2, 2), (15, 4, 1), (0, 0, 8)])
+                                                 (19, 2, 8), (0, 1, 4), (10, 2, 2), (15, 4, 1), (0, 0, 8),
+                                                 (19, 2, 16), (0, 1, 16), (12, 4, 16)])
 def test_small_batch_matches_oracle(G, expected, split, team, resident):
-    """Streamed tilings (resident = 0) and register-resident teams (resident vectors per thread r: a state of
-    nvec vectors is held by the power of two >= nvec / (1024 r) workgroups); team 0 here means the whole
-    grid per streamed instance."""
+    """Streamed tilings (resident = 0) and teams that hold the state on chip (resident vectors per thread r,
+    up to 8 in registers and 8 more in LDS: a state of nvec vectors is held by the power of two
+    >= nvec / (1024 r) workgroups); team 0 here means the whole grid per streamed instance."""
     rows = small_batch()
     b = make(G, rows)
     grid = b.query(G.grover.BQ_GRID)
@@ -155,7 +156,7 @@ def test_batch_tune_selects_a_candidate_and_stays_correct(G, expected):
     b = make(G, rows)
     split, team, resident, ms = b.tune()
     assert ms > 0.0 and (team == 1 or (split in (18, 19, 20) and team in (2, 4, 8)))
-    assert resident in (0, 2, 4, 8)
+    assert resident in (0, 4, 8, 16)
     assert (b.query(G.grover.BQ_SPLIT), b.query(G.grover.BQ_TEAM), b.query(G.grover.BQ_RESIDENT)) == (split, team,
                                                                                                      resident)
     b.run()
@@ -177,18 +178,24 @@ def test_batch_queries_and_tiling_limits(G, orc):
     with pytest.raises(G.GroverError):
         b.set_tiling(10, grid + 1)
     with pytest.raises(G.GroverError):
-        b.set_tiling(10, 2, 3)  # resident vectors must be a power of two <= 8
-    # a streamed team of 3 could not nest inside resident teams of 2, 4, ...; here every state fits the
-    # registers of a resident team (n <= 18), so no streamed phase exists and the tiling is accepted
+        b.set_tiling(10, 2, 3)  # resident vectors must be a power of two <= 16
+    with pytest.raises(G.GroverError):
+        b.set_tiling(10, 2, 32)
+    # a streamed team of 3 could not nest inside resident teams of 2, 4, ...; here every state fits on chip
+    # in a resident team (n <= 18), so no streamed phase exists and the tiling is accepted
     b.set_tiling(10, 3, 8)
-    assert b.query(G.grover.BQ_PHASES) == 1 + len({n for n, _, _ in rows if n >= 15})
+    assert b.query(G.grover.BQ_PHASES) == 1 + len({n for n, _, _ in rows if n >= 16})
+    # states of n <= 15 are held by one workgroup whatever the tiling; the rest stream in teams of 2
     b.set_tiling(15, 2)
-    assert b.query(G.grover.BQ_N_TEAM) == sum(1 for n, _, _ in rows if n >= 15)
+    assert b.query(G.grover.BQ_N_TEAM) == sum(1 for n, _, _ in rows if n >= 16)
     assert b.query(G.grover.BQ_PHASES) == 2
-    # resident teams of 2^k workgroups for n = 15 .. 18 (8 vectors per thread), nothing streamed
+    # resident teams of 2^k workgroups for n = 16 .. 18 (8 vectors per thread), nothing streamed
     b.set_tiling(15, 2, 8)
-    assert b.query(G.grover.BQ_N_TEAM) == sum(1 for n, _, _ in rows if n >= 15)
-    assert b.query(G.grover.BQ_PHASES) == 1 + len({n for n, _, _ in rows if n >= 15})
+    assert b.query(G.grover.BQ_N_TEAM) == sum(1 for n, _, _ in rows if n >= 16)
+    assert b.query(G.grover.BQ_PHASES) == 1 + len({n for n, _, _ in rows if n >= 16})
+    # 16 vectors per thread: n = 16 on 2 workgroups, 17 on 4, 18 on 8
+    b.set_tiling(15, 2, 16)
+    assert b.query(G.grover.BQ_PHASES) == 1 + len({n for n, _, _ in rows if n >= 16})
     ptr, nbytes = G.grover_batch_state(b.b, 3)
     assert ptr % 256 == 0 and nbytes == (1 << rows[3][0]) * 8
     with pytest.raises(G.GroverError):
