@@ -86,61 +86,73 @@ __device__ inline bool wait_pair(const uint64_t *w, uint32_t tag, const FusedArg
 }
 
 // Grid-wide sum of (xr, xi) at generation `gen`: every workgroup publishes its partial as tagged words in
-// its slot of the generation's parity; in workgroup 0, thread w waits for workgroup w's slot (all awaited
-// in parallel), the partials are added by a fixed tree (so the sum is reproducible run to run), and the sum
-// is published as tagged words, which the other workgroups poll.  A slot of parity p is rewritten two
-// generations later, after workgroup 0 has read it and every workgroup has read the sum in between; the
-// sum is double-buffered the same way.  Returns false when a wait gave up.
+// its slot of the generation's parity; in workgroup 0, wave 0 gathers them (lane l waits for the slots of
+// workgroups l, l + 64, ... and adds them in that order; the lanes' values are then added by butterflies),
+// so the sum is reproducible run to run, and publishes the sum as tagged words, which the other workgroups
+// poll.  A slot of parity p is rewritten two generations later, after workgroup 0 has read it and every
+// workgroup has read the sum in between; the sum is double-buffered the same way.  Two workgroup barriers:
+// one before thread 0 adds the wave partials, one before every thread reads the sum.  The LDS words are
+// written again only after the first barrier of the next call, which every thread reaches after its reads
+// here, so no barrier is needed behind them.  Returns false when a wait gave up.
 template <class V>
 __device__ bool grid_sum(V &xr, V &xi, const FusedArgs &a, uint64_t gen, Shared<V> &sh)
 {
     const uint32_t tag = uint32_t(gen);
     const unsigned p = unsigned(gen & 1u);
+    const unsigned lane = threadIdx.x % kWave, wave = threadIdx.x / kWave;
     uint64_t *slots = a.partials + uint64_t(p) * gridDim.x * 4u;
     uint64_t *bcast = a.partials + uint64_t(2) * gridDim.x * 4u + uint64_t(p) * 4u;
-    block_sum2(xr, xi, sh.red);
+    xr = wave_sum(xr);
+    xi = wave_sum(xi);
+    if (lane == 0) {
+        sh.red[2 * wave] = xr;
+        sh.red[2 * wave + 1] = xi;
+    }
+    __syncthreads();
     if (threadIdx.x == 0) {
+        V sr = V(0), si = V(0);
+        for (unsigned w = 0; w < kBlock / kWave; ++w) {
+            sr += sh.red[2 * w];
+            si += sh.red[2 * w + 1];
+        }
         uint64_t *slot = slots + uint64_t(blockIdx.x) * 4u;
-        put_tagged(slot, double(xr), tag);
-        put_tagged(slot + 2, double(xi), tag);
-        sh.abort = 0;
+        put_tagged(slot, double(sr), tag);
+        put_tagged(slot + 2, double(si), tag);
     }
     if (blockIdx.x == 0) {
-        V pr = V(0), pi = V(0);
-        bool ok = true;
-        for (unsigned w = threadIdx.x; w < gridDim.x && ok; w += kBlock) {
-            double x = 0.0, y = 0.0;
-            ok = wait_pair(slots + uint64_t(w) * 4u, tag, a, x, y);
-            pr += V(x);
-            pi += V(y);
-        }
-        const bool failed = __syncthreads_or(!ok) != 0;
-        block_sum2(pr, pi, sh.red);
-        if (threadIdx.x == 0) {
-            if (failed) {
-                sh.abort = 1;
-            } else {
-                put_tagged(bcast, double(pr), tag);
-                put_tagged(bcast + 2, double(pi), tag);
-                sh.sum[0] = pr;
-                sh.sum[1] = pi;
+        if (wave == 0) {
+            V pr = V(0), pi = V(0);
+            bool ok = true;
+            for (unsigned w = lane; w < gridDim.x && ok; w += kWave) {
+                double x = 0.0, y = 0.0;
+                ok = wait_pair(slots + uint64_t(w) * 4u, tag, a, x, y);
+                pr += V(x);
+                pi += V(y);
+            }
+            pr = wave_sum(pr);
+            pi = wave_sum(pi);
+            const bool failed = __any(!ok);
+            if (lane == 0) {
+                sh.abort = failed;
+                if (!failed) {
+                    put_tagged(bcast, double(pr), tag);
+                    put_tagged(bcast + 2, double(pi), tag);
+                    sh.sum[0] = pr;
+                    sh.sum[1] = pi;
+                }
             }
         }
     } else if (threadIdx.x == 0) {
         double x = 0.0, y = 0.0;
-        if (wait_pair(bcast, tag, a, x, y)) {
-            sh.sum[0] = V(x);
-            sh.sum[1] = V(y);
-        } else {
-            sh.abort = 1;
-        }
+        const bool ok = wait_pair(bcast, tag, a, x, y);
+        sh.abort = !ok;
+        sh.sum[0] = V(x);
+        sh.sum[1] = V(y);
     }
     __syncthreads();
-    const bool ok = sh.abort == 0;
     xr = sh.sum[0];
     xi = sh.sum[1];
-    __syncthreads();  // sh is reused by the next barrier
-    return ok;
+    return sh.abort == 0;
 }
 
 __device__ inline uint64_t gallop_lower_bound(const uint64_t *marks, uint64_t start, uint64_t m, uint64_t x)

@@ -41,6 +41,7 @@ __device__ inline C2 cmul(C2 a, C2 b) { return {a.re * b.re - a.im * b.im, a.re 
 struct PhaseShared {
     double red[kPV * (kStreamBlock / kWave)];
     double sum[kPV];
+    int failed;
 };
 
 struct PhaseTeam {
@@ -76,53 +77,91 @@ __device__ inline void block_sum_n(double (&v)[kPV], PhaseShared &sh)
     __syncthreads();
 }
 
+// Bounded wait until all kPV values of one member's slot carry generation `tag`, then adds them to w.
+// False when the wait gave up (time limit, or another workgroup gave up).
+__device__ inline bool wait_slot_n(const uint64_t *slot, uint32_t tag, const PhaseTeam &tm, double (&w)[kPV])
+{
+    const uint64_t t0 = wall_clock64();
+    uint64_t hi[kPV], lo[kPV];
+    for (;;) {
+        bool ready = true;
+#pragma unroll
+        for (int q = 0; q < kPV; ++q)
+            ready = tagged_ready(slot + 2 * q, tag, hi[q], lo[q]) && ready;
+        if (ready)
+            break;
+        if (__hip_atomic_load(&tm.sync->error, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0u)
+            return false;
+        if (uint64_t(wall_clock64()) - t0 > tm.timeout_ticks) {
+            __hip_atomic_store(&tm.sync->error, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            return false;
+        }
+        __builtin_amdgcn_s_sleep(1);
+    }
+#pragma unroll
+    for (int q = 0; q < kPV; ++q)
+        w[q] += tagged_value(hi[q], lo[q]);
+    return true;
+}
+
 // Team-wide sum of v, an all-gather as in the batched kernels' barrier: every member publishes its kPV
 // partials in its slot of the generation's parity as tagged words (two per value, each carrying the
-// generation; see put_tagged); in every member thread w waits until all of member w's words carry this
-// generation, and the partials are added by a fixed tree, so all members compute identical sums.  Slots
-// are double-buffered by parity (a slot is rewritten two generations later, after every member has read
-// it).  Every thread gets the sums; false when the wait gave up.
+// generation; see put_tagged); in every member the slots are awaited in parallel, one member per thread,
+// until all of a member's words carry this generation, and the partials are added by a fixed tree, so all
+// members compute identical sums.  Slots are double-buffered by parity (a slot is rewritten two
+// generations later, after every member has read it).  Every thread gets the sums; false when the wait
+// gave up.  For T <= 64 the gather is done by wave 0 alone and the sums are added by butterflies (the same
+// bits in every lane and member), so the barrier costs two workgroup barriers; LDS words are written again
+// only after the first barrier of the next call, which every thread reaches after reading them.
 __device__ bool team_sum_n(double (&v)[kPV], const PhaseTeam &tm, uint64_t gen, PhaseShared &sh)
 {
     const uint32_t tag = uint32_t(gen);
     uint64_t *slots = tm.partials + uint64_t(gen & 1u) * tm.size * 16u;
-    block_sum_n(v, sh);
+    const unsigned lane = threadIdx.x % kWave, wave = threadIdx.x / kWave;
+#pragma unroll
+    for (int q = 0; q < kPV; ++q)
+        v[q] = wave_sum(v[q]);
+    if (lane == 0) {
+#pragma unroll
+        for (int q = 0; q < kPV; ++q)
+            sh.red[q * (kStreamBlock / kWave) + wave] = v[q];
+    }
+    __syncthreads();
     if (threadIdx.x == 0) {
         uint64_t *slot = slots + uint64_t(tm.rank) * 16u;
 #pragma unroll
+        for (int q = 0; q < kPV; ++q) {
+            double s = 0.0;
+            for (unsigned w = 0; w < kStreamBlock / kWave; ++w)
+                s += sh.red[q * (kStreamBlock / kWave) + w];
+            put_tagged(slot + 2 * q, s, tag);
+        }
+    }
+    if (tm.size <= kWave) {
+        if (wave == 0) {
+            double w[kPV] = {};
+            const bool ok = lane < tm.size ? wait_slot_n(slots + uint64_t(lane) * 16u, tag, tm, w) : true;
+#pragma unroll
+            for (int q = 0; q < kPV; ++q)
+                w[q] = wave_sum(w[q]);
+            const bool failed = __any(!ok);
+            if (lane == 0) {
+#pragma unroll
+                for (int q = 0; q < kPV; ++q)
+                    sh.sum[q] = w[q];
+                sh.failed = failed;
+            }
+        }
+        __syncthreads();
+#pragma unroll
         for (int q = 0; q < kPV; ++q)
-            put_tagged(slot + 2 * q, v[q], tag);
+            v[q] = sh.sum[q];
+        return sh.failed == 0;
     }
     double w[kPV] = {};
     bool ok = true;
-    for (unsigned r = threadIdx.x; r < tm.size && ok; r += kStreamBlock) {
-        const uint64_t *slot = slots + uint64_t(r) * 16u;
-        const uint64_t t0 = wall_clock64();
-        uint64_t hi[kPV], lo[kPV];
-        for (;;) {
-            bool ready = true;
-#pragma unroll
-            for (int q = 0; q < kPV; ++q)
-                ready = tagged_ready(slot + 2 * q, tag, hi[q], lo[q]) && ready;
-            if (ready)
-                break;
-            if (__hip_atomic_load(&tm.sync->error, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0u) {
-                ok = false;
-                break;
-            }
-            if (uint64_t(wall_clock64()) - t0 > tm.timeout_ticks) {
-                __hip_atomic_store(&tm.sync->error, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                ok = false;
-                break;
-            }
-            __builtin_amdgcn_s_sleep(1);
-        }
-        if (ok) {
-#pragma unroll
-            for (int q = 0; q < kPV; ++q)
-                w[q] += tagged_value(hi[q], lo[q]);
-        }
-    }
+    for (unsigned r = threadIdx.x; r < tm.size && ok; r += kStreamBlock)
+        ok = wait_slot_n(slots + uint64_t(r) * 16u, tag, tm, w);
     const bool failed = __syncthreads_or(!ok) != 0;
     block_sum_n(w, sh);
     if (threadIdx.x == 0) {
@@ -134,7 +173,7 @@ __device__ bool team_sum_n(double (&v)[kPV], const PhaseTeam &tm, uint64_t gen, 
 #pragma unroll
     for (int q = 0; q < kPV; ++q)
         v[q] = sh.sum[q];
-    __syncthreads();
+    __syncthreads();  // sh.sum is rewritten by the next call before its first barrier on this path
     return !failed;
 }
 
