@@ -90,6 +90,31 @@ def test_small_batch_matches_oracle(G, expected, split, team, resident):
     b.close()
 
 
+@pytest.mark.parametrize("split,team,resident", [(19, 2, 16), (19, 2, 8), (0, 1, 0), (20, 0, 4)])
+def test_large_instances_match_oracle(G, orc, split, team, resident):
+    """The largest instance sizes (n = 21 ... 24) with a few iterations each, beside small ones: with 16
+    vectors per thread they are held by teams of 64, 128 and 256 workgroups (the whole grid) and n = 24
+    streams; with 8, n >= 23 streams; (0, 1, 0) streams every large state through one workgroup; team 0 is
+    the whole grid per streamed instance."""
+    rows = [(24, [1, 16777215], 3), (23, [4194304], 4), (22, [0, 7, 3000000], 3), (21, [2097151], 5),
+            (20, [12345], 2), (9, [3], None), (15, [0, 32767], 6)]
+    ks = iterations(orc, rows)
+    b = make(G, rows)
+    grid = b.query(G.grover.BQ_GRID)
+    if team == 0 and grid & (grid - 1):
+        b.close()
+        pytest.skip("a whole-grid streamed team nests inside the resident teams only for a power-of-two grid")
+    b.set_tiling(split, team if team else grid, resident)
+    b.run()
+    b.sync()
+    for i, ((n, mk, _), k) in enumerate(zip(rows, ks)):
+        want = orc.search(n, mk, k)
+        got = b.read_state(i).astype(np.complex128)
+        err = float(np.max(np.abs(got - want)))
+        assert err <= error_bound(n, max(k, 1), "c64", "f64", 1), (i, n, k, split, team, resident, err)
+    b.close()
+
+
 def test_batch_runs_are_bitwise_reproducible_and_graph_replays_match(G):
     import torch
 
