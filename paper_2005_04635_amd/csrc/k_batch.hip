@@ -39,29 +39,22 @@ struct BatchArgs {
     uint64_t timeout_ticks;
 };
 
-// Workgroup sum of (a, b) for every thread with one workgroup barrier: wave butterflies, then every thread
-// adds the wave values in wave order (the same bits everywhere).  The wave values alternate between two
+// Workgroup sum of (a, b) for every thread with one workgroup barrier: wave totals, then every thread adds
+// the wave values by the same fixed tree (the same bits everywhere).  The wave values alternate between two
 // buffers by `parity`: a buffer is rewritten two calls later, after the next call's barrier, which every
 // thread reaches only after reading it.
 __device__ inline void block_allsum(double &a, double &b, unsigned parity, TeamShared<double> &sh)
 {
     const unsigned lane = threadIdx.x % kWave, wave = threadIdx.x / kWave;
     double *red = sh.red[parity & 1u];
-    a = wave_sum(a);
-    b = wave_sum(b);
+    a = wave_total(a);
+    b = wave_total(b);
     if (lane == 0) {
         red[2 * wave] = a;
         red[2 * wave + 1] = b;
     }
     __syncthreads();
-    double sa = 0.0, sb = 0.0;
-#pragma unroll
-    for (unsigned w = 0; w < kStreamBlock / kWave; ++w) {
-        sa += red[2 * w];
-        sb += red[2 * w + 1];
-    }
-    a = sa;
-    b = sb;
+    add_wave_values(red, a, b);
 }
 
 __device__ inline float4 uniform_vec(double amp)
@@ -94,12 +87,108 @@ __device__ bool run_team_streamed(const BatchArgs &a, const BatchInstance &I, co
     return true;
 }
 
+// Update of one held vector as if it held no marked amplitude (c' = 2S/N - c per amplitude, the stored
+// values accumulated).  Marked amplitudes are handled around the sweep: their stored values are negated
+// before it (exactly), which makes this update produce 2S/N + c, their correct new value bit for bit, and
+// the sum is corrected after it by -2c' per marked amplitude (so it holds s c' for them, as the inversion
+// about the mean needs).  Every thread thus runs the same short update, and the few threads with marks
+// only add a few operations; the slowest wave sets the pace of every iteration.
+__device__ inline void unmarked_update(float4 &v, double mr, double mi, AccF64 &acc)
+{
+    v.x = float(mr - double(v.x));
+    v.y = float(mi - double(v.y));
+    v.z = float(mr - double(v.z));
+    v.w = float(mi - double(v.w));
+    acc.add(double(v.x), double(v.y));
+    acc.add(double(v.z), double(v.w));
+}
+
+// Negates the stored values of the marked amplitudes among a thread's held vectors (bits 2e, 2e + 1 of
+// `mask` for vector e).
+__device__ inline void negate_marked(float4 (&x)[kRegE], float4 *held, uint32_t mask)
+{
+#pragma unroll
+    for (int e = 0; e < kHoldE; ++e) {
+        const unsigned b = (mask >> (2 * e)) & 3u;
+        if (b != 0u) {
+            float4 v = e < kRegE ? x[e] : held[(e - kRegE) * kStreamBlock + threadIdx.x];
+            if (b & 1u) {
+                v.x = -v.x;
+                v.y = -v.y;
+            }
+            if (b & 2u) {
+                v.z = -v.z;
+                v.w = -v.w;
+            }
+            if (e < kRegE)
+                x[e] = v;
+            else
+                held[(e - kRegE) * kStreamBlock + threadIdx.x] = v;
+        }
+    }
+}
+
+// After the sweep: the sum holds +c' for the marked amplitudes; subtracting 2c' makes it s c'.
+__device__ inline void correct_marked(const float4 (&x)[kRegE], const float4 *held, uint32_t mask, AccF64 &acc)
+{
+#pragma unroll
+    for (int e = 0; e < kHoldE; ++e) {
+        const unsigned b = (mask >> (2 * e)) & 3u;
+        if (b != 0u) {
+            const float4 v = e < kRegE ? x[e] : held[(e - kRegE) * kStreamBlock + threadIdx.x];
+            if (b & 1u)
+                acc.add(-2.0 * double(v.x), -2.0 * double(v.y));
+            if (b & 2u)
+                acc.add(-2.0 * double(v.z), -2.0 * double(v.w));
+        }
+    }
+}
+
+// One iteration over a thread's held vectors (e < ne in order: x[e] in registers for e < kRegE, then the
+// LDS slots), each updated as unmarked.  When all 16 are held, the LDS vectors are loaded four at a time,
+// each group while the previous one (or the register half) is being updated, so that their latency hides
+// behind arithmetic.
+__device__ inline void held_sweep(float4 (&x)[kRegE], float4 *held, unsigned ne, double mr, double mi, AccF64 &acc)
+{
+    const unsigned tid = threadIdx.x;
+    if (ne == unsigned(kHoldE)) {
+        constexpr int kG = 4;
+        static_assert(2 * kG == kLdsE, "two groups cover the LDS half");
+        float4 y[kG], z[kG];
+#pragma unroll
+        for (int g = 0; g < kG; ++g)
+            y[g] = held[g * kStreamBlock + tid];
+#pragma unroll
+        for (int e = 0; e < kRegE; ++e)
+            unmarked_update(x[e], mr, mi, acc);
+#pragma unroll
+        for (int g = 0; g < kG; ++g)
+            z[g] = held[(kG + g) * kStreamBlock + tid];
+#pragma unroll
+        for (int g = 0; g < kG; ++g) {
+            unmarked_update(y[g], mr, mi, acc);
+            held[g * kStreamBlock + tid] = y[g];
+        }
+#pragma unroll
+        for (int g = 0; g < kG; ++g) {
+            unmarked_update(z[g], mr, mi, acc);
+            held[(kG + g) * kStreamBlock + tid] = z[g];
+        }
+    } else {
+#pragma unroll
+        for (int e = 0; e < kRegE; ++e)
+            if (unsigned(e) < ne)
+                unmarked_update(x[e], mr, mi, acc);
+    }
+}
+
 // One instance held on chip by a team for all its iterations: member `rank` owns the contiguous vectors
-// [rank * per, (rank + 1) * per), per = nvec / T <= kHoldE * 1024, thread `tid` the vectors
-// rank * per + e * 1024 + tid, e < kHoldE: the first kRegE in registers, the others in the thread's own
-// slots of LDS (held[(e - kRegE) * 1024 + tid]; no other thread touches them, so no workgroup barrier is
-// needed around them).  Marked bits travel packed, two per vector.  `reduce` is the team's (or the
-// workgroup's) sum; the state is written to memory once, at the end.  Returns false when a barrier gave up.
+// [rank * per, (rank + 1) * per), per = nvec / T a power of two <= kHoldE * 1024, thread `tid` the vectors
+// rank * per + e * 1024 + tid, e < ne = per / 1024 (or, when per < 1024, the one vector tid < per): the
+// first kRegE in registers, the others in the thread's own slots of LDS (held[(e - kRegE) * 1024 + tid]; no
+// other thread touches them, so no workgroup barrier is needed around them).  Marked bits travel packed, two
+// per vector.  `reduce` is the team's (or the workgroup's) sum; the state is written to memory once, at
+// the end.  Returns false when a barrier gave up.
 template <class Reduce>
 __device__ bool run_held(const BatchArgs &a, const BatchInstance &I, uint64_t base, uint64_t per, float4 *held,
                          TeamShared<double> &sh, Reduce reduce)
@@ -107,17 +196,21 @@ __device__ bool run_held(const BatchArgs &a, const BatchInstance &I, uint64_t ba
     float4 *st = a.state + I.state_off + base;
     const uint64_t *marks = a.marks + I.marks_off;
     const unsigned tid = threadIdx.x;
+    const unsigned ne = per >= kStreamBlock ? unsigned(per / kStreamBlock) : 1u;  // 1, 2, 4, 8 or 16
+    const bool active = tid < per;
     const float4 fill = uniform_vec(I.amp);
+    // 2/N is a power of two, so S * (2/N) rounds to the same binary64 value as 2S / N
+    const double scale = 2.0 / I.N;
     uint32_t mask = 0u;
     AccF64 acc0;
+    if (active) {
 #pragma unroll 1
-    for (int e = 0; e < kHoldE; ++e) {
-        const uint64_t v = uint64_t(e) * kStreamBlock + tid;
-        if (v < per) {
+        for (unsigned e = 0; e < ne; ++e) {
+            const uint64_t v = uint64_t(e) * kStreamBlock + tid;
             const unsigned bits = marked_bits<2>(marks, 0, I.m, (base + v) * 2u);
             mask |= uint32_t(bits) << (2 * e);
             accum_vec<C64>(fill, bits, acc0);
-            if (e >= kRegE)
+            if (e >= unsigned(kRegE))
                 held[(e - kRegE) * kStreamBlock + tid] = fill;
         }
     }
@@ -129,30 +222,25 @@ __device__ bool run_held(const BatchArgs &a, const BatchInstance &I, uint64_t ba
     if (!reduce(sr, si))
         return false;
     for (uint64_t it = 0; it < I.iters; ++it) {
-        const double mr = (sr * 2.0) / I.N, mi = (si * 2.0) / I.N;
+        const double mr = sr * scale, mi = si * scale;
         AccF64 acc;
-#pragma unroll
-        for (int e = 0; e < kRegE; ++e)
-            if (uint64_t(e) * kStreamBlock + tid < per)
-                update_vec<C64>(x[e], mr, mi, (mask >> (2 * e)) & 3u, acc);
-#pragma unroll 2
-        for (int e = kRegE; e < kHoldE; ++e) {
-            if (uint64_t(e) * kStreamBlock + tid >= per)
-                break;
-            float4 y = held[(e - kRegE) * kStreamBlock + tid];
-            update_vec<C64>(y, mr, mi, (mask >> (2 * e)) & 3u, acc);
-            held[(e - kRegE) * kStreamBlock + tid] = y;
+        if (active) {
+            if (mask != 0u)
+                negate_marked(x, held, mask);
+            held_sweep(x, held, ne, mr, mi, acc);
+            if (mask != 0u)
+                correct_marked(x, held, mask, acc);
         }
         sr = acc.r;
         si = acc.i;
         if (!reduce(sr, si))
             return false;
     }
+    if (active) {
 #pragma unroll
-    for (int e = 0; e < kHoldE; ++e) {
-        const uint64_t v = uint64_t(e) * kStreamBlock + tid;
-        if (v < per)
-            st[v] = e < kRegE ? x[e] : held[(e - kRegE) * kStreamBlock + tid];
+        for (int e = 0; e < kHoldE; ++e)
+            if (unsigned(e) < ne)
+                st[uint64_t(e) * kStreamBlock + tid] = e < kRegE ? x[e] : held[(e - kRegE) * kStreamBlock + tid];
     }
     return true;
 }
@@ -203,7 +291,9 @@ __global__ __launch_bounds__(kStreamBlock) void batch_kernel(BatchArgs a)
                 if (threadIdx.x == 0)
                     taken = atomicAdd(&a.heads[p], 1ull);
                 __syncthreads();
-                const uint64_t q = taken;
+                // the index is the same in every lane; saying so keeps the instance's fields in scalar registers
+                const uint64_t q = __builtin_amdgcn_readfirstlane(uint32_t(taken)) |
+                                   (uint64_t(__builtin_amdgcn_readfirstlane(uint32_t(taken >> 32))) << 32);
                 __syncthreads();
                 if (q >= count)
                     break;
@@ -231,7 +321,9 @@ __global__ __launch_bounds__(kStreamBlock) void batch_kernel(BatchArgs a)
                 zr = double(atomicAdd(&a.heads[p], 1ull));
             if (!team_sum<double>(zr, zi, tm, ++gen, sh))
                 return;
-            const uint64_t q = uint64_t(zr);
+            const uint64_t qv = uint64_t(zr);  // the same in every lane (a team sum); made scalar below
+            const uint64_t q = __builtin_amdgcn_readfirstlane(uint32_t(qv)) |
+                               (uint64_t(__builtin_amdgcn_readfirstlane(uint32_t(qv >> 32))) << 32);
             if (q >= count)
                 break;
             const BatchInstance I = a.inst[a.queue[q0 + q]];

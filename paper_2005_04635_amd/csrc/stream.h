@@ -23,6 +23,61 @@ struct TeamShared {
     int failed;
 };
 
+// Sum over the 64 lanes of a wave, the same bits returned in every lane, without a trip through the LDS
+// crossbar: four DPP row shifts (each lane adds the value 1, 2, 4, 8 lanes below it in its row of 16, zero
+// past the row's start) leave each row's sum in its last lane; the four row sums are read into scalar
+// registers and added as (r0 + r1) + (r2 + r3).  A fixed order, so the result is reproducible.
+template <int kCtrl>
+__device__ inline double dpp_row_shifted(double x)
+{
+    const long long b = __double_as_longlong(x);
+    const int lo = __builtin_amdgcn_update_dpp(0, int(b), kCtrl, 0xf, 0xf, true);
+    const int hi = __builtin_amdgcn_update_dpp(0, int(b >> 32), kCtrl, 0xf, 0xf, true);
+    return __longlong_as_double((static_cast<long long>(hi) << 32) | static_cast<unsigned>(lo));
+}
+
+__device__ inline double lane_value(double x, int lane)
+{
+    const long long b = __double_as_longlong(x);
+    const int lo = __builtin_amdgcn_readlane(int(b), lane);
+    const int hi = __builtin_amdgcn_readlane(int(b >> 32), lane);
+    return __longlong_as_double((static_cast<long long>(hi) << 32) | static_cast<unsigned>(lo));
+}
+
+__device__ inline double wave_total(double x)
+{
+    x += dpp_row_shifted<0x111>(x);  // row_shr:1
+    x += dpp_row_shifted<0x112>(x);  // row_shr:2
+    x += dpp_row_shifted<0x114>(x);  // row_shr:4
+    x += dpp_row_shifted<0x118>(x);  // row_shr:8
+    return (lane_value(x, 15) + lane_value(x, 31)) + (lane_value(x, 47) + lane_value(x, 63));
+}
+
+__device__ inline float wave_total(float x) { return wave_sum(x); }
+
+// The 16 wave values of a 1024-thread workgroup, (re, im) interleaved in red[0 .. 32), added as a balanced
+// tree (four levels of dependent additions instead of fifteen).
+template <class V>
+__device__ inline void add_wave_values(const V *red, V &sr, V &si)
+{
+    V r[kStreamBlock / kWave], i[kStreamBlock / kWave];
+#pragma unroll
+    for (unsigned w = 0; w < kStreamBlock / kWave; ++w) {
+        r[w] = red[2 * w];
+        i[w] = red[2 * w + 1];
+    }
+#pragma unroll
+    for (unsigned h = 1; h < kStreamBlock / kWave; h *= 2) {
+#pragma unroll
+        for (unsigned w = 0; w < kStreamBlock / kWave; w += 2 * h) {
+            r[w] += r[w + h];
+            i[w] += i[w + h];
+        }
+    }
+    sr = r[0];
+    si = i[0];
+}
+
 // Where a team's barrier lives: its error word (GridSync), its member slots [2][T][4] (the member's partial
 // sum as tagged words, see put_tagged; double-buffered by the generation's parity), the number of
 // workgroups T, this workgroup's rank, and the wait limit.
@@ -112,35 +167,32 @@ __device__ bool team_sum(V &xr, V &xi, const Team &tm, uint64_t gen, TeamShared<
     const uint32_t tag = uint32_t(gen);
     uint64_t *slots = tm.partials + uint64_t(gen & 1u) * tm.size * 4u;
     const unsigned lane = threadIdx.x % kWave, wave = threadIdx.x / kWave;
-    // this member's partial: wave butterflies, then thread 0 adds the wave values in wave order and publishes
+    // this member's partial: wave totals, then thread 0 adds the wave values by a fixed tree and publishes
     // it.  sh.red[0] is read by thread 0 only before the workgroup barrier below; a wave writes it again
     // only in the next call, after that barrier, so no barrier is needed behind the read.
-    xr = wave_sum(xr);
-    xi = wave_sum(xi);
+    xr = wave_total(xr);
+    xi = wave_total(xi);
     if (lane == 0) {
         sh.red[0][2 * wave] = xr;
         sh.red[0][2 * wave + 1] = xi;
     }
     __syncthreads();
     if (threadIdx.x == 0) {
-        V sr = V(0), si = V(0);
-        for (unsigned w = 0; w < kStreamBlock / kWave; ++w) {
-            sr += sh.red[0][2 * w];
-            si += sh.red[0][2 * w + 1];
-        }
+        V sr, si;
+        add_wave_values(sh.red[0], sr, si);
         uint64_t *slot = slots + uint64_t(tm.rank) * 4u;
         put_tagged(slot, double(sr), tag);
         put_tagged(slot + 2, double(si), tag);
     }
     if (tm.size <= kWave) {
         // every member's partial fits one wave: wave 0 gathers them (lane w waits for member w) and adds them
-        // by butterflies, which leave the same bits in every lane and in every member; one workgroup barrier
-        // hands the sum on.  sh.sum and sh.failed are written again only after the first barrier of the next
+        // with wave_total, which leaves the same bits in every lane and in every member; one workgroup
+        // barrier hands the sum on.  sh.sum and sh.failed are written again only after the first barrier of the next
         // call, which every thread reaches after reading them here.
         if (wave == 0) {
             double a = 0.0, b = 0.0;
             const bool ok = lane < tm.size ? wait_pair(slots + uint64_t(lane) * 4u, tag, tm, a, b) : true;
-            const V pr = wave_sum(V(a)), pi = wave_sum(V(b));
+            const V pr = wave_total(V(a)), pi = wave_total(V(b));
             const bool failed = __any(!ok);
             if (lane == 0) {
                 sh.sum[0] = pr;
