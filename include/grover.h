@@ -273,7 +273,9 @@ int grover_batch_read_state(grover_batch *b, uint64_t i, void *host, size_t byte
 
 /* grover_batch_query — key: 0 = count, 1 = persistent grid size, 2 = split_n, 3 = team, 4 = total amplitude
  * updates per run (sum of 2^n[i] * iterations[i]), 5 = 1 when a captured graph is in use, 6 = bytes of all
- * states, 7 = instances iterated by multi-workgroup teams, 8 = resident, 9 = phases of the tiling. */
+ * states, 7 = instances iterated by multi-workgroup teams, 8 = resident, 9 = phases of the tiling,
+ * 10 = 1 when some state of the tiling streams from memory (0: every state is held on chip, and the run uses
+ * the kernel compiled without the streamed paths). */
 int grover_batch_query(grover_batch *b, int key, int64_t *value);
 
 /* grover_batch_destroy — wait for the stream and release everything.  NULL is ignored. */

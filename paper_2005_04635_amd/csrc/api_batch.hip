@@ -34,6 +34,7 @@ struct grover_batch {
     uint32_t nphases = 0;
     uint64_t qoff[kBatchMaxPhases + 1] = {};
     uint32_t phase_team[kBatchMaxPhases] = {}, phase_resident[kBatchMaxPhases] = {};
+    uint32_t streams = 1;  // 0 when the tiling holds every state on chip
     uint64_t timeout_ticks = 0;
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
@@ -107,6 +108,7 @@ BatchLaunch launch_of(const grover_batch *b, uint64_t timeout_ticks)
         L.resident[p] = b->phase_resident[p];
     }
     L.nphases = b->nphases;
+    L.streams = b->streams;
     L.heads = b->heads;
     L.sync = b->team_sync;
     L.partials = b->team_partials;
@@ -209,6 +211,17 @@ int apply_tiling(grover_batch *b, uint32_t split_n, uint32_t team_size, uint32_t
     for (size_t p = phases.size(); p <= size_t(kBatchMaxPhases); ++p)
         b->qoff[p] = q.size();
     BATCH_HIP(b, hipMemcpy(b->queue, q.data(), q.size() * 4, hipMemcpyHostToDevice), "queue upload");
+    // the kernel without the streamed paths serves tilings whose phases all hold their states on chip
+    uint32_t streams = 0;
+    for (size_t p = 0; p < phases.size(); ++p) {
+        if (phases[p].first.second)
+            streams = 1;
+        if (phases[p].first.first == 1)
+            for (uint32_t i : phases[p].second)
+                if (b->nvec[i] > uint64_t(kBatchHoldE) * 1024u)
+                    streams = 1;
+    }
+    b->streams = streams;
     b->n_team = n_team;
     b->split_n = split_n;
     b->team_size = team_size;
@@ -228,7 +241,11 @@ int apply_tiling(grover_batch *b, uint32_t split_n, uint32_t team_size, uint32_t
 int select_grid(grover_batch *b, int clock_khz)
 {
     int per_cu = 0;
-    BATCH_HIP(b, hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, batch_kernel_fn(), 1024, 0), "occupancy");
+    int per_cu_held = 0;
+    BATCH_HIP(b, hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, batch_kernel_fn(true), 1024, 0), "occupancy");
+    BATCH_HIP(b, hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu_held, batch_kernel_fn(false), 1024, 0),
+              "occupancy");
+    per_cu = std::min(per_cu, per_cu_held);
     const int max_grid = std::max(1, per_cu) * b->cu_count;
     BATCH_HIP(b, balloc(&b->team_sync, size_t(max_grid) * kBatchMaxPhases * sizeof(GridSync)), "batch allocation");
     BATCH_HIP(b, balloc(&b->team_partials, size_t(max_grid) * kBatchMaxPhases * 8 * sizeof(uint64_t)),
@@ -236,11 +253,20 @@ int select_grid(grover_batch *b, int clock_khz)
     const uint64_t probe_ticks = uint64_t(clock_khz > 0 ? clock_khz : 100000) * 250;  // 0.25 s
     for (int pc = per_cu > 1 ? per_cu - 1 : 1; pc >= 1; --pc) {
         b->grid = pc * b->cu_count;
-        BatchLaunch L = launch_of(b, probe_ticks);
-        L.probe = 1;
-        BATCH_HIP(b, launch_batch(L), "batch grid check");
-        BATCH_HIP(b, hipStreamSynchronize(b->stream), "batch grid check");
-        if (check_barriers(b) == GROVER_OK)
+        // both instantiations of the kernel (with and without the streamed paths) must fit this grid
+        bool fits = true;
+        for (uint32_t streams : {1u, 0u}) {
+            BatchLaunch L = launch_of(b, probe_ticks);
+            L.probe = 1;
+            L.streams = streams;
+            BATCH_HIP(b, launch_batch(L), "batch grid check");
+            BATCH_HIP(b, hipStreamSynchronize(b->stream), "batch grid check");
+            if (check_barriers(b) != GROVER_OK) {
+                fits = false;
+                break;
+            }
+        }
+        if (fits)
             return GROVER_OK;
     }
     return bfail(b, GROVER_E_COOP, "no co-resident grid of the batch kernel on this device");
@@ -270,7 +296,7 @@ hipError_t make_node_cooperative(hipGraph_t g)
         e = hipGraphKernelNodeGetParams(node, &kp);
         if (e != hipSuccess)
             return e;
-        if (kp.func != batch_kernel_fn())
+        if (kp.func != batch_kernel_fn(true) && kp.func != batch_kernel_fn(false))
             continue;
         ++found;
         hipKernelNodeAttrValue v{};
@@ -581,6 +607,7 @@ int grover_batch_query(grover_batch *b, int key, int64_t *value)
     case 7: *value = int64_t(b->n_team); break;
     case 8: *value = b->resident; break;
     case 9: *value = b->nphases; break;
+    case 10: *value = b->streams; break;
     default: return bfail(b, GROVER_E_INVAL, "unknown query key");
     }
     return GROVER_OK;

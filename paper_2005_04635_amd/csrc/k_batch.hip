@@ -57,6 +57,14 @@ __device__ inline void block_allsum(double &a, double &b, unsigned parity, TeamS
     add_wave_values(red, a, b);
 }
 
+// Sets an error word (the team's, which its members' barrier waits poll, or the workgroup's own), which
+// the host reads after the run and reports as a failure.
+__device__ inline void flag_error(GridSync *word)
+{
+    if (threadIdx.x == 0)
+        __hip_atomic_store(&word->error, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
 __device__ inline float4 uniform_vec(double amp)
 {
     const float af = float(amp);
@@ -267,6 +275,11 @@ __device__ void run_single_streamed(const BatchArgs &a, const BatchInstance &I, 
     }
 }
 
+// kStreams = false compiles the kernel without the streamed paths, for tilings that hold every state on
+// chip: the held loops then get the registers to themselves.  The host launches that instantiation only
+// when no phase streams, so its streamed branches are never taken; were one taken, the kernel would report
+// it through the error word instead of computing.
+template <bool kStreams>
 __global__ __launch_bounds__(kStreamBlock) void batch_kernel(BatchArgs a)
 {
     __shared__ TeamShared<double> sh;
@@ -304,8 +317,10 @@ __global__ __launch_bounds__(kStreamBlock) void batch_kernel(BatchArgs a)
                         block_allsum(r, i, parity++, sh);
                         return true;
                     });
-                else
+                else if (kStreams)
                     run_single_streamed(a, I, sh, table);
+                else
+                    flag_error(a.sync + uint64_t(p) * grid + blockIdx.x);
             }
             continue;
         }
@@ -332,8 +347,11 @@ __global__ __launch_bounds__(kStreamBlock) void batch_kernel(BatchArgs a)
                 const uint64_t per = I.nvec / T;
                 ok = run_held(a, I, uint64_t(tm.rank) * per, per, held, sh,
                               [&](double &r, double &i) { return team_sum<double>(r, i, tm, ++gen, sh); });
-            } else {
+            } else if (kStreams) {
                 ok = run_team_streamed(a, I, tm, gen, sh, table);
+            } else {
+                flag_error(tm.sync);
+                ok = false;
             }
             if (!ok)
                 return;
@@ -359,7 +377,11 @@ __global__ void batch_reset_kernel(unsigned long long *heads, uint64_t nheads, u
 
 }  // namespace
 
-const void *batch_kernel_fn() { return reinterpret_cast<const void *>(&batch_kernel); }
+const void *batch_kernel_fn(bool streams)
+{
+    return streams ? reinterpret_cast<const void *>(&batch_kernel<true>)
+                   : reinterpret_cast<const void *>(&batch_kernel<false>);
+}
 
 hipError_t launch_batch(const BatchLaunch &L)
 {
@@ -392,8 +414,8 @@ hipError_t launch_batch(const BatchLaunch &L)
     if (e != hipSuccess)
         return e;
     void *args[] = {&a};
-    return hipLaunchCooperativeKernel(reinterpret_cast<const void *>(&batch_kernel), dim3(L.grid),
-                                      dim3(kStreamBlock), args, 0, L.stream);
+    return hipLaunchCooperativeKernel(batch_kernel_fn(L.streams != 0u), dim3(L.grid), dim3(kStreamBlock), args, 0,
+                                      L.stream);
 }
 
 }  // namespace grover

@@ -67,7 +67,8 @@ Q_FORM, Q_GRID, Q_BLOCK, Q_ELEM_BYTES, Q_N, Q_M = 0, 1, 2, 3, 4, 5
 
 
 # grover_batch_query keys
-BQ_COUNT, BQ_GRID, BQ_SPLIT, BQ_TEAM, BQ_UPDATES, BQ_GRAPH, BQ_BYTES, BQ_N_TEAM, BQ_RESIDENT, BQ_PHASES = range(10)
+(BQ_COUNT, BQ_GRID, BQ_SPLIT, BQ_TEAM, BQ_UPDATES, BQ_GRAPH, BQ_BYTES, BQ_N_TEAM, BQ_RESIDENT, BQ_PHASES,
+ BQ_STREAMS) = range(11)
 
 
 # grover_phase_query keys

@@ -84,6 +84,8 @@ def test_small_batch_matches_oracle(G, expected, split, team, resident):
     b.set_tiling(split, team if team else grid, resident)
     assert b.query(G.grover.BQ_TEAM) == (team if team else grid)
     assert b.query(G.grover.BQ_RESIDENT) == resident
+    # every state here (n <= 18) fits on chip when resident > 0: the kernel without streamed paths runs
+    assert b.query(G.grover.BQ_STREAMS) == (0 if resident else 1)
     b.run()
     b.sync()
     check_against(*expected, rows, b.read_state, (team, resident))
@@ -105,6 +107,7 @@ def test_large_instances_match_oracle(G, orc, split, team, resident):
         b.close()
         pytest.skip("a whole-grid streamed team nests inside the resident teams only for a power-of-two grid")
     b.set_tiling(split, team if team else grid, resident)
+    assert b.query(G.grover.BQ_STREAMS) == 1  # n = 24 never fits on chip
     b.run()
     b.sync()
     for i, ((n, mk, _), k) in enumerate(zip(rows, ks)):
