@@ -314,9 +314,25 @@ typedef struct grover_phase_config {
  * (NULL = default stream).  Synchronous. */
 int grover_phase_init(grover_phase **out, const grover_phase_config *cfg, void *hip_stream);
 
-/* grover_phase_set_team — workgroups per schedule (1 .. grid size; default: grid / B, at most the number of
- * 64 KiB tiles of one state).  Changes the order of additions in the sums, not the results' meaning. */
+/* grover_phase_set_team — workgroups per schedule in the streamed form (1 .. grid size; default: grid / B,
+ * at most the number of 64 KiB tiles of one state).  Changes the order of additions in the sums, not the
+ * results' meaning. */
 int grover_phase_set_team(grover_phase *p, uint32_t team);
+
+/* grover_phase_set_form — how the states are kept while they iterate:
+ *   GROVER_PHASE_FORM_STREAMED: in memory, read and written by every iteration (any size);
+ *   GROVER_PHASE_FORM_HELD: on chip (registers and LDS) for all K iterations, by teams of a power of two of
+ *     workgroups sized from the state (forward: 16 16-byte vectors per thread; adjoint: 8 of the state and
+ *     8 of the adjoint state); memory holds only the checkpoints and the final state.  Needs both teams to
+ *     fit the grid (n <= 22 on a grid of 256): GROVER_E_UNSUPPORTED otherwise;
+ *   GROVER_PHASE_FORM_AUTO (default): held when it fits, else streamed.
+ * Both forms keep the same checkpoints and final state, so a backward run may use either form whatever the
+ * forward run used.  The forms add in different orders, so their results agree to rounding.
+ * GROVER_E_INVAL for another value. */
+#define GROVER_PHASE_FORM_AUTO 0
+#define GROVER_PHASE_FORM_STREAMED 1
+#define GROVER_PHASE_FORM_HELD 2
+int grover_phase_set_form(grover_phase *p, uint32_t form);
 
 /* grover_phase_forward — run all B schedules.  phi, theta: device, binary64 [B][K] row-major (copied on
  * the stream before the run, so the caller may reuse them afterwards); loss: device, binary64 [B], written.
@@ -338,8 +354,10 @@ int grover_phase_sync(grover_phase *p);
 int grover_phase_state(grover_phase *p, uint32_t b, void **dev_ptr, size_t *bytes);
 int grover_phase_read_state(grover_phase *p, uint32_t b, void *host, size_t bytes);
 
-/* grover_phase_query — key: 0 = B, 1 = persistent grid size, 2 = workgroups per schedule, 3 = checkpoint
- * interval, 4 = stored checkpoints per schedule, 5 = device bytes held. */
+/* grover_phase_query — key: 0 = B, 1 = persistent grid size, 2 = workgroups per schedule (streamed form),
+ * 3 = checkpoint interval, 4 = stored checkpoints per schedule, 5 = device bytes held, 6 = the form the next
+ * run uses (GROVER_PHASE_FORM_STREAMED or _HELD), 7 / 8 = workgroups per schedule of the held form's
+ * forward / adjoint run (0 when the states do not fit on chip). */
 int grover_phase_query(grover_phase *p, int key, int64_t *value);
 
 /* grover_phase_destroy — wait for the stream and release everything (NULL is ignored);

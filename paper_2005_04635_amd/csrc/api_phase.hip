@@ -25,7 +25,9 @@ struct grover_phase {
     PhaseSync *sync = nullptr;
     uint64_t *partials = nullptr;
     int grid = 0;
-    uint32_t team = 1;
+    uint32_t team = 1;                           // workgroups per schedule, streamed form
+    uint32_t form = GROVER_PHASE_FORM_AUTO;      // as chosen by grover_phase_set_form
+    uint32_t held_team_f = 0, held_team_a = 0;   // on-chip form: workgroups per schedule (0: does not fit)
     uint64_t timeout_ticks = 0;
     bool forward_done = false;
     size_t device_bytes = 0;
@@ -104,6 +106,7 @@ PhaseLaunch launch_of(const grover_phase *p)
     L.sync = p->sync;
     L.partials = p->partials;
     L.team_size = p->team;
+    L.held = 0;
     L.teams_alloc = uint32_t(p->grid);
     L.grid = p->grid;
     L.timeout_ticks = p->timeout_ticks;
@@ -127,12 +130,15 @@ int check_barriers(grover_phase *p)
 // of the whole grid under a short wait limit (shrinking on a time-out), as for the other persistent kernels.
 int select_grid(grover_phase *p, int clock_khz)
 {
-    int per_cu_f = 0, per_cu_a = 0;
-    PHASE_HIP(p, hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu_f, phase_kernel_fn(false), 1024, 0),
-              "occupancy");
-    PHASE_HIP(p, hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu_a, phase_kernel_fn(true), 1024, 0),
-              "occupancy");
-    const int per_cu = std::max(1, std::min(per_cu_f, per_cu_a));
+    int per_cu = 1 << 30;
+    for (bool held : {false, true})
+        for (bool adjoint : {false, true}) {
+            int pc = 0;
+            PHASE_HIP(p, hipOccupancyMaxActiveBlocksPerMultiprocessor(&pc, phase_kernel_fn(adjoint, held), 1024, 0),
+                      "occupancy");
+            per_cu = std::min(per_cu, pc);
+        }
+    per_cu = std::max(1, per_cu);
     const int max_grid = per_cu * p->cu_count;
     PHASE_HIP(p, palloc(p, &p->sync, size_t(max_grid) * sizeof(PhaseSync)), "phase allocation");
     PHASE_HIP(p, palloc(p, &p->partials, size_t(max_grid) * 32 * sizeof(uint64_t)), "phase allocation");
@@ -144,19 +150,52 @@ int select_grid(grover_phase *p, int clock_khz)
         L.team_size = uint32_t(p->grid);
         L.timeout_ticks = probe_ticks;
         bool ok = true;
-        for (bool adjoint : {false, true}) {  // each launch zeroes the barriers first: check after each
-            PHASE_HIP(p, launch_phase(L, adjoint), "phase grid check");
-            ok = ok && check_barriers(p) == GROVER_OK;
-        }
+        for (uint32_t held : {0u, 1u})
+            for (bool adjoint : {false, true}) {  // each launch zeroes the barriers first: check after each
+                L.held = held;
+                PHASE_HIP(p, launch_phase(L, adjoint), "phase grid check");
+                ok = ok && check_barriers(p) == GROVER_OK;
+            }
         if (ok)
             return GROVER_OK;
     }
     return pfail(p, GROVER_E_COOP, "no co-resident grid of the phase kernels on this device");
 }
 
+uint32_t pow2_at_least(uint64_t x)
+{
+    uint32_t t = 1;
+    while (t < x)
+        t <<= 1;
+    return t;
+}
+
+// The on-chip form's team sizes: the power of two of workgroups whose threads can hold a state (forward)
+// or a state and its adjoint (adjoint); 0 when that exceeds the largest power of two <= grid.
+void held_teams(grover_phase *p)
+{
+    uint32_t max_team = 1;
+    while (uint64_t(max_team) * 2 <= uint64_t(p->grid))
+        max_team <<= 1;
+    const uint32_t tf = pow2_at_least((p->nvec + kPhaseHeldForwardVecs - 1) / kPhaseHeldForwardVecs);
+    const uint32_t ta = pow2_at_least((p->nvec + kPhaseHeldAdjointVecs - 1) / kPhaseHeldAdjointVecs);
+    const bool fits = tf <= max_team && ta <= max_team;
+    p->held_team_f = fits ? tf : 0;
+    p->held_team_a = fits ? ta : 0;
+}
+
+bool use_held(const grover_phase *p)
+{
+    return p->form == GROVER_PHASE_FORM_HELD || (p->form == GROVER_PHASE_FORM_AUTO && p->held_team_f > 0);
+}
+
 int run(grover_phase *p, bool adjoint, const double *dloss, double *loss, double *dphi, double *dtheta)
 {
     PhaseLaunch L = launch_of(p);
+    if (use_held(p)) {
+        L.held = 1;
+        L.team_size = adjoint ? p->held_team_a : p->held_team_f;
+    }
     L.loss = loss;
     L.dloss = dloss;
     L.dphi = dphi;
@@ -244,6 +283,7 @@ int grover_phase_init(grover_phase **out, const grover_phase_config *cfg, void *
         status = select_grid(p, clock_khz);
         if (status != GROVER_OK)
             throw status;
+        held_teams(p);
         // default team: the grid split evenly over the schedules, no larger than the tiles of one state
         const uint64_t tiles = (p->nvec + 4095) / 4096;
         p->team = uint32_t(std::max<uint64_t>(1, std::min<uint64_t>(uint64_t(p->grid) / p->B, tiles)));
@@ -265,6 +305,18 @@ int grover_phase_set_team(grover_phase *p, uint32_t team)
     if (team < 1 || team > uint32_t(p->grid))
         return pfail(p, GROVER_E_INVAL, "team size must lie in [1, grid size]");
     p->team = team;
+    return GROVER_OK;
+}
+
+int grover_phase_set_form(grover_phase *p, uint32_t form)
+{
+    if (!p)
+        return GROVER_E_INVAL;
+    if (form > GROVER_PHASE_FORM_HELD)
+        return pfail(p, GROVER_E_INVAL, "unknown form");
+    if (form == GROVER_PHASE_FORM_HELD && p->held_team_f == 0)
+        return pfail(p, GROVER_E_UNSUPPORTED, "the states are too large to hold on chip in this grid");
+    p->form = form;
     return GROVER_OK;
 }
 
@@ -336,6 +388,9 @@ int grover_phase_query(grover_phase *p, int key, int64_t *value)
     case 3: *value = p->every; break;
     case 4: *value = p->nck; break;
     case 5: *value = int64_t(p->device_bytes); break;
+    case 6: *value = use_held(p) ? GROVER_PHASE_FORM_HELD : GROVER_PHASE_FORM_STREAMED; break;
+    case 7: *value = p->held_team_f; break;
+    case 8: *value = p->held_team_a; break;
     default: return pfail(p, GROVER_E_INVAL, "unknown query key");
     }
     return GROVER_OK;

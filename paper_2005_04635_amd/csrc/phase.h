@@ -36,12 +36,18 @@ struct PhaseLaunch {
     uint32_t team_size;
     uint32_t teams_alloc;  // barrier objects zeroed before the launch
     uint32_t probe;
+    uint32_t held;  // 1: the on-chip kernels (team_size set from the state size)
     int grid;
     uint64_t timeout_ticks;
     hipStream_t stream;
 };
 
-const void *phase_kernel_fn(bool adjoint);
+// Largest state (vectors) the on-chip kernels hold per thread: forward 16 vectors, adjoint 8 of the state
+// and 8 of the adjoint state.
+constexpr uint64_t kPhaseHeldForwardVecs = 16 * 1024;
+constexpr uint64_t kPhaseHeldAdjointVecs = 8 * 1024;
+
+const void *phase_kernel_fn(bool adjoint, bool held);
 hipError_t launch_phase(const PhaseLaunch &L, bool adjoint);
 
 }  // namespace grover

@@ -6,7 +6,7 @@
 //   grover_cli copy --bytes 2147483648 [--reps 1]              (plain copy kernel of known size)
 //   grover_cli batch --instances FILE [--split S --team T [--resident V] | --tune] [--graph] [--runs R]
 //                   (many searches in one launch; FILE holds one instance per line: n m mark_1 ... mark_m)
-//   grover_cli phase --schedules FILE [--every S] [--team T] [--runs R]
+//   grover_cli phase --schedules FILE [--every S] [--team T] [--form auto|streamed|held] [--runs R]
 //                   (generalized iteration: forward runs and adjoint runs; FILE holds "n m K B", the m marks,
 //                    then B rows of K phases phi and B rows of K phases theta)
 //   run ... --calibrate-copy B                                  (also copy B bytes once, before the search)
@@ -44,7 +44,8 @@ int usage()
             "                      [--shots S] [--shot-seed U] [--steps T] [--calibrate-copy BYTES]\n"
             "       grover_cli copy --bytes B [--reps R]\n"
             "       grover_cli batch --instances FILE [--split S --team T [--resident V] | --tune] [--graph] [--runs R]\n"
-            "       grover_cli phase --schedules FILE [--every S] [--team T] [--runs R]\n");
+            "       grover_cli phase --schedules FILE [--every S] [--team T] [--form auto|streamed|held] "
+            "[--runs R]\n");
     return 2;
 }
 
@@ -359,11 +360,22 @@ int run_batch(int argc, char **argv)
 int run_phase(int argc, char **argv)
 {
     const char *path = nullptr;
-    unsigned every = 0, team = 0;
+    unsigned every = 0, team = 0, form = GROVER_PHASE_FORM_AUTO;
     int runs = 3;
     for (int i = 2; i < argc; ++i) {
         if (!strcmp(argv[i], "--schedules") && i + 1 < argc)
             path = argv[++i];
+        else if (!strcmp(argv[i], "--form") && i + 1 < argc) {
+            const std::string fm = argv[++i];
+            if (fm == "auto")
+                form = GROVER_PHASE_FORM_AUTO;
+            else if (fm == "streamed")
+                form = GROVER_PHASE_FORM_STREAMED;
+            else if (fm == "held")
+                form = GROVER_PHASE_FORM_HELD;
+            else
+                return usage();
+        }
         else if (!strcmp(argv[i], "--every") && i + 1 < argc)
             every = unsigned(atoi(argv[++i]));
         else if (!strcmp(argv[i], "--team") && i + 1 < argc)
@@ -411,6 +423,7 @@ int run_phase(int argc, char **argv)
     CHECK_PHASE(nullptr, grover_phase_init(&p, &cfg, stream));
     if (team)
         CHECK_PHASE(p, grover_phase_set_team(p, team));
+    CHECK_PHASE(p, grover_phase_set_form(p, form));
     const size_t pb = size_t(B) * K * sizeof(double);
     double *d_par = nullptr, *d_loss = nullptr, *d_dloss = nullptr, *d_grad = nullptr;
     CHECK_HIP(hipMalloc(&d_par, 2 * pb));
@@ -441,15 +454,23 @@ int run_phase(int argc, char **argv)
     }
     double loss0 = 0;
     CHECK_HIP(hipMemcpy(&loss0, d_loss, sizeof(double), hipMemcpyDeviceToHost));
-    int64_t grid = 0, tm = 0, ev = 0;
+    int64_t grid = 0, tm = 0, ev = 0, fo = 0, tf = 0, ta = 0;
     CHECK_PHASE(p, grover_phase_query(p, 1, &grid));
     CHECK_PHASE(p, grover_phase_query(p, 2, &tm));
     CHECK_PHASE(p, grover_phase_query(p, 3, &ev));
+    CHECK_PHASE(p, grover_phase_query(p, 6, &fo));
+    CHECK_PHASE(p, grover_phase_query(p, 7, &tf));
+    CHECK_PHASE(p, grover_phase_query(p, 8, &ta));
+    if (fo == GROVER_PHASE_FORM_HELD)  // the held form sizes its teams from the state
+        tm = tf;
     const double upd = double(B) * K * double(uint64_t(1) << n);
     printf("{\"mode\": \"phase\", \"n\": %u, \"m\": %zu, \"K\": %u, \"batch\": %u, \"grid\": %" PRId64
-           ", \"team\": %" PRId64 ", \"every\": %" PRId64 ", \"runs\": %d, \"forward_ms\": %.4f, \"adjoint_ms\": %.4f"
+           ", \"team\": %" PRId64 ", \"adjoint_team\": %" PRId64 ", \"form\": \"%s\", \"every\": %" PRId64
+           ", \"runs\": %d, \"forward_ms\": %.4f, \"adjoint_ms\": %.4f"
            ", \"forward_updates_per_s\": %.6e, \"loss0\": %.12f}\n",
-           n, marks.size(), K, B, grid, tm, ev, runs, fsum / runs, bsum / runs, upd / (fsum / runs / 1e3), loss0);
+           n, marks.size(), K, B, grid, tm, fo == GROVER_PHASE_FORM_HELD ? ta : tm,
+           fo == GROVER_PHASE_FORM_HELD ? "held" : "streamed", ev, runs, fsum / runs, bsum / runs,
+           upd / (fsum / runs / 1e3), loss0);
     fflush(stdout);
     CHECK_HIP(hipFree(d_par));
     CHECK_HIP(hipFree(d_loss));

@@ -72,7 +72,8 @@ Q_FORM, Q_GRID, Q_BLOCK, Q_ELEM_BYTES, Q_N, Q_M = 0, 1, 2, 3, 4, 5
 
 
 # grover_phase_query keys
-PQ_BATCH, PQ_GRID, PQ_TEAM, PQ_EVERY, PQ_CHECKPOINTS, PQ_BYTES = range(6)
+PQ_BATCH, PQ_GRID, PQ_TEAM, PQ_EVERY, PQ_CHECKPOINTS, PQ_BYTES, PQ_FORM, PQ_HELD_TEAM_F, PQ_HELD_TEAM_A = range(9)
+GROVER_PHASE_FORM_AUTO, GROVER_PHASE_FORM_STREAMED, GROVER_PHASE_FORM_HELD = 0, 1, 2
 
 
 class GroverError(RuntimeError):
@@ -132,8 +133,8 @@ EXPORTS = [
     "grover_batch_init", "grover_batch_set_tiling", "grover_batch_tune", "grover_batch_capture",
     "grover_batch_run", "grover_batch_sync", "grover_batch_state", "grover_batch_read_state",
     "grover_batch_query", "grover_batch_destroy", "grover_batch_last_error",
-    "grover_phase_init", "grover_phase_set_team", "grover_phase_forward", "grover_phase_backward",
-    "grover_phase_sync", "grover_phase_state", "grover_phase_read_state", "grover_phase_query",
+    "grover_phase_init", "grover_phase_set_team", "grover_phase_set_form", "grover_phase_forward",
+    "grover_phase_backward", "grover_phase_sync", "grover_phase_state", "grover_phase_read_state", "grover_phase_query",
     "grover_phase_destroy", "grover_phase_last_error",
 ]
 
@@ -192,6 +193,7 @@ def load(path: str = LIB_PATH):
             "grover_batch_last_error": (ctypes.c_char_p, [P]),
             "grover_phase_init": (i32, [ctypes.POINTER(P), ctypes.POINTER(grover_phase_config), P]),
             "grover_phase_set_team": (i32, [P, u32]),
+            "grover_phase_set_form": (i32, [P, u32]),
             "grover_phase_forward": (i32, [P, P, P, P]),
             "grover_phase_backward": (i32, [P, P, P, P]),
             "grover_phase_sync": (i32, [P]),
@@ -394,6 +396,10 @@ def grover_phase_init(cfg: grover_phase_config, hip_stream: int = 0):
 
 def grover_phase_set_team(p, team: int) -> None:
     _pcheck(p, load().grover_phase_set_team(p, team))
+
+
+def grover_phase_set_form(p, form: int) -> None:
+    _pcheck(p, load().grover_phase_set_form(p, form))
 
 
 def grover_phase_forward(p, phi: int, theta: int, loss: int) -> None:
@@ -717,6 +723,13 @@ class GroverPhase:
     def loss(self, phi, theta):
         """Differentiable loss: torch.autograd calls the adjoint kernel for the gradient."""
         return _PhaseLoss.apply(phi, theta, self)
+
+    def set_form(self, form: str) -> "GroverPhase":
+        """"auto", "streamed" (states in memory every iteration) or "held" (on chip for all iterations)."""
+        forms = {"auto": GROVER_PHASE_FORM_AUTO, "streamed": GROVER_PHASE_FORM_STREAMED,
+                 "held": GROVER_PHASE_FORM_HELD}
+        grover_phase_set_form(self.p, forms[form])
+        return self
 
     def sync(self) -> None:
         grover_phase_sync(self.p)

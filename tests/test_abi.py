@@ -270,5 +270,7 @@ def test_phase_init_rejects_bad_marks_and_nulls(lib):
     assert lib.grover_phase_forward(None, None, None, None) == -1
     assert lib.grover_phase_backward(None, None, None, None) == -1
     assert lib.grover_phase_sync(None) == -1
+    assert lib.grover_phase_set_form(None, 0) == -1
+    assert lib.grover_phase_set_team(None, 1) == -1
     assert lib.grover_phase_last_error(None) == b"no phase context"
     lib.grover_phase_destroy(None)

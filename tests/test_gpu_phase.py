@@ -70,13 +70,24 @@ CASES = [  # (n, marks, K, B, every, team or 0 for the default)
 ]
 
 
+@pytest.mark.parametrize("form", ["streamed", "held"])
 @pytest.mark.parametrize("n,marks,K,B,every,team", CASES)
-def test_forward_and_gradient_match_oracle(G, orc, n, marks, K, B, every, team):
+def test_forward_and_gradient_match_oracle(G, orc, n, marks, K, B, every, team, form):
+    """Both forms: states streamed from memory each iteration (team = workgroups per schedule, 0 for the
+    default) or held on chip by teams sized from the state (`team` unused)."""
     phi, theta = workloads.phase_schedule(K, seed=100 + n, spread=0.3, batch=B)
     g = np.array([1.0, -0.5, 2.0][:B])
     eng = G.GroverPhase(n, marks, K, batch=B, checkpoint_every=every)
     assert eng.query(G.grover.PQ_EVERY) == every
     assert eng.query(G.grover.PQ_CHECKPOINTS) == (K - 1) // every
+    assert eng.query(G.grover.PQ_FORM) == G.grover.GROVER_PHASE_FORM_HELD  # the default when it fits
+    eng.set_form(form)
+    assert eng.query(G.grover.PQ_FORM) == (G.grover.GROVER_PHASE_FORM_HELD if form == "held"
+                                           else G.grover.GROVER_PHASE_FORM_STREAMED)
+    # the held teams: the power of two of workgroups whose threads hold 16 vectors (forward) or 8 + 8
+    nvec = 1 << (n - 1)
+    assert eng.query(G.grover.PQ_HELD_TEAM_F) == max(1, 1 << max(0, (nvec - 1).bit_length() - 14))
+    assert eng.query(G.grover.PQ_HELD_TEAM_A) == max(1, 1 << max(0, (nvec - 1).bit_length() - 13))
     if team:
         G.grover_phase_set_team(eng.p, team)
     loss = eng.forward(cuda(phi), cuda(theta))
@@ -172,9 +183,13 @@ def test_team_sizes_agree_and_runs_reproduce(G):
     n, marks, K, B = 16, [12, 40000], 8, 2
     phi, theta = workloads.phase_schedule(K, seed=8, spread=0.3, batch=B)
     results = {}
-    for team in (1, 2, 4):
+    for team in (1, 2, 4, "held"):
         eng = G.GroverPhase(n, marks, K, batch=B)
-        G.grover_phase_set_team(eng.p, team)
+        if team == "held":
+            eng.set_form("held")
+        else:
+            eng.set_form("streamed")
+            G.grover_phase_set_team(eng.p, team)
         runs = []
         for _ in range(2):
             loss = eng.forward(cuda(phi), cuda(theta))
@@ -186,18 +201,64 @@ def test_team_sizes_agree_and_runs_reproduce(G):
         results[team] = runs[0]
         eng.close()
     tol = grad_bound(K, 3)
-    for team in (2, 4):
+    for team in (2, 4, "held"):
         assert np.max(np.abs(results[team][0] - results[1][0])) <= 2 * loss_bound(K)
         assert np.max(np.abs(results[team][1] - results[1][1])) <= 2 * tol
         assert np.max(np.abs(results[team][2] - results[1][2])) <= 2 * tol
 
 
-def test_barrier_timeout_is_reported(G, monkeypatch):
+def test_forms_mix_between_forward_and_backward(G, orc):
+    """Both forms keep the same checkpoints and final state: a backward run in either form after a forward
+    run in either form gives the oracle's gradient."""
+    n, marks, K, B, every = 14, [5, 9000, 16383], 12, 2, 3
+    phi, theta = workloads.phase_schedule(K, seed=21, spread=0.3, batch=B)
+    want = [orc.phase_grad_adjoint(n, marks, phi[b], theta[b]) for b in range(B)]
+    for f_form, b_form in (("held", "streamed"), ("streamed", "held")):
+        eng = G.GroverPhase(n, marks, K, batch=B, checkpoint_every=every)
+        eng.set_form(f_form)
+        loss = eng.forward(cuda(phi), cuda(theta))
+        eng.set_form(b_form)
+        dphi, dtheta = eng.backward(cuda([1.0, 1.0]))
+        eng.sync()
+        loss, dphi, dtheta = loss.cpu().numpy(), dphi.cpu().numpy(), dtheta.cpu().numpy()
+        for b in range(B):
+            ref = orc.phase_search(n, marks, phi[b], theta[b])
+            assert abs(loss[b] - orc.phase_loss(ref, marks)) <= loss_bound(K)
+            assert np.max(np.abs(dphi[b] - want[b][0])) <= grad_bound(K, every)
+            assert np.max(np.abs(dtheta[b] - want[b][1])) <= grad_bound(K, every)
+        assert np.all(eng.read_state(1) == np.complex64(np.float32(orc.uniform_amplitude(n))))
+        eng.close()
+
+
+def test_form_selection_limits(G):
+    eng = G.GroverPhase(8, [3], 4, batch=1)
+    with pytest.raises(G.GroverError) as e:
+        G.grover_phase_set_form(eng.p, 3)
+    assert e.value.status == G.grover.GROVER_E_INVAL
+    eng.set_form("streamed")
+    assert eng.query(G.grover.PQ_FORM) == G.grover.GROVER_PHASE_FORM_STREAMED
+    eng.set_form("auto")
+    assert eng.query(G.grover.PQ_FORM) == G.grover.GROVER_PHASE_FORM_HELD
+    eng.close()
+    # n = 23: the adjoint's team of 2^22 / 8192 = 512 workgroups exceeds the grid, so only streaming is left
+    big = G.GroverPhase(23, [1], 1, batch=1)
+    if big.query(G.grover.PQ_GRID) < 512:
+        assert big.query(G.grover.PQ_HELD_TEAM_F) == 0 and big.query(G.grover.PQ_HELD_TEAM_A) == 0
+        assert big.query(G.grover.PQ_FORM) == G.grover.GROVER_PHASE_FORM_STREAMED
+        with pytest.raises(G.GroverError) as e:
+            big.set_form("held")
+        assert e.value.status == G.grover.GROVER_E_UNSUPPORTED
+    big.close()
+
+
+@pytest.mark.parametrize("form", ["streamed", "held"])
+def test_barrier_timeout_is_reported(G, monkeypatch, form):
     monkeypatch.setenv("GROVER_BARRIER_TIMEOUT_MS", "0")
-    n, marks, K = 16, [5], 6
+    n, marks, K = 17, [5], 6
     phi, theta = workloads.phase_schedule(K, seed=2, batch=1)
     eng = G.GroverPhase(n, marks, K, batch=1)
-    G.grover_phase_set_team(eng.p, 8)
+    eng.set_form(form)
+    G.grover_phase_set_team(eng.p, 8)  # streamed: 8 workgroups; held: 4 from the state size
     eng.forward(cuda(phi), cuda(theta))
     with pytest.raises(G.GroverError) as e:
         eng.sync()
