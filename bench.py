@@ -387,11 +387,12 @@ def sweep_batch(pkg, hip, stream, runs: int) -> None:
 
 
 def sweep_adjoint(pkg, hip, stream, runs: int) -> None:
-    """The differentiable workload (n = 20, M = 3, K = 64 iterations, 64 phase schedules ~ N(pi, 0.1)):
-    forward runs (loss) and adjoint runs (gradient) timed with HIP events on the context's stream, their
-    amplitude rates and algorithmic HBM bandwidth, accuracy against the binary64 oracle on two schedules,
-    and the plain binary64 GPU form (standard iteration, complex128, separate kernels) at the same n for
-    comparison.  One JSON line."""
+    """The differentiable workload (n = 20, M = 3, K = 64 iterations, 64 phase schedules ~ N(pi, 0.1)) in
+    both forms of the library (states held on chip for all steps, the default at this size; states
+    streamed from memory every step): forward runs (loss) and adjoint runs (gradient) timed with HIP events
+    on the context's stream, their amplitude rates, memory traffic, accuracy against the binary64 oracle on
+    two schedules, and the plain binary64 GPU form (standard iteration, complex128, separate kernels) at
+    the same n for comparison.  One JSON line."""
     import numpy as np
 
     import oracle
@@ -408,6 +409,7 @@ def sweep_adjoint(pkg, hip, stream, runs: int) -> None:
     p = pkg.grover_phase_init(cfg, stream.value)
     every, nck = pkg.grover_phase_query(p, g.PQ_EVERY), pkg.grover_phase_query(p, g.PQ_CHECKPOINTS)
     team, grid = pkg.grover_phase_query(p, g.PQ_TEAM), pkg.grover_phase_query(p, g.PQ_GRID)
+    held_teams = (pkg.grover_phase_query(p, g.PQ_HELD_TEAM_F), pkg.grover_phase_query(p, g.PQ_HELD_TEAM_A))
     B, K, N = w.batch, w.K, 1 << w.n
     nbytes = B * K * 8
     bufs = {name: hip.malloc(size) for name, size in
@@ -424,61 +426,82 @@ def sweep_adjoint(pkg, hip, stream, runs: int) -> None:
     def bwd():
         pkg.grover_phase_backward(p, bufs["dloss"].value, bufs["dphi"].value, bufs["dtheta"].value)
 
-    fwd()
-    bwd()
-    pkg.grover_phase_sync(p)
-    f_ms, b_ms = [], []
-    for _ in range(runs):
-        e = [hip.event() for _ in range(3)]
-        hip.lib.hipEventRecord(e[0], stream)
+    def measure(form):
+        pkg.grover_phase_set_form(p, form)
         fwd()
-        hip.lib.hipEventRecord(e[1], stream)
         bwd()
-        hip.lib.hipEventRecord(e[2], stream)
-        f_ms.append(hip.elapsed_ms(e[0], e[1]))
-        b_ms.append(hip.elapsed_ms(e[1], e[2]))
         pkg.grover_phase_sync(p)
-    fm, bm = sorted(f_ms)[len(f_ms) // 2], sorted(b_ms)[len(b_ms) // 2]
-    # results of the last timed pair
-    fwd()
-    pkg.grover_phase_sync(p)
-    loss = np.empty(B)
-    hip.ok(hip.lib.hipMemcpy(ctypes.c_void_p(loss.ctypes.data), bufs["loss"], B * 8, 2), "hipMemcpy D2H")
-    bwd()
-    pkg.grover_phase_sync(p)
-    dphi, dtheta = np.empty((B, K)), np.empty((B, K))
-    hip.ok(hip.lib.hipMemcpy(ctypes.c_void_p(dphi.ctypes.data), bufs["dphi"], nbytes, 2), "hipMemcpy D2H")
-    hip.ok(hip.lib.hipMemcpy(ctypes.c_void_p(dtheta.ctypes.data), bufs["dtheta"], nbytes, 2), "hipMemcpy D2H")
+        f_ms, b_ms = [], []
+        for _ in range(runs):
+            e = [hip.event() for _ in range(3)]
+            hip.lib.hipEventRecord(e[0], stream)
+            fwd()
+            hip.lib.hipEventRecord(e[1], stream)
+            bwd()
+            hip.lib.hipEventRecord(e[2], stream)
+            f_ms.append(hip.elapsed_ms(e[0], e[1]))
+            b_ms.append(hip.elapsed_ms(e[1], e[2]))
+            pkg.grover_phase_sync(p)
+        fm, bm = sorted(f_ms)[len(f_ms) // 2], sorted(b_ms)[len(b_ms) // 2]
+        # results of one more pair
+        fwd()
+        pkg.grover_phase_sync(p)
+        loss = np.empty(B)
+        hip.ok(hip.lib.hipMemcpy(ctypes.c_void_p(loss.ctypes.data), bufs["loss"], B * 8, 2), "hipMemcpy D2H")
+        bwd()
+        pkg.grover_phase_sync(p)
+        dphi, dtheta = np.empty((B, K)), np.empty((B, K))
+        hip.ok(hip.lib.hipMemcpy(ctypes.c_void_p(dphi.ctypes.data), bufs["dphi"], nbytes, 2), "hipMemcpy D2H")
+        hip.ok(hip.lib.hipMemcpy(ctypes.c_void_p(dtheta.ctypes.data), bufs["dtheta"], nbytes, 2), "hipMemcpy D2H")
+        return fm, bm, loss, dphi, dtheta
+
+    runs_by_form = {"held": measure(g.GROVER_PHASE_FORM_HELD), "streamed": measure(g.GROVER_PHASE_FORM_STREAMED)}
     pkg.grover_phase_destroy(p)
     for b_ in bufs.values():
         hip.lib.hipFree(b_)
     orc = oracle.default()
-    acc = []
+    want = {}
     for b in (0, B - 1):
-        want_loss = orc.phase_loss(orc.phase_search(w.n, marks, phi[b], theta[b]), marks)
-        wphi, wtheta = orc.phase_grad_adjoint(w.n, marks, phi[b], theta[b])
-        acc.append({"schedule": b, "loss": loss[b], "loss_abs_err": abs(loss[b] - want_loss),
-                    "grad_max_abs_err": float(max(np.max(np.abs(dphi[b] - wphi)), np.max(np.abs(dtheta[b] - wtheta)))),
-                    "grad_max_abs": float(max(np.max(np.abs(wphi)), np.max(np.abs(wtheta))))})
+        want[b] = (orc.phase_loss(orc.phase_search(w.n, marks, phi[b], theta[b]), marks),
+                   orc.phase_grad_adjoint(w.n, marks, phi[b], theta[b]))
     plain = time_form(pkg, hip, stream, w.n, "c128", "two_pass", marks, 300, 48, 0)
-    fwd_bytes = B * (8.0 * N + 16.0 * N * K + 8.0 * N * nck)
-    bwd_bytes = B * (8.0 * N + 32.0 * N * K)
     updates = float(B) * K * N
+    # memory traffic per run: streamed, every step reads and writes the state (and the adjoint state);
+    # held, only the checkpoints and the final states
+    traffic = {"streamed": (B * (8.0 * N + 16.0 * N * K + 8.0 * N * nck), B * (8.0 * N + 32.0 * N * K)),
+               "held": (B * (8.0 * N * nck + 8.0 * N), B * (8.0 * N + 8.0 * N * nck + 8.0 * N))}
+    forms = {}
+    for form, (fm, bm, loss, dphi, dtheta) in runs_by_form.items():
+        fb, bb = traffic[form]
+        acc = []
+        for b in (0, B - 1):
+            want_loss, (wphi, wtheta) = want[b]
+            acc.append({"schedule": b, "loss": loss[b], "loss_abs_err": abs(loss[b] - want_loss),
+                        "grad_max_abs_err": float(max(np.max(np.abs(dphi[b] - wphi)),
+                                                      np.max(np.abs(dtheta[b] - wtheta)))),
+                        "grad_max_abs": float(max(np.max(np.abs(wphi)), np.max(np.abs(wtheta))))})
+        forms[form] = {
+            "teams": {"forward": held_teams[0], "adjoint": held_teams[1]} if form == "held" else team,
+            "forward_ms": round(fm, 3), "adjoint_ms": round(bm, 3),
+            "forward_amplitude_updates_per_s": updates / (fm / 1e3),
+            "adjoint_amplitude_steps_per_s": updates / (bm / 1e3),
+            "forward_memory_bytes": fb, "adjoint_memory_bytes": bb,
+            "forward_memory_gbs": round(fb / (fm / 1e3) / 1e9, 1),
+            "adjoint_memory_gbs": round(bb / (bm / 1e3) / 1e9, 1),
+            "forward_vs_plain_fp64": (updates / (fm / 1e3)) / plain["amplitude_updates_per_s"],
+            "forward_plus_adjoint_vs_plain_fp64_forward_only":
+                (updates / ((fm + bm) / 1e3)) / plain["amplitude_updates_per_s"],
+            "accuracy_vs_fp64_oracle": acc}
+    s_fm, s_bm = forms["streamed"]["forward_ms"], forms["streamed"]["adjoint_ms"]
+    sf, sb = traffic["streamed"]
     print(json.dumps({
         "sweep": "adjoint", "workload": w.name, "n": w.n, "m": w.m, "K": K, "batch": B, "storage": "complex64",
-        "arithmetic": "f64", "checkpoint_every": every, "checkpoints_per_schedule": nck, "team": team, "grid": grid,
-        "forward_ms": round(fm, 3), "adjoint_ms": round(bm, 3),
-        "forward_amplitude_updates_per_s": updates / (fm / 1e3),
-        "adjoint_amplitude_steps_per_s": updates / (bm / 1e3),
-        "forward_algorithmic_gbs": round(fwd_bytes / (fm / 1e3) / 1e9, 1),
-        "adjoint_algorithmic_gbs": round(bwd_bytes / (bm / 1e3) / 1e9, 1),
-        "forward_frac_of_hbm_peak": round(fwd_bytes / (fm / 1e3) / 1e9 / HBM_PEAK_GBS, 4),
-        "adjoint_frac_of_hbm_peak": round(bwd_bytes / (bm / 1e3) / 1e9 / HBM_PEAK_GBS, 4),
+        "arithmetic": "f64", "checkpoint_every": every, "checkpoints_per_schedule": nck, "grid": grid,
+        "default_form": "held", "forward_ms": forms["held"]["forward_ms"], "adjoint_ms": forms["held"]["adjoint_ms"],
+        "streamed_forward_frac_of_hbm_peak": round(sf / (s_fm / 1e3) / 1e9 / HBM_PEAK_GBS, 4),
+        "streamed_adjoint_frac_of_hbm_peak": round(sb / (s_bm / 1e3) / 1e9 / HBM_PEAK_GBS, 4),
         "plain_fp64_amplitude_updates_per_s": plain["amplitude_updates_per_s"],
-        "forward_vs_plain_fp64": (updates / (fm / 1e3)) / plain["amplitude_updates_per_s"],
-        "forward_plus_adjoint_vs_plain_fp64_forward_only":
-            (updates / ((fm + bm) / 1e3)) / plain["amplitude_updates_per_s"],
-        "accuracy_vs_fp64_oracle": acc, "runs": runs}), flush=True)
+        "forms": forms, "runs": runs}), flush=True)
 
 
 def main() -> int:
