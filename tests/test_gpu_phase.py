@@ -112,6 +112,32 @@ def test_forward_and_gradient_match_oracle(G, orc, n, marks, K, B, every, team, 
     eng.close()
 
 
+@pytest.mark.parametrize("form", ["streamed", "held"])
+@pytest.mark.parametrize("n,marks,K,every", [(22, [1, 4000000], 3, 1), (1, [1], 3, 2), (2, [0, 3], 4, 1)])
+def test_extreme_sizes_in_both_forms(G, orc, n, marks, K, every, form):
+    """The largest held state (n = 22: forward teams of 128 workgroups and adjoint teams of the whole grid,
+    so the team barrier gathers over several waves) and the smallest ones (one or two vectors)."""
+    phi, theta = workloads.phase_schedule(K, seed=300 + n, spread=0.3, batch=1)
+    eng = G.GroverPhase(n, marks, K, batch=1, checkpoint_every=every)
+    if form == "held" and eng.query(G.grover.PQ_HELD_TEAM_F) == 0:
+        eng.close()
+        pytest.skip("the grid is too small to hold this state")
+    eng.set_form(form)
+    loss = eng.forward(cuda(phi), cuda(theta))
+    eng.sync()
+    want = orc.phase_search(n, marks, phi[0], theta[0])
+    got = eng.read_state(0).astype(np.complex128)
+    assert np.max(np.abs(got - want)) <= forward_bound(K)
+    assert abs(float(loss.cpu()[0]) - orc.phase_loss(want, marks)) <= loss_bound(K)
+    dphi, dtheta = eng.backward(cuda([1.0]))
+    eng.sync()
+    wphi, wtheta = orc.phase_grad_adjoint(n, marks, phi[0], theta[0])
+    tol = grad_bound(K, every)
+    assert np.max(np.abs(dphi.cpu().numpy()[0] - wphi)) <= tol
+    assert np.max(np.abs(dtheta.cpu().numpy()[0] - wtheta)) <= tol
+    eng.close()
+
+
 def test_dense_torch_autograd_at_n6(G):
     from test_oracle_phase import dense_loss_and_grad
 
