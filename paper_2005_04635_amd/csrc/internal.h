@@ -272,6 +272,38 @@ __device__ inline V wave_sum(V x)
     return x;
 }
 
+// Sum over the 64 lanes of a wave, the same bits returned in every lane, without a trip through the LDS
+// crossbar: four DPP row shifts (each lane adds the value 1, 2, 4, 8 lanes below it in its row of 16, zero
+// past the row's start) leave each row's sum in its last lane; the four row sums are read into scalar
+// registers and added as (r0 + r1) + (r2 + r3).  A fixed order, so the result is reproducible.
+template <int kCtrl>
+__device__ inline double dpp_row_shifted(double x)
+{
+    const long long b = __double_as_longlong(x);
+    const int lo = __builtin_amdgcn_update_dpp(0, int(b), kCtrl, 0xf, 0xf, true);
+    const int hi = __builtin_amdgcn_update_dpp(0, int(b >> 32), kCtrl, 0xf, 0xf, true);
+    return __longlong_as_double((static_cast<long long>(hi) << 32) | static_cast<unsigned>(lo));
+}
+
+__device__ inline double lane_value(double x, int lane)
+{
+    const long long b = __double_as_longlong(x);
+    const int lo = __builtin_amdgcn_readlane(int(b), lane);
+    const int hi = __builtin_amdgcn_readlane(int(b >> 32), lane);
+    return __longlong_as_double((static_cast<long long>(hi) << 32) | static_cast<unsigned>(lo));
+}
+
+__device__ inline double wave_total(double x)
+{
+    x += dpp_row_shifted<0x111>(x);  // row_shr:1
+    x += dpp_row_shifted<0x112>(x);  // row_shr:2
+    x += dpp_row_shifted<0x114>(x);  // row_shr:4
+    x += dpp_row_shifted<0x118>(x);  // row_shr:8
+    return (lane_value(x, 15) + lane_value(x, 31)) + (lane_value(x, 47) + lane_value(x, 63));
+}
+
+__device__ inline float wave_total(float x) { return wave_sum(x); }
+
 // Workgroup sum of (a, b): wave butterflies, then thread 0 adds the per-wave values in wave order.
 // `red` must hold 2 * (blockDim / 64) values.  Result valid in thread 0 only.
 template <class V>

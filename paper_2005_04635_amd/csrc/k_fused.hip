@@ -87,7 +87,7 @@ __device__ inline bool wait_pair(const uint64_t *w, uint32_t tag, const FusedArg
 
 // Grid-wide sum of (xr, xi) at generation `gen`: every workgroup publishes its partial as tagged words in
 // its slot of the generation's parity; in workgroup 0, wave 0 gathers them (lane l waits for the slots of
-// workgroups l, l + 64, ... and adds them in that order; the lanes' values are then added by butterflies),
+// workgroups l, l + 64, ... and adds them in that order; the lanes' values are then added by wave_total),
 // so the sum is reproducible run to run, and publishes the sum as tagged words, which the other workgroups
 // poll.  A slot of parity p is rewritten two generations later, after workgroup 0 has read it and every
 // workgroup has read the sum in between; the sum is double-buffered the same way.  Two workgroup barriers:
@@ -102,8 +102,8 @@ __device__ bool grid_sum(V &xr, V &xi, const FusedArgs &a, uint64_t gen, Shared<
     const unsigned lane = threadIdx.x % kWave, wave = threadIdx.x / kWave;
     uint64_t *slots = a.partials + uint64_t(p) * gridDim.x * 4u;
     uint64_t *bcast = a.partials + uint64_t(2) * gridDim.x * 4u + uint64_t(p) * 4u;
-    xr = wave_sum(xr);
-    xi = wave_sum(xi);
+    xr = wave_total(xr);
+    xi = wave_total(xi);
     if (lane == 0) {
         sh.red[2 * wave] = xr;
         sh.red[2 * wave + 1] = xi;
@@ -129,8 +129,8 @@ __device__ bool grid_sum(V &xr, V &xi, const FusedArgs &a, uint64_t gen, Shared<
                 pr += V(x);
                 pi += V(y);
             }
-            pr = wave_sum(pr);
-            pi = wave_sum(pi);
+            pr = wave_total(pr);
+            pi = wave_total(pi);
             const bool failed = __any(!ok);
             if (lane == 0) {
                 sh.abort = failed;
