@@ -190,7 +190,7 @@ def sweep_table1(pkg, hip, stream) -> None:
         k_full = pkg.grover_optimal_iterations(n, 1)
         k = k_full if n <= 20 else 3
         res = {"sweep": "table1", "n": n, "iterations": k, "storage": "c64",
-               "form": ["", "fused", "resident", "two_pass"][pkg.grover_query(ctx, 0)]}
+               "form": ["", "fused", "resident", "two_pass", "held"][pkg.grover_query(ctx, 0)]}
         for path, fn in (("proposed", pkg.grover_iterate), ("gate_level", pkg.grover_gate_iterate),
                          ("gate_level_blocked", pkg.grover_gate_iterate_blocked)):
             pkg.grover_reset(ctx)

@@ -66,12 +66,18 @@ typedef enum grover_oracle_kind {
 } grover_oracle_kind;
 
 typedef enum grover_form {
-    GROVER_FORM_AUTO = 0,     /* RESIDENT for n <= 14 with f64/c64/c128 storage and binary64 sums, else FUSED */
+    GROVER_FORM_AUTO = 0,     /* RESIDENT for n <= 14 with f64/c64/c128 storage and binary64 sums; HELD for
+                                 larger complex64 states with binary64 sums while they fit on chip; else FUSED */
     GROVER_FORM_FUSED = 1,    /* one persistent cooperative kernel per grover_iterate call, one grid
                                  barrier per iteration, update fused with the next iteration's sum */
     GROVER_FORM_RESIDENT = 2, /* one workgroup holds the whole state on chip (n <= 14) */
-    GROVER_FORM_TWO_PASS = 3  /* plain form: per iteration an oracle flip, a sum pass and an update pass,
+    GROVER_FORM_TWO_PASS = 3, /* plain form: per iteration an oracle flip, a sum pass and an update pass,
                                  launched from the host (Algorithms 3 and 4 as separate kernels) */
+    GROVER_FORM_HELD = 4      /* complex64 with binary64 sums only: a team of T workgroups (a power of two;
+                                 8 16-byte vectors per thread in registers while T <= 64, else 16 with 8 in
+                                 LDS) loads the state once per grover_iterate call and keeps it on chip for
+                                 all k iterations, one team barrier each; n <= 23 on 256 CUs
+                                 (GROVER_E_UNSUPPORTED when the state does not fit) */
 } grover_form;
 
 /* ---------------------------------------------------------------------------------------- config */
@@ -178,7 +184,7 @@ int grover_marked(grover_ctx *ctx, uint64_t *out, uint64_t cap, uint64_t *count)
 int grover_sync(grover_ctx *ctx);
 
 /* grover_query — launch facts for diagnostics.  key: 0 = resolved form, 1 = persistent grid size
- * (workgroups), 2 = workgroup size, 3 = element size in bytes, 4 = N, 5 = number of marked indices,
+ * (workgroups; the held form's team), 2 = workgroup size, 3 = element size in bytes, 4 = N, 5 = number of marked indices,
  * 6 = grid-barrier wait limit in device wall-clock ticks, 7 = workgroups per CU of the fused kernel as the
  * runtime's occupancy calculator reports them (the grid actually used is confirmed on the device). */
 int grover_query(grover_ctx *ctx, int key, int64_t *value);

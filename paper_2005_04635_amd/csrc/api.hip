@@ -126,6 +126,26 @@ int select_persistent_grid(grover_ctx *c, int clock_khz)
     return fail(c, GROVER_E_COOP, "no persistent grid of the fused kernel is co-resident on this device");
 }
 
+// The held form's team must be co-resident (its members wait on each other): its barrier slots are
+// allocated and one team barrier is run under a short wait limit, as the fused form's grid is checked.
+int check_held_team(grover_ctx *c, int clock_khz)
+{
+    const int64_t team = int64_t(c->held_team);
+    GROVER_HIP(c, dev_alloc(&c->partials, barrier_slot_bytes(team)), "barrier allocation");
+    GROVER_HIP(c, hipMemset(c->partials, 0, barrier_slot_bytes(team)), "barrier allocation");
+    c->partials_grid = team;
+    GROVER_HIP(c, dev_alloc(&c->sync, sizeof(GridSync)), "barrier allocation");
+    GROVER_HIP(c, reset_barrier(c), "barrier reset before the team check");
+    const uint64_t probe_ticks = uint64_t(clock_khz > 0 ? clock_khz : 100000) * 250;  // 0.25 s
+    GROVER_HIP(c, launch_held_iterate(c, 0, probe_ticks, true), "held team check");
+    GROVER_HIP(c, hipStreamSynchronize(c->stream), "held team check");
+    GridSync gs;
+    GROVER_HIP(c, hipMemcpy(&gs, c->sync, sizeof(gs), hipMemcpyDeviceToHost), "held team check");
+    if (gs.error)
+        return fail(c, GROVER_E_COOP, "the held form's team is not co-resident on this device");
+    return GROVER_OK;
+}
+
 int run_iterations(grover_ctx *c, uint64_t k)
 {
     if (k == 0)
@@ -138,6 +158,11 @@ int run_iterations(grover_ctx *c, uint64_t k)
         GROVER_HIP(c, launch_fused_iterate(c, k, c->timeout_ticks), "fused iterate launch");
         break;
     case GROVER_FORM_RESIDENT: GROVER_HIP(c, launch_resident_iterate(c, k), "resident iterate launch"); break;
+    case GROVER_FORM_HELD:
+        if (c->generation + k + 2u >= (uint64_t(1) << 32))
+            GROVER_HIP(c, reset_barrier(c), "barrier reset");
+        GROVER_HIP(c, launch_held_iterate(c, k, c->timeout_ticks), "held iterate launch");
+        break;
     case GROVER_FORM_TWO_PASS: GROVER_HIP(c, launch_twopass_iterate(c, k), "two-pass iterate launch"); break;
     default: return fail(c, GROVER_E_INVAL, "context has no iteration form");
     }
@@ -189,7 +214,7 @@ int grover_init(grover_ctx **out, const grover_config *cfg, void *hip_stream, vo
     if (!cfg)
         return GROVER_E_INVAL;
     if (cfg->n < 1 || cfg->n > kMaxQubits || cfg->dtype > GROVER_CBF16 || cfg->oracle_kind > GROVER_ORACLE_HASH ||
-        cfg->form > GROVER_FORM_TWO_PASS || cfg->flags != 0 || cfg->hash_bits > 64 ||
+        cfg->form > GROVER_FORM_HELD || cfg->flags != 0 || cfg->hash_bits > 64 ||
         cfg->accum > GROVER_ACC_F32_KAHAN || cfg->reserved != 0)
         return GROVER_E_INVAL;
     const uint64_t N = uint64_t(1) << cfg->n;
@@ -198,9 +223,15 @@ int grover_init(grover_ctx **out, const grover_config *cfg, void *hip_stream, vo
     // bfloat16 storage and binary32 sums exist in the fused form only
     const bool fused_only = cfg->dtype == GROVER_CBF16 || cfg->accum != GROVER_ACC_F64;
     uint32_t form = cfg->form;
-    if (form == GROVER_FORM_AUTO)
+    const bool auto_form = form == GROVER_FORM_AUTO;
+    // the held form exists for complex64 storage with binary64 sums; AUTO picks it (after the device
+    // query, which says whether the state fits on chip) for the sizes above the one-workgroup form
+    const bool held_ok = cfg->dtype == GROVER_C64 && cfg->accum == GROVER_ACC_F64;
+    if (auto_form)
         form = cfg->n <= kResidentMaxQubits && !fused_only ? GROVER_FORM_RESIDENT : GROVER_FORM_FUSED;
     if (form == GROVER_FORM_RESIDENT && cfg->n > kResidentMaxQubits)
+        return GROVER_E_UNSUPPORTED;
+    if (form == GROVER_FORM_HELD && !held_ok)
         return GROVER_E_UNSUPPORTED;
     if (fused_only && form != GROVER_FORM_FUSED)
         return GROVER_E_UNSUPPORTED;
@@ -255,6 +286,22 @@ int grover_init(grover_ctx **out, const grover_config *cfg, void *hip_stream, vo
             status = hip_fail(c, e, "device query");
             throw status;
         }
+        {
+            uint32_t max_team = 1;
+            while (int64_t(max_team) * 2 <= int64_t(c->cu_count))
+                max_team <<= 1;
+            const uint32_t team = held_team_size(N / 2, max_team);
+            if (auto_form && form == GROVER_FORM_FUSED && held_ok && team > 0)
+                form = GROVER_FORM_HELD;
+            if (form == GROVER_FORM_HELD) {
+                if (team == 0) {
+                    status = fail(c, GROVER_E_UNSUPPORTED, "the state is too large for the held form on this device");
+                    throw status;
+                }
+                c->held_team = team;
+            }
+            c->form = form;
+        }
         uint64_t timeout_ms = kDefaultTimeoutMs;
         if (const char *env = getenv("GROVER_BARRIER_TIMEOUT_MS"))
             timeout_ms = strtoull(env, nullptr, 10);
@@ -291,6 +338,9 @@ int grover_init(grover_ctx **out, const grover_config *cfg, void *hip_stream, vo
         if (form == GROVER_FORM_RESIDENT) {
             c->grid = 1;
             c->block = kResidentBlock;
+        } else if (form == GROVER_FORM_HELD) {
+            c->grid = int(c->held_team);
+            c->block = 1024;
         } else {
             c->grid = twopass_blocks(c);
             c->block = 256;
@@ -358,6 +408,10 @@ int grover_init(grover_ctx **out, const grover_config *cfg, void *hip_stream, vo
         if (form == GROVER_FORM_FUSED) {
             // needs the marked list on the device and a written state: it runs the fused kernel
             status = select_persistent_grid(c, clock_khz);
+            if (status != GROVER_OK)
+                throw status;
+        } else if (form == GROVER_FORM_HELD) {
+            status = check_held_team(c, clock_khz);
             if (status != GROVER_OK)
                 throw status;
         }

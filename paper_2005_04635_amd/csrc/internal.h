@@ -374,6 +374,7 @@ struct grover_ctx {
     const void *fused_kernel = nullptr;        // the fused kernel variant chosen at creation
     const void *fused_check_kernel = nullptr;  // its code-identical twin for the residency check
     uint64_t fused_tile = 0;             // 16-byte vectors per tile of that variant
+    uint32_t held_team = 0;              // held form: workgroups holding the state (one launch of that many)
     uint64_t generation = 0;
     uint64_t timeout_ticks = 0;
     // two-pass form and reductions
@@ -410,6 +411,11 @@ uint64_t fused_tiles(const grover_ctx *c);
 hipError_t launch_fused_iterate(grover_ctx *c, uint64_t k, uint64_t timeout_ticks, bool check = false);
 
 hipError_t launch_resident_iterate(grover_ctx *c, uint64_t k);
+
+// Held form (complex64, binary64 sums): workgroups that hold a state of nvec vectors, 0 when it does not fit
+// a team of at most max_team (a power of two); and the launch (`probe`: one team barrier only).
+uint32_t held_team_size(uint64_t nvec, uint32_t max_team);
+hipError_t launch_held_iterate(grover_ctx *c, uint64_t k, uint64_t timeout_ticks, bool probe = false);
 
 hipError_t launch_twopass_iterate(grover_ctx *c, uint64_t k);
 int twopass_blocks(const grover_ctx *c);

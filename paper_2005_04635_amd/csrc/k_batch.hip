@@ -14,14 +14,16 @@
 // barrier is needed between phases.  Which phases exist and their parameters is the tiling the host
 // chooses; each instance starts from the uniform superposition.
 #include "batch.h"
+#include "held.h"
 #include "stream.h"
 
 namespace grover {
 namespace {
 
-constexpr int kRegE = kBatchRegE;
-constexpr int kLdsE = kBatchLdsE;
-constexpr int kHoldE = kBatchHoldE;
+constexpr int kRegE = kHeldRegE;
+constexpr int kLdsE = kHeldLdsE;
+constexpr int kHoldE = kHeldHoldE;
+static_assert(kHeldRegE == kBatchRegE && kHeldLdsE == kBatchLdsE, "the batch tiling assumes the held layout");
 
 struct BatchArgs {
     float4 *state;
@@ -93,101 +95,6 @@ __device__ bool run_team_streamed(const BatchArgs &a, const BatchInstance &I, co
             return false;
     }
     return true;
-}
-
-// Update of one held vector as if it held no marked amplitude (c' = 2S/N - c per amplitude, the stored
-// values accumulated).  Marked amplitudes are handled around the sweep: their stored values are negated
-// before it (exactly), which makes this update produce 2S/N + c, their correct new value bit for bit, and
-// the sum is corrected after it by -2c' per marked amplitude (so it holds s c' for them, as the inversion
-// about the mean needs).  Every thread thus runs the same short update, and the few threads with marks
-// only add a few operations; the slowest wave sets the pace of every iteration.
-__device__ inline void unmarked_update(float4 &v, double mr, double mi, AccF64 &acc)
-{
-    v.x = float(mr - double(v.x));
-    v.y = float(mi - double(v.y));
-    v.z = float(mr - double(v.z));
-    v.w = float(mi - double(v.w));
-    acc.add(double(v.x), double(v.y));
-    acc.add(double(v.z), double(v.w));
-}
-
-// Negates the stored values of the marked amplitudes among a thread's held vectors (bits 2e, 2e + 1 of
-// `mask` for vector e).
-__device__ inline void negate_marked(float4 (&x)[kRegE], float4 *held, uint32_t mask)
-{
-#pragma unroll
-    for (int e = 0; e < kHoldE; ++e) {
-        const unsigned b = (mask >> (2 * e)) & 3u;
-        if (b != 0u) {
-            float4 v = e < kRegE ? x[e] : held[(e - kRegE) * kStreamBlock + threadIdx.x];
-            if (b & 1u) {
-                v.x = -v.x;
-                v.y = -v.y;
-            }
-            if (b & 2u) {
-                v.z = -v.z;
-                v.w = -v.w;
-            }
-            if (e < kRegE)
-                x[e] = v;
-            else
-                held[(e - kRegE) * kStreamBlock + threadIdx.x] = v;
-        }
-    }
-}
-
-// After the sweep: the sum holds +c' for the marked amplitudes; subtracting 2c' makes it s c'.
-__device__ inline void correct_marked(const float4 (&x)[kRegE], const float4 *held, uint32_t mask, AccF64 &acc)
-{
-#pragma unroll
-    for (int e = 0; e < kHoldE; ++e) {
-        const unsigned b = (mask >> (2 * e)) & 3u;
-        if (b != 0u) {
-            const float4 v = e < kRegE ? x[e] : held[(e - kRegE) * kStreamBlock + threadIdx.x];
-            if (b & 1u)
-                acc.add(-2.0 * double(v.x), -2.0 * double(v.y));
-            if (b & 2u)
-                acc.add(-2.0 * double(v.z), -2.0 * double(v.w));
-        }
-    }
-}
-
-// One iteration over a thread's held vectors (e < ne in order: x[e] in registers for e < kRegE, then the
-// LDS slots), each updated as unmarked.  When all 16 are held, the LDS vectors are loaded four at a time,
-// each group while the previous one (or the register half) is being updated, so that their latency hides
-// behind arithmetic.
-__device__ inline void held_sweep(float4 (&x)[kRegE], float4 *held, unsigned ne, double mr, double mi, AccF64 &acc)
-{
-    const unsigned tid = threadIdx.x;
-    if (ne == unsigned(kHoldE)) {
-        constexpr int kG = 4;
-        static_assert(2 * kG == kLdsE, "two groups cover the LDS half");
-        float4 y[kG], z[kG];
-#pragma unroll
-        for (int g = 0; g < kG; ++g)
-            y[g] = held[g * kStreamBlock + tid];
-#pragma unroll
-        for (int e = 0; e < kRegE; ++e)
-            unmarked_update(x[e], mr, mi, acc);
-#pragma unroll
-        for (int g = 0; g < kG; ++g)
-            z[g] = held[(kG + g) * kStreamBlock + tid];
-#pragma unroll
-        for (int g = 0; g < kG; ++g) {
-            unmarked_update(y[g], mr, mi, acc);
-            held[g * kStreamBlock + tid] = y[g];
-        }
-#pragma unroll
-        for (int g = 0; g < kG; ++g) {
-            unmarked_update(z[g], mr, mi, acc);
-            held[(kG + g) * kStreamBlock + tid] = z[g];
-        }
-    } else {
-#pragma unroll
-        for (int e = 0; e < kRegE; ++e)
-            if (unsigned(e) < ne)
-                unmarked_update(x[e], mr, mi, acc);
-    }
 }
 
 // One instance held on chip by a team for all its iterations: member `rank` owns the contiguous vectors

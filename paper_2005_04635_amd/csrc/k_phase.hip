@@ -113,10 +113,11 @@ __device__ inline bool wait_slot_n(const uint64_t *slot, uint32_t tag, const Pha
 // parity (a slot is rewritten two generations later, after every member has read it).  Every thread gets
 // the sums; false when the wait gave up.  Each value costs two more words to publish and to poll, so
 // callers pass only the values the next step needs.  A member's partial: wave totals, then lane q of wave 0
-// adds value q's 16 wave values by a tree and publishes it (the values in parallel).  For T <= 64 the
-// gather is done by wave 0 alone and the sums are added by wave totals (the same bits in every lane and
-// member), so the barrier costs two workgroup barriers; LDS words are written again only after the first
-// barrier of the next call, which every thread reaches after reading them.
+// adds value q's 16 wave values by a tree and publishes it (the values in parallel).  For T <= 256 the
+// gather is done by wave 0 alone (lane l adds members l, l + 64, ... in order) and the lanes' sums are added
+// by wave totals (the same bits in every lane and member), so the barrier costs two workgroup barriers;
+// LDS words are written again only after the first barrier of the next call, which every thread reaches
+// after reading them.
 template <int NV = kPV>
 __device__ bool team_sum_n(double (&v)[kPV], const PhaseTeam &tm, uint64_t gen, PhaseShared &sh)
 {
@@ -146,10 +147,12 @@ __device__ bool team_sum_n(double (&v)[kPV], const PhaseTeam &tm, uint64_t gen, 
                 r[w] += r[w + h];
         put_tagged(slots + uint64_t(tm.rank) * 16u + 2 * lane, r[0], tag);
     }
-    if (tm.size <= kWave) {
+    if (tm.size <= 4u * kWave) {
         if (wave == 0) {
             double w[kPV] = {};
-            const bool ok = lane < tm.size ? wait_slot_n<NV>(slots + uint64_t(lane) * 16u, tag, tm, w) : true;
+            bool ok = true;
+            for (unsigned r = lane; r < tm.size && ok; r += kWave)  // members lane, lane + 64, ... in order
+                ok = wait_slot_n<NV>(slots + uint64_t(r) * 16u, tag, tm, w);
 #pragma unroll
             for (int q = 0; q < NV; ++q)
                 w[q] = wave_total(w[q]);

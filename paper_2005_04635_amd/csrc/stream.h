@@ -121,9 +121,9 @@ __device__ inline bool wait_pair(const uint64_t *w, uint32_t tag, const Team &tm
 // thread of the workgroup gets the same answer and the sum in (xr, xi).
 //
 // An all-gather: every member publishes its partial in its own slot of the generation's parity as tagged
-// words; then, in every member, thread w waits for member w's words of this generation (all members
-// awaited in parallel) and the partials are added by a fixed tree, so every member computes the same sum
-// bit for bit after one memory round trip.  A member rewrites a slot of parity p only at generation g + 2:
+// words; then, in every member, wave 0 waits for the members' words of this generation (lane l for members
+// l, l + 64, ...; in teams of more than 256 one thread per member) and the partials are added in a fixed
+// order, so every member computes the same sum bit for bit after one memory round trip.  A member rewrites a slot of parity p only at generation g + 2:
 // its partial for g + 1 depends on the sum of g, so its reads of generation g have returned before it
 // publishes g + 1, and g + 2 follows only after every member's g + 1 has been seen.  (Arrivals counted
 // with one atomic per member serialise at the counter's address, and a gather to one member followed by a
@@ -152,15 +152,21 @@ __device__ bool team_sum(V &xr, V &xi, const Team &tm, uint64_t gen, TeamShared<
         put_tagged(slot, double(sr), tag);
         put_tagged(slot + 2, double(si), tag);
     }
-    if (tm.size <= kWave) {
-        // every member's partial fits one wave: wave 0 gathers them (lane w waits for member w) and adds them
-        // with wave_total, which leaves the same bits in every lane and in every member; one workgroup
-        // barrier hands the sum on.  sh.sum and sh.failed are written again only after the first barrier of the next
-        // call, which every thread reaches after reading them here.
+    if (tm.size <= 4u * kWave) {
+        // wave 0 gathers the members' partials (lane l waits for members l, l + 64, ... and adds them in that
+        // order) and adds the lanes' values with wave_total, which leaves the same bits in every lane and in
+        // every member; one workgroup barrier hands the sum on.  sh.sum and sh.failed are written again only
+        // after the first barrier of the next call, which every thread reaches after reading them here.
         if (wave == 0) {
-            double a = 0.0, b = 0.0;
-            const bool ok = lane < tm.size ? wait_pair(slots + uint64_t(lane) * 4u, tag, tm, a, b) : true;
-            const V pr = wave_total(V(a)), pi = wave_total(V(b));
+            V ar = V(0), ai = V(0);
+            bool ok = true;
+            for (unsigned w = lane; w < tm.size && ok; w += kWave) {
+                double a = 0.0, b = 0.0;
+                ok = wait_pair(slots + uint64_t(w) * 4u, tag, tm, a, b);
+                ar += V(a);
+                ai += V(b);
+            }
+            const V pr = wave_total(ar), pi = wave_total(ai);
             const bool failed = __any(!ok);
             if (lane == 0) {
                 sh.sum[0] = pr;

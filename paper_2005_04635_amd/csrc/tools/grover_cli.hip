@@ -39,7 +39,7 @@ int usage()
 {
     fprintf(stderr,
             "usage: grover_cli run --n N [--dtype f64|c64|c128|cbf16] [--accum f64|f32|f32_kahan]\n"
-            "                      [--form auto|fused|resident|two_pass]\n"
+            "                      [--form auto|fused|resident|two_pass|held]\n"
             "                      [--mark I ... | --hash-seed S --hash-bits B --m M] [--iters K]\n"
             "                      [--shots S] [--shot-seed U] [--steps T] [--calibrate-copy BYTES]\n"
             "       grover_cli copy --bytes B [--reps R]\n"
@@ -134,6 +134,7 @@ int run_search(int argc, char **argv)
             cfg.form = !strcmp(v, "fused")      ? GROVER_FORM_FUSED
                        : !strcmp(v, "resident") ? GROVER_FORM_RESIDENT
                        : !strcmp(v, "two_pass") ? GROVER_FORM_TWO_PASS
+                       : !strcmp(v, "held")     ? GROVER_FORM_HELD
                                                 : GROVER_FORM_AUTO;
         else if (k == "--mark")
             marks.push_back(strtoull(v, nullptr, 0));

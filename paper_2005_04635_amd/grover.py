@@ -31,12 +31,12 @@ GROVER_E_TIMEOUT = -7
 GROVER_F64_REAL, GROVER_C64, GROVER_C128, GROVER_CBF16 = 0, 1, 2, 3
 GROVER_ACC_F64, GROVER_ACC_F32, GROVER_ACC_F32_KAHAN = 0, 1, 2
 GROVER_ORACLE_LIST, GROVER_ORACLE_HASH = 0, 1
-GROVER_FORM_AUTO, GROVER_FORM_FUSED, GROVER_FORM_RESIDENT, GROVER_FORM_TWO_PASS = 0, 1, 2, 3
+GROVER_FORM_AUTO, GROVER_FORM_FUSED, GROVER_FORM_RESIDENT, GROVER_FORM_TWO_PASS, GROVER_FORM_HELD = 0, 1, 2, 3, 4
 
 DTYPES = {"f64": GROVER_F64_REAL, "c64": GROVER_C64, "c128": GROVER_C128, "cbf16": GROVER_CBF16}
 ACCUMS = {"f64": GROVER_ACC_F64, "f32": GROVER_ACC_F32, "f32_kahan": GROVER_ACC_F32_KAHAN}
 FORMS = {"auto": GROVER_FORM_AUTO, "fused": GROVER_FORM_FUSED, "resident": GROVER_FORM_RESIDENT,
-         "two_pass": GROVER_FORM_TWO_PASS}
+         "two_pass": GROVER_FORM_TWO_PASS, "held": GROVER_FORM_HELD}
 ELEM_BYTES = {GROVER_F64_REAL: 8, GROVER_C64: 8, GROVER_C128: 16, GROVER_CBF16: 4}
 NUMPY_DTYPES = {GROVER_F64_REAL: np.float64, GROVER_C64: np.complex64, GROVER_C128: np.complex128}
 
@@ -446,7 +446,7 @@ class Grover:
     n          qubits (N = 2^n amplitudes)
     dtype      "f64" (real), "c64", "c128" or "cbf16" (complex bfloat16)
     marks      explicit marked indices (oracle list), or None with hash_seed/hash_bits/m for the predicate
-    form       "auto", "fused", "resident" or "two_pass"
+    form       "auto", "fused", "resident", "two_pass" or "held"
     accum      precision of the sum the mean is taken from: "f64", "f32" or "f32_kahan"
     state      optional torch tensor (on the current device) to adopt as the state; otherwise one is made
     The state tensor is `self.state` (torch, 1-D, N elements of the dtype); kernels run on torch's

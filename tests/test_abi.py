@@ -77,7 +77,7 @@ def test_status_strings_and_null_handling(lib):
     lib.grover_destroy(None)
 
 
-@pytest.mark.parametrize("field,value", [("n", 0), ("n", 35), ("dtype", 4), ("oracle_kind", 2), ("form", 4),
+@pytest.mark.parametrize("field,value", [("n", 0), ("n", 35), ("dtype", 4), ("oracle_kind", 2), ("form", 5),
                                          ("flags", 1), ("hash_bits", 65), ("accum", 3), ("reserved", 1)])
 def test_init_rejects_invalid_config_before_touching_the_device(lib, field, value):
     from paper_2005_04635_amd.grover import grover_config
@@ -120,6 +120,17 @@ def test_resident_form_limit(lib):
     cfg = grover_config()
     cfg.n = 15
     cfg.form = 2  # resident holds at most 2^14 amplitudes
+    ctx = ctypes.c_void_p()
+    assert lib.grover_init(ctypes.byref(ctx), ctypes.byref(cfg), None, None, 0) == -5
+
+
+@pytest.mark.parametrize("dtype,accum", [(0, 0), (2, 0), (3, 0), (1, 1), (1, 2)])
+def test_held_form_is_complex64_with_binary64_sums(lib, dtype, accum):
+    """The held form exists for complex64 storage and binary64 sums only; rejected before device work."""
+    from paper_2005_04635_amd.grover import grover_config
+
+    cfg = grover_config()
+    cfg.n, cfg.dtype, cfg.accum, cfg.form = 16, dtype, accum, 4
     ctx = ctypes.c_void_p()
     assert lib.grover_init(ctypes.byref(ctx), ctypes.byref(cfg), None, None, 0) == -5
 

@@ -74,6 +74,10 @@ for form, ns in [("resident", [1, 2, 3, 5, 10, 12, 14]), ("fused", [1, 3, 9, 11,
     for n in ns:
         for dtype in ["f64", "c64", "c128"]:
             CASES.append((form, n, dtype))
+# the held form (complex64 only): one workgroup with fewer vectors than threads, registers only (teams of
+# 1 .. 64 workgroups, n <= 20), 8 more vectors per thread in LDS (n = 21 .. 23, teams of 64 .. 256)
+for n in [1, 3, 9, 14, 15, 17, 20, 21, 23]:
+    CASES.append(("held", n, "c64"))
 
 
 @pytest.mark.parametrize("form,n,dtype", CASES)
@@ -96,7 +100,8 @@ def test_iterate_matches_oracle(G, orc, form, n, dtype):
 
 
 @pytest.mark.parametrize("form,n,dtype", [("resident", 10, "c64"), ("fused", 16, "c64"), ("fused", 18, "c128"),
-                                          ("two_pass", 14, "f64"), ("fused", 12, "f64")])
+                                          ("two_pass", 14, "f64"), ("fused", 12, "f64"), ("held", 18, "c64"),
+                                          ("held", 22, "c64")])
 def test_search_to_optimum_matches_oracle_and_closed_form(G, orc, form, n, dtype):
     m = 3
     marks = workloads.distinct_marks(n, m, seed=n)
@@ -116,7 +121,8 @@ def test_search_to_optimum_matches_oracle_and_closed_form(G, orc, form, n, dtype
     g.close()
 
 
-@pytest.mark.parametrize("form,n", [("resident", 9), ("fused", 13), ("fused", 19), ("two_pass", 12)])
+@pytest.mark.parametrize("form,n", [("resident", 9), ("fused", 13), ("fused", 19), ("two_pass", 12), ("held", 16),
+                                    ("held", 21)])
 def test_iterate_composes_bitwise(G, form, n):
     """iterate(a); iterate(b) equals iterate(a + b) bit for bit, and reruns are bitwise identical."""
     marks = workloads.distinct_marks(n, 5, seed=3)
@@ -258,6 +264,42 @@ def test_barrier_timeout_is_reported_and_recovers(G, orc, monkeypatch):
     g = G.Grover(16, "c64", marks=[5], form="fused").iterate(3)
     g.sync()
     assert_close(g.read_state(), orc.search(16, [5], 3), "c64")
+    g.close()
+
+
+def test_held_form_selection(G):
+    """AUTO takes the held form for complex64 states with binary64 sums between the one-workgroup form
+    and the largest state that fits on chip; other storage types and larger states keep the fused form."""
+    g = G.Grover(18, "c64", marks=[5])
+    assert g.query(0) == G.grover.GROVER_FORM_HELD
+    assert g.query(1) == 16  # 2^17 vectors, 8 per thread: 16 workgroups
+    g.close()
+    g = G.Grover(22, "c64", marks=[5])
+    assert g.query(0) == G.grover.GROVER_FORM_HELD and g.query(1) == 128  # 16 vectors per thread
+    g.close()
+    assert G.Grover(18, "c128", marks=[5]).query(0) == G.grover.GROVER_FORM_FUSED
+    assert G.Grover(18, "c64", marks=[5], accum="f32").query(0) == G.grover.GROVER_FORM_FUSED
+    assert G.Grover(12, "c64", marks=[5]).query(0) == G.grover.GROVER_FORM_RESIDENT
+    with pytest.raises(G.GroverError) as e:
+        G.Grover(16, "c128", marks=[5], form="held")
+    assert e.value.status == G.grover.GROVER_E_UNSUPPORTED
+    cu = G.Grover(10, "c64", marks=[5], form="held")
+    assert cu.query(1) == 1
+    cu.close()
+
+
+def test_held_barrier_timeout_is_reported_and_recovers(G, orc, monkeypatch):
+    monkeypatch.setenv("GROVER_BARRIER_TIMEOUT_MS", "0")
+    g = G.Grover(18, "c64", marks=[5], form="held")
+    g.iterate(3)
+    with pytest.raises(G.GroverError) as e:
+        g.sync()
+    assert e.value.status == -7
+    g.close()
+    monkeypatch.delenv("GROVER_BARRIER_TIMEOUT_MS")
+    g = G.Grover(18, "c64", marks=[5], form="held").iterate(3)
+    g.sync()
+    assert_close(g.read_state(), orc.search(18, [5], 3), "c64")
     g.close()
 
 
