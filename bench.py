@@ -205,6 +205,21 @@ def sweep_table1(pkg, hip, stream) -> None:
             pkg.grover_sync(ctx)
             res[path + "_s"] = ms / 1e3
             res[path + "_amplitude_iterations_per_s"] = (1 << n) * k / (ms / 1e3)
+        if res["form"] == "held":
+            # the fused form of the same search, for comparison with the held form AUTO chose
+            fcfg, fkeep = make_config(pkg, n, "c64", marks=mark, form="fused")
+            fctx = pkg.grover_init(fcfg, stream.value, 0, 0)
+            pkg.grover_iterate(fctx, 1)
+            pkg.grover_reset(fctx)
+            pkg.grover_sync(fctx)
+            e0, e1 = hip.event(), hip.event()
+            hip.lib.hipEventRecord(e0, stream)
+            pkg.grover_iterate(fctx, k)
+            hip.lib.hipEventRecord(e1, stream)
+            ms = hip.elapsed_ms(e0, e1)
+            pkg.grover_sync(fctx)
+            pkg.grover_destroy(fctx)
+            res["proposed_fused_s"] = ms / 1e3
         res["speedup_proposed_over_gate"] = res["gate_level_s"] / res["proposed_s"]
         res["speedup_proposed_over_blocked_gate"] = res["gate_level_blocked_s"] / res["proposed_s"]
         if n in PAPER_TABLE1_S:
