@@ -156,7 +156,8 @@ def test_fused_grid_shapes(G, orc, monkeypatch):
 
 
 # ----------------------------------------------------------------------------------- hash oracle
-def test_hash_predicate_marks_match_oracle(G, orc):
+@pytest.mark.parametrize("form", ["held", "fused"])
+def test_hash_predicate_marks_match_oracle(G, orc, form):
     n, bits = 20, 17
     seed = None
     for s in range(5000, 5200):
@@ -166,7 +167,7 @@ def test_hash_predicate_marks_match_oracle(G, orc):
             break
     assert seed is not None
     want, _ = orc.hash_marks(n, seed, bits, cap=64)
-    g = G.Grover(n, "c64", hash_seed=seed, hash_bits=bits, m=8)
+    g = G.Grover(n, "c64", hash_seed=seed, hash_bits=bits, m=8, form=form)
     assert np.array_equal(g.marked(), want)
     k = orc.optimal_iterations(n, 8)
     g.iterate(k)
