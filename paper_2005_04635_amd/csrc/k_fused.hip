@@ -194,20 +194,21 @@ constexpr int kMarkWords = 1024;  // LDS bitmap of this workgroup's tiles that h
 // identical in both modes.  `slow_tiles` (when `table`) flags the workgroup's tiles holding marked
 // amplitudes; without a table every tile is checked against the marked list.  Loads and stores carry the
 // nontemporal hint (+6 % measured on MI355X).
-// A workgroup keeps the last kHeldTiles tiles of its share in LDS for the whole launch (each thread its own
-// slots, held[(h * kUnroll + u) * kBlock + tid], so no barrier guards them): the launch's first pass loads
-// them while it sums them, every iteration then updates them there, and the end of the launch writes them
+// A workgroup keeps the last kHeldTiles tiles of its share on chip for the whole launch: the very last in
+// registers (rt[u], kUnroll vectors per thread), the ones before it in LDS (each thread its own slots,
+// held[(h * kUnroll + u) * kBlock + tid], so no barrier guards them).  The launch's first pass loads them
+// while it sums them, every iteration then updates them in place, and the end of the launch writes them
 // back.  They are the last tiles each pass visits, so the additions happen in the same order as when they
 // stream and the results are identical; an iteration's memory traffic drops by kHeldTiles of the
-// workgroup's tiles (1/64 of it at n = 28 on 256 workgroups).
-constexpr int kHeldTiles = 2;
+// workgroup's tiles (3/128 of it at n = 28 on 256 workgroups).
+constexpr int kHeldTiles = 3;
 
 // First held tile (local index) of this workgroup's share of cnt tiles.
 __device__ inline uint64_t held_start(uint64_t cnt) { return cnt > uint64_t(kHeldTiles) ? cnt - kHeldTiles : 0; }
 
 template <class T, class A, bool UPDATE>
 __device__ inline void chunk_pass(const FusedArgs &a, const uint32_t *slow_tiles, bool table, double mr, double mi,
-                                  A &acc, typename T::vec *held)
+                                  A &acc, typename T::vec *held, typename T::vec (&rt)[kUnroll])
 {
     using V = typename T::vec;
     V *st = static_cast<V *>(a.state);
@@ -269,8 +270,10 @@ __device__ inline void chunk_pass(const FusedArgs &a, const uint32_t *slow_tiles
             mp = mq;
         }
     }
-    // the held tiles: the same arithmetic on the thread's LDS slots (loaded from memory by the first pass)
-    for (uint64_t j = hstart; j < cnt; ++j) {
+    // the held tiles: the same arithmetic on the thread's LDS slots (loaded from memory by the first pass),
+    // then on the last tile, kept in registers
+    const uint64_t rlast = cnt > 0 ? cnt - 1 : 0;  // the register tile (when cnt > 0)
+    for (uint64_t j = hstart; j < rlast; ++j) {
         V *hv = held + (j - hstart) * kTile;
         const uint64_t t = blockIdx.x + j * gridDim.x;
         const uint64_t v0 = t * kTile;
@@ -319,6 +322,48 @@ __device__ inline void chunk_pass(const FusedArgs &a, const uint32_t *slow_tiles
         if (!full || marked)
             mp = mq;
     }
+    if (cnt > 0) {
+        const uint64_t j = rlast;
+        const uint64_t t = blockIdx.x + j * gridDim.x;
+        const uint64_t v0 = t * kTile;
+        const bool full = v0 + kTile <= a.nvec;
+        const bool marked = table ? ((slow_tiles[j >> 5] >> (j & 31)) & 1u) != 0u : a.m > 0;
+        uint64_t mq = mp;
+        bool in_regs = true;
+        uint64_t mk[kTileMarks];
+        if (!full || marked) {
+            mp = gallop_lower_bound(a.marks, mp, a.m, v0 * T::EPV);
+            mq = gallop_lower_bound(a.marks, mp, a.m, (v0 + kTile) * T::EPV);
+            in_regs = mq - mp <= uint64_t(kTileMarks);
+#pragma unroll
+            for (int q = 0; q < kTileMarks; ++q)
+                mk[q] = in_regs && mp + q < mq ? a.marks[mp + q] : ~uint64_t(0);
+        }
+        if (!UPDATE) {
+#pragma unroll
+            for (int u = 0; u < kUnroll; ++u) {
+                const uint64_t v = v0 + u * kBlock + tid;
+                if (v < a.nvec)
+                    rt[u] = load16<true>(st + v);
+            }
+        }
+#pragma unroll
+        for (int u = 0; u < kUnroll; ++u) {
+            const uint64_t v = v0 + u * kBlock + tid;
+            if (v < a.nvec) {
+                unsigned bits = 0u;
+                if (!full || marked)
+                    bits = in_regs ? bits_from_regs<T::EPV>(mk, v * T::EPV)
+                                   : marked_bits<T::EPV>(a.marks, mp, mq, v * T::EPV);
+                if (UPDATE)
+                    update_vec<T>(rt[u], mr, mi, bits, acc);
+                else
+                    accum_vec<T>(rt[u], bits, acc);
+            }
+        }
+        if (!full || marked)
+            mp = mq;
+    }
 }
 
 // CHECK only names a second, code-identical instantiation used for the residency check at context
@@ -329,7 +374,8 @@ __global__ __launch_bounds__(kBlock) void fused_iterate_kernel(FusedArgs a)
     using Val = typename A::value;
     __shared__ Shared<Val> sh;
     __shared__ uint32_t slow_tiles[kMarkWords];
-    __shared__ typename T::vec held[kHeldTiles * kTile];  // the last tiles of this workgroup's share
+    __shared__ typename T::vec held[(kHeldTiles - 1) * kTile];  // held tiles but the last, in LDS
+    typename T::vec rt[kUnroll];                                 // the last held tile, in registers
     // Table of this workgroup's tiles that hold marked amplitudes, built once per launch.
     const uint64_t ntiles = (a.nvec + kTile - 1) / kTile;
     const uint64_t cnt = blockIdx.x < ntiles ? (ntiles - blockIdx.x + gridDim.x - 1) / gridDim.x : 0;
@@ -348,14 +394,14 @@ __global__ __launch_bounds__(kBlock) void fused_iterate_kernel(FusedArgs a)
         __syncthreads();
     }
     A acc0;
-    chunk_pass<T, A, false>(a, slow_tiles, table, 0.0, 0.0, acc0, held);
+    chunk_pass<T, A, false>(a, slow_tiles, table, 0.0, 0.0, acc0, held, rt);
     Val sr = acc0.res_r(), si = acc0.res_i();
     if (!grid_sum<Val>(sr, si, a, a.gen0 + 1u, sh))
         return;
     for (uint64_t it = 0; it < a.iters; ++it) {
         const double mr = (double(sr) * 2.0) / a.N, mi = (double(si) * 2.0) / a.N;
         A acc;
-        chunk_pass<T, A, true>(a, slow_tiles, table, mr, mi, acc, held);
+        chunk_pass<T, A, true>(a, slow_tiles, table, mr, mi, acc, held, rt);
         sr = acc.res_r();
         si = acc.res_i();
         if (!grid_sum<Val>(sr, si, a, a.gen0 + 2u + it, sh))
@@ -364,7 +410,7 @@ __global__ __launch_bounds__(kBlock) void fused_iterate_kernel(FusedArgs a)
     if (a.iters > 0) {  // the held tiles go back to memory
         using V = typename T::vec;
         V *st = static_cast<V *>(a.state);
-        for (uint64_t j = held_start(cnt); j < cnt; ++j) {
+        for (uint64_t j = held_start(cnt); j + 1 < cnt; ++j) {
             const V *hv = held + (j - held_start(cnt)) * kTile;
             const uint64_t v0 = (blockIdx.x + j * gridDim.x) * kTile;
 #pragma unroll
@@ -372,6 +418,15 @@ __global__ __launch_bounds__(kBlock) void fused_iterate_kernel(FusedArgs a)
                 const uint64_t v = v0 + u * kBlock + threadIdx.x;
                 if (v < a.nvec)
                     store16<true>(hv[u * kBlock + threadIdx.x], st + v);
+            }
+        }
+        if (cnt > 0) {
+            const uint64_t v0 = (blockIdx.x + (cnt - 1) * gridDim.x) * kTile;
+#pragma unroll
+            for (int u = 0; u < kUnroll; ++u) {
+                const uint64_t v = v0 + u * kBlock + threadIdx.x;
+                if (v < a.nvec)
+                    store16<true>(rt[u], st + v);
             }
         }
     }
