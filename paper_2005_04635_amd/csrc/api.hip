@@ -647,6 +647,7 @@ int grover_query(grover_ctx *ctx, int key, int64_t *value)
     case 5: *value = int64_t(ctx->marks.size()); break;
     case 6: *value = int64_t(ctx->timeout_ticks); break;
     case 7: *value = ctx->per_cu_reported; break;
+    case 8: *value = ctx->fused_temporal ? 1 : 0; break;
     default: return fail(ctx, GROVER_E_INVAL, "unknown query key");
     }
     return GROVER_OK;

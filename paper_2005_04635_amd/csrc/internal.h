@@ -374,6 +374,7 @@ struct grover_ctx {
     const void *fused_kernel = nullptr;        // the fused kernel variant chosen at creation
     const void *fused_check_kernel = nullptr;  // its code-identical twin for the residency check
     uint64_t fused_tile = 0;             // 16-byte vectors per tile of that variant
+    bool fused_temporal = false;         // that variant streams with ordinary (not nontemporal) accesses
     uint32_t held_team = 0;              // held form: workgroups holding the state (one launch of that many)
     uint64_t generation = 0;
     uint64_t timeout_ticks = 0;

@@ -192,8 +192,9 @@ constexpr int kMarkWords = 1024;  // LDS bitmap of this workgroup's tiles that h
 // to start on lines the memory-side cache might still hold, measured no faster on MI355X.)  UPDATE:
 // c' = 2S/N - s c written back and s c' summed; otherwise s c summed.  The per-thread order of the sum is
 // identical in both modes.  `slow_tiles` (when `table`) flags the workgroup's tiles holding marked
-// amplitudes; without a table every tile is checked against the marked list.  Loads and stores carry the
-// nontemporal hint (+6 % measured on MI355X).
+// amplitudes; without a table every tile is checked against the marked list.  NT: loads and stores carry the
+// nontemporal hint (+6 % measured on MI355X at n = 28); a state that fits the memory-side cache streams
+// with ordinary accesses instead (kTemporalMaxBytes).
 // A workgroup keeps the last kHeldTiles tiles of its share on chip for the whole launch: the very last in
 // registers (rt[u], kUnroll vectors per thread), the ones before it in LDS (each thread its own slots,
 // held[(h * kUnroll + u) * kBlock + tid], so no barrier guards them).  The launch's first pass loads them
@@ -206,7 +207,7 @@ constexpr int kHeldTiles = 3;
 // First held tile (local index) of this workgroup's share of cnt tiles.
 __device__ inline uint64_t held_start(uint64_t cnt) { return cnt > uint64_t(kHeldTiles) ? cnt - kHeldTiles : 0; }
 
-template <class T, class A, bool UPDATE>
+template <class T, class A, bool UPDATE, bool NT>
 __device__ inline void chunk_pass(const FusedArgs &a, const uint32_t *slow_tiles, bool table, double mr, double mi,
                                   A &acc, typename T::vec *held, typename T::vec (&rt)[kUnroll])
 {
@@ -226,12 +227,12 @@ __device__ inline void chunk_pass(const FusedArgs &a, const uint32_t *slow_tiles
             V x[kUnroll];
 #pragma unroll
             for (int u = 0; u < kUnroll; ++u)
-                x[u] = load16<true>(st + v0 + u * kBlock + tid);
+                x[u] = load16<NT>(st + v0 + u * kBlock + tid);
 #pragma unroll
             for (int u = 0; u < kUnroll; ++u) {
                 if (UPDATE) {
                     update_vec<T>(x[u], mr, mi, 0u, acc);
-                    store16<true>(x[u], st + v0 + u * kBlock + tid);
+                    store16<NT>(x[u], st + v0 + u * kBlock + tid);
                 } else {
                     accum_vec<T>(x[u], 0u, acc);
                 }
@@ -251,7 +252,7 @@ __device__ inline void chunk_pass(const FusedArgs &a, const uint32_t *slow_tiles
             for (int u = 0; u < kUnroll; ++u) {
                 const uint64_t v = v0 + u * kBlock + tid;
                 if (v < a.nvec)
-                    x[u] = load16<true>(st + v);
+                    x[u] = load16<NT>(st + v);
             }
 #pragma unroll
             for (int u = 0; u < kUnroll; ++u) {
@@ -261,7 +262,7 @@ __device__ inline void chunk_pass(const FusedArgs &a, const uint32_t *slow_tiles
                                                   : marked_bits<T::EPV>(a.marks, mp, mq, v * T::EPV);
                     if (UPDATE) {
                         update_vec<T>(x[u], mr, mi, bits, acc);
-                        store16<true>(x[u], st + v);
+                        store16<NT>(x[u], st + v);
                     } else {
                         accum_vec<T>(x[u], bits, acc);
                     }
@@ -368,7 +369,7 @@ __device__ inline void chunk_pass(const FusedArgs &a, const uint32_t *slow_tiles
 
 // CHECK only names a second, code-identical instantiation used for the residency check at context
 // creation, so that profiles list it apart from the iteration launches.
-template <class T, class A, bool CHECK>
+template <class T, class A, bool CHECK, bool NT>
 __global__ __launch_bounds__(kBlock) void fused_iterate_kernel(FusedArgs a)
 {
     using Val = typename A::value;
@@ -394,14 +395,14 @@ __global__ __launch_bounds__(kBlock) void fused_iterate_kernel(FusedArgs a)
         __syncthreads();
     }
     A acc0;
-    chunk_pass<T, A, false>(a, slow_tiles, table, 0.0, 0.0, acc0, held, rt);
+    chunk_pass<T, A, false, NT>(a, slow_tiles, table, 0.0, 0.0, acc0, held, rt);
     Val sr = acc0.res_r(), si = acc0.res_i();
     if (!grid_sum<Val>(sr, si, a, a.gen0 + 1u, sh))
         return;
     for (uint64_t it = 0; it < a.iters; ++it) {
         const double mr = (double(sr) * 2.0) / a.N, mi = (double(si) * 2.0) / a.N;
         A acc;
-        chunk_pass<T, A, true>(a, slow_tiles, table, mr, mi, acc, held, rt);
+        chunk_pass<T, A, true, NT>(a, slow_tiles, table, mr, mi, acc, held, rt);
         sr = acc.res_r();
         si = acc.res_i();
         if (!grid_sum<Val>(sr, si, a, a.gen0 + 2u + it, sh))
@@ -432,38 +433,57 @@ __global__ __launch_bounds__(kBlock) void fused_iterate_kernel(FusedArgs a)
     }
 }
 
-template <class A, bool CHECK>
+template <class A, bool CHECK, bool NT>
 const void *pick_storage(uint32_t dtype)
 {
     switch (dtype) {
-    case GROVER_F64_REAL: return reinterpret_cast<const void *>(&fused_iterate_kernel<F64Real, A, CHECK>);
-    case GROVER_C64: return reinterpret_cast<const void *>(&fused_iterate_kernel<C64, A, CHECK>);
-    case GROVER_C128: return reinterpret_cast<const void *>(&fused_iterate_kernel<C128, A, CHECK>);
-    case GROVER_CBF16: return reinterpret_cast<const void *>(&fused_iterate_kernel<CBF16, A, CHECK>);
+    case GROVER_F64_REAL: return reinterpret_cast<const void *>(&fused_iterate_kernel<F64Real, A, CHECK, NT>);
+    case GROVER_C64: return reinterpret_cast<const void *>(&fused_iterate_kernel<C64, A, CHECK, NT>);
+    case GROVER_C128: return reinterpret_cast<const void *>(&fused_iterate_kernel<C128, A, CHECK, NT>);
+    case GROVER_CBF16: return reinterpret_cast<const void *>(&fused_iterate_kernel<CBF16, A, CHECK, NT>);
+    default: return nullptr;
+    }
+}
+
+template <bool CHECK, bool NT>
+const void *kernel_for_access(uint32_t dtype, uint32_t accum)
+{
+    switch (accum) {
+    case GROVER_ACC_F64: return pick_storage<AccF64, CHECK, NT>(dtype);
+    case GROVER_ACC_F32: return pick_storage<AccF32, CHECK, NT>(dtype);
+    case GROVER_ACC_F32_KAHAN: return pick_storage<AccF32Kahan, CHECK, NT>(dtype);
     default: return nullptr;
     }
 }
 
 template <bool CHECK>
-const void *kernel_for(uint32_t dtype, uint32_t accum)
+const void *kernel_for(uint32_t dtype, uint32_t accum, bool temporal)
 {
-    switch (accum) {
-    case GROVER_ACC_F64: return pick_storage<AccF64, CHECK>(dtype);
-    case GROVER_ACC_F32: return pick_storage<AccF32, CHECK>(dtype);
-    case GROVER_ACC_F32_KAHAN: return pick_storage<AccF32Kahan, CHECK>(dtype);
-    default: return nullptr;
-    }
+    return temporal ? kernel_for_access<CHECK, false>(dtype, accum) : kernel_for_access<CHECK, true>(dtype, accum);
 }
+
+// States up to this size are streamed with ordinary (temporal) loads and stores, so that iterations find
+// the state in the 256 MB memory-side cache: one optimal search at n = 23, 24, 25 (complex64: 64, 128,
+// 256 MiB) took 10 %, 7 % and 16 % less time on MI355X than with nontemporal accesses.  Larger states
+// evict themselves from that cache every pass and stream nontemporally (n = 26, 512 MiB: temporal
+// accesses cost 9 % more; nontemporal is 6 % faster at n = 28).
+constexpr uint64_t kTemporalMaxBytes = uint64_t(256) << 20;
 
 }  // namespace
 
 hipError_t fused_configure(grover_ctx *c, int *per_cu, int *block, int64_t *forced_grid)
 {
-    const void *k = kernel_for<false>(c->dtype, c->accum);
+    bool temporal = c->N * elem_bytes(c->dtype) <= kTemporalMaxBytes;
+    if (const char *env = getenv("GROVER_FUSED_TEMPORAL")) {
+        if (env[0] == '0' || env[0] == '1')
+            temporal = env[0] == '1';
+    }
+    const void *k = kernel_for<false>(c->dtype, c->accum, temporal);
     if (!k)
         return hipErrorInvalidValue;
     c->fused_kernel = k;
-    c->fused_check_kernel = kernel_for<true>(c->dtype, c->accum);
+    c->fused_check_kernel = kernel_for<true>(c->dtype, c->accum, temporal);
+    c->fused_temporal = temporal;
     c->fused_tile = kTile;
     int coop = 0;
     hipError_t e = hipDeviceGetAttribute(&coop, hipDeviceAttributeCooperativeLaunch, c->device);

@@ -63,7 +63,7 @@ def complex_to_bf16_pairs(psi: np.ndarray) -> np.ndarray:
     return (u >> np.uint32(16)).astype(np.uint16)
 
 # grover_query keys
-Q_FORM, Q_GRID, Q_BLOCK, Q_ELEM_BYTES, Q_N, Q_M = 0, 1, 2, 3, 4, 5
+Q_FORM, Q_GRID, Q_BLOCK, Q_ELEM_BYTES, Q_N, Q_M, Q_TIMEOUT, Q_PER_CU, Q_FUSED_TEMPORAL = range(9)
 
 
 # grover_batch_query keys

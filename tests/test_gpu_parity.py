@@ -121,8 +121,8 @@ def test_search_to_optimum_matches_oracle_and_closed_form(G, orc, form, n, dtype
     g.close()
 
 
-@pytest.mark.parametrize("form,n", [("resident", 9), ("fused", 13), ("fused", 19), ("two_pass", 12), ("held", 16),
-                                    ("held", 21)])
+@pytest.mark.parametrize("form,n", [("resident", 9), ("fused", 13), ("fused", 19), ("fused", 24), ("two_pass", 12),
+                                    ("held", 16), ("held", 21)])
 def test_iterate_composes_bitwise(G, form, n):
     """iterate(a); iterate(b) equals iterate(a + b) bit for bit, and reruns are bitwise identical."""
     marks = workloads.distinct_marks(n, 5, seed=3)
@@ -140,19 +140,45 @@ def test_iterate_composes_bitwise(G, form, n):
 
 
 def test_fused_grid_shapes(G, orc, monkeypatch):
-    """Forced persistent-grid sizes: more workgroups than tiles (empty chunks), a prime count (ragged
-    chunks) and a single workgroup."""
+    """Forced persistent-grid sizes over the 8 tiles of an n = 15 complex128 state: a single workgroup
+    (8 tiles: 5 streamed, 2 held in LDS, 1 in registers), 2 and 3 workgroups (4 tiles; 3, 3 and 2 tiles —
+    held tiles with none or one streamed before them), a prime count (ragged shares) and more workgroups
+    than tiles (empty shares); sparse marks and marks too many for a tile's registers."""
     n, dtype = 15, "c128"
-    marks = workloads.distinct_marks(n, 6, seed=8)
     psi0 = start_state(n, dtype, seed=8)
-    want = orc.iterate(as_c128(psi0), marks, 9)
-    for grid in ["1", "7", "97", "250"]:
-        monkeypatch.setenv("GROVER_FUSED_GRID", grid)
-        g = G.Grover(n, dtype, marks=marks, form="fused")
-        assert g.query(1) == int(grid)
-        g.write_state(psi0).iterate(9)
-        assert_close(g.read_state(), want, dtype, f"grid={grid}")
+    for m in [6, (1 << n) // 3]:
+        marks = workloads.distinct_marks(n, m, seed=8)
+        want = orc.iterate(as_c128(psi0), marks, 9)
+        for grid in ["1", "2", "3", "7", "97", "250"]:
+            monkeypatch.setenv("GROVER_FUSED_GRID", grid)
+            g = G.Grover(n, dtype, marks=marks, form="fused")
+            assert g.query(1) == int(grid)
+            g.write_state(psi0).iterate(9)
+            assert_close(g.read_state(), want, dtype, f"grid={grid} m={m}")
+            g.close()
+
+
+def test_fused_access_form(G, orc, monkeypatch):
+    """States up to 256 MiB stream with ordinary loads and stores (they stay in the memory-side cache
+    across iterations), larger ones with nontemporal ones; forcing either form leaves the results bit for bit
+    the same (n = 24 complex64: 8 tiles per workgroup, 5 of them streamed)."""
+    for n, dtype, want in [(16, "c64", 1), (24, "c128", 1), (25, "c64", 1), (25, "c128", 0), (26, "c64", 0)]:
+        g = G.Grover(n, dtype, marks=[3], form="fused")
+        assert g.query(G.grover.Q_FUSED_TEMPORAL) == want, (n, dtype)
         g.close()
+    n, dtype = 24, "c64"
+    psi0 = start_state(n, dtype, seed=24)
+    marks = workloads.distinct_marks(n, 7, seed=24)
+    states = []
+    for forced in ["0", "1"]:
+        monkeypatch.setenv("GROVER_FUSED_TEMPORAL", forced)
+        g = G.Grover(n, dtype, marks=marks, form="fused")
+        assert g.query(G.grover.Q_FUSED_TEMPORAL) == int(forced)
+        g.write_state(psi0).iterate(4).iterate(5)
+        states.append(g.read_state())
+        g.close()
+    assert np.array_equal(states[0].view(np.uint32), states[1].view(np.uint32))
+    assert_close(states[1], orc.iterate(as_c128(psi0), marks, 9), dtype, "n=24 fused")
 
 
 # ----------------------------------------------------------------------------------- hash oracle
