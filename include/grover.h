@@ -186,11 +186,12 @@ int grover_sync(grover_ctx *ctx);
 /* grover_query — launch facts for diagnostics.  key: 0 = resolved form, 1 = persistent grid size
  * (workgroups; the held form's team), 2 = workgroup size, 3 = element size in bytes, 4 = N, 5 = number of marked indices,
  * 6 = grid-barrier wait limit in device wall-clock ticks, 7 = workgroups per CU of the fused kernel as the
- * runtime's occupancy calculator reports them (the grid actually used is confirmed on the device), 8 = 1 when
- * the fused kernel streams the state with ordinary loads and stores (states up to 256 MiB, which the
- * memory-side cache can hold across iterations), 0 when with nontemporal ones (larger states); the
- * environment variable GROVER_FUSED_TEMPORAL=0 or 1, read at grover_init, overrides the choice.  Results
- * are identical either way. */
+ * runtime's occupancy calculator reports them (the grid actually used is confirmed on the device), 8 = bytes
+ * of the state per pass that the fused kernel streams with ordinary loads and stores, so that the next pass
+ * finds them in the memory-side cache (the whole state up to 288 MiB; above that, the leading tiles of each
+ * workgroup's share up to 288 MiB in all, the rest with nontemporal accesses; 0 for the other forms).  The
+ * environment variable GROVER_FUSED_TEMPORAL, read at grover_init, forces 0 (all nontemporal) or 1 (all
+ * ordinary).  Results are identical either way. */
 int grover_query(grover_ctx *ctx, int key, int64_t *value);
 
 /* grover_optimal_iterations — floor(pi/4 * sqrt(2^n / m)) (Algorithm 5's iteration count with m

@@ -647,7 +647,12 @@ int grover_query(grover_ctx *ctx, int key, int64_t *value)
     case 5: *value = int64_t(ctx->marks.size()); break;
     case 6: *value = int64_t(ctx->timeout_ticks); break;
     case 7: *value = ctx->per_cu_reported; break;
-    case 8: *value = ctx->fused_temporal ? 1 : 0; break;
+    case 8: {  // fused form: bytes per pass streamed with ordinary accesses
+        const uint64_t state = ctx->N * elem_bytes(ctx->dtype);
+        const uint64_t lead = fused_temporal_tiles(ctx) * uint64_t(ctx->grid) * ctx->fused_tile * 16u;
+        *value = int64_t(ctx->fused_temporal_bytes >= state ? state : std::min(state, lead));
+        break;
+    }
     default: return fail(ctx, GROVER_E_INVAL, "unknown query key");
     }
     return GROVER_OK;

@@ -374,7 +374,7 @@ struct grover_ctx {
     const void *fused_kernel = nullptr;        // the fused kernel variant chosen at creation
     const void *fused_check_kernel = nullptr;  // its code-identical twin for the residency check
     uint64_t fused_tile = 0;             // 16-byte vectors per tile of that variant
-    bool fused_temporal = false;         // that variant streams with ordinary (not nontemporal) accesses
+    uint64_t fused_temporal_bytes = 0;   // bytes per pass streamed with ordinary (not nontemporal) accesses
     uint32_t held_team = 0;              // held form: workgroups holding the state (one launch of that many)
     uint64_t generation = 0;
     uint64_t timeout_ticks = 0;
@@ -408,6 +408,8 @@ hipError_t launch_hash_marks(grover_ctx *c, uint64_t seed, uint32_t bits, uint64
 // GROVER_FUSED_GRID (0 when unset).
 hipError_t fused_configure(grover_ctx *c, int *per_cu, int *block, int64_t *forced_grid);
 uint64_t fused_tiles(const grover_ctx *c);
+// Leading unmarked tiles of each workgroup's share that the fused kernel streams with ordinary accesses.
+uint64_t fused_temporal_tiles(const grover_ctx *c);
 // `check`: launch the code-identical instantiation reserved for the residency check.
 hipError_t launch_fused_iterate(grover_ctx *c, uint64_t k, uint64_t timeout_ticks, bool check = false);
 

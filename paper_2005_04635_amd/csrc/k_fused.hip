@@ -38,6 +38,7 @@ struct FusedArgs {
     uint64_t iters;
     uint64_t gen0;
     uint64_t timeout_ticks;
+    uint64_t temporal_tiles;  // nontemporal kernels: leading tiles of each share streamed with ordinary accesses
 };
 
 template <class V>
@@ -193,8 +194,9 @@ constexpr int kMarkWords = 1024;  // LDS bitmap of this workgroup's tiles that h
 // c' = 2S/N - s c written back and s c' summed; otherwise s c summed.  The per-thread order of the sum is
 // identical in both modes.  `slow_tiles` (when `table`) flags the workgroup's tiles holding marked
 // amplitudes; without a table every tile is checked against the marked list.  NT: loads and stores carry the
-// nontemporal hint (+6 % measured on MI355X at n = 28); a state that fits the memory-side cache streams
-// with ordinary accesses instead (kTemporalMaxBytes).
+// nontemporal hint (+6 % measured on MI355X at n = 28), except in the first a.temporal_tiles unmarked tiles
+// of the share, whose ordinary accesses leave them in the memory-side cache for the next pass; without NT
+// (a state that fits that cache) every access is ordinary.  See kTemporalBytes.
 // A workgroup keeps the last kHeldTiles tiles of its share on chip for the whole launch: the very last in
 // registers (rt[u], kUnroll vectors per thread), the ones before it in LDS (each thread its own slots,
 // held[(h * kUnroll + u) * kBlock + tid], so no barrier guards them).  The launch's first pass loads them
@@ -206,6 +208,26 @@ constexpr int kHeldTiles = 3;
 
 // First held tile (local index) of this workgroup's share of cnt tiles.
 __device__ inline uint64_t held_start(uint64_t cnt) { return cnt > uint64_t(kHeldTiles) ? cnt - kHeldTiles : 0; }
+
+// A full tile without marked amplitudes: every sign is +1.  NT selects the nontemporal loads and stores.
+template <class T, class A, bool UPDATE, bool NT>
+__device__ __forceinline__ void plain_tile(typename T::vec *st, uint64_t v0, unsigned tid, double mr, double mi,
+                                           A &acc)
+{
+    typename T::vec x[kUnroll];
+#pragma unroll
+    for (int u = 0; u < kUnroll; ++u)
+        x[u] = load16<NT>(st + v0 + u * kBlock + tid);
+#pragma unroll
+    for (int u = 0; u < kUnroll; ++u) {
+        if (UPDATE) {
+            update_vec<T>(x[u], mr, mi, 0u, acc);
+            store16<NT>(x[u], st + v0 + u * kBlock + tid);
+        } else {
+            accum_vec<T>(x[u], 0u, acc);
+        }
+    }
+}
 
 template <class T, class A, bool UPDATE, bool NT>
 __device__ inline void chunk_pass(const FusedArgs &a, const uint32_t *slow_tiles, bool table, double mr, double mi,
@@ -223,20 +245,10 @@ __device__ inline void chunk_pass(const FusedArgs &a, const uint32_t *slow_tiles
         const uint64_t v0 = t * kTile;
         const bool full = v0 + kTile <= a.nvec;
         const bool marked = table ? ((slow_tiles[j >> 5] >> (j & 31)) & 1u) != 0u : a.m > 0;
-        if (full && !marked) {
-            V x[kUnroll];
-#pragma unroll
-            for (int u = 0; u < kUnroll; ++u)
-                x[u] = load16<NT>(st + v0 + u * kBlock + tid);
-#pragma unroll
-            for (int u = 0; u < kUnroll; ++u) {
-                if (UPDATE) {
-                    update_vec<T>(x[u], mr, mi, 0u, acc);
-                    store16<NT>(x[u], st + v0 + u * kBlock + tid);
-                } else {
-                    accum_vec<T>(x[u], 0u, acc);
-                }
-            }
+        if (full && !marked && (!NT || j < a.temporal_tiles)) {
+            plain_tile<T, A, UPDATE, false>(st, v0, tid, mr, mi, acc);
+        } else if (full && !marked) {
+            plain_tile<T, A, UPDATE, true>(st, v0, tid, mr, mi, acc);
         } else {
             // Ragged tail of the state, or a tile that may hold marked amplitudes: the same vector loads,
             // then each amplitude's sign from the tile's slice [mp, mq) of the sorted marked list.
@@ -462,28 +474,33 @@ const void *kernel_for(uint32_t dtype, uint32_t accum, bool temporal)
     return temporal ? kernel_for_access<CHECK, false>(dtype, accum) : kernel_for_access<CHECK, true>(dtype, accum);
 }
 
-// States up to this size are streamed with ordinary (temporal) loads and stores, so that iterations find
-// the state in the 256 MB memory-side cache: one optimal search at n = 23, 24, 25 (complex64: 64, 128,
-// 256 MiB) took 10 %, 7 % and 16 % less time on MI355X than with nontemporal accesses.  Larger states
-// evict themselves from that cache every pass and stream nontemporally (n = 26, 512 MiB: temporal
-// accesses cost 9 % more; nontemporal is 6 % faster at n = 28).
-constexpr uint64_t kTemporalMaxBytes = uint64_t(256) << 20;
+// Bytes of the state per pass streamed with ordinary (temporal) loads and stores, so that the next pass
+// finds them in MI355X's 256 MB memory-side cache; the rest streams with nontemporal accesses, which keep it
+// from evicting them.  A state no larger streams entirely with ordinary accesses: one optimal search at
+// n = 23, 24, 25 (complex64: 64, 128, 256 MiB) took 10 %, 7 % and 16 % less time than with nontemporal
+// ones.  At n = 28 the first 18 tiles of each workgroup's share (288 MiB on 256 workgroups) cut the time per
+// iteration by 1.9 %; 16 tiles by 1.2 %, 20 tiles by nothing, and all tiles cost 6 %.
+constexpr uint64_t kTemporalBytes = uint64_t(288) << 20;
 
 }  // namespace
 
 hipError_t fused_configure(grover_ctx *c, int *per_cu, int *block, int64_t *forced_grid)
 {
-    bool temporal = c->N * elem_bytes(c->dtype) <= kTemporalMaxBytes;
+    const uint64_t state_bytes = c->N * elem_bytes(c->dtype);
+    uint64_t budget = kTemporalBytes;
     if (const char *env = getenv("GROVER_FUSED_TEMPORAL")) {
-        if (env[0] == '0' || env[0] == '1')
-            temporal = env[0] == '1';
+        if (env[0] == '0')
+            budget = 0;  // every access nontemporal
+        else if (env[0] == '1')
+            budget = state_bytes;  // every access ordinary
     }
+    const bool temporal = state_bytes <= budget;
     const void *k = kernel_for<false>(c->dtype, c->accum, temporal);
     if (!k)
         return hipErrorInvalidValue;
     c->fused_kernel = k;
     c->fused_check_kernel = kernel_for<true>(c->dtype, c->accum, temporal);
-    c->fused_temporal = temporal;
+    c->fused_temporal_bytes = temporal ? state_bytes : budget;
     c->fused_tile = kTile;
     int coop = 0;
     hipError_t e = hipDeviceGetAttribute(&coop, hipDeviceAttributeCooperativeLaunch, c->device);
@@ -513,6 +530,12 @@ uint64_t fused_tiles(const grover_ctx *c)
     return (nvec + c->fused_tile - 1) / c->fused_tile;
 }
 
+uint64_t fused_temporal_tiles(const grover_ctx *c)
+{
+    const uint64_t share = uint64_t(c->grid > 0 ? c->grid : 1) * kTile * 16u;  // bytes of one tile per workgroup
+    return c->fused_temporal_bytes / share;
+}
+
 hipError_t launch_fused_iterate(grover_ctx *c, uint64_t k, uint64_t timeout_ticks, bool check)
 {
     FusedArgs a;
@@ -526,6 +549,7 @@ hipError_t launch_fused_iterate(grover_ctx *c, uint64_t k, uint64_t timeout_tick
     a.iters = k;
     a.gen0 = c->generation;
     a.timeout_ticks = timeout_ticks;
+    a.temporal_tiles = fused_temporal_tiles(c);
     void *args[] = {&a};
     const void *fn = check ? c->fused_check_kernel : c->fused_kernel;
     const hipError_t e = hipLaunchCooperativeKernel(fn, dim3(c->grid), dim3(c->block), args, 0, c->stream);

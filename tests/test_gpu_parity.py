@@ -159,26 +159,45 @@ def test_fused_grid_shapes(G, orc, monkeypatch):
 
 
 def test_fused_access_form(G, orc, monkeypatch):
-    """States up to 256 MiB stream with ordinary loads and stores (they stay in the memory-side cache
-    across iterations), larger ones with nontemporal ones; forcing either form leaves the results bit for bit
-    the same (n = 24 complex64: 8 tiles per workgroup, 5 of them streamed)."""
-    for n, dtype, want in [(16, "c64", 1), (24, "c128", 1), (25, "c64", 1), (25, "c128", 0), (26, "c64", 0)]:
+    """Up to 288 MiB of the state per pass streams with ordinary loads and stores (kept in the memory-side
+    cache across iterations): the whole of a state that small, else the leading tiles of each workgroup's
+    share, the rest with nontemporal accesses.  Every form gives the same results bit for bit: n = 24
+    complex64 (8 tiles per workgroup, 5 streamed) all ordinary, all nontemporal and against the oracle;
+    n = 26 complex64 (32 tiles per workgroup) split against all nontemporal."""
+    budget = 288 << 20
+    for n, dtype in [(16, "c64"), (24, "c128"), (25, "c64"), (25, "c128"), (26, "c64")]:
         g = G.Grover(n, dtype, marks=[3], form="fused")
+        state = (1 << n) * g.query(G.grover.Q_ELEM_BYTES)
+        share = g.query(G.grover.Q_GRID) * 4096 * 16
+        want = state if state <= budget else min(state, budget // share * share)
         assert g.query(G.grover.Q_FUSED_TEMPORAL) == want, (n, dtype)
         g.close()
+
+    def run(n, dtype, forced, psi0, marks, k1, k2):
+        if forced is None:
+            monkeypatch.delenv("GROVER_FUSED_TEMPORAL", raising=False)
+        else:
+            monkeypatch.setenv("GROVER_FUSED_TEMPORAL", forced)
+        g = G.Grover(n, dtype, marks=marks, form="fused")
+        state = (1 << n) * g.query(G.grover.Q_ELEM_BYTES)
+        if forced is not None:
+            assert g.query(G.grover.Q_FUSED_TEMPORAL) == (state if forced == "1" else 0)
+        g.write_state(psi0).iterate(k1).iterate(k2)
+        out = g.read_state()
+        g.close()
+        return out
+
     n, dtype = 24, "c64"
     psi0 = start_state(n, dtype, seed=24)
     marks = workloads.distinct_marks(n, 7, seed=24)
-    states = []
-    for forced in ["0", "1"]:
-        monkeypatch.setenv("GROVER_FUSED_TEMPORAL", forced)
-        g = G.Grover(n, dtype, marks=marks, form="fused")
-        assert g.query(G.grover.Q_FUSED_TEMPORAL) == int(forced)
-        g.write_state(psi0).iterate(4).iterate(5)
-        states.append(g.read_state())
-        g.close()
-    assert np.array_equal(states[0].view(np.uint32), states[1].view(np.uint32))
-    assert_close(states[1], orc.iterate(as_c128(psi0), marks, 9), dtype, "n=24 fused")
+    a, b = run(n, dtype, "0", psi0, marks, 4, 5), run(n, dtype, "1", psi0, marks, 4, 5)
+    assert np.array_equal(a.view(np.uint32), b.view(np.uint32))
+    assert_close(b, orc.iterate(as_c128(psi0), marks, 9), dtype, "n=24 fused")
+    n = 26
+    psi0 = start_state(n, dtype, seed=26)
+    marks = workloads.distinct_marks(n, 9, seed=26)
+    a, b = run(n, dtype, "0", psi0, marks, 2, 3), run(n, dtype, None, psi0, marks, 2, 3)
+    assert np.array_equal(a.view(np.uint32), b.view(np.uint32))
 
 
 # ----------------------------------------------------------------------------------- hash oracle
