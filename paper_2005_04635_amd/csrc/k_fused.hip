@@ -17,7 +17,9 @@
 // accumulation, which makes iterate(a); iterate(b) equal iterate(a + b) bit for bit.
 //
 // Template parameters: T = storage type (F64Real, C64, C128, CBF16), A = accumulator of the sum (AccF64,
-// AccF32, AccF32Kahan; the grid tree runs in A's precision).  The update itself is always binary64.
+// AccF32, AccF32Kahan; the grid tree runs in A's precision), CHECK = a second symbol of the same code for the
+// residency check at context creation, NT = nontemporal accesses beyond the part of the state kept in the
+// memory-side cache (kTemporalBytes).  The update itself is always binary64.
 #include "internal.h"
 
 namespace grover {
