@@ -531,8 +531,8 @@ def main() -> int:
                     help="instead of the headline line, print one JSON line per point of a sweep")
     args = ap.parse_args()
     if args.gpus != 1:
-        print("bench.py runs on exactly one GPU: the Grover iteration's state is not sharded across GPUs in "
-              "this build (see DESIGN.md for how it would shard); use --gpus 1", file=sys.stderr)
+        print("bench.py runs on exactly one GPU: the state of a search is not sharded across GPUs; use --gpus 1",
+              file=sys.stderr)
         return 2
 
     import numpy as np

@@ -39,7 +39,7 @@ extern "C" {
 #define GROVER_E_NOMEM (-2)       /* device or host allocation failed */
 #define GROVER_E_HIP (-3)         /* a HIP runtime call failed; message in grover_last_error */
 #define GROVER_E_COOP (-4)        /* the persistent grid cannot be made co-resident on this device */
-#define GROVER_E_UNSUPPORTED (-5) /* valid request this build does not implement (e.g. form/size mismatch) */
+#define GROVER_E_UNSUPPORTED (-5) /* valid request the library does not implement (e.g. form/size mismatch) */
 #define GROVER_E_PREDICATE (-6)   /* hash predicate hit count differs from the requested m */
 #define GROVER_E_TIMEOUT (-7)     /* a device-side grid barrier exceeded its time limit (reported by grover_sync) */
 

@@ -1,8 +1,8 @@
 """GPU parity: the HIP library (through its C ABI) against the CPU oracle on the same seeded inputs.
 
 Tolerances (max absolute amplitude error against the binary64 oracle): 1e-12 for binary64 storage
-(f64, c128) and 1e-5 for complex64 storage, as the specification of this build fixes them. Integer results
-(marked lists, sampled indices) must match exactly.
+(f64, c128) and 1e-5 for complex64 storage. Integer results (marked lists, sampled indices) must match
+exactly.
 """
 from __future__ import annotations
 
