@@ -96,8 +96,14 @@ __global__ __launch_bounds__(kStreamBlock) void held_iterate_kernel(HeldIterArgs
 }  // namespace
 
 // Team size of the held form for a complex64 state of nvec vectors on a device whose largest power-of-two
-// team is max_team: registers only (8 vectors per thread) while that takes at most 64 workgroups, else 16
-// vectors per thread (8 more in LDS); 0 when the state does not fit.
+// team is max_team; 0 when the state does not fit.  While a team of at most 128 workgroups can hold the state
+// in registers (8 vectors per thread), that team is used, but spread over at least 64 workgroups once the
+// state has 256 vectors per workgroup or more: the update's VALU work per iteration shrinks, while the team
+// barrier costs about the same up to 64 members.  Larger states take 16 vectors per thread, 8 of them in LDS.
+// One optimal search on MI355X, chosen team against the registers-only team of at most 64 workgroups:
+// n = 15 64 vs 2 workgroups 0.449 vs 0.496 ms, n = 16 64 vs 4 0.619 vs 0.692 ms (one box; teams of 16 and
+// 32 were slower than 64 at both sizes, 8 faster at n = 15 only), n = 18 64 vs 16 1.436 vs 1.572 ms, n = 19
+// 64 vs 32 2.188 vs 2.361 ms, n = 21 128 with 8 per thread vs 64 with 16 5.81 vs 5.93 ms; n = 17 equal.
 uint32_t held_team_size(uint64_t nvec, uint32_t max_team)
 {
     auto pow2 = [](uint64_t x) {
@@ -107,8 +113,12 @@ uint32_t held_team_size(uint64_t nvec, uint32_t max_team)
         return t;
     };
     const uint64_t t8 = pow2((nvec + uint64_t(kHeldRegE) * kStreamBlock - 1) / (uint64_t(kHeldRegE) * kStreamBlock));
-    if (t8 <= 64 && t8 <= max_team)
+    if (t8 <= 128 && t8 <= max_team) {
+        constexpr uint64_t kSpread = 64;
+        if (t8 < kSpread && kSpread <= max_team && nvec >= kSpread * 256)
+            return uint32_t(kSpread);
         return uint32_t(t8);
+    }
     const uint64_t t16 = pow2((nvec + uint64_t(kHeldHoldE) * kStreamBlock - 1) / (uint64_t(kHeldHoldE) * kStreamBlock));
     return t16 <= max_team ? uint32_t(t16) : 0u;
 }

@@ -74,8 +74,9 @@ for form, ns in [("resident", [1, 2, 3, 5, 10, 12, 14]), ("fused", [1, 3, 9, 11,
     for n in ns:
         for dtype in ["f64", "c64", "c128"]:
             CASES.append((form, n, dtype))
-# the held form (complex64 only): one workgroup with fewer vectors than threads, registers only (teams of
-# 1 .. 64 workgroups, n <= 20), 8 more vectors per thread in LDS (n = 21 .. 23, teams of 64 .. 256)
+# the held form (complex64 only): one workgroup with fewer vectors than threads (n = 1 .. 9), registers only
+# (up to 8 vectors per thread: a team of 1 workgroup at n = 14, spread over 64 workgroups at n = 15 .. 20,
+# 128 at n = 21), 8 more vectors per thread in LDS (n = 22, 23: teams of 128 and 256)
 for n in [1, 3, 9, 14, 15, 17, 20, 21, 23]:
     CASES.append(("held", n, "c64"))
 
@@ -318,11 +319,12 @@ def test_held_form_selection(G):
     and the largest state that fits on chip; other storage types and larger states keep the fused form."""
     g = G.Grover(18, "c64", marks=[5])
     assert g.query(0) == G.grover.GROVER_FORM_HELD
-    assert g.query(1) == 16  # 2^17 vectors, 8 per thread: 16 workgroups
+    assert g.query(1) == 64  # 2^17 vectors spread over 64 workgroups: 2 per thread
     g.close()
-    g = G.Grover(22, "c64", marks=[5])
-    assert g.query(0) == G.grover.GROVER_FORM_HELD and g.query(1) == 128  # 16 vectors per thread
-    g.close()
+    for n, team in [(15, 64), (16, 64), (20, 64), (21, 128), (22, 128), (23, 256)]:
+        g = G.Grover(n, "c64", marks=[5])  # 8 vectors per thread up to 128 workgroups, then 16 (8 in LDS)
+        assert g.query(0) == G.grover.GROVER_FORM_HELD and g.query(1) == team, n
+        g.close()
     assert G.Grover(18, "c128", marks=[5]).query(0) == G.grover.GROVER_FORM_FUSED
     assert G.Grover(18, "c64", marks=[5], accum="f32").query(0) == G.grover.GROVER_FORM_FUSED
     assert G.Grover(12, "c64", marks=[5]).query(0) == G.grover.GROVER_FORM_RESIDENT
