@@ -74,8 +74,8 @@ typedef enum grover_form {
     GROVER_FORM_TWO_PASS = 3, /* plain form: per iteration an oracle flip, a sum pass and an update pass,
                                  launched from the host (Algorithms 3 and 4 as separate kernels) */
     GROVER_FORM_HELD = 4      /* complex64 with binary64 sums only: a team of T workgroups (a power of two;
-                                 at most 8 16-byte vectors per thread in registers while T <= 128, spread
-                                 over 64 workgroups from n = 15; else 16 with 8 in LDS) loads the state once
+                                 about 2 16-byte vectors per thread up to 64 workgroups, at most 8 per
+                                 thread in registers while T <= 128, else 16 with 8 in LDS) loads the state once
                                  per grover_iterate call and keeps it on chip for all k iterations, one team
                                  barrier each; n <= 23 on 256 CUs (GROVER_E_UNSUPPORTED when the state does
                                  not fit) */

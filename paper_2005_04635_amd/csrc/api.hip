@@ -225,7 +225,8 @@ int grover_init(grover_ctx **out, const grover_config *cfg, void *hip_stream, vo
     uint32_t form = cfg->form;
     const bool auto_form = form == GROVER_FORM_AUTO;
     // the held form exists for complex64 storage with binary64 sums; AUTO picks it (after the device
-    // query, which says whether the state fits on chip) for the sizes above the one-workgroup form
+    // query, which says whether the state fits on chip) for the sizes above the one-workgroup form, which
+    // is faster up to n = 13 and as fast at n = 14 (one optimal search on MI355X, n = 13: 0.145 vs 0.204 ms)
     const bool held_ok = cfg->dtype == GROVER_C64 && cfg->accum == GROVER_ACC_F64;
     if (auto_form)
         form = cfg->n <= kResidentMaxQubits && !fused_only ? GROVER_FORM_RESIDENT : GROVER_FORM_FUSED;

@@ -97,13 +97,14 @@ __global__ __launch_bounds__(kStreamBlock) void held_iterate_kernel(HeldIterArgs
 
 // Team size of the held form for a complex64 state of nvec vectors on a device whose largest power-of-two
 // team is max_team; 0 when the state does not fit.  While a team of at most 128 workgroups can hold the state
-// in registers (8 vectors per thread), that team is used, but spread over at least 64 workgroups once the
-// state has 256 vectors per workgroup or more: the update's VALU work per iteration shrinks, while the team
-// barrier costs about the same up to 64 members.  Larger states take 16 vectors per thread, 8 of them in LDS.
-// One optimal search on MI355X, chosen team against the registers-only team of at most 64 workgroups:
-// n = 15 64 vs 2 workgroups 0.449 vs 0.496 ms, n = 16 64 vs 4 0.619 vs 0.692 ms (one box; teams of 16 and
-// 32 were slower than 64 at both sizes, 8 faster at n = 15 only), n = 18 64 vs 16 1.436 vs 1.572 ms, n = 19
-// 64 vs 32 2.188 vs 2.361 ms, n = 21 128 with 8 per thread vs 64 with 16 5.81 vs 5.93 ms; n = 17 equal.
+// in registers (8 vectors per thread), the state is spread over the team that gives each thread about two
+// vectors, up to 64 workgroups (never fewer than the registers need): the update's VALU work per iteration
+// shrinks, while the team barrier costs about the same up to 64 members.  Larger states take 16 vectors per
+// thread, 8 of them in LDS.  One optimal search on MI355X, chosen team against the fewest workgroups that
+// hold the state in registers: n = 14 4 vs 1 workgroup 0.264 vs 0.330 ms, n = 15 8 vs 2 0.413 vs 0.496 ms,
+// n = 17 32 vs 8 0.984 vs 1.008 ms, n = 18 64 vs 16 1.436 vs 1.572 ms, n = 19 64 vs 32 2.188 vs 2.361 ms,
+// n = 21 128 with 8 per thread vs 64 with 16 5.81 vs 5.93 ms (n = 16: 16 vs 4 0.650 vs 0.692 ms, where 64
+// took 0.619 ms and 32 0.671 ms).
 uint32_t held_team_size(uint64_t nvec, uint32_t max_team)
 {
     auto pow2 = [](uint64_t x) {
@@ -114,10 +115,12 @@ uint32_t held_team_size(uint64_t nvec, uint32_t max_team)
     };
     const uint64_t t8 = pow2((nvec + uint64_t(kHeldRegE) * kStreamBlock - 1) / (uint64_t(kHeldRegE) * kStreamBlock));
     if (t8 <= 128 && t8 <= max_team) {
-        constexpr uint64_t kSpread = 64;
-        if (t8 < kSpread && kSpread <= max_team && nvec >= kSpread * 256)
-            return uint32_t(kSpread);
-        return uint32_t(t8);
+        uint64_t t2 = pow2((nvec + 2u * kStreamBlock - 1) / (2u * kStreamBlock));  // about two vectors per thread
+        if (t2 > 64)
+            t2 = 64;
+        if (t2 > max_team)
+            t2 = max_team;
+        return uint32_t(t8 > t2 ? t8 : t2);
     }
     const uint64_t t16 = pow2((nvec + uint64_t(kHeldHoldE) * kStreamBlock - 1) / (uint64_t(kHeldHoldE) * kStreamBlock));
     return t16 <= max_team ? uint32_t(t16) : 0u;

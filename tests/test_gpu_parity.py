@@ -75,8 +75,8 @@ for form, ns in [("resident", [1, 2, 3, 5, 10, 12, 14]), ("fused", [1, 3, 9, 11,
         for dtype in ["f64", "c64", "c128"]:
             CASES.append((form, n, dtype))
 # the held form (complex64 only): one workgroup with fewer vectors than threads (n = 1 .. 9), registers only
-# (up to 8 vectors per thread: a team of 1 workgroup at n = 14, spread over 64 workgroups at n = 15 .. 20,
-# 128 at n = 21), 8 more vectors per thread in LDS (n = 22, 23: teams of 128 and 256)
+# (about 2 vectors per thread on teams of 4 .. 64 workgroups at n = 14 .. 17, up to 8 per thread on 64 and
+# 128 workgroups at n = 18 .. 21), 8 more vectors per thread in LDS (n = 22, 23: teams of 128 and 256)
 for n in [1, 3, 9, 14, 15, 17, 20, 21, 23]:
     CASES.append(("held", n, "c64"))
 
@@ -321,13 +321,18 @@ def test_held_form_selection(G):
     assert g.query(0) == G.grover.GROVER_FORM_HELD
     assert g.query(1) == 64  # 2^17 vectors spread over 64 workgroups: 2 per thread
     g.close()
-    for n, team in [(15, 64), (16, 64), (20, 64), (21, 128), (22, 128), (23, 256)]:
-        g = G.Grover(n, "c64", marks=[5])  # 8 vectors per thread up to 128 workgroups, then 16 (8 in LDS)
+    # about 2 vectors per thread up to 64 workgroups, at most 8 per thread up to 128, then 16 (8 in LDS)
+    for n, team in [(15, 8), (16, 16), (20, 64), (21, 128), (22, 128), (23, 256)]:
+        g = G.Grover(n, "c64", marks=[5])
         assert g.query(0) == G.grover.GROVER_FORM_HELD and g.query(1) == team, n
         g.close()
     assert G.Grover(18, "c128", marks=[5]).query(0) == G.grover.GROVER_FORM_FUSED
     assert G.Grover(18, "c64", marks=[5], accum="f32").query(0) == G.grover.GROVER_FORM_FUSED
     assert G.Grover(12, "c64", marks=[5]).query(0) == G.grover.GROVER_FORM_RESIDENT
+    assert G.Grover(12, "c128", marks=[5]).query(0) == G.grover.GROVER_FORM_RESIDENT
+    h = G.Grover(14, "c64", marks=[5], form="held")
+    assert h.query(1) == 4  # 2^13 vectors, 2 per thread
+    h.close()
     with pytest.raises(G.GroverError) as e:
         G.Grover(16, "c128", marks=[5], form="held")
     assert e.value.status == G.grover.GROVER_E_UNSUPPORTED
