@@ -1,6 +1,6 @@
 // On-chip iteration for small states (n <= 14): one workgroup of 1024 threads loads the whole state into
 // registers once, runs all k iterations of Algorithm 5's loop body there (oracle sign, sum, update), and
-// writes it back once.  The only synchronisation per iteration is the workgroup barrier of the sum, so
+// writes it back once.  The only synchronisation per iteration is the one workgroup barrier of the sum, so
 // small searches (e.g. n = 10, 25 iterations) cost one launch instead of 2k passes over memory.
 #include "internal.h"
 
@@ -18,13 +18,38 @@ struct ResidentArgs {
     uint64_t iters;
 };
 
+constexpr int kWaves = kBlock / kWave;
+
+// Sum of (a, b) over the workgroup, left with the same bits in every thread: wave totals into the LDS slots
+// of parity p, one workgroup barrier, then every thread adds the wave values in wave order.  A slot set is
+// written again two calls later, after the next call's barrier, which every thread reaches only after its
+// reads here, so one barrier per call suffices.
+__device__ inline void workgroup_sum(double &a, double &b, double (*red)[2 * kWaves], int p)
+{
+    const int lane = threadIdx.x % kWave, wave = threadIdx.x / kWave;
+    a = wave_total(a);
+    b = wave_total(b);
+    if (lane == 0) {
+        red[p][2 * wave] = a;
+        red[p][2 * wave + 1] = b;
+    }
+    __syncthreads();
+    double sa = 0.0, sb = 0.0;
+#pragma unroll
+    for (int w = 0; w < kWaves; ++w) {
+        sa += red[p][2 * w];
+        sb += red[p][2 * w + 1];
+    }
+    a = sa;
+    b = sb;
+}
+
 // E = 16-byte vectors per thread; vector v = e * kBlock + threadIdx.x (coalesced load and store).
 template <class T, int E>
 __global__ __launch_bounds__(kBlock) void resident_iterate_kernel(ResidentArgs a)
 {
     using V = typename T::vec;
-    __shared__ double red[2 * (kBlock / kWave)];
-    __shared__ double bsum[2];
+    __shared__ double red[2][2 * kWaves];
     V *st = static_cast<V *>(a.state);
     const unsigned tid = threadIdx.x;
     V x[E];
@@ -45,14 +70,7 @@ __global__ __launch_bounds__(kBlock) void resident_iterate_kernel(ResidentArgs a
         if (uint64_t(e) * kBlock + tid < a.nvec)
             accum_vec<T>(x[e], bits[e], acc0);
     double sr = acc0.r, si = acc0.i;
-    block_sum2(sr, si, red);
-    if (tid == 0) {
-        bsum[0] = sr;
-        bsum[1] = si;
-    }
-    __syncthreads();
-    sr = bsum[0];
-    si = bsum[1];
+    workgroup_sum(sr, si, red, 0);
     for (uint64_t it = 0; it < a.iters; ++it) {
         const double mr = (sr * 2.0) / a.N, mi = (si * 2.0) / a.N;
         AccF64 acc;
@@ -60,15 +78,9 @@ __global__ __launch_bounds__(kBlock) void resident_iterate_kernel(ResidentArgs a
         for (int e = 0; e < E; ++e)
             if (uint64_t(e) * kBlock + tid < a.nvec)
                 update_vec<T>(x[e], mr, mi, bits[e], acc);
-        double ar = acc.r, ai = acc.i;
-        block_sum2(ar, ai, red);
-        if (tid == 0) {
-            bsum[0] = ar;
-            bsum[1] = ai;
-        }
-        __syncthreads();
-        sr = bsum[0];
-        si = bsum[1];
+        sr = acc.r;
+        si = acc.i;
+        workgroup_sum(sr, si, red, int((it + 1) & 1u));
     }
 #pragma unroll
     for (int e = 0; e < E; ++e) {
