@@ -89,15 +89,19 @@ __device__ inline bool wait_pair(const uint64_t *w, uint32_t tag, const FusedArg
 }
 
 // Grid-wide sum of (xr, xi) at generation `gen`: every workgroup publishes its partial as tagged words in
-// its slot of the generation's parity; in workgroup 0, wave 0 gathers them (lane l waits for the slots of
-// workgroups l, l + 64, ... and adds them in that order; the lanes' values are then added by wave_total),
-// so the sum is reproducible run to run, and publishes the sum as tagged words, which the other workgroups
-// poll.  A slot of parity p is rewritten two generations later, after workgroup 0 has read it and every
-// workgroup has read the sum in between; the sum is double-buffered the same way.  Two workgroup barriers:
-// one before thread 0 adds the wave partials, one before every thread reads the sum.  The LDS words are
-// written again only after the first barrier of the next call, which every thread reaches after its reads
-// here, so no barrier is needed behind them.  Returns false when a wait gave up.
-template <class V>
+// its slot of the generation's parity; wave 0 gathers them (lane l waits for the slots of workgroups l,
+// l + 64, ... and adds them in that order; the lanes' values are then added by wave_total), so the sum is
+// reproducible run to run.  ALL: every workgroup gathers, and all of them compute the same bits in one
+// memory round trip.  Otherwise workgroup 0 gathers and publishes the sum as tagged words, which the other
+// workgroups poll: two round trips, but far fewer polls while other workgroups still stream (the form
+// for states too large for the memory-side cache).  A slot of parity p is rewritten two generations later:
+// its owner's next partial needs this generation's sum, and the one after that needs every workgroup's
+// next partial, which each publishes only after its reads here; the published sum is double-buffered the
+// same way.  Two workgroup barriers: one before thread 0 adds the wave partials, one before every thread
+// reads the sum.  The LDS words are written again only after the first barrier of the next call, which
+// every thread reaches after its reads here, so no barrier is needed behind them.  Returns false when a
+// wait gave up.
+template <class V, bool ALL>
 __device__ bool grid_sum(V &xr, V &xi, const FusedArgs &a, uint64_t gen, Shared<V> &sh)
 {
     const uint32_t tag = uint32_t(gen);
@@ -122,7 +126,7 @@ __device__ bool grid_sum(V &xr, V &xi, const FusedArgs &a, uint64_t gen, Shared<
         put_tagged(slot, double(sr), tag);
         put_tagged(slot + 2, double(si), tag);
     }
-    if (blockIdx.x == 0) {
+    if (ALL || blockIdx.x == 0) {
         if (wave == 0) {
             V pr = V(0), pi = V(0);
             bool ok = true;
@@ -138,8 +142,10 @@ __device__ bool grid_sum(V &xr, V &xi, const FusedArgs &a, uint64_t gen, Shared<
             if (lane == 0) {
                 sh.abort = failed;
                 if (!failed) {
-                    put_tagged(bcast, double(pr), tag);
-                    put_tagged(bcast + 2, double(pi), tag);
+                    if (!ALL) {
+                        put_tagged(bcast, double(pr), tag);
+                        put_tagged(bcast + 2, double(pi), tag);
+                    }
                     sh.sum[0] = pr;
                     sh.sum[1] = pi;
                 }
@@ -411,7 +417,7 @@ __global__ __launch_bounds__(kBlock) void fused_iterate_kernel(FusedArgs a)
     A acc0;
     chunk_pass<T, A, false, NT>(a, slow_tiles, table, 0.0, 0.0, acc0, held, rt);
     Val sr = acc0.res_r(), si = acc0.res_i();
-    if (!grid_sum<Val>(sr, si, a, a.gen0 + 1u, sh))
+    if (!grid_sum<Val, !NT>(sr, si, a, a.gen0 + 1u, sh))
         return;
     for (uint64_t it = 0; it < a.iters; ++it) {
         const double mr = (double(sr) * 2.0) / a.N, mi = (double(si) * 2.0) / a.N;
@@ -419,7 +425,7 @@ __global__ __launch_bounds__(kBlock) void fused_iterate_kernel(FusedArgs a)
         chunk_pass<T, A, true, NT>(a, slow_tiles, table, mr, mi, acc, held, rt);
         sr = acc.res_r();
         si = acc.res_i();
-        if (!grid_sum<Val>(sr, si, a, a.gen0 + 2u + it, sh))
+        if (!grid_sum<Val, !NT>(sr, si, a, a.gen0 + 2u + it, sh))
             return;
     }
     if (a.iters > 0) {  // the held tiles go back to memory
