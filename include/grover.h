@@ -189,8 +189,8 @@ int grover_sync(grover_ctx *ctx);
  * 6 = grid-barrier wait limit in device wall-clock ticks, 7 = workgroups per CU of the fused kernel as the
  * runtime's occupancy calculator reports them (the grid actually used is confirmed on the device), 8 = bytes
  * of the state per pass that the fused kernel streams with ordinary loads and stores, so that the next pass
- * finds them in the memory-side cache (the whole state up to 288 MiB; above that, the leading tiles of each
- * workgroup's share up to 288 MiB in all, the rest with nontemporal accesses; 0 for the other forms).  The
+ * finds them in the memory-side cache (the whole state up to 272 MiB; above that, the leading tiles of each
+ * workgroup's share up to 272 MiB in all, the rest with nontemporal accesses; 0 for the other forms).  The
  * environment variable GROVER_FUSED_TEMPORAL, read at grover_init, forces 0 (all nontemporal) or 1 (all
  * ordinary).  Results are identical either way. */
 int grover_query(grover_ctx *ctx, int key, int64_t *value);

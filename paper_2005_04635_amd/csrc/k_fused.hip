@@ -486,9 +486,11 @@ const void *kernel_for(uint32_t dtype, uint32_t accum, bool temporal)
 // finds them in MI355X's 256 MB memory-side cache; the rest streams with nontemporal accesses, which keep it
 // from evicting them.  A state no larger streams entirely with ordinary accesses: one optimal search at
 // n = 23, 24, 25 (complex64: 64, 128, 256 MiB) took 10 %, 7 % and 16 % less time than with nontemporal
-// ones.  At n = 28 the first 18 tiles of each workgroup's share (288 MiB on 256 workgroups) cut the time per
-// iteration by 1.9 %; 16 tiles by 1.2 %, 20 tiles by nothing, and all tiles cost 6 %.
-constexpr uint64_t kTemporalBytes = uint64_t(288) << 20;
+// ones.  At n = 28 the first 17 tiles of each workgroup's share (272 MiB on 256 workgroups) cut the time per
+// iteration the most: on one box 17 tiles 292.3-293.3 ms per 400 iterations, 16 295.4, 18 294.4, 19 296.3;
+// on another 16 tiles -1.2 % and 18 -1.9 % against none, 20 tiles nothing, all tiles +6 %.  17 keeps a
+// margin below the size where the gain vanishes.
+constexpr uint64_t kTemporalBytes = uint64_t(272) << 20;
 
 }  // namespace
 

@@ -160,12 +160,12 @@ def test_fused_grid_shapes(G, orc, monkeypatch):
 
 
 def test_fused_access_form(G, orc, monkeypatch):
-    """Up to 288 MiB of the state per pass streams with ordinary loads and stores (kept in the memory-side
+    """Up to 272 MiB of the state per pass streams with ordinary loads and stores (kept in the memory-side
     cache across iterations): the whole of a state that small, else the leading tiles of each workgroup's
     share, the rest with nontemporal accesses.  Every form gives the same results bit for bit: n = 24
     complex64 (8 tiles per workgroup, 5 streamed) all ordinary, all nontemporal and against the oracle;
     n = 26 complex64 (32 tiles per workgroup) split against all nontemporal."""
-    budget = 288 << 20
+    budget = 272 << 20
     for n, dtype in [(16, "c64"), (24, "c128"), (25, "c64"), (25, "c128"), (26, "c64")]:
         g = G.Grover(n, dtype, marks=[3], form="fused")
         state = (1 << n) * g.query(G.grover.Q_ELEM_BYTES)
