@@ -26,6 +26,11 @@ struct HeldIterArgs {
     uint32_t probe;  // 1: one team barrier only (residency check)
 };
 
+// kTogether: a lane of the team barrier waits for its 2 to 4 member slots together (teams of more than 64
+// workgroups; n = 21 and 22: 5.29 vs 5.84 ms and 8.59 vs 9.58 ms per optimal search on MI355X).  Teams of
+// at most 64 use the kernel without it, whose code keeps fewer registers in flight (with it n = 18 took
+// 1.61 instead of 1.43 ms).
+template <bool kTogether>
 __global__ __launch_bounds__(kStreamBlock) void held_iterate_kernel(HeldIterArgs a)
 {
     __shared__ TeamShared<double> sh;
@@ -34,7 +39,7 @@ __global__ __launch_bounds__(kStreamBlock) void held_iterate_kernel(HeldIterArgs
     uint64_t gen = a.gen0;
     if (a.probe) {
         double zr = 0.0, zi = 0.0;
-        (void)team_sum<double>(zr, zi, tm, ++gen, sh);
+        (void)team_sum<double, kTogether>(zr, zi, tm, ++gen, sh);
         return;
     }
     const unsigned tid = threadIdx.x;
@@ -64,7 +69,7 @@ __global__ __launch_bounds__(kStreamBlock) void held_iterate_kernel(HeldIterArgs
             correct_marked(x, held, mask, acc0);
     }
     double sr = acc0.r, si = acc0.i;
-    if (!team_sum<double>(sr, si, tm, ++gen, sh))
+    if (!team_sum<double, kTogether>(sr, si, tm, ++gen, sh))
         return;
     for (uint64_t it = 0; it < a.iters; ++it) {
         const double mr = sr * a.scale, mi = si * a.scale;
@@ -78,7 +83,7 @@ __global__ __launch_bounds__(kStreamBlock) void held_iterate_kernel(HeldIterArgs
         }
         sr = acc.r;
         si = acc.i;
-        if (!team_sum<double>(sr, si, tm, ++gen, sh))
+        if (!team_sum<double, kTogether>(sr, si, tm, ++gen, sh))
             return;
     }
     if (active) {
@@ -141,8 +146,9 @@ hipError_t launch_held_iterate(grover_ctx *c, uint64_t k, uint64_t timeout_ticks
     a.timeout_ticks = timeout_ticks;
     a.probe = probe ? 1u : 0u;
     void *args[] = {&a};
-    const hipError_t e = hipLaunchCooperativeKernel(reinterpret_cast<const void *>(&held_iterate_kernel),
-                                                    dim3(c->held_team), dim3(kStreamBlock), args, 0, c->stream);
+    const void *fn = c->held_team > 64u ? reinterpret_cast<const void *>(&held_iterate_kernel<true>)
+                                         : reinterpret_cast<const void *>(&held_iterate_kernel<false>);
+    const hipError_t e = hipLaunchCooperativeKernel(fn, dim3(c->held_team), dim3(kStreamBlock), args, 0, c->stream);
     if (e == hipSuccess)
         c->generation += probe ? 1u : k + 1u;
     return e;

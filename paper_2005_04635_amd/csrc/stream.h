@@ -115,6 +115,42 @@ __device__ inline bool wait_pair(const uint64_t *w, uint32_t tag, const Team &tm
     return true;
 }
 
+// Bounded wait for the value pairs of up to four slots w + 4 kWave i (i < cnt, slot i of a lane that gathers
+// members lane + kWave i), polled together so that the wait ends one memory round trip after the last of
+// them is published instead of one round trip per slot; same limits as wait_pair.
+__device__ inline bool wait_pairs4(const uint64_t *w, unsigned cnt, uint32_t tag, const Team &tm, double (&a)[4],
+                                   double (&b)[4])
+{
+    const uint64_t t0 = wall_clock64();
+    const unsigned all = (1u << cnt) - 1u;
+    unsigned done = 0u;  // bit i: slot i read
+    for (;;) {
+#pragma unroll
+        for (unsigned i = 0; i < 4u; ++i) {
+            if (i < cnt && ((done >> i) & 1u) == 0u) {
+                const uint64_t *slot = w + uint64_t(i) * kWave * 4u;
+                uint64_t h0, l0, h1, l1;
+                const bool ra = tagged_ready(slot, tag, h0, l0);
+                const bool rb = tagged_ready(slot + 2, tag, h1, l1);
+                if (ra && rb) {
+                    a[i] = tagged_value(h0, l0);
+                    b[i] = tagged_value(h1, l1);
+                    done |= 1u << i;
+                }
+            }
+        }
+        if (done == all)
+            return true;
+        if (__hip_atomic_load(&tm.sync->error, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0u)
+            return false;
+        if (uint64_t(wall_clock64()) - t0 > tm.timeout_ticks) {
+            __hip_atomic_store(&tm.sync->error, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            return false;
+        }
+        __builtin_amdgcn_s_sleep(1);
+    }
+}
+
 // Team-wide sum of (xr, xi) at barrier generation `gen` (1, 2, ... per barrier object; slots zeroed before
 // the launch), in the arithmetic of V (binary64 or binary32; partials travel as binary64, which holds a
 // binary32 exactly).  Returns false when the wait gave up (time limit, or another workgroup gave up); every
@@ -129,7 +165,7 @@ __device__ inline bool wait_pair(const uint64_t *w, uint32_t tag, const Team &tm
 // with one atomic per member serialise at the counter's address, and a gather to one member followed by a
 // broadcast costs two round trips.)  The team's workgroups share no other memory within a launch, so the
 // barrier orders nothing but these values.
-template <class V>
+template <class V, bool kTogether = false>
 __device__ bool team_sum(V &xr, V &xi, const Team &tm, uint64_t gen, TeamShared<V> &sh)
 {
     const uint32_t tag = uint32_t(gen);
@@ -160,11 +196,22 @@ __device__ bool team_sum(V &xr, V &xi, const Team &tm, uint64_t gen, TeamShared<
         if (wave == 0) {
             V ar = V(0), ai = V(0);
             bool ok = true;
-            for (unsigned w = lane; w < tm.size && ok; w += kWave) {
-                double a = 0.0, b = 0.0;
-                ok = wait_pair(slots + uint64_t(w) * 4u, tag, tm, a, b);
-                ar += V(a);
-                ai += V(b);
+            if (kTogether && tm.size > kWave) {
+                // 2 to 4 members per lane, waited for together and added in member order
+                const unsigned cnt = lane < tm.size ? (tm.size - lane + kWave - 1u) / kWave : 0u;
+                double a[4], b[4];
+                ok = wait_pairs4(slots + uint64_t(lane) * 4u, cnt, tag, tm, a, b);
+                for (unsigned i = 0; i < cnt && ok; ++i) {
+                    ar += V(a[i]);
+                    ai += V(b[i]);
+                }
+            } else {
+                for (unsigned w = lane; w < tm.size && ok; w += kWave) {
+                    double a = 0.0, b = 0.0;
+                    ok = wait_pair(slots + uint64_t(w) * 4u, tag, tm, a, b);
+                    ar += V(a);
+                    ai += V(b);
+                }
             }
             const V pr = wave_total(ar), pi = wave_total(ai);
             const bool failed = __any(!ok);

@@ -341,18 +341,19 @@ def test_held_form_selection(G):
     cu.close()
 
 
-def test_held_barrier_timeout_is_reported_and_recovers(G, orc, monkeypatch):
+@pytest.mark.parametrize("n", [18, 22])  # a team of 64 (one slot per lane) and of 128 (slots waited together)
+def test_held_barrier_timeout_is_reported_and_recovers(G, orc, monkeypatch, n):
     monkeypatch.setenv("GROVER_BARRIER_TIMEOUT_MS", "0")
-    g = G.Grover(18, "c64", marks=[5], form="held")
+    g = G.Grover(n, "c64", marks=[5], form="held")
     g.iterate(3)
     with pytest.raises(G.GroverError) as e:
         g.sync()
     assert e.value.status == -7
     g.close()
     monkeypatch.delenv("GROVER_BARRIER_TIMEOUT_MS")
-    g = G.Grover(18, "c64", marks=[5], form="held").iterate(3)
+    g = G.Grover(n, "c64", marks=[5], form="held").iterate(3)
     g.sync()
-    assert_close(g.read_state(), orc.search(18, [5], 3), "c64")
+    assert_close(g.read_state(), orc.search(n, [5], 3), "c64")
     g.close()
 
 
