@@ -83,7 +83,8 @@ typedef enum grover_form {
 
 /* ---------------------------------------------------------------------------------------- config */
 typedef struct grover_config {
-    uint32_t n;              /* qubits, 1 <= n <= 34; N = 2^n amplitudes */
+    uint32_t n;              /* qubits, 1 <= n <= 34; N = 2^n amplitudes (GROVER_CBF16: n >= 2, since every
+                                kernel moves whole 16-byte vectors; n = 1 is GROVER_E_UNSUPPORTED) */
     uint32_t dtype;          /* grover_dtype */
     uint32_t oracle_kind;    /* grover_oracle_kind */
     uint32_t hash_bits;      /* HASH only: width of the zero test, 0 <= hash_bits <= 64 */

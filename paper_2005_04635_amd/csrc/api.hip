@@ -71,16 +71,27 @@ int check_ctx(const grover_ctx *c) { return c ? GROVER_OK : GROVER_E_INVAL; }
 size_t barrier_slot_bytes(int64_t grid) { return size_t(8 * grid + 8) * sizeof(uint64_t); }
 
 // Clear the grid-barrier state (after a wait gave up, the device grid has exited by then; or before the
-// generation tags would wrap).
-hipError_t reset_barrier(grover_ctx *c)
+// generation tags would wrap).  A failure is reported with the name of the call that failed.
+int reset_barrier(grover_ctx *c, const char *why)
 {
-    hipError_t e = hipMemsetAsync(c->sync, 0, sizeof(GridSync), c->stream);
-    if (e == hipSuccess && c->partials && c->partials_grid > 0)
-        e = hipMemsetAsync(c->partials, 0, barrier_slot_bytes(c->partials_grid), c->stream);
-    if (e == hipSuccess)
-        e = hipStreamSynchronize(c->stream);
     c->generation = 0;
-    return e;
+    const std::string w(why);
+    GROVER_HIP(c, hipMemsetAsync(c->sync, 0, sizeof(GridSync), c->stream), (w + ": clearing the barrier words").c_str());
+    if (c->partials && c->partials_grid > 0)
+        GROVER_HIP(c, hipMemsetAsync(c->partials, 0, barrier_slot_bytes(c->partials_grid), c->stream),
+                   (w + ": clearing the barrier slots").c_str());
+    GROVER_HIP(c, hipStreamSynchronize(c->stream), (w + ": synchronising the stream").c_str());
+    return GROVER_OK;
+}
+
+// A residency check must not share the device with work still running on other streams: torch's streams
+// are non-blocking, so a persistent kernel launched on one of them (another context's, or a batch's) is not
+// ordered before this context's stream and may still hold CUs, and a check grid that cannot become
+// resident times out and shrinks.  Waiting for the whole device first makes the check see only itself.
+int quiesce_device(grover_ctx *c, const char *what)
+{
+    GROVER_HIP(c, hipDeviceSynchronize(), what);
+    return GROVER_OK;
 }
 
 // Persistent grid of the fused form.  Every workgroup of a launch must be resident at once, or the first
@@ -102,7 +113,10 @@ int select_persistent_grid(grover_ctx *c, int clock_khz)
     GROVER_HIP(c, hipMemset(c->partials, 0, barrier_slot_bytes(max_grid)), "barrier allocation");
     c->partials_grid = max_grid;
     GROVER_HIP(c, dev_alloc(&c->sync, sizeof(GridSync)), "barrier allocation");
-    GROVER_HIP(c, reset_barrier(c), "barrier reset before the grid check");
+    if (int st = reset_barrier(c, "barrier reset before the grid check"))
+        return st;
+    if (int st = quiesce_device(c, "device synchronise before the grid check"))
+        return st;
     const uint64_t probe_ticks = uint64_t(clock_khz > 0 ? clock_khz : 100000) * 250;  // 0.25 s
     const uint64_t tiles = fused_tiles(c);
     c->block = block;
@@ -119,7 +133,8 @@ int select_persistent_grid(grover_ctx *c, int clock_khz)
         GROVER_HIP(c, hipMemcpy(&gs, c->sync, sizeof(gs), hipMemcpyDeviceToHost), "persistent grid check");
         if (!gs.error)
             return GROVER_OK;
-        GROVER_HIP(c, reset_barrier(c), "barrier reset after a failed grid check");
+        if (int st = reset_barrier(c, "barrier reset after a failed grid check"))
+            return st;
         if (forced > 0)
             break;
     }
@@ -135,7 +150,10 @@ int check_held_team(grover_ctx *c, int clock_khz)
     GROVER_HIP(c, hipMemset(c->partials, 0, barrier_slot_bytes(team)), "barrier allocation");
     c->partials_grid = team;
     GROVER_HIP(c, dev_alloc(&c->sync, sizeof(GridSync)), "barrier allocation");
-    GROVER_HIP(c, reset_barrier(c), "barrier reset before the team check");
+    if (int st = reset_barrier(c, "barrier reset before the team check"))
+        return st;
+    if (int st = quiesce_device(c, "device synchronise before the team check"))
+        return st;
     const uint64_t probe_ticks = uint64_t(clock_khz > 0 ? clock_khz : 100000) * 250;  // 0.25 s
     GROVER_HIP(c, launch_held_iterate(c, 0, probe_ticks, true), "held team check");
     GROVER_HIP(c, hipStreamSynchronize(c->stream), "held team check");
@@ -154,13 +172,15 @@ int run_iterations(grover_ctx *c, uint64_t k)
     case GROVER_FORM_FUSED:
         // barrier generations are tagged modulo 2^32: start again from clear slots before they would wrap
         if (c->generation + k + 2u >= (uint64_t(1) << 32))
-            GROVER_HIP(c, reset_barrier(c), "barrier reset");
+            if (int st = reset_barrier(c, "barrier reset before the generation tags wrap"))
+                return st;
         GROVER_HIP(c, launch_fused_iterate(c, k, c->timeout_ticks), "fused iterate launch");
         break;
     case GROVER_FORM_RESIDENT: GROVER_HIP(c, launch_resident_iterate(c, k), "resident iterate launch"); break;
     case GROVER_FORM_HELD:
         if (c->generation + k + 2u >= (uint64_t(1) << 32))
-            GROVER_HIP(c, reset_barrier(c), "barrier reset");
+            if (int st = reset_barrier(c, "barrier reset before the generation tags wrap"))
+                return st;
         GROVER_HIP(c, launch_held_iterate(c, k, c->timeout_ticks), "held iterate launch");
         break;
     case GROVER_FORM_TWO_PASS: GROVER_HIP(c, launch_twopass_iterate(c, k), "two-pass iterate launch"); break;
@@ -220,6 +240,10 @@ int grover_init(grover_ctx **out, const grover_config *cfg, void *hip_stream, vo
     const uint64_t N = uint64_t(1) << cfg->n;
     if (cfg->m > N)
         return GROVER_E_INVAL;
+    // every kernel moves the state in whole 16-byte vectors: a state smaller than one (complex bfloat16 at
+    // n = 1, two amplitudes in 8 bytes) would never be written or read
+    if (N < elems_per_vec(cfg->dtype))
+        return GROVER_E_UNSUPPORTED;
     // bfloat16 storage and binary32 sums exist in the fused form only
     const bool fused_only = cfg->dtype == GROVER_CBF16 || cfg->accum != GROVER_ACC_F64;
     uint32_t form = cfg->form;
@@ -628,7 +652,8 @@ int grover_sync(grover_ctx *ctx)
         GridSync gs;
         GROVER_HIP(ctx, hipMemcpy(&gs, ctx->sync, sizeof(gs), hipMemcpyDeviceToHost), "barrier status download");
         if (gs.error) {
-            GROVER_HIP(ctx, reset_barrier(ctx), "barrier reset");
+            if (int st = reset_barrier(ctx, "barrier reset after a timed-out wait"))
+                return st;
             return fail(ctx, GROVER_E_TIMEOUT, "a grid barrier wait exceeded its limit; state undefined");
         }
     }

@@ -250,6 +250,8 @@ int select_grid(grover_batch *b, int clock_khz)
     BATCH_HIP(b, balloc(&b->team_sync, size_t(max_grid) * kBatchMaxPhases * sizeof(GridSync)), "batch allocation");
     BATCH_HIP(b, balloc(&b->team_partials, size_t(max_grid) * kBatchMaxPhases * 8 * sizeof(uint64_t)),
               "batch allocation");
+    // work still running on other (non-blocking) streams could hold CUs and starve the check
+    BATCH_HIP(b, hipDeviceSynchronize(), "device synchronise before the grid check");
     const uint64_t probe_ticks = uint64_t(clock_khz > 0 ? clock_khz : 100000) * 250;  // 0.25 s
     for (int pc = per_cu > 1 ? per_cu - 1 : 1; pc >= 1; --pc) {
         b->grid = pc * b->cu_count;

@@ -142,6 +142,8 @@ int select_grid(grover_phase *p, int clock_khz)
     const int max_grid = per_cu * p->cu_count;
     PHASE_HIP(p, palloc(p, &p->sync, size_t(max_grid) * sizeof(PhaseSync)), "phase allocation");
     PHASE_HIP(p, palloc(p, &p->partials, size_t(max_grid) * 32 * sizeof(uint64_t)), "phase allocation");
+    // work still running on other (non-blocking) streams could hold CUs and starve the check
+    PHASE_HIP(p, hipDeviceSynchronize(), "device synchronise before the grid check");
     const uint64_t probe_ticks = uint64_t(clock_khz > 0 ? clock_khz : 100000) * 250;  // 0.25 s
     for (int pc = per_cu > 1 ? per_cu - 1 : 1; pc >= 1; --pc) {
         p->grid = pc * p->cu_count;

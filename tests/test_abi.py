@@ -146,6 +146,18 @@ def test_reduced_precision_needs_the_fused_form(lib, dtype, accum, form):
     assert lib.grover_init(ctypes.byref(ctx), ctypes.byref(cfg), None, None, 0) == -5
 
 
+def test_state_smaller_than_one_vector_is_rejected(lib):
+    """Every kernel moves the state in whole 16-byte vectors; complex bfloat16 at n = 1 (two amplitudes, 8
+    bytes) is less than one and is rejected before any device work; every other type fits at n = 1."""
+    from paper_2005_04635_amd.grover import grover_config
+
+    cfg = grover_config()
+    cfg.n, cfg.dtype, cfg.form = 1, 3, 1
+    ctx = ctypes.c_void_p()
+    assert lib.grover_init(ctypes.byref(ctx), ctypes.byref(cfg), None, None, 0) == -5
+    assert not ctx.value
+
+
 def test_bf16_host_conversions_round_once_to_nearest_even():
     import numpy as np
 

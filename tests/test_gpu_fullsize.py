@@ -236,3 +236,57 @@ def test_n28_blocked_gate_iterations(G, orc):
     for s in range(0, un.size, 1 << 24):
         assert np.max(np.abs(un[s:s + (1 << 24)].astype(np.complex128) - b)) <= 1e-5
     g.close()
+
+
+def two_class_check(got: np.ndarray, mask: np.ndarray, a: float, b: float, tol: float) -> None:
+    """Every marked amplitude bitwise equal to every other, likewise every unmarked one, and both values
+    within tol of the oracle's two-class values (a, b); chunked so that the 2 and 4 GiB states stay cheap."""
+    view = np.uint64 if got.dtype == np.complex64 else np.complex128
+    gm = got[mask]
+    assert np.all(gm.view(view) == gm.view(view)[0])
+    assert abs(complex(gm[0]) - a) <= tol
+    idx = np.flatnonzero(~mask[:64])[0]
+    ref = got[idx:idx + 1].view(view)[0]
+    assert abs(complex(got[idx]) - b) <= tol
+    chunk = 1 << 24
+    for s in range(0, got.size, chunk):
+        part = got[s:s + chunk]
+        keep = ~mask[s:s + chunk]
+        assert np.all(part[keep].view(view) == ref), s
+
+
+@pytest.mark.parametrize("dtype", ["c64", "c128"])
+def test_n28_two_pass_form(G, orc, dtype):
+    """The plain form as the benchmark times it (n = 28, the hash workload's marks; its sum and update
+    kernels stride over 128 or 512 vectors per thread): three iterations from the uniform state against the
+    oracle's two-class values, with each class bitwise constant."""
+    w = workloads.HASH_N28
+    g = G.Grover(w.n, dtype, hash_seed=w.hash_seed, hash_bits=w.hash_bits, m=w.m, form="two_pass")
+    marks = g.marked()
+    g.iterate(3)
+    got = g.read_state()
+    mask = np.zeros(1 << w.n, dtype=bool)
+    mask[marks.astype(np.int64)] = True
+    a, b = orc.two_class(w.n, w.m, 3)
+    two_class_check(got, mask, a, b, 1e-5 if dtype == "c64" else 1e-12)
+    g.close()
+
+
+def test_n28_single_qubit_gate_iteration(G, orc):
+    """The per-qubit gate path at n = 28 (58 passes, each thread over 128 butterfly pairs): one conventional
+    iteration from the uniform state against the oracle's two-class values.  Rounding in the passes depends
+    on the index's bits, so the classes are checked by value, not bitwise."""
+    w = workloads.HASH_N28
+    g = G.Grover(w.n, w.dtype, hash_seed=w.hash_seed, hash_bits=w.hash_bits, m=w.m, form="fused")
+    marks = g.marked()
+    g.reset().gate_iterate(1)
+    got = g.read_state()
+    mask = np.zeros(1 << w.n, dtype=bool)
+    mask[marks.astype(np.int64)] = True
+    a, b = orc.two_class(w.n, w.m, 1)
+    assert np.max(np.abs(got[mask].astype(np.complex128) - a)) <= 1e-5
+    chunk = 1 << 24
+    for s in range(0, got.size, chunk):
+        part = got[s:s + chunk][~mask[s:s + chunk]]
+        assert np.max(np.abs(part.astype(np.complex128) - b)) <= 1e-5, s
+    g.close()

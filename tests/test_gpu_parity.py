@@ -243,6 +243,37 @@ def test_gate_level_path_matches_oracle(G, orc, n, dtype):
     g2.close()
 
 
+@pytest.mark.parametrize("dtype", ["c128", "c64", "f64"])
+def test_two_pass_form_where_its_grid_wraps(G, orc, dtype):
+    """The plain form caps its grid at 2048 x 256 threads, so at n = 22 every thread of its sum and update
+    kernels visits 2 (f64, c64) or 8 (c128) vectors: element-wise parity there, several iterations."""
+    n = 22
+    marks = workloads.distinct_marks(n, 5, seed=2222)
+    psi0 = start_state(n, dtype, seed=2200)
+    g = G.Grover(n, dtype, marks=marks, form="two_pass").write_state(psi0)
+    want = as_c128(psi0)
+    for k in (1, 3):
+        g.iterate(k)
+        orc.iterate(want, marks, k)
+        assert_close(g.read_state(), want, dtype, f"two_pass n={n} k={k}")
+    g.close()
+
+
+@pytest.mark.parametrize("dtype", ["c64", "c128"])
+def test_single_qubit_gate_passes_where_their_grid_wraps(G, orc, dtype):
+    """The single-qubit passes of the gate-level path cap their grid at 4096 x 256 threads: at n = 23 each
+    thread visits 4 butterfly pairs per pass.  H^n and one conventional iteration, element by element."""
+    n = 23
+    marks = workloads.distinct_marks(n, 2, seed=2323)
+    psi0 = start_state(n, dtype, seed=2300)
+    g = G.Grover(n, dtype, marks=marks, form="fused").write_state(psi0)
+    g.hadamard_all()
+    assert_close(g.read_state(), orc.hadamard_all(as_c128(psi0)), dtype, "H^n")
+    g.write_state(psi0).gate_iterate(1)
+    assert_close(g.read_state(), orc.gate_iterate(as_c128(psi0), marks, 1), dtype, "gate iterate")
+    g.close()
+
+
 # ----------------------------------------------------------------------------------- measurement
 @pytest.mark.parametrize("n,dtype", [(1, "c64"), (4, "f64"), (12, "c64"), (13, "c128"), (18, "c64")])
 def test_sampler_bit_exact_on_identical_input(G, orc, n, dtype):

@@ -127,6 +127,31 @@ def test_bf16_sampler_and_norm(G, orc, accum):
     g.close()
 
 
+@pytest.mark.parametrize("n", [2, 3])
+def test_bf16_smallest_states(G, orc, n):
+    """One and two 16-byte vectors of complex bfloat16 (N = 4, 8): the fill, the iteration, the norm and the
+    sampler against the oracle.  Every sum here is exact in binary64 (at most 8 values of 8 significant bits),
+    so the device's state equals the oracle's stored two-class iteration bit for bit, every iteration."""
+    g = G.Grover(n, "cbf16", marks=[1], form="fused")
+    mask = np.zeros(1 << n, dtype=bool)
+    mask[1] = True
+    u = workloads.uniforms_u53(77 + n, 4000)
+    for k in range(0, 5):
+        got = g.read_state().astype(np.complex128)
+        a, b = orc.two_class_stored(n, 1, k, BITS["cbf16"])
+        assert np.all(got[mask] == a) and np.all(got[~mask] == b), (n, k, got, a, b)
+        assert abs(g.norm() - orc.norm(got)) < 1e-15
+        assert np.array_equal(g.sample(u.size, u53=u), orc.sample(got, u)), (n, k)
+        g.iterate(1)
+    g.close()
+
+
+def test_bf16_one_qubit_is_unsupported(G):
+    with pytest.raises(G.GroverError) as e:
+        G.Grover(1, "cbf16", marks=[1], form="fused")
+    assert e.value.status == -5
+
+
 def test_bf16_gate_path_is_unsupported(G):
     g = G.Grover(8, "cbf16", marks=[1])
     with pytest.raises(G.GroverError) as e:
