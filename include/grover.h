@@ -206,9 +206,31 @@ void grover_destroy(grover_ctx *ctx);
 
 /* grover_status_str — static text for a status code.  grover_last_error — the last failure message on ctx
  * (empty string when none); with ctx NULL, the message of the last grover_init failure on the calling
- * thread that got past validation, else a static message. */
+ * thread that got past validation (or of the last failed grover_iterate_static call), else a static
+ * message. */
 const char *grover_status_str(int status);
 const char *grover_last_error(const grover_ctx *ctx);
+
+/* grover_iterate_static — for callers that cannot allocate device memory (code under HIP graph capture,
+ * tight serving loops, harnesses that forbid hipMalloc): k iterations of the proposed method exactly as
+ * grover_iterate computes them on a GROVER_FORM_FUSED context with binary64 sums (the same kernel, grid and
+ * order of additions, so the same bits), on a state and a marked list the caller holds, with no context.
+ * The grid barrier's memory is a fixed array inside the library, 17472 bytes per GPU (barrier slots for a
+ * persistent grid of at most 256 workgroups), held until the process ends; nothing is allocated or freed.
+ *   hip_stream  stream to enqueue on (NULL = default); the device is the current one.
+ *   state_dev   device, 2^n amplitudes of `dtype` (grover_dtype), 16-byte aligned; updated in place.
+ *   n           1 .. 34 (GROVER_CBF16: from 2).
+ *   marks_dev   device, m strictly increasing indices < 2^n (checked on the device: otherwise the state is
+ *               left untouched and the status word reads 2); may be NULL when m = 0.
+ *   k           iterations, k < 2^32 - 2 (0: nothing is iterated; the marked list is still checked).
+ *   status_dev  optional device uint32, written after the iterations: 0 = done, 1 = a grid-barrier wait
+ *               exceeded its 10 s limit (state undefined), 2 = marked list rejected (state untouched).
+ * Host-side validation failures return GROVER_E_INVAL / GROVER_E_UNSUPPORTED before any device work, with
+ * a message in grover_last_error(NULL).  Asynchronous.  Every call on one GPU shares that GPU's barrier
+ * memory and clears it first: calls whose device work overlaps (on different streams) race and must not be
+ * made. */
+int grover_iterate_static(void *hip_stream, void *state_dev, uint32_t n, uint32_t dtype, const uint64_t *marks_dev,
+                          uint64_t m, uint64_t k, uint32_t *status_dev);
 
 /* ------------------------------------------------------------------------------------- batches
  * Many independent searches advanced together (Algorithm 5 per instance, from the uniform superposition of

@@ -191,6 +191,13 @@ int run_iterations(grover_ctx *c, uint64_t k)
 
 }  // namespace
 
+// The message of the last grover_init (or grover_iterate_static) failure on this thread.
+thread_local std::string init_error;
+
+namespace grover {
+void set_thread_error(const std::string &msg) { init_error = msg; }
+}  // namespace grover
+
 extern "C" {
 
 uint64_t grover_optimal_iterations(uint32_t n, uint64_t m)
@@ -216,8 +223,6 @@ const char *grover_status_str(int status)
     }
 }
 
-// The message of the last grover_init failure on this thread (its context is gone by then).
-thread_local std::string init_error;
 
 const char *grover_last_error(const grover_ctx *ctx)
 {

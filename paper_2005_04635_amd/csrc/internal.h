@@ -412,6 +412,26 @@ uint64_t fused_tiles(const grover_ctx *c);
 uint64_t fused_temporal_tiles(const grover_ctx *c);
 // `check`: launch the code-identical instantiation reserved for the residency check.
 hipError_t launch_fused_iterate(grover_ctx *c, uint64_t k, uint64_t timeout_ticks, bool check = false);
+// Tiles of the fused kernel over a state of N amplitudes of the given type.
+uint64_t fused_tiles_of(uint32_t dtype, uint64_t N);
+// The fused kernel (binary64 sums, the default access split) on barrier memory the caller provides:
+// slots [2][grid][4] + [2][4] tagged words and a GridSync, all zero, generations from 1.
+struct FusedExternal {
+    void *state;
+    uint32_t dtype;
+    uint64_t N;
+    const uint64_t *marks;
+    uint64_t m;
+    uint64_t k;
+    int grid;
+    uint64_t *slots;
+    GridSync *sync;
+    uint64_t timeout_ticks;
+    hipStream_t stream;
+};
+hipError_t launch_fused_external(const FusedExternal &x);
+// The message the last failing grover_init or grover_iterate_static left on the calling thread.
+void set_thread_error(const std::string &msg);
 
 hipError_t launch_resident_iterate(grover_ctx *c, uint64_t k);
 

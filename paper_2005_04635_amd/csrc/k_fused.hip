@@ -397,6 +397,15 @@ __global__ __launch_bounds__(kBlock) void fused_iterate_kernel(FusedArgs a)
     __shared__ uint32_t slow_tiles[kMarkWords];
     __shared__ typename T::vec held[(kHeldTiles - 1) * kTile];  // held tiles but the last, in LDS
     typename T::vec rt[kUnroll];                                 // the last held tile, in registers
+    // A launch enqueued behind a failure (a wait that gave up, or input rejected on the device) leaves the
+    // state as it is; the error word is cleared before the next launch that should run.  Thread 0 decides
+    // for the whole workgroup (the word may change while its threads read it); grid_sum writes sh.abort
+    // again only after its first workgroup barrier, which every thread reaches after reading it here.
+    if (threadIdx.x == 0)
+        sh.abort = __hip_atomic_load(&a.sync->error, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0u;
+    __syncthreads();
+    if (sh.abort)
+        return;
     // Table of this workgroup's tiles that hold marked amplitudes, built once per launch.
     const uint64_t ntiles = (a.nvec + kTile - 1) / kTile;
     const uint64_t cnt = blockIdx.x < ntiles ? (ntiles - blockIdx.x + gridDim.x - 1) / gridDim.x : 0;
@@ -407,7 +416,7 @@ __global__ __launch_bounds__(kBlock) void fused_iterate_kernel(FusedArgs a)
         __syncthreads();
         for (uint64_t q = threadIdx.x; q < a.m; q += kBlock) {
             const uint64_t t = a.marks[q] / T::EPV / kTile;
-            if (t % gridDim.x == blockIdx.x) {
+            if (t < ntiles && t % gridDim.x == blockIdx.x) {
                 const uint64_t j = t / gridDim.x;
                 atomicOr(&slow_tiles[j >> 5], 1u << (j & 31));
             }
@@ -532,6 +541,35 @@ hipError_t fused_configure(grover_ctx *c, int *per_cu, int *block, int64_t *forc
         }
     }
     return hipSuccess;
+}
+
+uint64_t fused_tiles_of(uint32_t dtype, uint64_t N)
+{
+    const uint64_t nvec = N / elems_per_vec(dtype);
+    return (nvec + kTile - 1) / kTile;
+}
+
+hipError_t launch_fused_external(const FusedExternal &x)
+{
+    const uint64_t state_bytes = x.N * elem_bytes(x.dtype);
+    const bool temporal = state_bytes <= kTemporalBytes;
+    const void *fn = kernel_for<false>(x.dtype, GROVER_ACC_F64, temporal);
+    if (!fn || x.grid < 1)
+        return hipErrorInvalidValue;
+    FusedArgs a;
+    a.state = x.state;
+    a.nvec = x.N / elems_per_vec(x.dtype);
+    a.N = double(x.N);
+    a.marks = x.marks;
+    a.m = x.m;
+    a.partials = x.slots;
+    a.sync = x.sync;
+    a.iters = x.k;
+    a.gen0 = 0;
+    a.timeout_ticks = x.timeout_ticks;
+    a.temporal_tiles = kTemporalBytes / (uint64_t(x.grid) * kTile * 16u);
+    void *args[] = {&a};
+    return hipLaunchCooperativeKernel(fn, dim3(x.grid), dim3(kBlock), args, 0, x.stream);
 }
 
 uint64_t fused_tiles(const grover_ctx *c)

@@ -129,7 +129,7 @@ EXPORTS = [
     "grover_sample", "grover_sample_u53", "grover_norm", "grover_read_state", "grover_write_state",
     "grover_state_device", "grover_marked", "grover_sync", "grover_query", "grover_optimal_iterations",
     "grover_destroy", "grover_status_str", "grover_last_error",
-    "grover_gate_iterate_blocked", "grover_apply_hadamard_all_blocked",
+    "grover_gate_iterate_blocked", "grover_apply_hadamard_all_blocked", "grover_iterate_static",
     "grover_batch_init", "grover_batch_set_tiling", "grover_batch_tune", "grover_batch_capture",
     "grover_batch_run", "grover_batch_sync", "grover_batch_state", "grover_batch_read_state",
     "grover_batch_query", "grover_batch_destroy", "grover_batch_last_error",
@@ -177,6 +177,7 @@ def load(path: str = LIB_PATH):
             "grover_query": (i32, [P, i32, ctypes.POINTER(ctypes.c_int64)]),
             "grover_optimal_iterations": (u64, [u32, u64]),
             "grover_destroy": (None, [P]),
+            "grover_iterate_static": (i32, [P, P, u32, u32, P, u64, u64, P]),
             "grover_status_str": (ctypes.c_char_p, [i32]),
             "grover_last_error": (ctypes.c_char_p, [P]),
             "grover_batch_init": (i32, [ctypes.POINTER(P), ctypes.POINTER(grover_batch_config), P]),
@@ -307,6 +308,12 @@ def grover_optimal_iterations(n: int, m: int) -> int:
 def grover_destroy(ctx) -> None:
     if ctx:
         load().grover_destroy(ctx)
+
+
+def grover_iterate_static(hip_stream: int, state_dev: int, n: int, dtype: int, marks_dev: int, m: int, k: int,
+                          status_dev: int = 0) -> None:
+    _check(None, load().grover_iterate_static(hip_stream or None, state_dev or None, n, dtype, marks_dev or None, m,
+                                              k, status_dev or None))
 
 
 def grover_status_str(status: int) -> str:
