@@ -63,6 +63,8 @@ def load(path: str = _LIB):
             "orc_two_class": (None, [u32, u64, u64, pd, pd]),
             "orc_round_to_bits": (dbl, [dbl, ctypes.c_int]),
             "orc_two_class_stored": (None, [u32, u64, u64, ctypes.c_int, pd, pd]),
+            "orc_two_class_stored_update": (None, [u32, u64, u64, ctypes.c_int, ctypes.c_int, pd, pd]),
+            "orc_grover_iterate_stored": (None, [u32, pd, pu, u64, u64, ctypes.c_int, ctypes.c_int]),
             "orc_sample": (ctypes.c_int, [u32, pd, pu, u64, pu]),
             "orc_uniforms_u53": (None, [u64, u64, pu]),
             "orc_phase_oracle": (None, [pd, pu, u64, dbl]),
@@ -205,6 +207,18 @@ class Oracle:
         a, b = ctypes.c_double(), ctypes.c_double()
         self.lib.orc_two_class_stored(n, m, iters, p, ctypes.byref(a), ctypes.byref(b))
         return a.value, b.value
+
+    def two_class_stored_update(self, n: int, m: int, iters: int, p_store: int, p_update: int):
+        a, b = ctypes.c_double(), ctypes.c_double()
+        self.lib.orc_two_class_stored_update(n, m, iters, p_store, p_update, ctypes.byref(a), ctypes.byref(b))
+        return a.value, b.value
+
+    def iterate_stored(self, psi: np.ndarray, marks, iters: int, p_store: int, p_update: int) -> np.ndarray:
+        """Iterations with the state stored at p_store bits and the update computed at p_update bits (in
+        place); psi must already hold values representable at p_store bits."""
+        k = _marks(marks)
+        self.lib.orc_grover_iterate_stored(_n_of(psi), _pd(_state(psi)), _pu(k), k.size, iters, p_store, p_update)
+        return psi
 
     def sample(self, psi: np.ndarray, u53: np.ndarray) -> np.ndarray:
         u = np.ascontiguousarray(np.asarray(u53, dtype=np.uint64))

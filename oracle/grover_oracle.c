@@ -305,6 +305,52 @@ void orc_two_class_stored(uint32_t n, uint64_t m, uint64_t iters, int p, double 
     *b_out = b;
 }
 
+/* The two-class form with a reduced-precision update as well as reduced-precision storage: the new
+ * amplitude is computed at p_update significand bits from 2s/N rounded to p_update bits, then stored at
+ * p_store bits,
+ *   mean2 = fl_u(2 s / N),  a <- fl_s(fl_u(mean2 + a)),  b <- fl_s(fl_u(mean2 - b)),
+ * with s = (N - M) b - M a in binary64.  p_update = 53 is orc_two_class_stored (the update in binary64);
+ * p_update = 24 is an update in binary32: the exact difference of two binary32 values rounded to binary64
+ * and then to binary32 equals its single rounding to binary32, since 53 >= 2 * 24 + 2. */
+void orc_two_class_stored_update(uint32_t n, uint64_t m, uint64_t iters, int p_store, int p_update, double *a_out,
+                                 double *b_out)
+{
+    const double N = ldexp(1.0, (int)n);
+    double a = orc_round_to_bits(orc_uniform_amplitude(n), p_store), b = a;
+    for (uint64_t it = 0; it < iters; ++it) {
+        const double s = (N - (double)m) * b - (double)m * a;
+        const double mean2 = orc_round_to_bits((s * 2.0) / N, p_update);
+        a = orc_round_to_bits(orc_round_to_bits(mean2 + a, p_update), p_store);
+        b = orc_round_to_bits(orc_round_to_bits(mean2 - b, p_update), p_store);
+    }
+    *a_out = a;
+    *b_out = b;
+}
+
+/* Algorithm 5's loop body on a state whose amplitudes are stored at p_store significand bits, with the
+ * second loop of Algorithm 4 computed at p_update bits: the oracle (Algorithm 3; a negation is exact), the
+ * sum of the first loop in binary64 (pairwise), then for every basis state
+ *   c_i <- fl_s(fl_u(fl_u(2 s / N) - c_i))
+ * for the real and the imaginary part.  With p_store = p_update = 53 this is orc_grover_iterate; p_update
+ * = 53 is an update in binary64 rounded once to the storage, p_update = 24 an update in binary32.  psi
+ * must hold values representable at p_store bits (the state as stored). */
+void orc_grover_iterate_stored(uint32_t n, double *psi, const uint64_t *k, uint64_t m, uint64_t iters, int p_store,
+                               int p_update)
+{
+    const uint64_t N = (uint64_t)1 << n;
+    for (uint64_t it = 0; it < iters; ++it) {
+        orc_oracle(psi, k, m);
+        double re, im;
+        pairwise_sum(psi, 0, N, &re, &im);
+        const double mr = orc_round_to_bits((re * 2.0) / ldexp(1.0, (int)n), p_update);
+        const double mi = orc_round_to_bits((im * 2.0) / ldexp(1.0, (int)n), p_update);
+        for (uint64_t i = 0; i < N; ++i) {
+            psi[2 * i] = orc_round_to_bits(orc_round_to_bits(mr - psi[2 * i], p_update), p_store);
+            psi[2 * i + 1] = orc_round_to_bits(orc_round_to_bits(mi - psi[2 * i + 1], p_update), p_store);
+        }
+    }
+}
+
 /* Measurement (Background, step 6) by inverse transform over an integer CDF:
  *   p_i = Re^2 + Im^2 (binary64),  q_i = floor(p_i * 2^62),  Q_i = q_0 + ... + q_i,
  *   t_j = floor(U_j * Q_{N-1} / 2^53) for a 53-bit uniform integer U_j,

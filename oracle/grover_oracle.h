@@ -29,6 +29,10 @@ double orc_norm(uint32_t n, const double *psi);
 void orc_two_class(uint32_t n, uint64_t m, uint64_t iters, double *a_out, double *b_out);
 double orc_round_to_bits(double x, int p);
 void orc_two_class_stored(uint32_t n, uint64_t m, uint64_t iters, int p, double *a_out, double *b_out);
+void orc_two_class_stored_update(uint32_t n, uint64_t m, uint64_t iters, int p_store, int p_update, double *a_out,
+                                 double *b_out);
+void orc_grover_iterate_stored(uint32_t n, double *psi, const uint64_t *k, uint64_t m, uint64_t iters, int p_store,
+                               int p_update);
 int orc_sample(uint32_t n, const double *psi, const uint64_t *u53, uint64_t shots, uint64_t *out);
 void orc_uniforms_u53(uint64_t seed, uint64_t shots, uint64_t *out);
 void orc_phase_oracle(double *psi, const uint64_t *k, uint64_t m, double phi);

@@ -69,6 +69,18 @@ MUTANTS = [
      "const double r = nearbyint(ldexp(m, p - 1));"),
     ("round_to_bits truncates", "const double r = nearbyint(ldexp(m, p));", "const double r = trunc(ldexp(m, p));"),
     ("stored two-class skips rounding b", "b = orc_round_to_bits(mean2 - b, p);", "b = mean2 - b;"),
+    ("two-class update model keeps the mean in binary64",
+     "const double mean2 = orc_round_to_bits((s * 2.0) / N, p_update);", "const double mean2 = (s * 2.0) / N;"),
+    ("stored update keeps the mean in binary64",
+     "const double mr = orc_round_to_bits((re * 2.0) / ldexp(1.0, (int)n), p_update);",
+     "const double mr = (re * 2.0) / ldexp(1.0, (int)n);"),
+    ("stored update never rounds to the storage",
+     "psi[2 * i] = orc_round_to_bits(orc_round_to_bits(mr - psi[2 * i], p_update), p_store);",
+     "psi[2 * i] = orc_round_to_bits(mr - psi[2 * i], p_update);"),
+    ("stored iteration skips the oracle", "        orc_oracle(psi, k, m);\n        double re, im;",
+     "        double re, im;"),
+    ("stored update conjugates the mean", "orc_round_to_bits(mi - psi[2 * i + 1], p_update)",
+     "orc_round_to_bits(-mi - psi[2 * i + 1], p_update)"),
     ("phase diffusion conjugates its phase", "const orc_c e = c_expi(theta);", "const orc_c e = c_expi(-theta);"),
     ("phase oracle conjugates its phase", "const orc_c e = c_expi(phi);", "const orc_c e = c_expi(-phi);"),
     ("phase diffusion mean over N/2", "const orc_c mean = {re / ldexp(1.0, (int)n), im / ldexp(1.0, (int)n)};\n    const orc_c e",
@@ -119,6 +131,10 @@ def battery(orc) -> None:
     pins.test_round_to_bits_bfloat16_brute_force(orc)
     pins.test_two_class_stored_at_53_bits_is_two_class(orc, 10, 1, 25)
     pins.test_two_class_stored_binary32_matches_float32_full_state(orc)
+    pins.test_iterate_stored_at_53_bits_is_the_iteration(orc, 7, 3, 5)
+    pins.test_two_class_stored_update_at_53_bits(orc, 24)
+    for update32 in (False, True):
+        pins.test_stored_iteration_matches_float32_arithmetic(orc, 12, 2, 30, update32)
     phase.test_phases_at_pi_are_the_standard_iteration(orc)
     phase.test_fig2_through_the_generalized_iteration(orc)
     phase.test_dense_matrices_and_torch_autograd(orc, 5, [1, 30], 5, 2)

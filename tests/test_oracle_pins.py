@@ -343,6 +343,66 @@ def test_two_class_stored_binary32_matches_float32_full_state(orc):
     assert abs(psi[~mask][0].real - b) <= 2 * 2.0 ** -24 * abs(b)
 
 
+# ------------------------------------------------- stored amplitudes, update in binary64 or in binary32
+@pytest.mark.parametrize("n,m,k", [(7, 3, 5), (9, 1, 12)])
+def test_iterate_stored_at_53_bits_is_the_iteration(orc, n, m, k):
+    """Storage and update at 53 bits: the stored iteration is Algorithm 5's loop itself, bit for bit, on a
+    random complex state (so the imaginary parts are exercised too)."""
+    marks = workloads.distinct_marks(n, m, seed=n + 100)
+    psi = workloads.random_state(n, seed=n + 200)
+    a = orc.iterate(psi.copy(), marks, k)
+    b = orc.iterate_stored(psi.copy(), marks, k, 53, 53)
+    assert np.array_equal(a.view(np.uint64), b.view(np.uint64))
+
+
+@pytest.mark.parametrize("p", [8, 24, 53])
+def test_two_class_stored_update_at_53_bits(orc, p):
+    """An update at 53 bits is the stored two-class iteration with a binary64 update."""
+    for n, m, k in [(10, 1, 25), (16, 3, 100)]:
+        assert orc.two_class_stored_update(n, m, k, p, 53) == orc.two_class_stored(n, m, k, p)
+
+
+def float32_run(n: int, marks, k: int, update32: bool) -> np.ndarray:
+    """numpy's own arithmetic: the uniform state 2^(-n/2) (even n: exact) stored as complex64; per iteration
+    the marked amplitudes negated, the sum S of the stored values taken in binary64, and every amplitude
+    replaced by 2S/N - c, either in binary64 and then cast to complex64, or in complex64 arithmetic from
+    2S/N cast to complex64 (round to nearest even, each part)."""
+    assert n % 2 == 0
+    N = 1 << n
+    idx = np.asarray(marks, dtype=np.int64)
+    psi = np.full(N, np.complex64(2.0 ** (-n // 2)))
+    for _ in range(k):
+        psi[idx] = -psi[idx]
+        mean2 = 2.0 * np.sum(psi.astype(np.complex128)) / N
+        if update32:
+            psi = np.complex64(mean2) - psi
+        else:
+            psi = (mean2 - psi.astype(np.complex128)).astype(np.complex64)
+    return psi
+
+
+@pytest.mark.parametrize("update32", [False, True])
+@pytest.mark.parametrize("n,m,k", [(12, 2, 30), (10, 1, 25)])
+def test_stored_iteration_matches_float32_arithmetic(orc, n, m, k, update32):
+    """From the uniform state every stored value is a binary32 number and the state has two values, so
+    every partial sum of any order (numpy's and the oracle's pairwise one) is an integer combination of the
+    two that fits 53 bits: all sums are exact and the oracle must reproduce numpy's float32 run bit for bit,
+    with the update in binary64 (p_update = 53) or in binary32 (p_update = 24); its two-class form too.  The
+    two updates end at least one binary32 ulp apart, so the pin tells them apart."""
+    N = 1 << n
+    marks = workloads.distinct_marks(n, m, seed=3 * n + m)
+    want = float32_run(n, marks, k, update32).astype(np.complex128)
+    pu = 24 if update32 else 53
+    got = orc.iterate_stored(np.full(N, 2.0 ** (-n // 2) + 0j), marks, k, 24, pu)
+    assert np.array_equal(got.view(np.uint64), want.view(np.uint64))
+    a, b = orc.two_class_stored_update(n, m, k, 24, pu)
+    mask = np.zeros(N, dtype=bool)
+    mask[marks.astype(np.int64)] = True
+    assert np.all(want[mask] == a) and np.all(want[~mask] == b)
+    other = float32_run(n, marks, k, not update32).astype(np.complex128)
+    assert np.max(np.abs(other - want)) >= 2.0 ** -24 * np.max(np.abs(want))
+
+
 # ------------------------------------------------------------------------------------ random numbers
 def test_splitmix64_published_vectors(orc):
     with open(os.path.join(GOLDEN, "splitmix64_vectors.txt")) as f:
