@@ -53,12 +53,20 @@ typedef enum grover_dtype {
 } grover_dtype;
 
 /* Precision of the sum S = sum_i s_i c_i that the mean is taken from (per-thread accumulation and the
- * reduction tree above it).  The update c' = 2S/N - s c is always computed in binary64. */
+ * reduction tree above it).  The precision of the update c' = 2S/N - s c is grover_update. */
 typedef enum grover_accum {
     GROVER_ACC_F64 = 0,       /* binary64 (default) */
     GROVER_ACC_F32 = 1,       /* binary32; fused form only */
     GROVER_ACC_F32_KAHAN = 2  /* binary32 with Kahan-compensated per-thread sums; fused form only */
 } grover_accum;
+
+/* Precision of the element update c' = 2S/N - s c (Algorithm 4's second loop). */
+typedef enum grover_update {
+    GROVER_UPDATE_F64 = 0, /* computed in binary64 from 2S/N and rounded once to the storage type (default) */
+    GROVER_UPDATE_F32 = 1  /* complex64 storage with binary64 sums only: 2S/N rounded to binary32, then each
+                              part of c' = fl32(2S/N) - s c is one binary32 operation; forms FUSED, RESIDENT,
+                              HELD (AUTO picks among them as for GROVER_UPDATE_F64) */
+} grover_update;
 
 typedef enum grover_oracle_kind {
     GROVER_ORACLE_LIST = 0, /* marked set given as an explicit list of indices (Algorithm 3's k[]) */
@@ -94,15 +102,15 @@ typedef struct grover_config {
     uint32_t form;           /* grover_form */
     uint32_t flags;          /* reserved, must be 0 */
     uint32_t accum;          /* grover_accum */
-    uint32_t reserved;       /* must be 0 */
+    uint32_t update;         /* grover_update */
 } grover_config;
 
 typedef struct grover_ctx grover_ctx;
 
 /* grover_init — create a context and prepare the initial state (Algorithm 5: psi = H^n |0>).
  *   out         receives the new context (set to NULL on failure).
- *   cfg         problem description, validated: n range, dtype/form/kind/accum values, flags == 0,
- *               reserved == 0, the form supports the dtype and accum (else GROVER_E_UNSUPPORTED), marked
+ *   cfg         problem description, validated: n range, dtype/form/kind/accum/update values, flags == 0,
+ *               the form supports the dtype, accum and update (else GROVER_E_UNSUPPORTED), marked
  *               indices distinct and < N, m <= N; for HASH the predicate is evaluated on the device over
  *               all N indices, its hits compacted into the marked list, and GROVER_E_PREDICATE returned
  *               when their number differs from cfg->m.
@@ -235,9 +243,9 @@ int grover_iterate_static(void *hip_stream, void *state_dev, uint32_t n, uint32_
 /* ------------------------------------------------------------------------------------- batches
  * Many independent searches advanced together (Algorithm 5 per instance, from the uniform superposition of
  * Algorithm 5's first step, with the oracle of Algorithm 3 and the inversion of Eq. 2 / Algorithm 4), in
- * one persistent launch.  Instance states are GROVER_C64 (interleaved float re, im; the update and the sums
- * are computed in binary64 and rounded once per amplitude and iteration, as in the single-state
- * GROVER_C64 + GROVER_ACC_F64 context).  Instance i has n[i] qubits (1 <= n[i] <= 24), m[i] marked
+ * one persistent launch.  Instance states are GROVER_C64 (interleaved float re, im; the sums are computed in
+ * binary64 and the update in the precision cfg->update names, as in the single-state GROVER_C64 +
+ * GROVER_ACC_F64 context with that update).  Instance i has n[i] qubits (1 <= n[i] <= 24), m[i] marked
  * indices and iterations[i] iterations (k_opt(n[i], m[i]) when `iterations` is NULL).
  *
  * How the device divides the work is the tiling (split_n, team, resident):
@@ -263,7 +271,8 @@ typedef struct grover_batch_config {
     const uint64_t *iterations;  /* host, count entries, or NULL for k_opt(n[i], m[i]) */
     uint32_t dtype;              /* GROVER_C64 (other types: GROVER_E_UNSUPPORTED) */
     uint32_t flags;              /* must be 0 */
-    uint64_t reserved;           /* must be 0 */
+    uint32_t update;             /* grover_update: the element update in binary64 (default) or binary32 */
+    uint32_t reserved;           /* must be 0 */
 } grover_batch_config;
 
 /* grover_batch_init — validate cfg, copy its arrays, allocate every instance's state (each 256-byte

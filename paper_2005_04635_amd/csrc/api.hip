@@ -240,7 +240,7 @@ int grover_init(grover_ctx **out, const grover_config *cfg, void *hip_stream, vo
         return GROVER_E_INVAL;
     if (cfg->n < 1 || cfg->n > kMaxQubits || cfg->dtype > GROVER_CBF16 || cfg->oracle_kind > GROVER_ORACLE_HASH ||
         cfg->form > GROVER_FORM_HELD || cfg->flags != 0 || cfg->hash_bits > 64 ||
-        cfg->accum > GROVER_ACC_F32_KAHAN || cfg->reserved != 0)
+        cfg->accum > GROVER_ACC_F32_KAHAN || cfg->update > GROVER_UPDATE_F32)
         return GROVER_E_INVAL;
     const uint64_t N = uint64_t(1) << cfg->n;
     if (cfg->m > N)
@@ -267,6 +267,11 @@ int grover_init(grover_ctx **out, const grover_config *cfg, void *hip_stream, vo
         return GROVER_E_UNSUPPORTED;
     if (cfg->oracle_kind == GROVER_ORACLE_HASH && cfg->m > kHashMarkCap)
         return GROVER_E_UNSUPPORTED;
+    // the binary32 update exists for complex64 storage with binary64 sums, in the fused, one-workgroup and
+    // held forms (the plain two-pass comparator stays binary64)
+    if (cfg->update == GROVER_UPDATE_F32 &&
+        (cfg->dtype != GROVER_C64 || cfg->accum != GROVER_ACC_F64 || form == GROVER_FORM_TWO_PASS))
+        return GROVER_E_UNSUPPORTED;
 
     grover_ctx *c = new (std::nothrow) grover_ctx;
     if (!c)
@@ -277,6 +282,7 @@ int grover_init(grover_ctx **out, const grover_config *cfg, void *hip_stream, vo
         c->N = N;
         c->dtype = cfg->dtype;
         c->accum = cfg->accum;
+        c->update = cfg->update;
         c->form = form;
         c->kind = cfg->oracle_kind;
         c->stream = static_cast<hipStream_t>(hip_stream);

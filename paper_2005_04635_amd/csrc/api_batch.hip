@@ -35,6 +35,7 @@ struct grover_batch {
     uint64_t qoff[kBatchMaxPhases + 1] = {};
     uint32_t phase_team[kBatchMaxPhases] = {}, phase_resident[kBatchMaxPhases] = {};
     uint32_t streams = 1;  // 0 when the tiling holds every state on chip
+    uint32_t update = 0;   // grover_update of the element update
     uint64_t timeout_ticks = 0;
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
@@ -109,6 +110,7 @@ BatchLaunch launch_of(const grover_batch *b, uint64_t timeout_ticks)
     }
     L.nphases = b->nphases;
     L.streams = b->streams;
+    L.update = b->update;
     L.heads = b->heads;
     L.sync = b->team_sync;
     L.partials = b->team_partials;
@@ -242,8 +244,10 @@ int select_grid(grover_batch *b, int clock_khz)
 {
     int per_cu = 0;
     int per_cu_held = 0;
-    BATCH_HIP(b, hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, batch_kernel_fn(true), 1024, 0), "occupancy");
-    BATCH_HIP(b, hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu_held, batch_kernel_fn(false), 1024, 0),
+    const bool u32 = b->update == GROVER_UPDATE_F32;
+    BATCH_HIP(b, hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, batch_kernel_fn(true, u32), 1024, 0),
+              "occupancy");
+    BATCH_HIP(b, hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu_held, batch_kernel_fn(false, u32), 1024, 0),
               "occupancy");
     per_cu = std::min(per_cu, per_cu_held);
     const int max_grid = std::max(1, per_cu) * b->cu_count;
@@ -298,7 +302,11 @@ hipError_t make_node_cooperative(hipGraph_t g)
         e = hipGraphKernelNodeGetParams(node, &kp);
         if (e != hipSuccess)
             return e;
-        if (kp.func != batch_kernel_fn(true) && kp.func != batch_kernel_fn(false))
+        bool batch_node = false;
+        for (bool streams : {true, false})
+            for (bool u32 : {true, false})
+                batch_node = batch_node || kp.func == batch_kernel_fn(streams, u32);
+        if (!batch_node)
             continue;
         ++found;
         hipKernelNodeAttrValue v{};
@@ -324,7 +332,8 @@ int grover_batch_init(grover_batch **out, const grover_batch_config *cfg, void *
     if (!out)
         return GROVER_E_INVAL;
     *out = nullptr;
-    if (!cfg || cfg->count == 0 || !cfg->n || !cfg->m || cfg->flags != 0 || cfg->reserved != 0)
+    if (!cfg || cfg->count == 0 || !cfg->n || !cfg->m || cfg->flags != 0 || cfg->reserved != 0 ||
+        cfg->update > GROVER_UPDATE_F32)
         return GROVER_E_INVAL;
     if (cfg->dtype != GROVER_C64)
         return GROVER_E_UNSUPPORTED;
@@ -334,6 +343,7 @@ int grover_batch_init(grover_batch **out, const grover_batch_config *cfg, void *
     int status = GROVER_OK;
     try {
         b->count = cfg->count;
+        b->update = cfg->update;
         b->stream = static_cast<hipStream_t>(hip_stream);
         uint64_t total_m = 0;
         for (uint64_t i = 0; i < cfg->count; ++i) {

@@ -38,6 +38,7 @@ struct BatchLaunch {
     uint32_t nphases;
     uint32_t probe;              // 1: one barrier of the whole grid, nothing else (residency check)
     uint32_t streams;            // 0: every state is held on chip (the kernel without the streamed paths)
+    uint32_t update;             // grover_update of the element update
     unsigned long long *heads;   // one per phase
     GridSync *sync;              // [phase][grid]
     uint64_t *partials;          // [phase][grid * 8]: team slots [2][T][4]
@@ -46,8 +47,9 @@ struct BatchLaunch {
     hipStream_t stream;
 };
 
-// The persistent kernel with the streamed paths (streams = 1) or without them (0: every state on chip).
-const void *batch_kernel_fn(bool streams);
+// The persistent kernel with the streamed paths (streams = 1) or without them (0: every state on chip), with
+// the update in binary32 (u32) or binary64.
+const void *batch_kernel_fn(bool streams, bool u32);
 hipError_t launch_batch(const BatchLaunch &L);
 
 }  // namespace grover

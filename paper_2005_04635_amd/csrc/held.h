@@ -30,6 +30,19 @@ __device__ inline void unmarked_update(float4 &v, double mr, double mi, AccF64 &
     acc.add(double(v.z), double(v.w));
 }
 
+// The same update in binary32 from 2S/N rounded to binary32 (mr, mi): one binary32 subtraction per part,
+// where the binary64 form takes a conversion, a binary64 subtraction and a rounding conversion.  A negated
+// marked value gives mr + c, the marked result of fl32(mr - s c), as above.
+__device__ inline void unmarked_update(float4 &v, float mr, float mi, AccF64 &acc)
+{
+    v.x = mr - v.x;
+    v.y = mi - v.y;
+    v.z = mr - v.z;
+    v.w = mi - v.w;
+    acc.add(double(v.x), double(v.y));
+    acc.add(double(v.z), double(v.w));
+}
+
 // Negates the stored values of the marked amplitudes among a thread's held vectors (bits 2e, 2e + 1 of
 // `mask` for vector e).
 __device__ inline void negate_marked(float4 (&x)[kHeldRegE], float4 *held, uint32_t mask)
@@ -74,8 +87,10 @@ __device__ inline void correct_marked(const float4 (&x)[kHeldRegE], const float4
 // One iteration over a thread's held vectors (e < ne in order: x[e] in registers for e < kHeldRegE, then the
 // LDS slots), each updated as unmarked.  When all 16 are held, the LDS vectors are loaded four at a time,
 // each group while the previous one (or the register half) is being updated, so that their latency hides
-// behind arithmetic.
-__device__ inline void held_sweep(float4 (&x)[kHeldRegE], float4 *held, unsigned ne, double mr, double mi, AccF64 &acc)
+// behind arithmetic.  M is the type of 2S/N: double for the binary64 update, float (already rounded) for
+// the binary32 one.
+template <class M>
+__device__ inline void held_sweep(float4 (&x)[kHeldRegE], float4 *held, unsigned ne, M mr, M mi, AccF64 &acc)
 {
     const unsigned tid = threadIdx.x;
     if (ne == unsigned(kHeldHoldE)) {

@@ -210,6 +210,22 @@ __device__ inline void update_vec(typename T::vec &v, double mr, double mi, unsi
     }
 }
 
+// The same update computed in binary32, for complex64 storage: (mr, mi) = 2S/N already rounded to
+// binary32, and each part of c' = mr - s c is one binary32 operation (mr + c for a marked amplitude, the same
+// rounding as mr - (-c)).  The stored values, times s, are added to the binary64 accumulator in the order of
+// update_vec and accum_vec.
+template <class A>
+__device__ inline void update_vec_f32(float4 &v, float mr, float mi, unsigned marked, A &acc)
+{
+    const bool m0 = (marked & 1u) != 0u, m1 = (marked & 2u) != 0u;
+    v.x = m0 ? mr + v.x : mr - v.x;
+    v.y = m0 ? mi + v.y : mi - v.y;
+    v.z = m1 ? mr + v.z : mr - v.z;
+    v.w = m1 ? mi + v.w : mi - v.w;
+    acc.add(m0 ? -double(v.x) : double(v.x), m0 ? -double(v.y) : double(v.y));
+    acc.add(m1 ? -double(v.z) : double(v.z), m1 ? -double(v.w) : double(v.w));
+}
+
 // Sum of s*c over one vector, in exactly the order update_vec accumulates (so a fresh sum of a stored
 // state equals, bit for bit, the sum the fused update produced while writing it).
 template <class T, class A>
@@ -357,6 +373,7 @@ struct grover_ctx {
     uint64_t N = 0;
     uint32_t dtype = 0;
     uint32_t accum = 0;
+    uint32_t update = 0;  // grover_update: precision of the element update
     uint32_t form = 0;  // resolved (never AUTO)
     uint32_t kind = 0;
     void *state = nullptr;

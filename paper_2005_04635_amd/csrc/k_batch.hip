@@ -1,5 +1,5 @@
 // Batched searches in one persistent launch (many independent instances of Algorithm 5, complex64 states,
-// binary64 update and sums).  The grid (one workgroup per CU, all co-resident) works through a sequence of
+// binary64 sums, the update in binary64 or binary32).  The grid (one workgroup per CU, all co-resident) works through a sequence of
 // phases, each with its own queue ordered by decreasing work N * k and its own team size T:
 //   - in a phase with T > 1 the grid is split into teams of T consecutive workgroups; a team's leader takes
 //     the next instance and publishes it through the team barrier, and the team iterates it with one team
@@ -74,6 +74,7 @@ __device__ inline float4 uniform_vec(double amp)
 }
 
 // One instance streamed by the T workgroups of a team.  Returns false when a barrier gave up.
+template <bool U32>
 __device__ bool run_team_streamed(const BatchArgs &a, const BatchInstance &I, const Team &tm, uint64_t &gen,
                                   TeamShared<double> &sh, uint32_t *table)
 {
@@ -88,7 +89,7 @@ __device__ bool run_team_streamed(const BatchArgs &a, const BatchInstance &I, co
     for (uint64_t it = 0; it < I.iters; ++it) {
         const double mr = (sr * 2.0) / I.N, mi = (si * 2.0) / I.N;
         AccF64 acc;
-        stream_pass<C64, AccF64, kUpdate>(share, table, use_table, mr, mi, none, acc);
+        stream_pass<C64, AccF64, kUpdate, U32>(share, table, use_table, mr, mi, none, acc);
         sr = acc.r;
         si = acc.i;
         if (!team_sum<double>(sr, si, tm, ++gen, sh))
@@ -104,7 +105,7 @@ __device__ bool run_team_streamed(const BatchArgs &a, const BatchInstance &I, co
 // other thread touches them, so no workgroup barrier is needed around them).  Marked bits travel packed, two
 // per vector.  `reduce` is the team's (or the workgroup's) sum; the state is written to memory once, at
 // the end.  Returns false when a barrier gave up.
-template <class Reduce>
+template <bool U32, class Reduce>
 __device__ bool run_held(const BatchArgs &a, const BatchInstance &I, uint64_t base, uint64_t per, float4 *held,
                          TeamShared<double> &sh, Reduce reduce)
 {
@@ -142,7 +143,10 @@ __device__ bool run_held(const BatchArgs &a, const BatchInstance &I, uint64_t ba
         if (active) {
             if (mask != 0u)
                 negate_marked(x, held, mask);
-            held_sweep(x, held, ne, mr, mi, acc);
+            if constexpr (U32)
+                held_sweep(x, held, ne, float(mr), float(mi), acc);
+            else
+                held_sweep(x, held, ne, mr, mi, acc);
             if (mask != 0u)
                 correct_marked(x, held, mask, acc);
         }
@@ -161,6 +165,7 @@ __device__ bool run_held(const BatchArgs &a, const BatchInstance &I, uint64_t ba
 }
 
 // One instance iterated by one workgroup, its state streamed from memory.
+template <bool U32>
 __device__ void run_single_streamed(const BatchArgs &a, const BatchInstance &I, TeamShared<double> &sh,
                                     uint32_t *table)
 {
@@ -175,7 +180,7 @@ __device__ void run_single_streamed(const BatchArgs &a, const BatchInstance &I, 
     for (uint64_t it = 0; it < I.iters; ++it) {
         const double mr = (sr * 2.0) / I.N, mi = (si * 2.0) / I.N;
         AccF64 acc;
-        stream_pass<C64, AccF64, kUpdate>(share, table, use_table, mr, mi, none, acc);
+        stream_pass<C64, AccF64, kUpdate, U32>(share, table, use_table, mr, mi, none, acc);
         sr = acc.r;
         si = acc.i;
         block_allsum(sr, si, parity++, sh);
@@ -185,8 +190,9 @@ __device__ void run_single_streamed(const BatchArgs &a, const BatchInstance &I, 
 // kStreams = false compiles the kernel without the streamed paths, for tilings that hold every state on
 // chip: the held loops then get the registers to themselves.  The host launches that instantiation only
 // when no phase streams, so its streamed branches are never taken; were one taken, the kernel would report
-// it through the error word instead of computing.
-template <bool kStreams>
+// it through the error word instead of computing.  U32: the update in binary32 from 2S/N rounded to
+// binary32; otherwise in binary64.
+template <bool kStreams, bool U32>
 __global__ __launch_bounds__(kStreamBlock) void batch_kernel(BatchArgs a)
 {
     __shared__ TeamShared<double> sh;
@@ -220,12 +226,12 @@ __global__ __launch_bounds__(kStreamBlock) void batch_kernel(BatchArgs a)
                 const BatchInstance I = a.inst[a.queue[q0 + q]];
                 unsigned parity = 0;
                 if (I.nvec <= uint64_t(kHoldE) * kStreamBlock)
-                    (void)run_held(a, I, 0, I.nvec, held, sh, [&](double &r, double &i) {
+                    (void)run_held<U32>(a, I, 0, I.nvec, held, sh, [&](double &r, double &i) {
                         block_allsum(r, i, parity++, sh);
                         return true;
                     });
                 else if (kStreams)
-                    run_single_streamed(a, I, sh, table);
+                    run_single_streamed<U32>(a, I, sh, table);
                 else
                     flag_error(a.sync + uint64_t(p) * grid + blockIdx.x);
             }
@@ -252,10 +258,10 @@ __global__ __launch_bounds__(kStreamBlock) void batch_kernel(BatchArgs a)
             bool ok;
             if (a.resident[p]) {
                 const uint64_t per = I.nvec / T;
-                ok = run_held(a, I, uint64_t(tm.rank) * per, per, held, sh,
-                              [&](double &r, double &i) { return team_sum<double>(r, i, tm, ++gen, sh); });
+                ok = run_held<U32>(a, I, uint64_t(tm.rank) * per, per, held, sh,
+                                   [&](double &r, double &i) { return team_sum<double>(r, i, tm, ++gen, sh); });
             } else if (kStreams) {
-                ok = run_team_streamed(a, I, tm, gen, sh, table);
+                ok = run_team_streamed<U32>(a, I, tm, gen, sh, table);
             } else {
                 flag_error(tm.sync);
                 ok = false;
@@ -284,10 +290,13 @@ __global__ void batch_reset_kernel(unsigned long long *heads, uint64_t nheads, u
 
 }  // namespace
 
-const void *batch_kernel_fn(bool streams)
+const void *batch_kernel_fn(bool streams, bool u32)
 {
-    return streams ? reinterpret_cast<const void *>(&batch_kernel<true>)
-                   : reinterpret_cast<const void *>(&batch_kernel<false>);
+    if (u32)
+        return streams ? reinterpret_cast<const void *>(&batch_kernel<true, true>)
+                       : reinterpret_cast<const void *>(&batch_kernel<false, true>);
+    return streams ? reinterpret_cast<const void *>(&batch_kernel<true, false>)
+                   : reinterpret_cast<const void *>(&batch_kernel<false, false>);
 }
 
 hipError_t launch_batch(const BatchLaunch &L)
@@ -321,8 +330,8 @@ hipError_t launch_batch(const BatchLaunch &L)
     if (e != hipSuccess)
         return e;
     void *args[] = {&a};
-    return hipLaunchCooperativeKernel(batch_kernel_fn(L.streams != 0u), dim3(L.grid), dim3(kStreamBlock), args, 0,
-                                      L.stream);
+    return hipLaunchCooperativeKernel(batch_kernel_fn(L.streams != 0u, L.update != 0u), dim3(L.grid),
+                                      dim3(kStreamBlock), args, 0, L.stream);
 }
 
 }  // namespace grover

@@ -19,7 +19,8 @@
 // Template parameters: T = storage type (F64Real, C64, C128, CBF16), A = accumulator of the sum (AccF64,
 // AccF32, AccF32Kahan; the grid tree runs in A's precision), CHECK = a second symbol of the same code for the
 // residency check at context creation, NT = nontemporal accesses beyond the part of the state kept in the
-// memory-side cache (kTemporalBytes).  The update itself is always binary64.
+// memory-side cache (kTemporalBytes), U32 = the update in binary32 from 2S/N rounded to binary32 (complex64
+// storage with binary64 sums only; otherwise the update is binary64, rounded once to the storage type).
 #include "internal.h"
 
 namespace grover {
@@ -217,10 +218,22 @@ constexpr int kHeldTiles = 3;
 // First held tile (local index) of this workgroup's share of cnt tiles.
 __device__ inline uint64_t held_start(uint64_t cnt) { return cnt > uint64_t(kHeldTiles) ? cnt - kHeldTiles : 0; }
 
+// The update of one vector in the kernel's update precision: U32, binary32 from 2S/N rounded to binary32
+// (complex64 storage only); otherwise binary64, rounded once to the storage type.
+template <class T, bool U32, class A>
+__device__ __forceinline__ void update_one(typename T::vec &v, double mr, double mi, float mr32, float mi32,
+                                           unsigned bits, A &acc)
+{
+    if constexpr (U32)
+        update_vec_f32(v, mr32, mi32, bits, acc);
+    else
+        update_vec<T>(v, mr, mi, bits, acc);
+}
+
 // A full tile without marked amplitudes: every sign is +1.  NT selects the nontemporal loads and stores.
-template <class T, class A, bool UPDATE, bool NT>
+template <class T, class A, bool UPDATE, bool NT, bool U32>
 __device__ __forceinline__ void plain_tile(typename T::vec *st, uint64_t v0, unsigned tid, double mr, double mi,
-                                           A &acc)
+                                           float mr32, float mi32, A &acc)
 {
     typename T::vec x[kUnroll];
 #pragma unroll
@@ -229,7 +242,7 @@ __device__ __forceinline__ void plain_tile(typename T::vec *st, uint64_t v0, uns
 #pragma unroll
     for (int u = 0; u < kUnroll; ++u) {
         if (UPDATE) {
-            update_vec<T>(x[u], mr, mi, 0u, acc);
+            update_one<T, U32>(x[u], mr, mi, mr32, mi32, 0u, acc);
             store16<NT>(x[u], st + v0 + u * kBlock + tid);
         } else {
             accum_vec<T>(x[u], 0u, acc);
@@ -237,11 +250,12 @@ __device__ __forceinline__ void plain_tile(typename T::vec *st, uint64_t v0, uns
     }
 }
 
-template <class T, class A, bool UPDATE, bool NT>
+template <class T, class A, bool UPDATE, bool NT, bool U32>
 __device__ inline void chunk_pass(const FusedArgs &a, const uint32_t *slow_tiles, bool table, double mr, double mi,
                                   A &acc, typename T::vec *held, typename T::vec (&rt)[kUnroll])
 {
     using V = typename T::vec;
+    const float mr32 = float(mr), mi32 = float(mi);  // the binary32 update's 2S/N (rounded to nearest even)
     V *st = static_cast<V *>(a.state);
     const unsigned tid = threadIdx.x;
     const uint64_t ntiles = (a.nvec + kTile - 1) / kTile;
@@ -254,9 +268,9 @@ __device__ inline void chunk_pass(const FusedArgs &a, const uint32_t *slow_tiles
         const bool full = v0 + kTile <= a.nvec;
         const bool marked = table ? ((slow_tiles[j >> 5] >> (j & 31)) & 1u) != 0u : a.m > 0;
         if (full && !marked && (!NT || j < a.temporal_tiles)) {
-            plain_tile<T, A, UPDATE, false>(st, v0, tid, mr, mi, acc);
+            plain_tile<T, A, UPDATE, false, U32>(st, v0, tid, mr, mi, mr32, mi32, acc);
         } else if (full && !marked) {
-            plain_tile<T, A, UPDATE, true>(st, v0, tid, mr, mi, acc);
+            plain_tile<T, A, UPDATE, true, U32>(st, v0, tid, mr, mi, mr32, mi32, acc);
         } else {
             // Ragged tail of the state, or a tile that may hold marked amplitudes: the same vector loads,
             // then each amplitude's sign from the tile's slice [mp, mq) of the sorted marked list.
@@ -281,7 +295,7 @@ __device__ inline void chunk_pass(const FusedArgs &a, const uint32_t *slow_tiles
                     const unsigned bits = in_regs ? bits_from_regs<T::EPV>(mk, v * T::EPV)
                                                   : marked_bits<T::EPV>(a.marks, mp, mq, v * T::EPV);
                     if (UPDATE) {
-                        update_vec<T>(x[u], mr, mi, bits, acc);
+                        update_one<T, U32>(x[u], mr, mi, mr32, mi32, bits, acc);
                         store16<NT>(x[u], st + v);
                     } else {
                         accum_vec<T>(x[u], bits, acc);
@@ -333,7 +347,7 @@ __device__ inline void chunk_pass(const FusedArgs &a, const uint32_t *slow_tiles
                     bits = in_regs ? bits_from_regs<T::EPV>(mk, v * T::EPV)
                                    : marked_bits<T::EPV>(a.marks, mp, mq, v * T::EPV);
                 if (UPDATE) {
-                    update_vec<T>(x[u], mr, mi, bits, acc);
+                    update_one<T, U32>(x[u], mr, mi, mr32, mi32, bits, acc);
                     hv[u * kBlock + tid] = x[u];
                 } else {
                     accum_vec<T>(x[u], bits, acc);
@@ -377,7 +391,7 @@ __device__ inline void chunk_pass(const FusedArgs &a, const uint32_t *slow_tiles
                     bits = in_regs ? bits_from_regs<T::EPV>(mk, v * T::EPV)
                                    : marked_bits<T::EPV>(a.marks, mp, mq, v * T::EPV);
                 if (UPDATE)
-                    update_vec<T>(rt[u], mr, mi, bits, acc);
+                    update_one<T, U32>(rt[u], mr, mi, mr32, mi32, bits, acc);
                 else
                     accum_vec<T>(rt[u], bits, acc);
             }
@@ -389,7 +403,7 @@ __device__ inline void chunk_pass(const FusedArgs &a, const uint32_t *slow_tiles
 
 // CHECK only names a second, code-identical instantiation used for the residency check at context
 // creation, so that profiles list it apart from the iteration launches.
-template <class T, class A, bool CHECK, bool NT>
+template <class T, class A, bool CHECK, bool NT, bool U32>
 __global__ __launch_bounds__(kBlock) void fused_iterate_kernel(FusedArgs a)
 {
     using Val = typename A::value;
@@ -424,14 +438,14 @@ __global__ __launch_bounds__(kBlock) void fused_iterate_kernel(FusedArgs a)
         __syncthreads();
     }
     A acc0;
-    chunk_pass<T, A, false, NT>(a, slow_tiles, table, 0.0, 0.0, acc0, held, rt);
+    chunk_pass<T, A, false, NT, U32>(a, slow_tiles, table, 0.0, 0.0, acc0, held, rt);
     Val sr = acc0.res_r(), si = acc0.res_i();
     if (!grid_sum<Val, !NT>(sr, si, a, a.gen0 + 1u, sh))
         return;
     for (uint64_t it = 0; it < a.iters; ++it) {
         const double mr = (double(sr) * 2.0) / a.N, mi = (double(si) * 2.0) / a.N;
         A acc;
-        chunk_pass<T, A, true, NT>(a, slow_tiles, table, mr, mi, acc, held, rt);
+        chunk_pass<T, A, true, NT, U32>(a, slow_tiles, table, mr, mi, acc, held, rt);
         sr = acc.res_r();
         si = acc.res_i();
         if (!grid_sum<Val, !NT>(sr, si, a, a.gen0 + 2u + it, sh))
@@ -466,17 +480,21 @@ template <class A, bool CHECK, bool NT>
 const void *pick_storage(uint32_t dtype)
 {
     switch (dtype) {
-    case GROVER_F64_REAL: return reinterpret_cast<const void *>(&fused_iterate_kernel<F64Real, A, CHECK, NT>);
-    case GROVER_C64: return reinterpret_cast<const void *>(&fused_iterate_kernel<C64, A, CHECK, NT>);
-    case GROVER_C128: return reinterpret_cast<const void *>(&fused_iterate_kernel<C128, A, CHECK, NT>);
-    case GROVER_CBF16: return reinterpret_cast<const void *>(&fused_iterate_kernel<CBF16, A, CHECK, NT>);
+    case GROVER_F64_REAL: return reinterpret_cast<const void *>(&fused_iterate_kernel<F64Real, A, CHECK, NT, false>);
+    case GROVER_C64: return reinterpret_cast<const void *>(&fused_iterate_kernel<C64, A, CHECK, NT, false>);
+    case GROVER_C128: return reinterpret_cast<const void *>(&fused_iterate_kernel<C128, A, CHECK, NT, false>);
+    case GROVER_CBF16: return reinterpret_cast<const void *>(&fused_iterate_kernel<CBF16, A, CHECK, NT, false>);
     default: return nullptr;
     }
 }
 
 template <bool CHECK, bool NT>
-const void *kernel_for_access(uint32_t dtype, uint32_t accum)
+const void *kernel_for_access(uint32_t dtype, uint32_t accum, uint32_t update)
 {
+    if (update == GROVER_UPDATE_F32)  // complex64 storage with binary64 sums only
+        return dtype == GROVER_C64 && accum == GROVER_ACC_F64
+                   ? reinterpret_cast<const void *>(&fused_iterate_kernel<C64, AccF64, CHECK, NT, true>)
+                   : nullptr;
     switch (accum) {
     case GROVER_ACC_F64: return pick_storage<AccF64, CHECK, NT>(dtype);
     case GROVER_ACC_F32: return pick_storage<AccF32, CHECK, NT>(dtype);
@@ -486,9 +504,10 @@ const void *kernel_for_access(uint32_t dtype, uint32_t accum)
 }
 
 template <bool CHECK>
-const void *kernel_for(uint32_t dtype, uint32_t accum, bool temporal)
+const void *kernel_for(uint32_t dtype, uint32_t accum, bool temporal, uint32_t update = GROVER_UPDATE_F64)
 {
-    return temporal ? kernel_for_access<CHECK, false>(dtype, accum) : kernel_for_access<CHECK, true>(dtype, accum);
+    return temporal ? kernel_for_access<CHECK, false>(dtype, accum, update)
+                    : kernel_for_access<CHECK, true>(dtype, accum, update);
 }
 
 // Bytes of the state per pass streamed with ordinary (temporal) loads and stores, so that the next pass
@@ -514,11 +533,11 @@ hipError_t fused_configure(grover_ctx *c, int *per_cu, int *block, int64_t *forc
             budget = state_bytes;  // every access ordinary
     }
     const bool temporal = state_bytes <= budget;
-    const void *k = kernel_for<false>(c->dtype, c->accum, temporal);
+    const void *k = kernel_for<false>(c->dtype, c->accum, temporal, c->update);
     if (!k)
         return hipErrorInvalidValue;
     c->fused_kernel = k;
-    c->fused_check_kernel = kernel_for<true>(c->dtype, c->accum, temporal);
+    c->fused_check_kernel = kernel_for<true>(c->dtype, c->accum, temporal, c->update);
     c->fused_temporal_bytes = temporal ? state_bytes : budget;
     c->fused_tile = kTile;
     int coop = 0;

@@ -30,7 +30,8 @@ struct HeldIterArgs {
 // workgroups; n = 21 and 22: 5.29 vs 5.84 ms and 8.59 vs 9.58 ms per optimal search on MI355X).  Teams of
 // at most 64 use the kernel without it, whose code keeps fewer registers in flight (with it n = 18 took
 // 1.61 instead of 1.43 ms).
-template <bool kTogether>
+// U32: the update in binary32 from 2S/N rounded to binary32; otherwise in binary64.
+template <bool kTogether, bool U32>
 __global__ __launch_bounds__(kStreamBlock) void held_iterate_kernel(HeldIterArgs a)
 {
     __shared__ TeamShared<double> sh;
@@ -77,7 +78,10 @@ __global__ __launch_bounds__(kStreamBlock) void held_iterate_kernel(HeldIterArgs
         if (active) {
             if (mask != 0u)
                 negate_marked(x, held, mask);
-            held_sweep(x, held, ne, mr, mi, acc);
+            if constexpr (U32)
+                held_sweep(x, held, ne, float(mr), float(mi), acc);
+            else
+                held_sweep(x, held, ne, mr, mi, acc);
             if (mask != 0u)
                 correct_marked(x, held, mask, acc);
         }
@@ -146,8 +150,12 @@ hipError_t launch_held_iterate(grover_ctx *c, uint64_t k, uint64_t timeout_ticks
     a.timeout_ticks = timeout_ticks;
     a.probe = probe ? 1u : 0u;
     void *args[] = {&a};
-    const void *fn = c->held_team > 64u ? reinterpret_cast<const void *>(&held_iterate_kernel<true>)
-                                         : reinterpret_cast<const void *>(&held_iterate_kernel<false>);
+    const bool u32 = c->update == GROVER_UPDATE_F32;
+    const void *fn = c->held_team > 64u
+                         ? (u32 ? reinterpret_cast<const void *>(&held_iterate_kernel<true, true>)
+                                : reinterpret_cast<const void *>(&held_iterate_kernel<true, false>))
+                         : (u32 ? reinterpret_cast<const void *>(&held_iterate_kernel<false, true>)
+                                : reinterpret_cast<const void *>(&held_iterate_kernel<false, false>));
     const hipError_t e = hipLaunchCooperativeKernel(fn, dim3(c->held_team), dim3(kStreamBlock), args, 0, c->stream);
     if (e == hipSuccess)
         c->generation += probe ? 1u : k + 1u;

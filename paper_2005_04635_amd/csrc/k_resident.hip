@@ -44,8 +44,9 @@ __device__ inline void workgroup_sum(double &a, double &b, double (*red)[2 * kWa
     b = sb;
 }
 
-// E = 16-byte vectors per thread; vector v = e * kBlock + threadIdx.x (coalesced load and store).
-template <class T, int E>
+// E = 16-byte vectors per thread; vector v = e * kBlock + threadIdx.x (coalesced load and store).  U32: the
+// update in binary32 from 2S/N rounded to binary32 (complex64 only); otherwise binary64.
+template <class T, int E, bool U32>
 __global__ __launch_bounds__(kBlock) void resident_iterate_kernel(ResidentArgs a)
 {
     using V = typename T::vec;
@@ -76,8 +77,12 @@ __global__ __launch_bounds__(kBlock) void resident_iterate_kernel(ResidentArgs a
         AccF64 acc;
 #pragma unroll
         for (int e = 0; e < E; ++e)
-            if (uint64_t(e) * kBlock + tid < a.nvec)
-                update_vec<T>(x[e], mr, mi, bits[e], acc);
+            if (uint64_t(e) * kBlock + tid < a.nvec) {
+                if constexpr (U32)
+                    update_vec_f32(x[e], float(mr), float(mi), bits[e], acc);
+                else
+                    update_vec<T>(x[e], mr, mi, bits[e], acc);
+            }
         sr = acc.r;
         si = acc.i;
         workgroup_sum(sr, si, red, int((it + 1) & 1u));
@@ -90,15 +95,15 @@ __global__ __launch_bounds__(kBlock) void resident_iterate_kernel(ResidentArgs a
     }
 }
 
-template <class T>
+template <class T, bool U32 = false>
 const void *pick(uint64_t vec_per_thread)
 {
     switch (vec_per_thread) {
-    case 1: return reinterpret_cast<const void *>(&resident_iterate_kernel<T, 1>);
-    case 2: return reinterpret_cast<const void *>(&resident_iterate_kernel<T, 2>);
-    case 4: return reinterpret_cast<const void *>(&resident_iterate_kernel<T, 4>);
-    case 8: return reinterpret_cast<const void *>(&resident_iterate_kernel<T, 8>);
-    case 16: return reinterpret_cast<const void *>(&resident_iterate_kernel<T, 16>);
+    case 1: return reinterpret_cast<const void *>(&resident_iterate_kernel<T, 1, U32>);
+    case 2: return reinterpret_cast<const void *>(&resident_iterate_kernel<T, 2, U32>);
+    case 4: return reinterpret_cast<const void *>(&resident_iterate_kernel<T, 4, U32>);
+    case 8: return reinterpret_cast<const void *>(&resident_iterate_kernel<T, 8, U32>);
+    case 16: return reinterpret_cast<const void *>(&resident_iterate_kernel<T, 16, U32>);
     default: return nullptr;
     }
 }
@@ -121,7 +126,7 @@ hipError_t launch_resident_iterate(grover_ctx *c, uint64_t k)
     const void *fn = nullptr;
     switch (c->dtype) {
     case GROVER_F64_REAL: fn = pick<F64Real>(e); break;
-    case GROVER_C64: fn = pick<C64>(e); break;
+    case GROVER_C64: fn = c->update == GROVER_UPDATE_F32 ? pick<C64, true>(e) : pick<C64>(e); break;
     case GROVER_C128: fn = pick<C128>(e); break;
     }
     if (!fn)

@@ -320,12 +320,20 @@ enum PassMode { kAccumulate, kUpdate, kFill };
 // One pass over the workgroup's tiles.  kUpdate: c' = 2S/N - s c written back (nontemporal) and s c' added
 // to the accumulator; kAccumulate: s c added; kFill: `fill` written everywhere and s * fill added.  The
 // per-thread order of the sum is identical in all modes, so a fresh sum of a stored state equals, bit for
-// bit, the sum the pass that wrote it produced.
-template <class T, class A, PassMode MODE>
+// bit, the sum the pass that wrote it produced.  U32: the update in binary32 from 2S/N rounded to binary32
+// (complex64 storage only); otherwise in binary64.
+template <class T, class A, PassMode MODE, bool U32 = false>
 __device__ inline void stream_pass(const Share<T> &sh, const uint32_t *table, bool use_table, double mr, double mi,
                                    const typename T::vec &fill, A &acc)
 {
     using V = typename T::vec;
+    const float mr32 = float(mr), mi32 = float(mi);
+    auto update = [&](V &v, unsigned bits) {
+        if constexpr (U32)
+            update_vec_f32(v, mr32, mi32, bits, acc);
+        else
+            update_vec<T>(v, mr, mi, bits, acc);
+    };
     const unsigned tid = threadIdx.x;
     const uint64_t cnt = sh.count();
     uint64_t mp = 0;  // marked entries before this position lie in tiles already visited
@@ -344,7 +352,7 @@ __device__ inline void stream_pass(const Share<T> &sh, const uint32_t *table, bo
 #pragma unroll
             for (int u = 0; u < kStreamUnroll; ++u) {
                 if (MODE == kUpdate) {
-                    update_vec<T>(x[u], mr, mi, 0u, acc);
+                    update(x[u], 0u);
                     store16<true>(x[u], sh.st + v0 + u * kStreamBlock + tid);
                 } else if (MODE == kFill) {
                     store16<true>(fill, sh.st + v0 + u * kStreamBlock + tid);
@@ -377,7 +385,7 @@ __device__ inline void stream_pass(const Share<T> &sh, const uint32_t *table, bo
                     const unsigned bits = in_regs ? bits_from_regs<T::EPV>(mk, v * T::EPV)
                                                   : marked_bits<T::EPV>(sh.marks, mp, mq, v * T::EPV);
                     if (MODE == kUpdate) {
-                        update_vec<T>(x[u], mr, mi, bits, acc);
+                        update(x[u], bits);
                         store16<true>(x[u], sh.st + v);
                     } else {
                         if (MODE == kFill)

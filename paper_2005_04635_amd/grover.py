@@ -30,11 +30,13 @@ GROVER_E_TIMEOUT = -7
 
 GROVER_F64_REAL, GROVER_C64, GROVER_C128, GROVER_CBF16 = 0, 1, 2, 3
 GROVER_ACC_F64, GROVER_ACC_F32, GROVER_ACC_F32_KAHAN = 0, 1, 2
+GROVER_UPDATE_F64, GROVER_UPDATE_F32 = 0, 1
 GROVER_ORACLE_LIST, GROVER_ORACLE_HASH = 0, 1
 GROVER_FORM_AUTO, GROVER_FORM_FUSED, GROVER_FORM_RESIDENT, GROVER_FORM_TWO_PASS, GROVER_FORM_HELD = 0, 1, 2, 3, 4
 
 DTYPES = {"f64": GROVER_F64_REAL, "c64": GROVER_C64, "c128": GROVER_C128, "cbf16": GROVER_CBF16}
 ACCUMS = {"f64": GROVER_ACC_F64, "f32": GROVER_ACC_F32, "f32_kahan": GROVER_ACC_F32_KAHAN}
+UPDATES = {"f64": GROVER_UPDATE_F64, "f32": GROVER_UPDATE_F32}
 FORMS = {"auto": GROVER_FORM_AUTO, "fused": GROVER_FORM_FUSED, "resident": GROVER_FORM_RESIDENT,
          "two_pass": GROVER_FORM_TWO_PASS, "held": GROVER_FORM_HELD}
 ELEM_BYTES = {GROVER_F64_REAL: 8, GROVER_C64: 8, GROVER_C128: 16, GROVER_CBF16: 4}
@@ -94,7 +96,7 @@ class grover_config(ctypes.Structure):
         ("form", ctypes.c_uint32),
         ("flags", ctypes.c_uint32),
         ("accum", ctypes.c_uint32),
-        ("reserved", ctypes.c_uint32),
+        ("update", ctypes.c_uint32),
     ]
 
 
@@ -120,7 +122,8 @@ class grover_batch_config(ctypes.Structure):
         ("iterations", ctypes.POINTER(ctypes.c_uint64)),
         ("dtype", ctypes.c_uint32),
         ("flags", ctypes.c_uint32),
-        ("reserved", ctypes.c_uint64),
+        ("update", ctypes.c_uint32),
+        ("reserved", ctypes.c_uint32),
     ]
 
 
@@ -455,6 +458,8 @@ class Grover:
     marks      explicit marked indices (oracle list), or None with hash_seed/hash_bits/m for the predicate
     form       "auto", "fused", "resident", "two_pass" or "held"
     accum      precision of the sum the mean is taken from: "f64", "f32" or "f32_kahan"
+    update     precision of the element update: "f64" (rounded once to the storage) or "f32" (complex64
+               storage with binary64 sums: binary32 arithmetic from 2S/N rounded to binary32)
     state      optional torch tensor (on the current device) to adopt as the state; otherwise one is made
     The state tensor is `self.state` (torch, 1-D, N elements of the dtype); kernels run on torch's
     current stream at construction.
@@ -462,7 +467,7 @@ class Grover:
 
     def __init__(self, n: int, dtype: str = "c64", marks=None, *, hash_seed: Optional[int] = None,
                  hash_bits: int = 0, m: Optional[int] = None, form: str = "auto", accum: str = "f64",
-                 state=None):
+                 update: str = "f64", state=None):
         import torch
 
         self.n = n
@@ -481,6 +486,7 @@ class Grover:
         cfg.form = FORMS[form]
         cfg.flags = 0
         cfg.accum = ACCUMS[accum]
+        cfg.update = UPDATES[update]
         if hash_seed is not None:
             cfg.oracle_kind = GROVER_ORACLE_HASH
             cfg.hash_seed = hash_seed & (2**64 - 1)
@@ -595,7 +601,7 @@ class GroverBatch:
     superposition and performs its iterations; `read_state(i)` returns instance i's state (complex64).
     """
 
-    def __init__(self, n, m, marks, iterations=None):
+    def __init__(self, n, m, marks, iterations=None, update: str = "f64"):
         import torch
 
         self._n = np.ascontiguousarray(np.asarray(n, dtype=np.uint32))
@@ -614,6 +620,7 @@ class GroverBatch:
         if self._iters is not None:
             cfg.iterations = self._iters.ctypes.data_as(ctypes.POINTER(ctypes.c_uint64))
         cfg.dtype = GROVER_C64
+        cfg.update = UPDATES[update]
         self.stream = torch.cuda.current_stream()
         self.b = grover_batch_init(cfg, self.stream.cuda_stream)
         self.count = int(self._n.size)

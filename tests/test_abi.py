@@ -78,7 +78,7 @@ def test_status_strings_and_null_handling(lib):
 
 
 @pytest.mark.parametrize("field,value", [("n", 0), ("n", 35), ("dtype", 4), ("oracle_kind", 2), ("form", 5),
-                                         ("flags", 1), ("hash_bits", 65), ("accum", 3), ("reserved", 1)])
+                                         ("flags", 1), ("hash_bits", 65), ("accum", 3), ("update", 2)])
 def test_init_rejects_invalid_config_before_touching_the_device(lib, field, value):
     from paper_2005_04635_amd.grover import grover_config
 
@@ -131,6 +131,19 @@ def test_held_form_is_complex64_with_binary64_sums(lib, dtype, accum):
 
     cfg = grover_config()
     cfg.n, cfg.dtype, cfg.accum, cfg.form = 16, dtype, accum, 4
+    ctx = ctypes.c_void_p()
+    assert lib.grover_init(ctypes.byref(ctx), ctypes.byref(cfg), None, None, 0) == -5
+
+
+@pytest.mark.parametrize("dtype,accum,form", [(0, 0, 1), (2, 0, 1), (3, 0, 1), (1, 1, 1), (1, 2, 0), (1, 0, 3),
+                                               (2, 0, 2)])
+def test_binary32_update_needs_complex64_binary64_sums(lib, dtype, accum, form):
+    """The binary32 update exists for complex64 storage with binary64 sums, in the fused, one-workgroup and
+    held forms; anything else is rejected before device work."""
+    from paper_2005_04635_amd.grover import grover_config
+
+    cfg = grover_config()
+    cfg.n, cfg.dtype, cfg.accum, cfg.form, cfg.update = 10, dtype, accum, form, 1
     ctx = ctypes.c_void_p()
     assert lib.grover_init(ctypes.byref(ctx), ctypes.byref(cfg), None, None, 0) == -5
 
@@ -222,7 +235,9 @@ def test_batch_init_rejects_other_fields(lib):
     assert lib.grover_batch_init(ctypes.byref(b), ctypes.byref(cfg), None) == -1
     cfg.flags, cfg.reserved = 0, 1
     assert lib.grover_batch_init(ctypes.byref(b), ctypes.byref(cfg), None) == -1
-    cfg.reserved, cfg.count = 0, 0
+    cfg.reserved, cfg.update = 0, 2
+    assert lib.grover_batch_init(ctypes.byref(b), ctypes.byref(cfg), None) == -1
+    cfg.update, cfg.count = 0, 0
     assert lib.grover_batch_init(ctypes.byref(b), ctypes.byref(cfg), None) == -1
     assert lib.grover_batch_init(None, ctypes.byref(cfg), None) == -1
     assert lib.grover_batch_init(ctypes.byref(b), None, None) == -1
