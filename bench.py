@@ -6,6 +6,7 @@ per Grover iteration at n = 28, against the plain binary64 form.
     python bench.py --sweep precision   (storage x accumulator of the mean at n = 26, one line each)
     python bench.py --sweep batch       (4096 independent searches: tilings, the tuned graph, one-by-one)
     python bench.py --sweep adjoint     (generalized iteration with phases: forward + adjoint gradient)
+    python bench.py --sweep update      (element update in binary32 against binary64: on-chip forms, batch)
 
 Workload (synthetic by construction; the paper uses no dataset): the single large instance, n = 28
 (2^28 complex64 amplitudes, 2 GiB), M = 8 marked indices defined by the hash predicate
@@ -77,10 +78,12 @@ class Hip:
 
     def __init__(self):
         self.lib = ctypes.CDLL("libamdhip64.so.7")
+        self.events = []  # every event created and not yet destroyed
         P = ctypes.c_void_p
         for name, args in {
             "hipSetDevice": [ctypes.c_int], "hipDeviceSynchronize": [], "hipStreamCreate": [ctypes.POINTER(P)],
-            "hipStreamSynchronize": [P], "hipEventCreate": [ctypes.POINTER(P)], "hipEventRecord": [P, P],
+            "hipStreamSynchronize": [P], "hipStreamDestroy": [P], "hipEventCreate": [ctypes.POINTER(P)],
+            "hipEventDestroy": [P], "hipEventRecord": [P, P],
             "hipEventSynchronize": [P], "hipEventElapsedTime": [ctypes.POINTER(ctypes.c_float), P, P],
             "hipMalloc": [ctypes.POINTER(P), ctypes.c_size_t], "hipFree": [P],
             "hipMemcpy": [P, P, ctypes.c_size_t, ctypes.c_int],
@@ -98,7 +101,21 @@ class Hip:
     def event(self):
         e = ctypes.c_void_p()
         self.ok(self.lib.hipEventCreate(ctypes.byref(e)), "hipEventCreate")
+        self.events.append(e)
         return e
+
+    def destroy_events(self, *evs) -> None:
+        for e in evs:
+            if any(e is x for x in self.events):
+                self.events = [x for x in self.events if x is not e]
+                self.lib.hipEventDestroy(e)
+
+    def close(self, stream) -> None:
+        """Wait for the device, then release every event still held and the stream."""
+        self.lib.hipDeviceSynchronize()
+        self.destroy_events(*list(self.events))
+        if stream is not None and stream.value:
+            self.lib.hipStreamDestroy(stream)
 
     def elapsed_ms(self, e0, e1) -> float:
         ms = ctypes.c_float()
@@ -117,12 +134,13 @@ class Hip:
         return buf.value.decode(errors="replace")
 
 
-def make_config(pkg, n, dtype, marks=None, hash_seed=None, hash_bits=0, m=0, form="fused"):
+def make_config(pkg, n, dtype, marks=None, hash_seed=None, hash_bits=0, m=0, form="fused", update="f64"):
     import numpy as np
 
     g = pkg.grover
     cfg = g.grover_config()
     cfg.n, cfg.dtype, cfg.form, cfg.flags = n, g.DTYPES[dtype], g.FORMS[form], 0
+    cfg.update = g.UPDATES[update]
     keep = None
     if hash_seed is not None:
         cfg.oracle_kind, cfg.hash_seed, cfg.hash_bits, cfg.m = g.GROVER_ORACLE_HASH, hash_seed, hash_bits, m
@@ -172,8 +190,74 @@ def cpu_baseline(w, marks, iters):
             "host_cpus": os.cpu_count()}
 
 
+def cpu_worker(spec: str) -> int:
+    """One process of the all-core CPU baseline (no GPU is touched): the binary64 oracle from the uniform
+    state of the n = 28 workload for a few iterations; prints its own time as one JSON line."""
+    import numpy as np
+
+    import oracle
+    import workloads
+
+    iters = int(spec)
+    w = workloads.HASH_N28
+    marks = np.loadtxt(os.path.join(ROOT, "tests", "golden", "hash_marks_n28.txt"), dtype=np.uint64, comments="#")
+    orc = oracle.default()
+    psi = orc.init_uniform(w.n)
+    t1 = time.perf_counter()
+    orc.iterate(psi, marks, iters)
+    t2 = time.perf_counter()
+    print(json.dumps({"iterations": iters, "s": t2 - t1}), flush=True)
+    return 0
+
+
+def cpu_baseline_all_cores(w, iters, single):
+    """The same oracle on every host core at once: one child process per core (bench.py --cpu-worker; the
+    oracle is single-threaded and unchanged), each iterating its own copy of the n = 28 state from the
+    uniform superposition; the aggregate rate is the sum of the processes' updates over the longest one's
+    time.  Returned as the baseline, with the single-thread figure beside it."""
+    import subprocess
+
+    procs = min(os.cpu_count() or 1, 16)  # the GPU box grants 16 host cores per GPU
+    cmd = [sys.executable, os.path.abspath(__file__), "--cpu-worker", str(iters)]
+    children = [subprocess.Popen(cmd, stdout=subprocess.PIPE, text=True) for _ in range(procs)]
+    times = []
+    for c in children:
+        out, _ = c.communicate()
+        if c.returncode != 0:
+            raise RuntimeError(f"CPU baseline worker failed with status {c.returncode}")
+        times.append(json.loads(out.strip().splitlines()[-1])["s"])
+    N = 1 << w.n
+    rate = procs * N * iters / max(times)
+    return {"value": rate, "unit": "amplitude-updates/s", "cores": procs, "kind": "oracle",
+            "sample": f"n={w.n} M={w.m} hash marks: {procs} concurrent processes of the single-threaded binary64 "
+                      f"oracle, each {iters} iterations from the uniform state on its own 4 GiB state "
+                      f"(slowest {max(times):.1f} s, fastest {min(times):.1f} s); rate = all updates / slowest",
+            "single_thread": single, "host_cpus": os.cpu_count()}
+
+
 PAPER_TABLE1_S = {  # Table 1: seconds on an Intel i3-5005U, one thread (conventional, proposed)
     10: (0.010, 0.025), 16: (3.768, 0.349), 18: (37.708, 2.579), 20: (357.029, 20.005)}
+
+
+def cpu_table1_times(n: int, mark, k: int) -> dict:
+    """The binary64 CPU oracle on this host, one thread, at one of Table 1's sizes: the proposed search
+    (uniform state, then k iterations of Algorithms 3 and 4) and the conventional one (Algorithm 2's
+    iteration: H^n by n applications of Algorithm 1, the phase shift, H^n).  The conventional search runs in
+    full up to n = 16; above, 4 of its iterations are timed and scaled to k (labelled)."""
+    import oracle
+
+    orc = oracle.default()
+    t0 = time.perf_counter()
+    orc.search(n, mark, k)
+    t_prop = time.perf_counter() - t0
+    k_conv = k if n <= 16 else 4
+    psi = orc.init_uniform(n)
+    t0 = time.perf_counter()
+    orc.gate_iterate(psi, mark, k_conv)
+    t_conv = (time.perf_counter() - t0) * k / k_conv
+    return {"proposed": t_prop, "conventional": t_conv, "speedup": t_conv / t_prop,
+            "conventional_basis": "full search" if k_conv == k else f"{k_conv} iterations timed, scaled to {k}",
+            "host_cpus": os.cpu_count()}
 
 
 def sweep_table1(pkg, hip, stream) -> None:
@@ -225,6 +309,7 @@ def sweep_table1(pkg, hip, stream) -> None:
         if n in PAPER_TABLE1_S:
             conv, prop = PAPER_TABLE1_S[n]
             res["paper_i3_1thread_s"] = {"conventional": conv, "proposed": prop, "speedup": conv / prop}
+            res["cpu_oracle_1thread_s"] = cpu_table1_times(n, mark, k)
         pkg.grover_destroy(ctx)
         print(json.dumps(res), flush=True)
 
@@ -289,7 +374,7 @@ def sweep_precision(pkg, hip, stream) -> None:
                 "speedup_vs_plain_fp64": plain_ms / (ms / w.iterations)}), flush=True)
 
 
-def batch_config(pkg, n, m, marks):
+def batch_config(pkg, n, m, marks, update="f64"):
     import numpy as np
 
     g = pkg.grover
@@ -301,6 +386,7 @@ def batch_config(pkg, n, m, marks):
     cfg.m = keep[1].ctypes.data_as(ctypes.POINTER(ctypes.c_uint64))
     cfg.marked = keep[2].ctypes.data_as(ctypes.POINTER(ctypes.c_uint64))
     cfg.dtype = g.GROVER_C64
+    cfg.update = g.UPDATES[update]
     return cfg, keep
 
 
@@ -399,6 +485,102 @@ def sweep_batch(pkg, hip, stream, runs: int) -> None:
         "speedup_vs_plain_fp64_one_by_one": rate / one_by_one["c128_two_pass"]["amplitude_updates_per_s"],
         "speedup_vs_best_single_form_one_by_one": rate / one_by_one["c64_auto"]["amplitude_updates_per_s"],
     }), flush=True)
+
+
+def sweep_update(pkg, hip, stream, runs: int) -> None:
+    """The element update in binary32 (from 2S/N rounded to binary32) against binary64, complex64 storage and
+    binary64 sums, where the update's instruction count bounds the time: one workgroup holding the state
+    (n = 12), a held team (n = 16, 20, 22), the batch of 4096 searches (each update with its own tuned
+    tiling, replayed from a captured graph); and the fused form at n = 28 (bound by HBM, for contrast; 400
+    iterations).  For each: device time of one search (median of `runs`), amplitude-updates/s, and the error
+    of the final state against the exact iteration (the binary64 oracle's two-class values) and against the
+    oracle's model of that update.  One JSON line per case."""
+    import numpy as np
+
+    import oracle
+    import workloads
+
+    orc = oracle.default()
+    g = pkg.grover
+    for n, m, form in ((12, 2, "auto"), (16, 1, "auto"), (20, 1, "auto"), (22, 3, "auto"), (28, 8, "fused")):
+        marks = np.sort(workloads.distinct_marks(n, m, seed=4000 + n))
+        k = orc.optimal_iterations(n, m) if n < 28 else 400
+        N = 1 << n
+        a_ex, b_ex = orc.two_class(n, m, k)
+        res = {"sweep": "update", "n": n, "m": m, "iterations": k, "storage": "c64", "accum": "f64"}
+        for update in ("f64", "f32"):
+            cfg, keep = make_config(pkg, n, "c64", marks=marks, form=form, update=update)
+            ctx = pkg.grover_init(cfg, stream.value, 0, 0)
+            res["form"] = ["", "fused", "resident", "two_pass", "held"][pkg.grover_query(ctx, 0)]
+            pkg.grover_iterate(ctx, 1)
+            times = []
+            for _ in range(runs):
+                pkg.grover_reset(ctx)
+                e0, e1 = hip.event(), hip.event()
+                hip.lib.hipEventRecord(e0, stream)
+                pkg.grover_iterate(ctx, k)
+                hip.lib.hipEventRecord(e1, stream)
+                times.append(hip.elapsed_ms(e0, e1))
+                hip.destroy_events(e0, e1)
+            pkg.grover_sync(ctx)
+            ms = sorted(times)[len(times) // 2]
+            psi = np.empty(N, dtype=np.complex64)
+            pkg.grover_read_state(ctx, psi.ctypes.data, psi.nbytes)
+            pkg.grover_destroy(ctx)
+            a = complex(psi[int(marks[0])])
+            b = complex(psi[0 if 0 not in marks else int(np.setdiff1d(np.arange(8), marks)[0])])
+            del psi
+            a_md, b_md = orc.two_class_stored_update(n, m, k, 24, 24 if update == "f32" else 53)
+            res[update] = {"ms": round(ms, 4), "amplitude_updates_per_s": N * k / (ms / 1e3),
+                           "max_abs_err_vs_exact": max(abs(a - a_ex), abs(b - b_ex)),
+                           "max_abs_err_vs_oracle_model": max(abs(a - a_md), abs(b - b_md))}
+        res["speedup_f32_update"] = res["f64"]["ms"] / res["f32"]["ms"]
+        print(json.dumps(res), flush=True)
+        log(f"[bench] update n={n}: f64 {res['f64']['ms']:.3f} ms, f32 {res['f32']['ms']:.3f} ms")
+
+    w = workloads.BATCH_4096
+    n, m, marks = w.instances()
+    res = {"sweep": "update", "workload": w.name, "instances": w.count, "storage": "c64", "accum": "f64"}
+    for update in ("f64", "f32"):
+        cfg, keep = batch_config(pkg, n, m, marks, update=update)
+        b = pkg.grover_batch_init(cfg, stream.value)
+        updates = pkg.grover_batch_query(b, g.BQ_UPDATES)
+        split, team, resident, tuned_ms = pkg.grover_batch_tune(b)
+        pkg.grover_batch_capture(b)
+        pkg.grover_batch_run(b)
+        pkg.grover_batch_sync(b)
+        times = []
+        for _ in range(runs):
+            e0, e1 = hip.event(), hip.event()
+            hip.lib.hipEventRecord(e0, stream)
+            pkg.grover_batch_run(b)
+            hip.lib.hipEventRecord(e1, stream)
+            times.append(hip.elapsed_ms(e0, e1))
+            hip.destroy_events(e0, e1)
+        pkg.grover_batch_sync(b)
+        ms = sorted(times)[len(times) // 2]
+        worst_ex, worst_md = 0.0, 0.0
+        for i in range(w.count):
+            ni, mi = int(n[i]), int(m[i])
+            ki = orc.optimal_iterations(ni, mi)
+            psi = np.empty(1 << ni, dtype=np.complex64)
+            pkg.grover_batch_read_state(b, i, psi.ctypes.data, psi.nbytes)
+            mk = marks[i].astype(np.int64)
+            a = complex(psi[mk[0]])
+            um = np.ones(1 << ni, dtype=bool)
+            um[mk] = False
+            u = complex(psi[int(np.argmax(um))])
+            a_ex, u_ex = orc.two_class(ni, mi, ki)
+            a_md, u_md = orc.two_class_stored_update(ni, mi, ki, 24, 24 if update == "f32" else 53)
+            worst_ex = max(worst_ex, abs(a - a_ex), abs(u - u_ex))
+            worst_md = max(worst_md, abs(a - a_md), abs(u - u_md))
+        pkg.grover_batch_destroy(b)
+        res[update] = {"tiling": {"split_n": split, "team": team, "resident": resident}, "ms_per_run": round(ms, 3),
+                       "amplitude_updates_per_s": updates / (ms / 1e3), "max_abs_err_vs_exact": worst_ex,
+                       "max_abs_err_vs_oracle_model": worst_md}
+        log(f"[bench] update batch {update}: {ms:.2f} ms (tiling {split}/{team}/{resident})")
+    res["speedup_f32_update"] = res["f64"]["ms_per_run"] / res["f32"]["ms_per_run"]
+    print(json.dumps(res), flush=True)
 
 
 def sweep_adjoint(pkg, hip, stream, runs: int) -> None:
@@ -527,24 +709,37 @@ def main() -> int:
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-forms", action="store_true")
     ap.add_argument("--cpu-iters", type=int, default=40)
-    ap.add_argument("--sweep", choices=["table1", "precision", "batch", "adjoint"], default=None,
+    ap.add_argument("--cpu-all-iters", type=int, default=4,
+                    help="iterations per process of the all-core CPU baseline (one oracle process per host core)")
+    ap.add_argument("--cpu-worker", type=str, default=None, help=argparse.SUPPRESS)
+    ap.add_argument("--sweep", choices=["table1", "precision", "batch", "adjoint", "update"], default=None,
                     help="instead of the headline line, print one JSON line per point of a sweep")
     args = ap.parse_args()
+    if args.cpu_worker:
+        return cpu_worker(args.cpu_worker)
     if args.gpus != 1:
         print("bench.py runs on exactly one GPU: the state of a search is not sharded across GPUs; use --gpus 1",
               file=sys.stderr)
         return 2
 
-    import numpy as np
-
     import paper_2005_04635_amd as pkg
-    import workloads
 
     pkg.load()
     hip = Hip()
     hip.ok(hip.lib.hipSetDevice(0), "hipSetDevice")
     stream = ctypes.c_void_p()
     hip.ok(hip.lib.hipStreamCreate(ctypes.byref(stream)), "hipStreamCreate")
+    try:
+        return run(args, pkg, hip, stream)
+    finally:
+        hip.close(stream)
+
+
+def run(args, pkg, hip, stream) -> int:
+    import numpy as np
+
+    import workloads
+
     if args.sweep == "table1":
         sweep_table1(pkg, hip, stream)
         return 0
@@ -556,6 +751,9 @@ def main() -> int:
         return 0
     if args.sweep == "adjoint":
         sweep_adjoint(pkg, hip, stream, max(args.steps, 1))
+        return 0
+    if args.sweep == "update":
+        sweep_update(pkg, hip, stream, max(args.steps, 3))
         return 0
     w = workloads.HASH_N28
     N = 1 << w.n
@@ -606,9 +804,20 @@ def main() -> int:
     alg_bytes = 16.0 * N * w.iterations + 8.0 * N
     achieved = alg_bytes / (it_ms_mean / 1e3) / 1e9
     traffic = committed_traffic()
-    # the runtime's own device-to-device copy of the same 2 GiB (read + write), for context
+    # the measured ceiling of the fused kernel's access pattern: the bandwidth probe (same grid, tiles and
+    # nontemporal accesses, no arithmetic) over a buffer of the state's size, in-place read + write and
+    # read-only; and the runtime's own device-to-device copy of the same bytes, for context
     state_ptr, state_bytes = pkg.grover_state_device(ctx)
     dst = hip.malloc(state_bytes)
+    hip.ok(hip.lib.hipMemcpy(dst, ctypes.c_void_p(state_ptr), state_bytes, 3), "hipMemcpy D2D")
+    probe_passes = 20
+    pkg.grover_stream_probe(stream.value, dst.value, state_bytes, 2)  # warm
+    ceiling_gbs = (2.0 * state_bytes * probe_passes
+                   / (pkg.grover_stream_probe(stream.value, dst.value, state_bytes, probe_passes) / 1e3) / 1e9)
+    ceiling_read_gbs = (1.0 * state_bytes * probe_passes
+                        / (pkg.grover_stream_probe(stream.value, dst.value, state_bytes, probe_passes, True) / 1e3)
+                        / 1e9)
+    log(f"[bench] probe: in-place nontemporal stream {ceiling_gbs:.1f} GB/s, read-only {ceiling_read_gbs:.1f} GB/s")
     c0, c1 = hip.event(), hip.event()
     hip.lib.hipMemcpyAsync(dst, ctypes.c_void_p(state_ptr), state_bytes, 3, stream)
     hip.lib.hipEventRecord(c0, stream)
@@ -616,6 +825,7 @@ def main() -> int:
         hip.lib.hipMemcpyAsync(dst, ctypes.c_void_p(state_ptr), state_bytes, 3, stream)
     hip.lib.hipEventRecord(c1, stream)
     copy_gbs = 5 * 2 * state_bytes / (hip.elapsed_ms(c0, c1) / 1e3) / 1e9
+    hip.destroy_events(c0, c1)
     hip.lib.hipFree(dst)
     hip.lib.hipFree(u_dev)
     hip.lib.hipFree(out_dev)
@@ -632,8 +842,10 @@ def main() -> int:
 
     cpu = None
     if not args.no_cpu_baseline:
-        log(f"[bench] CPU oracle baseline: {args.cpu_iters} iterations at n={w.n}")
+        log(f"[bench] CPU oracle baseline: {args.cpu_iters} iterations at n={w.n}, one thread")
         cpu = cpu_baseline(w, marks, args.cpu_iters)
+        log(f"[bench] CPU oracle baseline on all host cores: {args.cpu_all_iters} iterations per process")
+        cpu = cpu_baseline_all_cores(w, args.cpu_all_iters, cpu)
 
     value = N * w.iterations / (ms_per_step / 1e3)
     plain = forms[0]["amplitude_updates_per_s"] if forms else None
@@ -656,9 +868,20 @@ def main() -> int:
                    "block": block, "parallelism": "single GPU"},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(achieved / HBM_PEAK_GBS, 4),
+                     "frac_basis": "algorithmic bytes (16 B per amplitude-update + 8 B per amplitude for the "
+                                   "prologue sum) per launch / kernel time; includes the bytes the kernel keeps on "
+                                   "chip (3 of each workgroup's tiles) and those the memory-side cache serves "
+                                   "(272 MiB of each pass)",
                      "traffic": traffic, "kernel": "fused_iterate_kernel<C64>",
                      "kernel_ms_per_launch": round(it_ms_mean, 3),
-                     "algorithmic_bytes_per_launch": alg_bytes},
+                     "algorithmic_bytes_per_launch": alg_bytes,
+                     "counter_gbs": round(traffic / (it_ms_mean / 1e3) / 1e9, 1) if traffic else None,
+                     "counter_frac": round(traffic / (it_ms_mean / 1e3) / 1e9 / HBM_PEAK_GBS, 4) if traffic else None,
+                     "ceiling_gbs": round(ceiling_gbs, 1), "ceiling_read_only_gbs": round(ceiling_read_gbs, 1),
+                     "frac_of_ceiling": round(achieved / ceiling_gbs, 4),
+                     "ceiling": "bandwidth probe in the same run: the fused kernel's grid, tiles and nontemporal "
+                                "16-byte loads and stores without its arithmetic, in place over 2 GiB, "
+                                f"{probe_passes} passes"},
         "runtime_copy_gbs": round(copy_gbs, 1),
         "vs_plain_fp64": (value / plain) if plain else None,
         "forms": forms,

@@ -204,6 +204,20 @@ int grover_sync(grover_ctx *ctx);
  * ordinary).  Results are identical either way. */
 int grover_query(grover_ctx *ctx, int key, int64_t *value);
 
+/* grover_stream_probe — measurement helper, not a step of the method: the bandwidth ceiling that the fused
+ * iteration (Algorithm 5's loop as one streaming pass per iteration) is measured against.  It runs the
+ * fused kernel's streaming skeleton without its arithmetic over a caller-owned device buffer: the same
+ * persistent grid (one 1024-thread workgroup per CU), 64 KiB tiles each owned by one workgroup in every
+ * pass, nontemporal 16-byte loads and stores.  Each pass negates every 16-byte vector in place (a read and a
+ * write of `bytes`), or, with read_only != 0, only reads it.  `passes` passes run in one launch on hip_stream
+ * (NULL = default stream), timed there with HIP events; the call synchronises and writes the elapsed
+ * milliseconds to *ms_out.
+ *   buf_dev  device, 16-byte aligned, bytes >= 16 (a tail shorter than 16 bytes is not touched); its values
+ *            are negated `passes` times (the same again after an even number).
+ * GROVER_E_INVAL for bad arguments, GROVER_E_HIP when a runtime call fails. */
+int grover_stream_probe(void *hip_stream, void *buf_dev, size_t bytes, uint32_t passes, int read_only,
+                        float *ms_out);
+
 /* grover_optimal_iterations — floor(pi/4 * sqrt(2^n / m)) (Algorithm 5's iteration count with m
  * solutions; the Fig. 2 example fixes the floor), 0 when m == 0 or m > 2^n or n > 63. */
 uint64_t grover_optimal_iterations(uint32_t n, uint64_t m);

@@ -1,0 +1,106 @@
+// Measured bandwidth ceiling of the fused iteration's memory access pattern (a measurement helper, not a
+// step of the paper's method).  The probe runs the fused kernel's streaming skeleton with the arithmetic
+// taken out: the same persistent grid (one 1024-thread workgroup per CU), the same tiles (four 16-byte
+// vectors per thread, tile t owned by workgroup t mod G for every pass) and the same nontemporal loads and
+// stores, each element negated in place (read + write), or only read.  What it reaches is what an in-place
+// streaming pass of this shape can reach on the device; the fused kernel's own rate is then read against it.
+#include "internal.h"
+
+namespace grover {
+namespace {
+
+constexpr int kBlock = 1024;
+constexpr int kUnroll = 4;
+constexpr int kTile = kBlock * kUnroll;
+
+template <bool WRITE>
+__global__ __launch_bounds__(kBlock) void stream_probe_kernel(float4 *st, uint64_t nvec, uint32_t passes,
+                                                              uint32_t *sink)
+{
+    const uint64_t ntiles = (nvec + kTile - 1) / kTile;
+    const unsigned tid = threadIdx.x;
+    uint32_t acc = 0u;
+    for (uint32_t p = 0; p < passes; ++p) {
+        for (uint64_t t = blockIdx.x; t < ntiles; t += gridDim.x) {
+            const uint64_t v0 = t * kTile;
+            float4 x[kUnroll];
+#pragma unroll
+            for (int u = 0; u < kUnroll; ++u) {
+                const uint64_t v = v0 + uint64_t(u) * kBlock + tid;
+                if (v < nvec)
+                    x[u] = load16<true>(st + v);
+            }
+#pragma unroll
+            for (int u = 0; u < kUnroll; ++u) {
+                const uint64_t v = v0 + uint64_t(u) * kBlock + tid;
+                if (v < nvec) {
+                    if (WRITE) {
+                        x[u].x = -x[u].x;
+                        x[u].y = -x[u].y;
+                        x[u].z = -x[u].z;
+                        x[u].w = -x[u].w;
+                        store16<true>(x[u], st + v);
+                    } else {
+                        acc ^= __float_as_uint(x[u].x) ^ __float_as_uint(x[u].y) ^ __float_as_uint(x[u].z) ^
+                               __float_as_uint(x[u].w);
+                    }
+                }
+            }
+        }
+    }
+    // the read-only probe must keep its loads: their values feed a store that (practically) never happens
+    if (!WRITE && acc == 0x9E3779B9u && sink)
+        sink[0] = acc;
+}
+
+}  // namespace
+}  // namespace grover
+
+using namespace grover;
+
+extern "C" int grover_stream_probe(void *hip_stream, void *buf_dev, size_t bytes, uint32_t passes, int read_only,
+                                   float *ms_out)
+{
+    if (!buf_dev || (reinterpret_cast<uintptr_t>(buf_dev) & 15u) != 0 || bytes < 16 || !ms_out)
+        return GROVER_E_INVAL;
+    hipStream_t stream = static_cast<hipStream_t>(hip_stream);
+    int dev = 0, cus = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e == hipSuccess)
+        e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+    if (e != hipSuccess)
+        return GROVER_E_HIP;
+    uint64_t nvec = bytes / 16;
+    const uint64_t ntiles = (nvec + kTile - 1) / kTile;
+    const unsigned grid = unsigned(uint64_t(cus > 0 ? cus : 1) < ntiles ? uint64_t(cus > 0 ? cus : 1) : ntiles);
+    float4 *st = static_cast<float4 *>(buf_dev);
+    uint32_t *sink = nullptr;  // never written in practice; a null sink disables the store altogether
+    void *args[] = {&st, &nvec, &passes, &sink};
+    const void *fn = read_only ? reinterpret_cast<const void *>(&stream_probe_kernel<false>)
+                               : reinterpret_cast<const void *>(&stream_probe_kernel<true>);
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    e = hipEventCreate(&e0);
+    if (e == hipSuccess)
+        e = hipEventCreate(&e1);
+    if (e == hipSuccess)
+        e = hipEventRecord(e0, stream);
+    if (e == hipSuccess)
+        e = hipLaunchKernel(fn, dim3(grid), dim3(kBlock), args, 0, stream);
+    if (e == hipSuccess)
+        e = hipEventRecord(e1, stream);
+    if (e == hipSuccess)
+        e = hipEventSynchronize(e1);
+    float ms = 0.0f;
+    if (e == hipSuccess)
+        e = hipEventElapsedTime(&ms, e0, e1);
+    if (e0)
+        (void)hipEventDestroy(e0);
+    if (e1)
+        (void)hipEventDestroy(e1);
+    if (e != hipSuccess) {
+        (void)hipGetLastError();
+        return GROVER_E_HIP;
+    }
+    *ms_out = ms;
+    return GROVER_OK;
+}

@@ -4,12 +4,16 @@
 //                   [--iters K] [--shots 1000000] [--shot-seed 11] [--steps 1]
 //   grover_cli run  --n 10 --dtype f64 --mark 123 ...          (explicit marked indices, repeatable)
 //   grover_cli copy --bytes 2147483648 [--reps 1]              (plain copy kernel of known size)
+//   grover_cli stream --bytes 2147483648 [--passes 20] [--read-only]
+//                   (the bandwidth probe: the fused kernel's access pattern without its arithmetic)
 //   grover_cli batch --instances FILE [--split S --team T [--resident V] | --tune] [--graph] [--runs R]
 //                   (many searches in one launch; FILE holds one instance per line: n m mark_1 ... mark_m)
 //   grover_cli phase --schedules FILE [--every S] [--team T] [--form auto|streamed|held] [--runs R]
 //                   (generalized iteration: forward runs and adjoint runs; FILE holds "n m K B", the m marks,
 //                    then B rows of K phases phi and B rows of K phases theta)
 //   run ... --calibrate-copy B                                  (also copy B bytes once, before the search)
+//   run ... --calibrate-stream B                                (and one in-place probe pass over B bytes)
+//   run ... --update f32, batch ... --update f32                (the element update in binary32)
 //
 // `run` creates a context, then per step: writes the uniform state, runs the iterations (timed with HIP
 // events on the context's stream), takes the norm and samples the shots with device-generated uniforms.
@@ -42,8 +46,11 @@ int usage()
             "                      [--form auto|fused|resident|two_pass|held]\n"
             "                      [--mark I ... | --hash-seed S --hash-bits B --m M] [--iters K]\n"
             "                      [--shots S] [--shot-seed U] [--steps T] [--calibrate-copy BYTES]\n"
+            "                      [--calibrate-stream BYTES] [--update f64|f32]\n"
             "       grover_cli copy --bytes B [--reps R]\n"
+            "       grover_cli stream --bytes B [--passes P] [--read-only]\n"
             "       grover_cli batch --instances FILE [--split S --team T [--resident V] | --tune] [--graph] [--runs R]\n"
+            "                        [--update f64|f32]\n"
             "       grover_cli phase --schedules FILE [--every S] [--team T] [--form auto|streamed|held] "
             "[--runs R]\n");
     return 2;
@@ -100,8 +107,43 @@ int run_copy(int argc, char **argv)
     printf("{\"mode\": \"copy\", \"bytes_read\": %" PRIu64 ", \"bytes_written\": %" PRIu64
            ", \"reps\": %d, \"ms\": %.4f, \"gbs\": %.1f}\n",
            n * 16, n * 16, reps, ms, 2.0 * n * 16 * reps / (ms / 1e3) / 1e9);
+    CHECK_HIP(hipEventDestroy(e0));
+    CHECK_HIP(hipEventDestroy(e1));
     CHECK_HIP(hipFree(a));
     CHECK_HIP(hipFree(b));
+    return 0;
+}
+
+// The bandwidth probe (grover_stream_probe): `passes` in-place nontemporal passes (or read-only) over a
+// buffer of `bytes`, in the fused kernel's access pattern.
+int run_stream(int argc, char **argv)
+{
+    uint64_t bytes = uint64_t(1) << 31;
+    uint32_t passes = 20;
+    int read_only = 0;
+    for (int i = 2; i < argc; ++i) {
+        if (!strcmp(argv[i], "--bytes") && i + 1 < argc)
+            bytes = strtoull(argv[++i], nullptr, 0);
+        else if (!strcmp(argv[i], "--passes") && i + 1 < argc)
+            passes = uint32_t(strtoul(argv[++i], nullptr, 0));
+        else if (!strcmp(argv[i], "--read-only"))
+            read_only = 1;
+        else
+            return usage();
+    }
+    void *buf = nullptr;
+    CHECK_HIP(hipMalloc(&buf, bytes));
+    CHECK_HIP(hipMemset(buf, 0, bytes));
+    CHECK_HIP(hipDeviceSynchronize());
+    float ms = 0.0f;
+    CHECK_GROVER(nullptr, grover_stream_probe(nullptr, buf, bytes, 1, read_only, &ms));  // warm
+    CHECK_GROVER(nullptr, grover_stream_probe(nullptr, buf, bytes, passes, read_only, &ms));
+    const double moved = double(bytes) * passes * (read_only ? 1.0 : 2.0);
+    printf("{\"mode\": \"stream\", \"bytes\": %" PRIu64 ", \"passes\": %u, \"read_only\": %s, \"ms\": %.4f"
+           ", \"gbs\": %.1f}\n",
+           bytes, passes, read_only ? "true" : "false", ms, moved / (ms / 1e3) / 1e9);
+    fflush(stdout);
+    CHECK_HIP(hipFree(buf));
     return 0;
 }
 
@@ -112,7 +154,7 @@ int run_search(int argc, char **argv)
     cfg.dtype = GROVER_C64;
     cfg.form = GROVER_FORM_AUTO;
     std::vector<uint64_t> marks;
-    uint64_t iters = UINT64_MAX, shots = 0, shot_seed = 1, calib_bytes = 0;
+    uint64_t iters = UINT64_MAX, shots = 0, shot_seed = 1, calib_bytes = 0, stream_bytes = 0;
     int steps = 1;
     bool hash = false;
     for (int i = 2; i < argc; ++i) {
@@ -155,6 +197,10 @@ int run_search(int argc, char **argv)
             steps = atoi(v);
         else if (k == "--calibrate-copy")
             calib_bytes = strtoull(v, nullptr, 0);
+        else if (k == "--calibrate-stream")
+            stream_bytes = strtoull(v, nullptr, 0);
+        else if (k == "--update")
+            cfg.update = !strcmp(v, "f32") ? GROVER_UPDATE_F32 : GROVER_UPDATE_F64;
         else
             return usage();
     }
@@ -173,6 +219,19 @@ int run_search(int argc, char **argv)
         CHECK_HIP(hipFree(ca));
         CHECK_HIP(hipFree(cb));
         fprintf(stderr, "[grover_cli] calibration copy of %" PRIu64 " bytes done\n", cn * 16);
+    }
+    if (stream_bytes > 0) {
+        // one in-place nontemporal pass of the bandwidth probe (the fused kernel's access pattern) over a
+        // buffer of known size, in the same process, for counter calibration of nontemporal accesses
+        void *buf = nullptr;
+        CHECK_HIP(hipMalloc(&buf, stream_bytes));
+        CHECK_HIP(hipMemset(buf, 0, stream_bytes));
+        CHECK_HIP(hipDeviceSynchronize());
+        float pms = 0.0f;
+        CHECK_GROVER(nullptr, grover_stream_probe(nullptr, buf, stream_bytes, 1, 0, &pms));
+        CHECK_HIP(hipFree(buf));
+        fprintf(stderr, "[grover_cli] calibration stream pass over %" PRIu64 " bytes done (%.3f ms)\n",
+                stream_bytes, pms);
     }
     if (hash) {
         cfg.oracle_kind = GROVER_ORACLE_HASH;
@@ -219,6 +278,10 @@ int run_search(int argc, char **argv)
         step_ms_sum += step_ms;
         fprintf(stderr, "[grover_cli] step %d/%d: iterate %.3f ms, step %.3f ms\n", s + 1, steps, it_ms, step_ms);
     }
+    CHECK_HIP(hipEventDestroy(e0));
+    CHECK_HIP(hipEventDestroy(e1));
+    CHECK_HIP(hipEventDestroy(s0));
+    CHECK_HIP(hipEventDestroy(s1));
     const double N = double(uint64_t(1) << cfg.n);
     const double it_ms = it_ms_sum / steps;
     printf("{\"mode\": \"run\", \"n\": %u, \"dtype\": %u, \"form\": %" PRId64 ", \"m\": %" PRIu64
@@ -250,6 +313,7 @@ int run_batch(int argc, char **argv)
     long split = -1, team = -1, resident = 0;
     int runs = 3;
     bool tune = false, graph = false;
+    uint32_t update = GROVER_UPDATE_F64;
     for (int i = 2; i < argc; ++i) {
         if (!strcmp(argv[i], "--instances") && i + 1 < argc)
             path = argv[++i];
@@ -265,6 +329,8 @@ int run_batch(int argc, char **argv)
             tune = true;
         else if (!strcmp(argv[i], "--graph"))
             graph = true;
+        else if (!strcmp(argv[i], "--update") && i + 1 < argc)
+            update = !strcmp(argv[++i], "f32") ? GROVER_UPDATE_F32 : GROVER_UPDATE_F64;
         else
             return usage();
     }
@@ -303,6 +369,7 @@ int run_batch(int argc, char **argv)
     cfg.m = ms.data();
     cfg.marked = marks.empty() ? nullptr : marks.data();
     cfg.dtype = GROVER_C64;
+    cfg.update = update;
     hipStream_t stream;
     CHECK_HIP(hipStreamCreate(&stream));
     grover_batch *b = nullptr;
@@ -336,6 +403,8 @@ int run_batch(int argc, char **argv)
         ms_sum += ms;
         fprintf(stderr, "[grover_cli] batch run %d/%d: %.3f ms\n", r + 1, runs, ms);
     }
+    CHECK_HIP(hipEventDestroy(e0));
+    CHECK_HIP(hipEventDestroy(e1));
     const double run_ms = ms_sum / runs;
     printf("{\"mode\": \"batch\", \"instances\": %zu, \"amplitude_updates\": %" PRId64 ", \"grid\": %" PRId64
            ", \"split_n\": %" PRId64 ", \"team\": %" PRId64 ", \"graph\": %s, \"runs\": %d, \"ms_per_run\": %.4f"
@@ -473,6 +542,9 @@ int run_phase(int argc, char **argv)
            fo == GROVER_PHASE_FORM_HELD ? "held" : "streamed", ev, runs, fsum / runs, bsum / runs,
            upd / (fsum / runs / 1e3), loss0);
     fflush(stdout);
+    CHECK_HIP(hipEventDestroy(e0));
+    CHECK_HIP(hipEventDestroy(e1));
+    CHECK_HIP(hipEventDestroy(e2));
     CHECK_HIP(hipFree(d_par));
     CHECK_HIP(hipFree(d_loss));
     CHECK_HIP(hipFree(d_dloss));
@@ -490,6 +562,8 @@ int main(int argc, char **argv)
         return usage();
     if (!strcmp(argv[1], "copy"))
         return run_copy(argc, argv);
+    if (!strcmp(argv[1], "stream"))
+        return run_stream(argc, argv);
     if (!strcmp(argv[1], "run"))
         return run_search(argc, argv);
     if (!strcmp(argv[1], "batch"))

@@ -133,6 +133,7 @@ EXPORTS = [
     "grover_state_device", "grover_marked", "grover_sync", "grover_query", "grover_optimal_iterations",
     "grover_destroy", "grover_status_str", "grover_last_error",
     "grover_gate_iterate_blocked", "grover_apply_hadamard_all_blocked", "grover_iterate_static",
+    "grover_stream_probe",
     "grover_batch_init", "grover_batch_set_tiling", "grover_batch_tune", "grover_batch_capture",
     "grover_batch_run", "grover_batch_sync", "grover_batch_state", "grover_batch_read_state",
     "grover_batch_query", "grover_batch_destroy", "grover_batch_last_error",
@@ -181,6 +182,7 @@ def load(path: str = LIB_PATH):
             "grover_optimal_iterations": (u64, [u32, u64]),
             "grover_destroy": (None, [P]),
             "grover_iterate_static": (i32, [P, P, u32, u32, P, u64, u64, P]),
+            "grover_stream_probe": (i32, [P, P, ctypes.c_size_t, u32, i32, ctypes.POINTER(ctypes.c_float)]),
             "grover_status_str": (ctypes.c_char_p, [i32]),
             "grover_last_error": (ctypes.c_char_p, [P]),
             "grover_batch_init": (i32, [ctypes.POINTER(P), ctypes.POINTER(grover_batch_config), P]),
@@ -317,6 +319,14 @@ def grover_iterate_static(hip_stream: int, state_dev: int, n: int, dtype: int, m
                           status_dev: int = 0) -> None:
     _check(None, load().grover_iterate_static(hip_stream or None, state_dev or None, n, dtype, marks_dev or None, m,
                                               k, status_dev or None))
+
+
+def grover_stream_probe(hip_stream: int, buf_dev: int, nbytes: int, passes: int, read_only: bool = False) -> float:
+    """Milliseconds for `passes` in-place (or read-only) streaming passes over a device buffer."""
+    ms = ctypes.c_float()
+    _check(None, load().grover_stream_probe(hip_stream or None, buf_dev or None, nbytes, passes, int(read_only),
+                                            ctypes.byref(ms)))
+    return ms.value
 
 
 def grover_status_str(status: int) -> str:
