@@ -2,8 +2,11 @@
 // step of the paper's method).  The probe runs the fused kernel's streaming skeleton with the arithmetic
 // taken out: the same persistent grid (one 1024-thread workgroup per CU), the same tiles (four 16-byte
 // vectors per thread, tile t owned by workgroup t mod G for every pass) and the same nontemporal loads and
-// stores, each element negated in place (read + write), or only read.  What it reaches is what an in-place
-// streaming pass of this shape can reach on the device; the fused kernel's own rate is then read against it.
+// stores, each element negated in place (read + write), or only read.  In one launch the workgroups run
+// through the passes freely; with one launch per pass, every pass starts only when the previous one has
+// ended everywhere, as the fused kernel's grid barrier makes every iteration do, so that the whole grid
+// streams one window of the buffer at a time.  What it reaches is what an in-place streaming pass of this
+// shape can reach on the device; the fused kernel's own rate is then read against it.
 #include "internal.h"
 
 namespace grover {
@@ -58,11 +61,14 @@ __global__ __launch_bounds__(kBlock) void stream_probe_kernel(float4 *st, uint64
 
 using namespace grover;
 
-extern "C" int grover_stream_probe(void *hip_stream, void *buf_dev, size_t bytes, uint32_t passes, int read_only,
+extern "C" int grover_stream_probe(void *hip_stream, void *buf_dev, size_t bytes, uint32_t passes, uint32_t mode,
                                    float *ms_out)
 {
-    if (!buf_dev || (reinterpret_cast<uintptr_t>(buf_dev) & 15u) != 0 || bytes < 16 || !ms_out)
+    if (!buf_dev || (reinterpret_cast<uintptr_t>(buf_dev) & 15u) != 0 || bytes < 16 || !ms_out ||
+        (mode & ~uint32_t(GROVER_PROBE_READ_ONLY | GROVER_PROBE_LAUNCH_PER_PASS)) != 0u)
         return GROVER_E_INVAL;
+    const bool read_only = (mode & GROVER_PROBE_READ_ONLY) != 0u;
+    const bool per_pass = (mode & GROVER_PROBE_LAUNCH_PER_PASS) != 0u;
     hipStream_t stream = static_cast<hipStream_t>(hip_stream);
     int dev = 0, cus = 0;
     hipError_t e = hipGetDevice(&dev);
@@ -75,7 +81,9 @@ extern "C" int grover_stream_probe(void *hip_stream, void *buf_dev, size_t bytes
     const unsigned grid = unsigned(uint64_t(cus > 0 ? cus : 1) < ntiles ? uint64_t(cus > 0 ? cus : 1) : ntiles);
     float4 *st = static_cast<float4 *>(buf_dev);
     uint32_t *sink = nullptr;  // never written in practice; a null sink disables the store altogether
-    void *args[] = {&st, &nvec, &passes, &sink};
+    uint32_t launch_passes = per_pass ? 1u : passes;
+    const uint32_t launches = per_pass ? passes : (passes > 0u ? 1u : 0u);
+    void *args[] = {&st, &nvec, &launch_passes, &sink};
     const void *fn = read_only ? reinterpret_cast<const void *>(&stream_probe_kernel<false>)
                                : reinterpret_cast<const void *>(&stream_probe_kernel<true>);
     hipEvent_t e0 = nullptr, e1 = nullptr;
@@ -84,7 +92,7 @@ extern "C" int grover_stream_probe(void *hip_stream, void *buf_dev, size_t bytes
         e = hipEventCreate(&e1);
     if (e == hipSuccess)
         e = hipEventRecord(e0, stream);
-    if (e == hipSuccess)
+    for (uint32_t l = 0; l < launches && e == hipSuccess; ++l)
         e = hipLaunchKernel(fn, dim3(grid), dim3(kBlock), args, 0, stream);
     if (e == hipSuccess)
         e = hipEventRecord(e1, stream);

@@ -4,7 +4,7 @@
 //                   [--iters K] [--shots 1000000] [--shot-seed 11] [--steps 1]
 //   grover_cli run  --n 10 --dtype f64 --mark 123 ...          (explicit marked indices, repeatable)
 //   grover_cli copy --bytes 2147483648 [--reps 1]              (plain copy kernel of known size)
-//   grover_cli stream --bytes 2147483648 [--passes 20] [--read-only]
+//   grover_cli stream --bytes 2147483648 [--passes 20] [--read-only] [--launch-per-pass]
 //                   (the bandwidth probe: the fused kernel's access pattern without its arithmetic)
 //   grover_cli batch --instances FILE [--split S --team T [--resident V] | --tune] [--graph] [--runs R]
 //                   (many searches in one launch; FILE holds one instance per line: n m mark_1 ... mark_m)
@@ -48,7 +48,7 @@ int usage()
             "                      [--shots S] [--shot-seed U] [--steps T] [--calibrate-copy BYTES]\n"
             "                      [--calibrate-stream BYTES] [--update f64|f32]\n"
             "       grover_cli copy --bytes B [--reps R]\n"
-            "       grover_cli stream --bytes B [--passes P] [--read-only]\n"
+            "       grover_cli stream --bytes B [--passes P] [--read-only] [--launch-per-pass]\n"
             "       grover_cli batch --instances FILE [--split S --team T [--resident V] | --tune] [--graph] [--runs R]\n"
             "                        [--update f64|f32]\n"
             "       grover_cli phase --schedules FILE [--every S] [--team T] [--form auto|streamed|held] "
@@ -121,6 +121,7 @@ int run_stream(int argc, char **argv)
     uint64_t bytes = uint64_t(1) << 31;
     uint32_t passes = 20;
     int read_only = 0;
+    uint32_t mode = 0;
     for (int i = 2; i < argc; ++i) {
         if (!strcmp(argv[i], "--bytes") && i + 1 < argc)
             bytes = strtoull(argv[++i], nullptr, 0);
@@ -128,20 +129,25 @@ int run_stream(int argc, char **argv)
             passes = uint32_t(strtoul(argv[++i], nullptr, 0));
         else if (!strcmp(argv[i], "--read-only"))
             read_only = 1;
+        else if (!strcmp(argv[i], "--launch-per-pass"))
+            mode |= GROVER_PROBE_LAUNCH_PER_PASS;
         else
             return usage();
     }
+    if (read_only)
+        mode |= GROVER_PROBE_READ_ONLY;
     void *buf = nullptr;
     CHECK_HIP(hipMalloc(&buf, bytes));
     CHECK_HIP(hipMemset(buf, 0, bytes));
     CHECK_HIP(hipDeviceSynchronize());
     float ms = 0.0f;
-    CHECK_GROVER(nullptr, grover_stream_probe(nullptr, buf, bytes, 1, read_only, &ms));  // warm
-    CHECK_GROVER(nullptr, grover_stream_probe(nullptr, buf, bytes, passes, read_only, &ms));
+    CHECK_GROVER(nullptr, grover_stream_probe(nullptr, buf, bytes, 1, mode, &ms));  // warm
+    CHECK_GROVER(nullptr, grover_stream_probe(nullptr, buf, bytes, passes, mode, &ms));
     const double moved = double(bytes) * passes * (read_only ? 1.0 : 2.0);
-    printf("{\"mode\": \"stream\", \"bytes\": %" PRIu64 ", \"passes\": %u, \"read_only\": %s, \"ms\": %.4f"
-           ", \"gbs\": %.1f}\n",
-           bytes, passes, read_only ? "true" : "false", ms, moved / (ms / 1e3) / 1e9);
+    printf("{\"mode\": \"stream\", \"bytes\": %" PRIu64 ", \"passes\": %u, \"read_only\": %s"
+           ", \"launch_per_pass\": %s, \"ms\": %.4f, \"gbs\": %.1f}\n",
+           bytes, passes, read_only ? "true" : "false", (mode & GROVER_PROBE_LAUNCH_PER_PASS) ? "true" : "false", ms,
+           moved / (ms / 1e3) / 1e9);
     fflush(stdout);
     CHECK_HIP(hipFree(buf));
     return 0;

@@ -182,7 +182,7 @@ def load(path: str = LIB_PATH):
             "grover_optimal_iterations": (u64, [u32, u64]),
             "grover_destroy": (None, [P]),
             "grover_iterate_static": (i32, [P, P, u32, u32, P, u64, u64, P]),
-            "grover_stream_probe": (i32, [P, P, ctypes.c_size_t, u32, i32, ctypes.POINTER(ctypes.c_float)]),
+            "grover_stream_probe": (i32, [P, P, ctypes.c_size_t, u32, u32, ctypes.POINTER(ctypes.c_float)]),
             "grover_status_str": (ctypes.c_char_p, [i32]),
             "grover_last_error": (ctypes.c_char_p, [P]),
             "grover_batch_init": (i32, [ctypes.POINTER(P), ctypes.POINTER(grover_batch_config), P]),
@@ -321,10 +321,13 @@ def grover_iterate_static(hip_stream: int, state_dev: int, n: int, dtype: int, m
                                               k, status_dev or None))
 
 
-def grover_stream_probe(hip_stream: int, buf_dev: int, nbytes: int, passes: int, read_only: bool = False) -> float:
+GROVER_PROBE_READ_ONLY, GROVER_PROBE_LAUNCH_PER_PASS = 1, 2
+
+
+def grover_stream_probe(hip_stream: int, buf_dev: int, nbytes: int, passes: int, mode: int = 0) -> float:
     """Milliseconds for `passes` in-place (or read-only) streaming passes over a device buffer."""
     ms = ctypes.c_float()
-    _check(None, load().grover_stream_probe(hip_stream or None, buf_dev or None, nbytes, passes, int(read_only),
+    _check(None, load().grover_stream_probe(hip_stream or None, buf_dev or None, nbytes, passes, mode,
                                             ctypes.byref(ms)))
     return ms.value
 
