@@ -209,16 +209,18 @@ int grover_query(grover_ctx *ctx, int key, int64_t *value);
  * fused kernel's streaming skeleton without its arithmetic over a caller-owned device buffer: the same
  * persistent grid (one 1024-thread workgroup per CU), 64 KiB tiles each owned by one workgroup in every
  * pass, nontemporal 16-byte loads and stores.  Each pass negates every 16-byte vector in place (a read and a
- * write of `bytes`), or, with GROVER_PROBE_READ_ONLY in `mode`, only reads it.  The `passes` passes run in
+ * write of `bytes`), or, with GROVER_PROBE_READ_ONLY in `mode`, only reads it, or, with
+ * GROVER_PROBE_WRITE_ONLY, only writes it (the pass number as values; not with READ_ONLY).  The `passes` passes run in
  * one launch (the workgroups move through them freely), or with GROVER_PROBE_LAUNCH_PER_PASS one launch
  * each (a pass starts when the previous one has ended everywhere, as after the fused kernel's grid barrier),
  * on hip_stream (NULL = default stream), timed there with HIP events; the call synchronises and writes the
  * elapsed milliseconds to *ms_out.
  *   buf_dev  device, 16-byte aligned, bytes >= 16 (a tail shorter than 16 bytes is not touched); its values
- *            are negated `passes` times (the same again after an even number).
+ *            are negated `passes` times (the same again after an even number), or overwritten (write-only).
  * GROVER_E_INVAL for bad arguments or unknown mode bits, GROVER_E_HIP when a runtime call fails. */
 #define GROVER_PROBE_READ_ONLY 1u
 #define GROVER_PROBE_LAUNCH_PER_PASS 2u
+#define GROVER_PROBE_WRITE_ONLY 4u
 int grover_stream_probe(void *hip_stream, void *buf_dev, size_t bytes, uint32_t passes, uint32_t mode,
                         float *ms_out);
 

@@ -16,7 +16,8 @@ constexpr int kBlock = 1024;
 constexpr int kUnroll = 4;
 constexpr int kTile = kBlock * kUnroll;
 
-template <bool WRITE>
+// WRITE: read, negate, write back; READ: only read; neither: only write (a constant).
+template <bool WRITE, bool READ = true>
 __global__ __launch_bounds__(kBlock) void stream_probe_kernel(float4 *st, uint64_t nvec, uint32_t passes,
                                                               uint32_t *sink)
 {
@@ -30,14 +31,20 @@ __global__ __launch_bounds__(kBlock) void stream_probe_kernel(float4 *st, uint64
 #pragma unroll
             for (int u = 0; u < kUnroll; ++u) {
                 const uint64_t v = v0 + uint64_t(u) * kBlock + tid;
-                if (v < nvec)
-                    x[u] = load16<true>(st + v);
+                if (v < nvec) {
+                    if (READ)
+                        x[u] = load16<true>(st + v);
+                    else
+                        x[u] = make_float4(float(p), 0.0f, float(p), 0.0f);
+                }
             }
 #pragma unroll
             for (int u = 0; u < kUnroll; ++u) {
                 const uint64_t v = v0 + uint64_t(u) * kBlock + tid;
                 if (v < nvec) {
-                    if (WRITE) {
+                    if (!READ) {
+                        store16<true>(x[u], st + v);
+                    } else if (WRITE) {
                         x[u].x = -x[u].x;
                         x[u].y = -x[u].y;
                         x[u].z = -x[u].z;
@@ -52,7 +59,7 @@ __global__ __launch_bounds__(kBlock) void stream_probe_kernel(float4 *st, uint64
         }
     }
     // the read-only probe must keep its loads: their values feed a store that (practically) never happens
-    if (!WRITE && acc == 0x9E3779B9u && sink)
+    if (READ && !WRITE && acc == 0x9E3779B9u && sink)
         sink[0] = acc;
 }
 
@@ -65,9 +72,11 @@ extern "C" int grover_stream_probe(void *hip_stream, void *buf_dev, size_t bytes
                                    float *ms_out)
 {
     if (!buf_dev || (reinterpret_cast<uintptr_t>(buf_dev) & 15u) != 0 || bytes < 16 || !ms_out ||
-        (mode & ~uint32_t(GROVER_PROBE_READ_ONLY | GROVER_PROBE_LAUNCH_PER_PASS)) != 0u)
+        (mode & ~uint32_t(GROVER_PROBE_READ_ONLY | GROVER_PROBE_LAUNCH_PER_PASS | GROVER_PROBE_WRITE_ONLY)) != 0u ||
+        (mode & GROVER_PROBE_READ_ONLY) && (mode & GROVER_PROBE_WRITE_ONLY))
         return GROVER_E_INVAL;
     const bool read_only = (mode & GROVER_PROBE_READ_ONLY) != 0u;
+    const bool write_only = (mode & GROVER_PROBE_WRITE_ONLY) != 0u;
     const bool per_pass = (mode & GROVER_PROBE_LAUNCH_PER_PASS) != 0u;
     hipStream_t stream = static_cast<hipStream_t>(hip_stream);
     int dev = 0, cus = 0;
@@ -84,8 +93,9 @@ extern "C" int grover_stream_probe(void *hip_stream, void *buf_dev, size_t bytes
     uint32_t launch_passes = per_pass ? 1u : passes;
     const uint32_t launches = per_pass ? passes : (passes > 0u ? 1u : 0u);
     void *args[] = {&st, &nvec, &launch_passes, &sink};
-    const void *fn = read_only ? reinterpret_cast<const void *>(&stream_probe_kernel<false>)
-                               : reinterpret_cast<const void *>(&stream_probe_kernel<true>);
+    const void *fn = read_only    ? reinterpret_cast<const void *>(&stream_probe_kernel<false>)
+                     : write_only ? reinterpret_cast<const void *>(&stream_probe_kernel<false, false>)
+                                  : reinterpret_cast<const void *>(&stream_probe_kernel<true>);
     hipEvent_t e0 = nullptr, e1 = nullptr;
     e = hipEventCreate(&e0);
     if (e == hipSuccess)

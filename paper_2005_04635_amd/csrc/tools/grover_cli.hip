@@ -4,7 +4,7 @@
 //                   [--iters K] [--shots 1000000] [--shot-seed 11] [--steps 1]
 //   grover_cli run  --n 10 --dtype f64 --mark 123 ...          (explicit marked indices, repeatable)
 //   grover_cli copy --bytes 2147483648 [--reps 1]              (plain copy kernel of known size)
-//   grover_cli stream --bytes 2147483648 [--passes 20] [--read-only] [--launch-per-pass]
+//   grover_cli stream --bytes 2147483648 [--passes 20] [--read-only | --write-only] [--launch-per-pass]
 //                   (the bandwidth probe: the fused kernel's access pattern without its arithmetic)
 //   grover_cli batch --instances FILE [--split S --team T [--resident V] | --tune] [--graph] [--runs R]
 //                   (many searches in one launch; FILE holds one instance per line: n m mark_1 ... mark_m)
@@ -48,7 +48,7 @@ int usage()
             "                      [--shots S] [--shot-seed U] [--steps T] [--calibrate-copy BYTES]\n"
             "                      [--calibrate-stream BYTES] [--update f64|f32]\n"
             "       grover_cli copy --bytes B [--reps R]\n"
-            "       grover_cli stream --bytes B [--passes P] [--read-only] [--launch-per-pass]\n"
+            "       grover_cli stream --bytes B [--passes P] [--read-only | --write-only] [--launch-per-pass]\n"
             "       grover_cli batch --instances FILE [--split S --team T [--resident V] | --tune] [--graph] [--runs R]\n"
             "                        [--update f64|f32]\n"
             "       grover_cli phase --schedules FILE [--every S] [--team T] [--form auto|streamed|held] "
@@ -131,6 +131,8 @@ int run_stream(int argc, char **argv)
             read_only = 1;
         else if (!strcmp(argv[i], "--launch-per-pass"))
             mode |= GROVER_PROBE_LAUNCH_PER_PASS;
+        else if (!strcmp(argv[i], "--write-only"))
+            mode |= GROVER_PROBE_WRITE_ONLY;
         else
             return usage();
     }
@@ -143,11 +145,12 @@ int run_stream(int argc, char **argv)
     float ms = 0.0f;
     CHECK_GROVER(nullptr, grover_stream_probe(nullptr, buf, bytes, 1, mode, &ms));  // warm
     CHECK_GROVER(nullptr, grover_stream_probe(nullptr, buf, bytes, passes, mode, &ms));
-    const double moved = double(bytes) * passes * (read_only ? 1.0 : 2.0);
-    printf("{\"mode\": \"stream\", \"bytes\": %" PRIu64 ", \"passes\": %u, \"read_only\": %s"
+    const bool write_only = (mode & GROVER_PROBE_WRITE_ONLY) != 0u;
+    const double moved = double(bytes) * passes * (read_only || write_only ? 1.0 : 2.0);
+    printf("{\"mode\": \"stream\", \"bytes\": %" PRIu64 ", \"passes\": %u, \"read_only\": %s, \"write_only\": %s"
            ", \"launch_per_pass\": %s, \"ms\": %.4f, \"gbs\": %.1f}\n",
-           bytes, passes, read_only ? "true" : "false", (mode & GROVER_PROBE_LAUNCH_PER_PASS) ? "true" : "false", ms,
-           moved / (ms / 1e3) / 1e9);
+           bytes, passes, read_only ? "true" : "false", write_only ? "true" : "false",
+           (mode & GROVER_PROBE_LAUNCH_PER_PASS) ? "true" : "false", ms, moved / (ms / 1e3) / 1e9);
     fflush(stdout);
     CHECK_HIP(hipFree(buf));
     return 0;
@@ -560,9 +563,29 @@ int run_phase(int argc, char **argv)
     return 0;
 }
 
-}  // namespace
+// With GROVER_CLI_MAPS=FILE in the environment, the process's memory map is copied to FILE when main
+// returns, so that addresses a crash handler prints after that (in exit-time destructors) can be matched
+// to the libraries that hold them.
+void save_maps()
+{
+    const char *path = getenv("GROVER_CLI_MAPS");
+    if (!path || !*path)
+        return;
+    FILE *in = fopen("/proc/self/maps", "r");
+    FILE *out = fopen(path, "w");
+    if (in && out) {
+        char buf[4096];
+        size_t n;
+        while ((n = fread(buf, 1, sizeof(buf), in)) > 0)
+            fwrite(buf, 1, n, out);
+    }
+    if (in)
+        fclose(in);
+    if (out)
+        fclose(out);
+}
 
-int main(int argc, char **argv)
+int dispatch(int argc, char **argv)
 {
     if (argc < 2)
         return usage();
@@ -577,4 +600,13 @@ int main(int argc, char **argv)
     if (!strcmp(argv[1], "phase"))
         return run_phase(argc, argv);
     return usage();
+}
+
+}  // namespace
+
+int main(int argc, char **argv)
+{
+    const int rc = dispatch(argc, argv);
+    save_maps();
+    return rc;
 }
