@@ -16,11 +16,13 @@ constexpr int kBlock = 1024;
 constexpr int kUnroll = 4;
 constexpr int kTile = kBlock * kUnroll;
 
-// WRITE: read, negate, write back; READ: only read; neither: only write (a constant).
-template <bool WRITE, bool READ = true>
-__global__ __launch_bounds__(kBlock) void stream_probe_kernel(float4 *st, uint64_t nvec, uint32_t passes,
-                                                              uint32_t *sink)
+// WRITE: read, negate, write back; READ: only read; neither: only write (a constant).  B threads per
+// workgroup, U vectors per thread per tile (B * U = kTile: 64 KiB tiles either way).
+template <bool WRITE, bool READ = true, int B = kBlock, int U = kUnroll>
+__global__ __launch_bounds__(B) void stream_probe_kernel(float4 *st, uint64_t nvec, uint32_t passes, uint32_t *sink)
 {
+    static_assert(B * U == kTile, "64 KiB tiles");
+    constexpr int kBlock = B, kUnroll = U;
     const uint64_t ntiles = (nvec + kTile - 1) / kTile;
     const unsigned tid = threadIdx.x;
     uint32_t acc = 0u;
@@ -72,11 +74,13 @@ extern "C" int grover_stream_probe(void *hip_stream, void *buf_dev, size_t bytes
                                    float *ms_out)
 {
     if (!buf_dev || (reinterpret_cast<uintptr_t>(buf_dev) & 15u) != 0 || bytes < 16 || !ms_out ||
-        (mode & ~uint32_t(GROVER_PROBE_READ_ONLY | GROVER_PROBE_LAUNCH_PER_PASS | GROVER_PROBE_WRITE_ONLY)) != 0u ||
+        (mode & ~uint32_t(GROVER_PROBE_READ_ONLY | GROVER_PROBE_LAUNCH_PER_PASS | GROVER_PROBE_WRITE_ONLY |
+                          GROVER_PROBE_WIDE)) != 0u ||
         (mode & GROVER_PROBE_READ_ONLY) && (mode & GROVER_PROBE_WRITE_ONLY))
         return GROVER_E_INVAL;
     const bool read_only = (mode & GROVER_PROBE_READ_ONLY) != 0u;
     const bool write_only = (mode & GROVER_PROBE_WRITE_ONLY) != 0u;
+    const bool wide = (mode & GROVER_PROBE_WIDE) != 0u;
     const bool per_pass = (mode & GROVER_PROBE_LAUNCH_PER_PASS) != 0u;
     hipStream_t stream = static_cast<hipStream_t>(hip_stream);
     int dev = 0, cus = 0;
@@ -93,9 +97,16 @@ extern "C" int grover_stream_probe(void *hip_stream, void *buf_dev, size_t bytes
     uint32_t launch_passes = per_pass ? 1u : passes;
     const uint32_t launches = per_pass ? passes : (passes > 0u ? 1u : 0u);
     void *args[] = {&st, &nvec, &launch_passes, &sink};
-    const void *fn = read_only    ? reinterpret_cast<const void *>(&stream_probe_kernel<false>)
-                     : write_only ? reinterpret_cast<const void *>(&stream_probe_kernel<false, false>)
-                                  : reinterpret_cast<const void *>(&stream_probe_kernel<true>);
+    const void *fn = nullptr;
+    if (wide)
+        fn = read_only    ? reinterpret_cast<const void *>(&stream_probe_kernel<false, true, 512, 8>)
+             : write_only ? reinterpret_cast<const void *>(&stream_probe_kernel<false, false, 512, 8>)
+                          : reinterpret_cast<const void *>(&stream_probe_kernel<true, true, 512, 8>);
+    else
+        fn = read_only    ? reinterpret_cast<const void *>(&stream_probe_kernel<false>)
+             : write_only ? reinterpret_cast<const void *>(&stream_probe_kernel<false, false>)
+                          : reinterpret_cast<const void *>(&stream_probe_kernel<true>);
+    const unsigned block = wide ? 512u : unsigned(kBlock);
     hipEvent_t e0 = nullptr, e1 = nullptr;
     e = hipEventCreate(&e0);
     if (e == hipSuccess)
@@ -103,7 +114,7 @@ extern "C" int grover_stream_probe(void *hip_stream, void *buf_dev, size_t bytes
     if (e == hipSuccess)
         e = hipEventRecord(e0, stream);
     for (uint32_t l = 0; l < launches && e == hipSuccess; ++l)
-        e = hipLaunchKernel(fn, dim3(grid), dim3(kBlock), args, 0, stream);
+        e = hipLaunchKernel(fn, dim3(grid), dim3(block), args, 0, stream);
     if (e == hipSuccess)
         e = hipEventRecord(e1, stream);
     if (e == hipSuccess)
