@@ -815,6 +815,7 @@ def run(args, pkg, hip, stream) -> int:
     probe = {}
     pkg.grover_stream_probe(stream.value, dst.value, state_bytes, 2)  # warm
     for name, mode, rw in (("in_place", 0, 2.0), ("in_place_launch_per_pass", g.GROVER_PROBE_LAUNCH_PER_PASS, 2.0),
+                           ("in_place_narrow", g.GROVER_PROBE_NARROW, 2.0),
                            ("read_only", g.GROVER_PROBE_READ_ONLY, 1.0),
                            ("read_only_launch_per_pass", g.GROVER_PROBE_READ_ONLY | g.GROVER_PROBE_LAUNCH_PER_PASS,
                             1.0)):
@@ -874,7 +875,7 @@ def run(args, pkg, hip, stream) -> int:
                      "frac": round(achieved / HBM_PEAK_GBS, 4),
                      "frac_basis": "algorithmic bytes (16 B per amplitude-update + 8 B per amplitude for the "
                                    "prologue sum) per launch / kernel time; includes the bytes the kernel keeps on "
-                                   "chip (3 of each workgroup's tiles) and those the memory-side cache serves "
+                                   "chip (6 of each workgroup's tiles) and those the memory-side cache serves "
                                    "(272 MiB of each pass)",
                      "traffic": traffic, "kernel": "fused_iterate_kernel<C64>",
                      "kernel_ms_per_launch": round(it_ms_mean, 3),
@@ -882,9 +883,10 @@ def run(args, pkg, hip, stream) -> int:
                      "counter_gbs": round(traffic / (it_ms_mean / 1e3) / 1e9, 1) if traffic else None,
                      "counter_frac": round(traffic / (it_ms_mean / 1e3) / 1e9 / HBM_PEAK_GBS, 4) if traffic else None,
                      "ceiling_gbs": ceiling_gbs, "frac_of_ceiling": round(achieved / ceiling_gbs, 4),
-                     "ceiling": "bandwidth probe in the same run: the fused kernel's grid, tiles and nontemporal "
-                                "16-byte loads and stores without its arithmetic over 2 GiB, "
-                                f"{probe_passes} passes; ceiling_gbs = the faster in-place form",
+                     "ceiling": "bandwidth probe in the same run: the fused kernel's grid, workgroup shape, tiles "
+                                "and nontemporal 16-byte loads and stores without its arithmetic over 2 GiB, "
+                                f"{probe_passes} passes; ceiling_gbs = the faster in-place form of that shape "
+                                "(in_place_narrow: 1024 threads of 4 vectors, for context)",
                      "probe_gbs": probe},
         "runtime_copy_gbs": round(copy_gbs, 1),
         "vs_plain_fp64": (value / plain) if plain else None,

@@ -207,13 +207,13 @@ int grover_query(grover_ctx *ctx, int key, int64_t *value);
 /* grover_stream_probe — measurement helper, not a step of the method: the bandwidth ceiling that the fused
  * iteration (Algorithm 5's loop as one streaming pass per iteration) is measured against.  It runs the
  * fused kernel's streaming skeleton without its arithmetic over a caller-owned device buffer: the same
- * persistent grid (one 1024-thread workgroup per CU), 64 KiB tiles each owned by one workgroup in every
- * pass, nontemporal 16-byte loads and stores.  Each pass negates every 16-byte vector in place (a read and a
+ * persistent grid (one 512-thread workgroup per CU), 64 KiB tiles each owned by one workgroup in every
+ * pass, eight nontemporal 16-byte loads and stores per thread and tile.  Each pass negates every 16-byte vector in place (a read and a
  * write of `bytes`), or, with GROVER_PROBE_READ_ONLY in `mode`, only reads it, or, with
  * GROVER_PROBE_WRITE_ONLY, only writes it (the pass number as values; not with READ_ONLY).  The `passes` passes run in
  * one launch (the workgroups move through them freely), or with GROVER_PROBE_LAUNCH_PER_PASS one launch
  * each (a pass starts when the previous one has ended everywhere, as after the fused kernel's grid barrier);
- * GROVER_PROBE_WIDE runs the same 64 KiB tiles with 512-thread workgroups and 8 vectors per thread,
+ * GROVER_PROBE_NARROW moves the same 64 KiB tiles with 1024-thread workgroups of 4 vectors per thread;
  * on hip_stream (NULL = default stream), timed there with HIP events; the call synchronises and writes the
  * elapsed milliseconds to *ms_out.
  *   buf_dev  device, 16-byte aligned, bytes >= 16 (a tail shorter than 16 bytes is not touched); its values
@@ -222,7 +222,7 @@ int grover_query(grover_ctx *ctx, int key, int64_t *value);
 #define GROVER_PROBE_READ_ONLY 1u
 #define GROVER_PROBE_LAUNCH_PER_PASS 2u
 #define GROVER_PROBE_WRITE_ONLY 4u
-#define GROVER_PROBE_WIDE 8u /* 512-thread workgroups with 8 vectors per thread per tile (same tiles) */
+#define GROVER_PROBE_NARROW 8u /* 1024-thread workgroups with 4 vectors per thread per tile (same tiles) */
 int grover_stream_probe(void *hip_stream, void *buf_dev, size_t bytes, uint32_t passes, uint32_t mode,
                         float *ms_out);
 

@@ -26,9 +26,21 @@
 namespace grover {
 namespace {
 
-constexpr int kBlock = 1024;  // one workgroup per CU: fewest barrier participants, 16 waves per CU
-constexpr int kUnroll = 4;    // 16-byte vectors per thread per tile
-constexpr int kTile = kBlock * kUnroll;
+// Tiles of 4096 16-byte vectors (64 KiB), moved by one persistent workgroup per CU in one of two shapes.
+// 512 threads of 8 vectors each (two waves per SIMD, so a thread may hold up to 256 VGPRs): on MI355X this
+// shape streams a 2 GiB in-place pass at 5.77 TB/s against 5.66 for 1024 threads of 4 vectors, and its
+// registers hold 4 tiles where the 1024-thread shape (128 VGPRs a thread) holds one; n = 28 complex64,
+// 27 complex128 and 27 binary64 searches ran 4.3-4.8 % faster with it.  Complex bfloat16, whose conversions
+// make it the most arithmetic per byte, keeps 1024 threads (the 512-thread shape ran 9 % slower at n = 27).
+constexpr int kTile = 4096;
+constexpr int kMaxBlock = 1024;
+
+template <class T>
+struct Shape {
+    static constexpr int block = T::EPV == 4 ? 1024 : 512;  // threads per workgroup
+    static constexpr int unroll = kTile / block;             // 16-byte vectors per thread per tile
+    static constexpr int reg_tiles = T::EPV == 4 ? 1 : 4;    // held tiles in registers (32 VGPRs each)
+};
 
 struct FusedArgs {
     void *state;
@@ -46,7 +58,7 @@ struct FusedArgs {
 
 template <class V>
 struct Shared {
-    V red[2 * (kBlock / kWave)];
+    V red[2 * (kMaxBlock / kWave)];
     V sum[2];
     int abort;
 };
@@ -102,8 +114,8 @@ __device__ inline bool wait_pair(const uint64_t *w, uint32_t tag, const FusedArg
 // reads the sum.  The LDS words are written again only after the first barrier of the next call, which
 // every thread reaches after its reads here, so no barrier is needed behind them.  Returns false when a
 // wait gave up.
-template <class V, bool ALL>
-__device__ bool grid_sum(V &xr, V &xi, const FusedArgs &a, uint64_t gen, Shared<V> &sh)
+template <class V, bool ALL, int B>
+__device__ __forceinline__ bool grid_sum(V &xr, V &xi, const FusedArgs &a, uint64_t gen, Shared<V> &sh)
 {
     const uint32_t tag = uint32_t(gen);
     const unsigned p = unsigned(gen & 1u);
@@ -119,7 +131,7 @@ __device__ bool grid_sum(V &xr, V &xi, const FusedArgs &a, uint64_t gen, Shared<
     __syncthreads();
     if (threadIdx.x == 0) {
         V sr = V(0), si = V(0);
-        for (unsigned w = 0; w < kBlock / kWave; ++w) {
+        for (unsigned w = 0; w < B / kWave; ++w) {
             sr += sh.red[2 * w];
             si += sh.red[2 * w + 1];
         }
@@ -206,17 +218,31 @@ constexpr int kMarkWords = 1024;  // LDS bitmap of this workgroup's tiles that h
 // nontemporal hint (+6 % measured on MI355X at n = 28), except in the first a.temporal_tiles unmarked tiles
 // of the share, whose ordinary accesses leave them in the memory-side cache for the next pass; without NT
 // (a state that fits that cache) every access is ordinary.  See kTemporalBytes.
-// A workgroup keeps the last kHeldTiles tiles of its share on chip for the whole launch: the very last in
-// registers (rt[u], kUnroll vectors per thread), the ones before it in LDS (each thread its own slots,
-// held[(h * kUnroll + u) * kBlock + tid], so no barrier guards them).  The launch's first pass loads them
+// A workgroup keeps the last held_tiles<T>() tiles of its share on chip for the whole launch: the last
+// reg_tiles<T>() in registers (rt[r][u], U vectors per thread each, always indexed by compile-time r and u
+// so that they stay in registers), the kLdsTiles before them in LDS (each thread its own slots,
+// held[(h * U + u) * B + tid], so no barrier guards them).  The launch's first pass loads them
 // while it sums them, every iteration then updates them in place, and the end of the launch writes them
 // back.  They are the last tiles each pass visits, so the additions happen in the same order as when they
-// stream and the results are identical; an iteration's memory traffic drops by kHeldTiles of the
-// workgroup's tiles (3/128 of it at n = 28 on 256 workgroups).
-constexpr int kHeldTiles = 3;
+// stream and the results are identical; an iteration's memory traffic drops by held_tiles<T>() of the
+// workgroup's tiles (6/128 of it at n = 28, complex64, on 256 workgroups; 3/64 for complex bfloat16).
+constexpr int kLdsTiles = 2;
+template <class T>
+constexpr int reg_tiles() { return Shape<T>::reg_tiles; }
+template <class T>
+constexpr int held_tiles() { return kLdsTiles + reg_tiles<T>(); }
 
-// First held tile (local index) of this workgroup's share of cnt tiles.
-__device__ inline uint64_t held_start(uint64_t cnt) { return cnt > uint64_t(kHeldTiles) ? cnt - kHeldTiles : 0; }
+// First held tile (local index) of this workgroup's share of cnt tiles, and the first held in registers.
+template <class T>
+__device__ inline uint64_t held_start(uint64_t cnt)
+{
+    return cnt > uint64_t(held_tiles<T>()) ? cnt - held_tiles<T>() : 0;
+}
+template <class T>
+__device__ inline uint64_t reg_start(uint64_t cnt)
+{
+    return cnt > uint64_t(reg_tiles<T>()) ? cnt - reg_tiles<T>() : 0;
+}
 
 // The update of one vector in the kernel's update precision: U32, binary32 from 2S/N rounded to binary32
 // (complex64 storage only); otherwise binary64, rounded once to the storage type.
@@ -235,32 +261,85 @@ template <class T, class A, bool UPDATE, bool NT, bool U32>
 __device__ __forceinline__ void plain_tile(typename T::vec *st, uint64_t v0, unsigned tid, double mr, double mi,
                                            float mr32, float mi32, A &acc)
 {
-    typename T::vec x[kUnroll];
+    constexpr int B = Shape<T>::block, U = Shape<T>::unroll;
+    typename T::vec x[U];
 #pragma unroll
-    for (int u = 0; u < kUnroll; ++u)
-        x[u] = load16<NT>(st + v0 + u * kBlock + tid);
+    for (int u = 0; u < U; ++u)
+        x[u] = load16<NT>(st + v0 + u * B + tid);
 #pragma unroll
-    for (int u = 0; u < kUnroll; ++u) {
+    for (int u = 0; u < U; ++u) {
         if (UPDATE) {
             update_one<T, U32>(x[u], mr, mi, mr32, mi32, 0u, acc);
-            store16<NT>(x[u], st + v0 + u * kBlock + tid);
+            store16<NT>(x[u], st + v0 + u * B + tid);
         } else {
             accum_vec<T>(x[u], 0u, acc);
         }
     }
 }
 
-template <class T, class A, bool UPDATE, bool NT, bool U32>
-__device__ inline void chunk_pass(const FusedArgs &a, const uint32_t *slow_tiles, bool table, double mr, double mi,
-                                  A &acc, typename T::vec *held, typename T::vec (&rt)[kUnroll])
+// One held tile in registers (local index j of the share), updated in place or, in the first pass, loaded
+// and summed; mp is the running position in the marked list, as in the streamed tiles.
+template <class T, class A, bool UPDATE, bool U32>
+__device__ __forceinline__ void reg_tile(const FusedArgs &a, const uint32_t *slow_tiles, bool table, double mr,
+                                         double mi, float mr32, float mi32, A &acc, uint64_t j, uint64_t &mp,
+                                         typename T::vec (&r)[Shape<T>::unroll])
 {
+    constexpr int B = Shape<T>::block, U = Shape<T>::unroll;
+    using V = typename T::vec;
+    V *st = static_cast<V *>(a.state);
+    const unsigned tid = threadIdx.x;
+    const uint64_t t = blockIdx.x + j * gridDim.x;
+    const uint64_t v0 = t * kTile;
+    const bool full = v0 + kTile <= a.nvec;
+    const bool marked = table ? ((slow_tiles[j >> 5] >> (j & 31)) & 1u) != 0u : a.m > 0;
+    uint64_t mq = mp;
+    bool in_regs = true;
+    uint64_t mk[kTileMarks];
+    if (!full || marked) {
+        mp = gallop_lower_bound(a.marks, mp, a.m, v0 * T::EPV);
+        mq = gallop_lower_bound(a.marks, mp, a.m, (v0 + kTile) * T::EPV);
+        in_regs = mq - mp <= uint64_t(kTileMarks);
+#pragma unroll
+        for (int q = 0; q < kTileMarks; ++q)
+            mk[q] = in_regs && mp + q < mq ? a.marks[mp + q] : ~uint64_t(0);
+    }
+    if (!UPDATE) {
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const uint64_t v = v0 + u * B + tid;
+            if (v < a.nvec)
+                r[u] = load16<true>(st + v);
+        }
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+        const uint64_t v = v0 + u * B + tid;
+        if (v < a.nvec) {
+            unsigned bits = 0u;
+            if (!full || marked)
+                bits = in_regs ? bits_from_regs<T::EPV>(mk, v * T::EPV) : marked_bits<T::EPV>(a.marks, mp, mq, v * T::EPV);
+            if (UPDATE)
+                update_one<T, U32>(r[u], mr, mi, mr32, mi32, bits, acc);
+            else
+                accum_vec<T>(r[u], bits, acc);
+        }
+    }
+    if (!full || marked)
+        mp = mq;
+}
+
+template <class T, class A, bool UPDATE, bool NT, bool U32>
+__device__ __forceinline__ void chunk_pass(const FusedArgs &a, const uint32_t *slow_tiles, bool table, double mr, double mi,
+                                  A &acc, typename T::vec *held, typename T::vec (&rt)[reg_tiles<T>()][Shape<T>::unroll])
+{
+    constexpr int B = Shape<T>::block, U = Shape<T>::unroll;
     using V = typename T::vec;
     const float mr32 = float(mr), mi32 = float(mi);  // the binary32 update's 2S/N (rounded to nearest even)
     V *st = static_cast<V *>(a.state);
     const unsigned tid = threadIdx.x;
     const uint64_t ntiles = (a.nvec + kTile - 1) / kTile;
     const uint64_t cnt = blockIdx.x < ntiles ? (ntiles - blockIdx.x + gridDim.x - 1) / gridDim.x : 0;
-    const uint64_t hstart = held_start(cnt);
+    const uint64_t hstart = held_start<T>(cnt);
     uint64_t mp = 0;  // marked entries before this position lie in tiles already visited
     for (uint64_t j = 0; j < hstart; ++j) {
         const uint64_t t = blockIdx.x + j * gridDim.x;
@@ -281,16 +360,16 @@ __device__ inline void chunk_pass(const FusedArgs &a, const uint32_t *slow_tiles
 #pragma unroll
             for (int q = 0; q < kTileMarks; ++q)
                 mk[q] = in_regs && mp + q < mq ? a.marks[mp + q] : ~uint64_t(0);
-            V x[kUnroll];
+            V x[U];
 #pragma unroll
-            for (int u = 0; u < kUnroll; ++u) {
-                const uint64_t v = v0 + u * kBlock + tid;
+            for (int u = 0; u < U; ++u) {
+                const uint64_t v = v0 + u * B + tid;
                 if (v < a.nvec)
                     x[u] = load16<NT>(st + v);
             }
 #pragma unroll
-            for (int u = 0; u < kUnroll; ++u) {
-                const uint64_t v = v0 + u * kBlock + tid;
+            for (int u = 0; u < U; ++u) {
+                const uint64_t v = v0 + u * B + tid;
                 if (v < a.nvec) {
                     const unsigned bits = in_regs ? bits_from_regs<T::EPV>(mk, v * T::EPV)
                                                   : marked_bits<T::EPV>(a.marks, mp, mq, v * T::EPV);
@@ -306,9 +385,9 @@ __device__ inline void chunk_pass(const FusedArgs &a, const uint32_t *slow_tiles
         }
     }
     // the held tiles: the same arithmetic on the thread's LDS slots (loaded from memory by the first pass),
-    // then on the last tile, kept in registers
-    const uint64_t rlast = cnt > 0 ? cnt - 1 : 0;  // the register tile (when cnt > 0)
-    for (uint64_t j = hstart; j < rlast; ++j) {
+    // then on the last tiles, kept in registers
+    const uint64_t rstart = reg_start<T>(cnt);
+    for (uint64_t j = hstart; j < rstart; ++j) {
         V *hv = held + (j - hstart) * kTile;
         const uint64_t t = blockIdx.x + j * gridDim.x;
         const uint64_t v0 = t * kTile;
@@ -325,22 +404,22 @@ __device__ inline void chunk_pass(const FusedArgs &a, const uint32_t *slow_tiles
             for (int q = 0; q < kTileMarks; ++q)
                 mk[q] = in_regs && mp + q < mq ? a.marks[mp + q] : ~uint64_t(0);
         }
-        V x[kUnroll];
+        V x[U];
 #pragma unroll
-        for (int u = 0; u < kUnroll; ++u) {
-            const uint64_t v = v0 + u * kBlock + tid;
+        for (int u = 0; u < U; ++u) {
+            const uint64_t v = v0 + u * B + tid;
             if (v < a.nvec) {
                 if (UPDATE) {
-                    x[u] = hv[u * kBlock + tid];
+                    x[u] = hv[u * B + tid];
                 } else {
                     x[u] = load16<true>(st + v);
-                    hv[u * kBlock + tid] = x[u];
+                    hv[u * B + tid] = x[u];
                 }
             }
         }
 #pragma unroll
-        for (int u = 0; u < kUnroll; ++u) {
-            const uint64_t v = v0 + u * kBlock + tid;
+        for (int u = 0; u < U; ++u) {
+            const uint64_t v = v0 + u * B + tid;
             if (v < a.nvec) {
                 unsigned bits = 0u;
                 if (!full || marked)
@@ -348,7 +427,7 @@ __device__ inline void chunk_pass(const FusedArgs &a, const uint32_t *slow_tiles
                                    : marked_bits<T::EPV>(a.marks, mp, mq, v * T::EPV);
                 if (UPDATE) {
                     update_one<T, U32>(x[u], mr, mi, mr32, mi32, bits, acc);
-                    hv[u * kBlock + tid] = x[u];
+                    hv[u * B + tid] = x[u];
                 } else {
                     accum_vec<T>(x[u], bits, acc);
                 }
@@ -357,60 +436,23 @@ __device__ inline void chunk_pass(const FusedArgs &a, const uint32_t *slow_tiles
         if (!full || marked)
             mp = mq;
     }
-    if (cnt > 0) {
-        const uint64_t j = rlast;
-        const uint64_t t = blockIdx.x + j * gridDim.x;
-        const uint64_t v0 = t * kTile;
-        const bool full = v0 + kTile <= a.nvec;
-        const bool marked = table ? ((slow_tiles[j >> 5] >> (j & 31)) & 1u) != 0u : a.m > 0;
-        uint64_t mq = mp;
-        bool in_regs = true;
-        uint64_t mk[kTileMarks];
-        if (!full || marked) {
-            mp = gallop_lower_bound(a.marks, mp, a.m, v0 * T::EPV);
-            mq = gallop_lower_bound(a.marks, mp, a.m, (v0 + kTile) * T::EPV);
-            in_regs = mq - mp <= uint64_t(kTileMarks);
 #pragma unroll
-            for (int q = 0; q < kTileMarks; ++q)
-                mk[q] = in_regs && mp + q < mq ? a.marks[mp + q] : ~uint64_t(0);
-        }
-        if (!UPDATE) {
-#pragma unroll
-            for (int u = 0; u < kUnroll; ++u) {
-                const uint64_t v = v0 + u * kBlock + tid;
-                if (v < a.nvec)
-                    rt[u] = load16<true>(st + v);
-            }
-        }
-#pragma unroll
-        for (int u = 0; u < kUnroll; ++u) {
-            const uint64_t v = v0 + u * kBlock + tid;
-            if (v < a.nvec) {
-                unsigned bits = 0u;
-                if (!full || marked)
-                    bits = in_regs ? bits_from_regs<T::EPV>(mk, v * T::EPV)
-                                   : marked_bits<T::EPV>(a.marks, mp, mq, v * T::EPV);
-                if (UPDATE)
-                    update_one<T, U32>(rt[u], mr, mi, mr32, mi32, bits, acc);
-                else
-                    accum_vec<T>(rt[u], bits, acc);
-            }
-        }
-        if (!full || marked)
-            mp = mq;
-    }
+    for (int r = 0; r < reg_tiles<T>(); ++r)
+        if (rstart + uint64_t(r) < cnt)
+            reg_tile<T, A, UPDATE, U32>(a, slow_tiles, table, mr, mi, mr32, mi32, acc, rstart + uint64_t(r), mp, rt[r]);
 }
 
 // CHECK only names a second, code-identical instantiation used for the residency check at context
 // creation, so that profiles list it apart from the iteration launches.
 template <class T, class A, bool CHECK, bool NT, bool U32>
-__global__ __launch_bounds__(kBlock) void fused_iterate_kernel(FusedArgs a)
+__global__ __launch_bounds__(Shape<T>::block) void fused_iterate_kernel(FusedArgs a)
 {
+    constexpr int B = Shape<T>::block, U = Shape<T>::unroll;
     using Val = typename A::value;
     __shared__ Shared<Val> sh;
     __shared__ uint32_t slow_tiles[kMarkWords];
-    __shared__ typename T::vec held[(kHeldTiles - 1) * kTile];  // held tiles but the last, in LDS
-    typename T::vec rt[kUnroll];                                 // the last held tile, in registers
+    __shared__ typename T::vec held[kLdsTiles * kTile];  // held tiles in LDS
+    typename T::vec rt[reg_tiles<T>()][U];               // the last held tiles, in registers
     // A launch enqueued behind a failure (a wait that gave up, or input rejected on the device) leaves the
     // state as it is; the error word is cleared before the next launch that should run.  Thread 0 decides
     // for the whole workgroup (the word may change while its threads read it); grid_sum writes sh.abort
@@ -423,12 +465,12 @@ __global__ __launch_bounds__(kBlock) void fused_iterate_kernel(FusedArgs a)
     // Table of this workgroup's tiles that hold marked amplitudes, built once per launch.
     const uint64_t ntiles = (a.nvec + kTile - 1) / kTile;
     const uint64_t cnt = blockIdx.x < ntiles ? (ntiles - blockIdx.x + gridDim.x - 1) / gridDim.x : 0;
-    const bool table = cnt <= uint64_t(kMarkWords) * 32u && a.m <= uint64_t(64) * kBlock;
+    const bool table = cnt <= uint64_t(kMarkWords) * 32u && a.m <= uint64_t(64) * B;
     if (table) {
-        for (unsigned w = threadIdx.x; w < kMarkWords; w += kBlock)
+        for (unsigned w = threadIdx.x; w < kMarkWords; w += B)
             slow_tiles[w] = 0u;
         __syncthreads();
-        for (uint64_t q = threadIdx.x; q < a.m; q += kBlock) {
+        for (uint64_t q = threadIdx.x; q < a.m; q += B) {
             const uint64_t t = a.marks[q] / T::EPV / kTile;
             if (t < ntiles && t % gridDim.x == blockIdx.x) {
                 const uint64_t j = t / gridDim.x;
@@ -440,7 +482,7 @@ __global__ __launch_bounds__(kBlock) void fused_iterate_kernel(FusedArgs a)
     A acc0;
     chunk_pass<T, A, false, NT, U32>(a, slow_tiles, table, 0.0, 0.0, acc0, held, rt);
     Val sr = acc0.res_r(), si = acc0.res_i();
-    if (!grid_sum<Val, !NT>(sr, si, a, a.gen0 + 1u, sh))
+    if (!grid_sum<Val, !NT, B>(sr, si, a, a.gen0 + 1u, sh))
         return;
     for (uint64_t it = 0; it < a.iters; ++it) {
         const double mr = (double(sr) * 2.0) / a.N, mi = (double(si) * 2.0) / a.N;
@@ -448,29 +490,33 @@ __global__ __launch_bounds__(kBlock) void fused_iterate_kernel(FusedArgs a)
         chunk_pass<T, A, true, NT, U32>(a, slow_tiles, table, mr, mi, acc, held, rt);
         sr = acc.res_r();
         si = acc.res_i();
-        if (!grid_sum<Val, !NT>(sr, si, a, a.gen0 + 2u + it, sh))
+        if (!grid_sum<Val, !NT, B>(sr, si, a, a.gen0 + 2u + it, sh))
             return;
     }
     if (a.iters > 0) {  // the held tiles go back to memory
         using V = typename T::vec;
         V *st = static_cast<V *>(a.state);
-        for (uint64_t j = held_start(cnt); j + 1 < cnt; ++j) {
-            const V *hv = held + (j - held_start(cnt)) * kTile;
+        for (uint64_t j = held_start<T>(cnt); j < reg_start<T>(cnt); ++j) {
+            const V *hv = held + (j - held_start<T>(cnt)) * kTile;
             const uint64_t v0 = (blockIdx.x + j * gridDim.x) * kTile;
 #pragma unroll
-            for (int u = 0; u < kUnroll; ++u) {
-                const uint64_t v = v0 + u * kBlock + threadIdx.x;
+            for (int u = 0; u < U; ++u) {
+                const uint64_t v = v0 + u * B + threadIdx.x;
                 if (v < a.nvec)
-                    store16<true>(hv[u * kBlock + threadIdx.x], st + v);
+                    store16<true>(hv[u * B + threadIdx.x], st + v);
             }
         }
-        if (cnt > 0) {
-            const uint64_t v0 = (blockIdx.x + (cnt - 1) * gridDim.x) * kTile;
 #pragma unroll
-            for (int u = 0; u < kUnroll; ++u) {
-                const uint64_t v = v0 + u * kBlock + threadIdx.x;
-                if (v < a.nvec)
-                    store16<true>(rt[u], st + v);
+        for (int r = 0; r < reg_tiles<T>(); ++r) {
+            const uint64_t j = reg_start<T>(cnt) + uint64_t(r);
+            if (j < cnt) {
+                const uint64_t v0 = (blockIdx.x + j * gridDim.x) * kTile;
+#pragma unroll
+                for (int u = 0; u < U; ++u) {
+                    const uint64_t v = v0 + u * B + threadIdx.x;
+                    if (v < a.nvec)
+                        store16<true>(rt[r][u], st + v);
+                }
             }
         }
     }
@@ -520,6 +566,12 @@ const void *kernel_for(uint32_t dtype, uint32_t accum, bool temporal, uint32_t u
 // margin below the size where the gain vanishes.
 constexpr uint64_t kTemporalBytes = uint64_t(272) << 20;
 
+// Threads per workgroup of the fused kernel for a storage type.
+int fused_block(uint32_t dtype)
+{
+    return dtype == GROVER_CBF16 ? Shape<CBF16>::block : Shape<C64>::block;
+}
+
 }  // namespace
 
 hipError_t fused_configure(grover_ctx *c, int *per_cu, int *block, int64_t *forced_grid)
@@ -546,10 +598,10 @@ hipError_t fused_configure(grover_ctx *c, int *per_cu, int *block, int64_t *forc
         return e;
     if (!coop)
         return hipErrorCooperativeLaunchTooLarge;
-    e = hipOccupancyMaxActiveBlocksPerMultiprocessor(per_cu, k, kBlock, 0);
+    e = hipOccupancyMaxActiveBlocksPerMultiprocessor(per_cu, k, fused_block(c->dtype), 0);
     if (e != hipSuccess)
         return e;
-    *block = kBlock;
+    *block = fused_block(c->dtype);
     *forced_grid = 0;
     if (const char *env = getenv("GROVER_FUSED_GRID")) {
         const long long want = atoll(env);
@@ -588,7 +640,7 @@ hipError_t launch_fused_external(const FusedExternal &x)
     a.timeout_ticks = x.timeout_ticks;
     a.temporal_tiles = kTemporalBytes / (uint64_t(x.grid) * kTile * 16u);
     void *args[] = {&a};
-    return hipLaunchCooperativeKernel(fn, dim3(x.grid), dim3(kBlock), args, 0, x.stream);
+    return hipLaunchCooperativeKernel(fn, dim3(x.grid), dim3(fused_block(x.dtype)), args, 0, x.stream);
 }
 
 uint64_t fused_tiles(const grover_ctx *c)

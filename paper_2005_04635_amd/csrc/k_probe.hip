@@ -1,8 +1,11 @@
 // Measured bandwidth ceiling of the fused iteration's memory access pattern (a measurement helper, not a
 // step of the paper's method).  The probe runs the fused kernel's streaming skeleton with the arithmetic
-// taken out: the same persistent grid (one 1024-thread workgroup per CU), the same tiles (four 16-byte
+// taken out: the same persistent grid (one 512-thread workgroup per CU), the same tiles (eight 16-byte
 // vectors per thread, tile t owned by workgroup t mod G for every pass) and the same nontemporal loads and
-// stores, each element negated in place (read + write), or only read.  In one launch the workgroups run
+// stores, each element negated in place (read + write), or only read; full tiles take the same unchecked
+// path as the fused kernel's (per-vector bounds checks on every tile cost the stream 6 %, 5.40 against 5.73
+// TB/s in place on MI355X).  The narrow form moves the same tiles with 1024 threads of four vectors each,
+// the shape the fused kernel had before (5.66 against 5.77 TB/s in place).  In one launch the workgroups run
 // through the passes freely; with one launch per pass, every pass starts only when the previous one has
 // ended everywhere, as the fused kernel's grid barrier makes every iteration do, so that the whole grid
 // streams one window of the buffer at a time.  What it reaches is what an in-place streaming pass of this
@@ -12,9 +15,11 @@
 namespace grover {
 namespace {
 
-constexpr int kBlock = 1024;
-constexpr int kUnroll = 4;
+constexpr int kBlock = 512;
+constexpr int kUnroll = 8;
 constexpr int kTile = kBlock * kUnroll;
+constexpr int kNarrowBlock = 1024;
+constexpr int kNarrowUnroll = 4;
 
 // WRITE: read, negate, write back; READ: only read; neither: only write (a constant).  B threads per
 // workgroup, U vectors per thread per tile (B * U = kTile: 64 KiB tiles either way).
@@ -26,36 +31,45 @@ __global__ __launch_bounds__(B) void stream_probe_kernel(float4 *st, uint64_t nv
     const uint64_t ntiles = (nvec + kTile - 1) / kTile;
     const unsigned tid = threadIdx.x;
     uint32_t acc = 0u;
+    auto visit = [&](float4 (&x)[kUnroll], uint64_t v, int u) {
+        if (!READ) {
+            store16<true>(x[u], st + v);
+        } else if (WRITE) {
+            x[u].x = -x[u].x;
+            x[u].y = -x[u].y;
+            x[u].z = -x[u].z;
+            x[u].w = -x[u].w;
+            store16<true>(x[u], st + v);
+        } else {
+            acc ^= __float_as_uint(x[u].x) ^ __float_as_uint(x[u].y) ^ __float_as_uint(x[u].z) ^
+                   __float_as_uint(x[u].w);
+        }
+    };
     for (uint32_t p = 0; p < passes; ++p) {
         for (uint64_t t = blockIdx.x; t < ntiles; t += gridDim.x) {
             const uint64_t v0 = t * kTile;
             float4 x[kUnroll];
+            if (v0 + kTile <= nvec) {
+                // a full tile, like the fused kernel's: no bounds checks
 #pragma unroll
-            for (int u = 0; u < kUnroll; ++u) {
-                const uint64_t v = v0 + uint64_t(u) * kBlock + tid;
-                if (v < nvec) {
-                    if (READ)
-                        x[u] = load16<true>(st + v);
-                    else
-                        x[u] = make_float4(float(p), 0.0f, float(p), 0.0f);
+                for (int u = 0; u < kUnroll; ++u)
+                    x[u] = READ ? load16<true>(st + v0 + uint64_t(u) * kBlock + tid)
+                                : make_float4(float(p), 0.0f, float(p), 0.0f);
+#pragma unroll
+                for (int u = 0; u < kUnroll; ++u)
+                    visit(x, v0 + uint64_t(u) * kBlock + tid, u);
+            } else {
+#pragma unroll
+                for (int u = 0; u < kUnroll; ++u) {
+                    const uint64_t v = v0 + uint64_t(u) * kBlock + tid;
+                    if (v < nvec)
+                        x[u] = READ ? load16<true>(st + v) : make_float4(float(p), 0.0f, float(p), 0.0f);
                 }
-            }
 #pragma unroll
-            for (int u = 0; u < kUnroll; ++u) {
-                const uint64_t v = v0 + uint64_t(u) * kBlock + tid;
-                if (v < nvec) {
-                    if (!READ) {
-                        store16<true>(x[u], st + v);
-                    } else if (WRITE) {
-                        x[u].x = -x[u].x;
-                        x[u].y = -x[u].y;
-                        x[u].z = -x[u].z;
-                        x[u].w = -x[u].w;
-                        store16<true>(x[u], st + v);
-                    } else {
-                        acc ^= __float_as_uint(x[u].x) ^ __float_as_uint(x[u].y) ^ __float_as_uint(x[u].z) ^
-                               __float_as_uint(x[u].w);
-                    }
+                for (int u = 0; u < kUnroll; ++u) {
+                    const uint64_t v = v0 + uint64_t(u) * kBlock + tid;
+                    if (v < nvec)
+                        visit(x, v, u);
                 }
             }
         }
@@ -75,12 +89,12 @@ extern "C" int grover_stream_probe(void *hip_stream, void *buf_dev, size_t bytes
 {
     if (!buf_dev || (reinterpret_cast<uintptr_t>(buf_dev) & 15u) != 0 || bytes < 16 || !ms_out ||
         (mode & ~uint32_t(GROVER_PROBE_READ_ONLY | GROVER_PROBE_LAUNCH_PER_PASS | GROVER_PROBE_WRITE_ONLY |
-                          GROVER_PROBE_WIDE)) != 0u ||
+                          GROVER_PROBE_NARROW)) != 0u ||
         (mode & GROVER_PROBE_READ_ONLY) && (mode & GROVER_PROBE_WRITE_ONLY))
         return GROVER_E_INVAL;
     const bool read_only = (mode & GROVER_PROBE_READ_ONLY) != 0u;
     const bool write_only = (mode & GROVER_PROBE_WRITE_ONLY) != 0u;
-    const bool wide = (mode & GROVER_PROBE_WIDE) != 0u;
+    const bool narrow = (mode & GROVER_PROBE_NARROW) != 0u;
     const bool per_pass = (mode & GROVER_PROBE_LAUNCH_PER_PASS) != 0u;
     hipStream_t stream = static_cast<hipStream_t>(hip_stream);
     int dev = 0, cus = 0;
@@ -98,15 +112,16 @@ extern "C" int grover_stream_probe(void *hip_stream, void *buf_dev, size_t bytes
     const uint32_t launches = per_pass ? passes : (passes > 0u ? 1u : 0u);
     void *args[] = {&st, &nvec, &launch_passes, &sink};
     const void *fn = nullptr;
-    if (wide)
-        fn = read_only    ? reinterpret_cast<const void *>(&stream_probe_kernel<false, true, 512, 8>)
-             : write_only ? reinterpret_cast<const void *>(&stream_probe_kernel<false, false, 512, 8>)
-                          : reinterpret_cast<const void *>(&stream_probe_kernel<true, true, 512, 8>);
+    constexpr int NB = kNarrowBlock, NU = kNarrowUnroll;
+    if (narrow)
+        fn = read_only    ? reinterpret_cast<const void *>(&stream_probe_kernel<false, true, NB, NU>)
+             : write_only ? reinterpret_cast<const void *>(&stream_probe_kernel<false, false, NB, NU>)
+                          : reinterpret_cast<const void *>(&stream_probe_kernel<true, true, NB, NU>);
     else
         fn = read_only    ? reinterpret_cast<const void *>(&stream_probe_kernel<false>)
              : write_only ? reinterpret_cast<const void *>(&stream_probe_kernel<false, false>)
                           : reinterpret_cast<const void *>(&stream_probe_kernel<true>);
-    const unsigned block = wide ? 512u : unsigned(kBlock);
+    const unsigned block = narrow ? unsigned(kNarrowBlock) : unsigned(kBlock);
     hipEvent_t e0 = nullptr, e1 = nullptr;
     e = hipEventCreate(&e0);
     if (e == hipSuccess)

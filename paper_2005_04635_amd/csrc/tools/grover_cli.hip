@@ -48,7 +48,7 @@ int usage()
             "                      [--shots S] [--shot-seed U] [--steps T] [--calibrate-copy BYTES]\n"
             "                      [--calibrate-stream BYTES] [--update f64|f32]\n"
             "       grover_cli copy --bytes B [--reps R]\n"
-            "       grover_cli stream --bytes B [--passes P] [--read-only | --write-only] [--launch-per-pass] [--wide]\n"
+            "       grover_cli stream --bytes B [--passes P] [--read-only | --write-only] [--launch-per-pass] [--narrow]\n"
             "       grover_cli batch --instances FILE [--split S --team T [--resident V] | --tune] [--graph] [--runs R]\n"
             "                        [--update f64|f32]\n"
             "       grover_cli phase --schedules FILE [--every S] [--team T] [--form auto|streamed|held] "
@@ -133,8 +133,8 @@ int run_stream(int argc, char **argv)
             mode |= GROVER_PROBE_LAUNCH_PER_PASS;
         else if (!strcmp(argv[i], "--write-only"))
             mode |= GROVER_PROBE_WRITE_ONLY;
-        else if (!strcmp(argv[i], "--wide"))
-            mode |= GROVER_PROBE_WIDE;
+        else if (!strcmp(argv[i], "--narrow"))
+            mode |= GROVER_PROBE_NARROW;
         else
             return usage();
     }

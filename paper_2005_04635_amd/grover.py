@@ -321,7 +321,7 @@ def grover_iterate_static(hip_stream: int, state_dev: int, n: int, dtype: int, m
                                               k, status_dev or None))
 
 
-GROVER_PROBE_READ_ONLY, GROVER_PROBE_LAUNCH_PER_PASS, GROVER_PROBE_WRITE_ONLY, GROVER_PROBE_WIDE = 1, 2, 4, 8
+GROVER_PROBE_READ_ONLY, GROVER_PROBE_LAUNCH_PER_PASS, GROVER_PROBE_WRITE_ONLY, GROVER_PROBE_NARROW = 1, 2, 4, 8
 
 
 def grover_stream_probe(hip_stream: int, buf_dev: int, nbytes: int, passes: int, mode: int = 0) -> float:

@@ -312,3 +312,13 @@ def test_phase_init_rejects_bad_marks_and_nulls(lib):
     assert lib.grover_phase_set_team(None, 1) == -1
     assert lib.grover_phase_last_error(None) == b"no phase context"
     lib.grover_phase_destroy(None)
+
+
+def test_stream_probe_rejects_bad_arguments_before_touching_the_device(lib):
+    ms = ctypes.c_float()
+    assert lib.grover_stream_probe(None, None, 256, 1, 0, ctypes.byref(ms)) == -1
+    assert lib.grover_stream_probe(None, ctypes.c_void_p(0x1004), 256, 1, 0, ctypes.byref(ms)) == -1
+    assert lib.grover_stream_probe(None, ctypes.c_void_p(0x1000), 8, 1, 0, ctypes.byref(ms)) == -1
+    assert lib.grover_stream_probe(None, ctypes.c_void_p(0x1000), 256, 1, 32, ctypes.byref(ms)) == -1
+    assert lib.grover_stream_probe(None, ctypes.c_void_p(0x1000), 256, 1, 5, ctypes.byref(ms)) == -1
+    assert lib.grover_stream_probe(None, ctypes.c_void_p(0x1000), 256, 1, 0, None) == -1

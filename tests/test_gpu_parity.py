@@ -141,16 +141,17 @@ def test_iterate_composes_bitwise(G, form, n):
 
 
 def test_fused_grid_shapes(G, orc, monkeypatch):
-    """Forced persistent-grid sizes over the 8 tiles of an n = 15 complex128 state: a single workgroup
-    (8 tiles: 5 streamed, 2 held in LDS, 1 in registers), 2 and 3 workgroups (4 tiles; 3, 3 and 2 tiles —
-    held tiles with none or one streamed before them), a prime count (ragged shares) and more workgroups
-    than tiles (empty shares); sparse marks and marks too many for a tile's registers."""
-    n, dtype = 15, "c128"
+    """Forced persistent-grid sizes over the 16 tiles of an n = 16 complex128 state (each workgroup holds
+    its last 6 tiles on chip, 2 in LDS and then 4 in registers): a single workgroup (10 tiles streamed
+    before the held ones), 2 workgroups (8 tiles: 2 streamed), 3 (6, 5 and 5 tiles: none streamed, 2 or 1
+    in LDS), 4 (4 tiles: registers only), 7 (3 and 2 tiles), a prime count (ragged shares) and more
+    workgroups than tiles (empty shares); sparse marks and marks too many for a tile's registers."""
+    n, dtype = 16, "c128"
     psi0 = start_state(n, dtype, seed=8)
     for m in [6, (1 << n) // 3]:
         marks = workloads.distinct_marks(n, m, seed=8)
         want = orc.iterate(as_c128(psi0), marks, 9)
-        for grid in ["1", "2", "3", "7", "97", "250"]:
+        for grid in ["1", "2", "3", "4", "7", "97", "250"]:
             monkeypatch.setenv("GROVER_FUSED_GRID", grid)
             g = G.Grover(n, dtype, marks=marks, form="fused")
             assert g.query(1) == int(grid)
@@ -163,7 +164,7 @@ def test_fused_access_form(G, orc, monkeypatch):
     """Up to 272 MiB of the state per pass streams with ordinary loads and stores (kept in the memory-side
     cache across iterations): the whole of a state that small, else the leading tiles of each workgroup's
     share, the rest with nontemporal accesses.  Every form gives the same results bit for bit: n = 24
-    complex64 (8 tiles per workgroup, 5 streamed) all ordinary, all nontemporal and against the oracle;
+    complex64 (8 tiles per workgroup, 2 streamed) all ordinary, all nontemporal and against the oracle;
     n = 26 complex64 (32 tiles per workgroup) split against all nontemporal."""
     budget = 272 << 20
     for n, dtype in [(16, "c64"), (24, "c128"), (25, "c64"), (25, "c128"), (26, "c64")]:
