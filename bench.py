@@ -217,7 +217,7 @@ def cpu_baseline_all_cores(w, iters, single):
     time.  Returned as the baseline, with the single-thread figure beside it."""
     import subprocess
 
-    procs = min(os.cpu_count() or 1, 16)  # the GPU box grants 16 host cores per GPU
+    procs = min(os.cpu_count() or 1, 16)  # at most 16: one GPU's share of a shared host
     cmd = [sys.executable, os.path.abspath(__file__), "--cpu-worker", str(iters)]
     children = [subprocess.Popen(cmd, stdout=subprocess.PIPE, text=True) for _ in range(procs)]
     times = []
