@@ -208,7 +208,7 @@ int grover_query(grover_ctx *ctx, int key, int64_t *value);
  * iteration (Algorithm 5's loop as one streaming pass per iteration) is measured against.  It runs the
  * fused kernel's streaming skeleton without its arithmetic over a caller-owned device buffer: the same
  * persistent grid (one 512-thread workgroup per CU), 64 KiB tiles each owned by one workgroup in every
- * pass, eight nontemporal 16-byte loads and stores per thread and tile.  Each pass negates every 16-byte vector in place (a read and a
+ * pass, eight nontemporal 16-byte buffer loads and stores per thread and tile (as for a complex64 state).  Each pass negates every 16-byte vector in place (a read and a
  * write of `bytes`), or, with GROVER_PROBE_READ_ONLY in `mode`, only reads it, or, with
  * GROVER_PROBE_WRITE_ONLY, only writes it (the pass number as values; not with READ_ONLY).  The `passes` passes run in
  * one launch (the workgroups move through them freely), or with GROVER_PROBE_LAUNCH_PER_PASS one launch

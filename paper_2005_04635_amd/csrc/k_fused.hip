@@ -40,6 +40,9 @@ struct Shape {
     static constexpr int block = T::EPV == 4 ? 1024 : 512;  // threads per workgroup
     static constexpr int unroll = kTile / block;             // 16-byte vectors per thread per tile
     static constexpr int reg_tiles = T::EPV == 4 ? 1 : 4;    // held tiles in registers (32 VGPRs each)
+    // Nontemporal stores: nt sc1 streamed binary64 and complex128 states 1.6-1.9 % faster than nt alone on
+    // MI355X (n = 26, 27), nt alone complex64 and complex bfloat16 states 0.4-1.6 % faster (n = 26-28).
+    static constexpr int store_nt = T::kBytes == 16 || !T::kComplex ? kBufNTDevice : kBufNT;
 };
 
 struct FusedArgs {
@@ -256,21 +259,43 @@ __device__ __forceinline__ void update_one(typename T::vec &v, double mr, double
         update_vec<T>(v, mr, mi, bits, acc);
 }
 
+// The state is accessed through one buffer resource per tile: vectors [v0, v0 + kTile) cut at nvec, each
+// thread's u-th vector at byte offset (u B + tid) 16, the same for every tile.  NT: loads nt, stores
+// Shape<T>::store_nt; otherwise ordinary.  (One resource over the whole state, with the tile's byte offset
+// added to every lane's, made the kernel 0.2-2.3 % slower on MI355X at n = 26-28.)
+template <class V>
+__device__ inline __amdgpu_buffer_rsrc_t tile_rsrc(void *state, uint64_t nvec, uint64_t v0)
+{
+    const uint64_t n = nvec - v0 < uint64_t(kTile) ? nvec - v0 : uint64_t(kTile);
+    return buffer_rsrc(static_cast<V *>(state) + v0, uint32_t(n * 16u));
+}
+template <int B>
+__device__ inline uint32_t lane_off(int u, unsigned tid)
+{
+    return (uint32_t(u) * uint32_t(B) + tid) * 16u;
+}
+template <bool NT>
+constexpr int load_policy() { return NT ? kBufNT : kBufPlain; }
+template <class T, bool NT>
+constexpr int store_policy() { return NT ? Shape<T>::store_nt : kBufPlain; }
+
 // A full tile without marked amplitudes: every sign is +1.  NT selects the nontemporal loads and stores.
 template <class T, class A, bool UPDATE, bool NT, bool U32>
-__device__ __forceinline__ void plain_tile(typename T::vec *st, uint64_t v0, unsigned tid, double mr, double mi,
-                                           float mr32, float mi32, A &acc)
+__device__ __forceinline__ void plain_tile(void *state, uint64_t nvec, uint64_t v0, unsigned tid, double mr,
+                                           double mi, float mr32, float mi32, A &acc)
 {
     constexpr int B = Shape<T>::block, U = Shape<T>::unroll;
-    typename T::vec x[U];
+    using V = typename T::vec;
+    const auto rs = tile_rsrc<V>(state, nvec, v0);
+    V x[U];
 #pragma unroll
     for (int u = 0; u < U; ++u)
-        x[u] = load16<NT>(st + v0 + u * B + tid);
+        x[u] = bload16<load_policy<NT>(), V>(rs, lane_off<B>(u, tid));
 #pragma unroll
     for (int u = 0; u < U; ++u) {
         if (UPDATE) {
             update_one<T, U32>(x[u], mr, mi, mr32, mi32, 0u, acc);
-            store16<NT>(x[u], st + v0 + u * B + tid);
+            bstore16<store_policy<T, NT>()>(x[u], rs, lane_off<B>(u, tid));
         } else {
             accum_vec<T>(x[u], 0u, acc);
         }
@@ -286,7 +311,6 @@ __device__ __forceinline__ void reg_tile(const FusedArgs &a, const uint32_t *slo
 {
     constexpr int B = Shape<T>::block, U = Shape<T>::unroll;
     using V = typename T::vec;
-    V *st = static_cast<V *>(a.state);
     const unsigned tid = threadIdx.x;
     const uint64_t t = blockIdx.x + j * gridDim.x;
     const uint64_t v0 = t * kTile;
@@ -304,11 +328,12 @@ __device__ __forceinline__ void reg_tile(const FusedArgs &a, const uint32_t *slo
             mk[q] = in_regs && mp + q < mq ? a.marks[mp + q] : ~uint64_t(0);
     }
     if (!UPDATE) {
+        const auto rs = tile_rsrc<V>(a.state, a.nvec, v0);
 #pragma unroll
         for (int u = 0; u < U; ++u) {
             const uint64_t v = v0 + u * B + tid;
             if (v < a.nvec)
-                r[u] = load16<true>(st + v);
+                r[u] = bload16<kBufNT, V>(rs, lane_off<B>(u, tid));
         }
     }
 #pragma unroll
@@ -335,7 +360,6 @@ __device__ __forceinline__ void chunk_pass(const FusedArgs &a, const uint32_t *s
     constexpr int B = Shape<T>::block, U = Shape<T>::unroll;
     using V = typename T::vec;
     const float mr32 = float(mr), mi32 = float(mi);  // the binary32 update's 2S/N (rounded to nearest even)
-    V *st = static_cast<V *>(a.state);
     const unsigned tid = threadIdx.x;
     const uint64_t ntiles = (a.nvec + kTile - 1) / kTile;
     const uint64_t cnt = blockIdx.x < ntiles ? (ntiles - blockIdx.x + gridDim.x - 1) / gridDim.x : 0;
@@ -347,9 +371,9 @@ __device__ __forceinline__ void chunk_pass(const FusedArgs &a, const uint32_t *s
         const bool full = v0 + kTile <= a.nvec;
         const bool marked = table ? ((slow_tiles[j >> 5] >> (j & 31)) & 1u) != 0u : a.m > 0;
         if (full && !marked && (!NT || j < a.temporal_tiles)) {
-            plain_tile<T, A, UPDATE, false, U32>(st, v0, tid, mr, mi, mr32, mi32, acc);
+            plain_tile<T, A, UPDATE, false, U32>(a.state, a.nvec, v0, tid, mr, mi, mr32, mi32, acc);
         } else if (full && !marked) {
-            plain_tile<T, A, UPDATE, true, U32>(st, v0, tid, mr, mi, mr32, mi32, acc);
+            plain_tile<T, A, UPDATE, true, U32>(a.state, a.nvec, v0, tid, mr, mi, mr32, mi32, acc);
         } else {
             // Ragged tail of the state, or a tile that may hold marked amplitudes: the same vector loads,
             // then each amplitude's sign from the tile's slice [mp, mq) of the sorted marked list.
@@ -360,12 +384,13 @@ __device__ __forceinline__ void chunk_pass(const FusedArgs &a, const uint32_t *s
 #pragma unroll
             for (int q = 0; q < kTileMarks; ++q)
                 mk[q] = in_regs && mp + q < mq ? a.marks[mp + q] : ~uint64_t(0);
+            const auto rs = tile_rsrc<V>(a.state, a.nvec, v0);
             V x[U];
 #pragma unroll
             for (int u = 0; u < U; ++u) {
                 const uint64_t v = v0 + u * B + tid;
                 if (v < a.nvec)
-                    x[u] = load16<NT>(st + v);
+                    x[u] = bload16<load_policy<NT>(), V>(rs, lane_off<B>(u, tid));
             }
 #pragma unroll
             for (int u = 0; u < U; ++u) {
@@ -375,7 +400,7 @@ __device__ __forceinline__ void chunk_pass(const FusedArgs &a, const uint32_t *s
                                                   : marked_bits<T::EPV>(a.marks, mp, mq, v * T::EPV);
                     if (UPDATE) {
                         update_one<T, U32>(x[u], mr, mi, mr32, mi32, bits, acc);
-                        store16<NT>(x[u], st + v);
+                        bstore16<store_policy<T, NT>()>(x[u], rs, lane_off<B>(u, tid));
                     } else {
                         accum_vec<T>(x[u], bits, acc);
                     }
@@ -404,6 +429,7 @@ __device__ __forceinline__ void chunk_pass(const FusedArgs &a, const uint32_t *s
             for (int q = 0; q < kTileMarks; ++q)
                 mk[q] = in_regs && mp + q < mq ? a.marks[mp + q] : ~uint64_t(0);
         }
+        const auto rs = tile_rsrc<V>(a.state, a.nvec, v0);
         V x[U];
 #pragma unroll
         for (int u = 0; u < U; ++u) {
@@ -412,7 +438,7 @@ __device__ __forceinline__ void chunk_pass(const FusedArgs &a, const uint32_t *s
                 if (UPDATE) {
                     x[u] = hv[u * B + tid];
                 } else {
-                    x[u] = load16<true>(st + v);
+                    x[u] = bload16<kBufNT, V>(rs, lane_off<B>(u, tid));
                     hv[u * B + tid] = x[u];
                 }
             }
@@ -495,15 +521,15 @@ __global__ __launch_bounds__(Shape<T>::block) void fused_iterate_kernel(FusedArg
     }
     if (a.iters > 0) {  // the held tiles go back to memory
         using V = typename T::vec;
-        V *st = static_cast<V *>(a.state);
         for (uint64_t j = held_start<T>(cnt); j < reg_start<T>(cnt); ++j) {
             const V *hv = held + (j - held_start<T>(cnt)) * kTile;
             const uint64_t v0 = (blockIdx.x + j * gridDim.x) * kTile;
+            const auto rs = tile_rsrc<V>(a.state, a.nvec, v0);
 #pragma unroll
             for (int u = 0; u < U; ++u) {
                 const uint64_t v = v0 + u * B + threadIdx.x;
                 if (v < a.nvec)
-                    store16<true>(hv[u * B + threadIdx.x], st + v);
+                    bstore16<Shape<T>::store_nt>(hv[u * B + threadIdx.x], rs, lane_off<B>(u, threadIdx.x));
             }
         }
 #pragma unroll
@@ -511,11 +537,12 @@ __global__ __launch_bounds__(Shape<T>::block) void fused_iterate_kernel(FusedArg
             const uint64_t j = reg_start<T>(cnt) + uint64_t(r);
             if (j < cnt) {
                 const uint64_t v0 = (blockIdx.x + j * gridDim.x) * kTile;
+                const auto rs = tile_rsrc<V>(a.state, a.nvec, v0);
 #pragma unroll
                 for (int u = 0; u < U; ++u) {
                     const uint64_t v = v0 + u * B + threadIdx.x;
                     if (v < a.nvec)
-                        store16<true>(rt[r][u], st + v);
+                        bstore16<Shape<T>::store_nt>(rt[r][u], rs, lane_off<B>(u, threadIdx.x));
                 }
             }
         }

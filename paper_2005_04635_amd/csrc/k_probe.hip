@@ -1,15 +1,16 @@
 // Measured bandwidth ceiling of the fused iteration's memory access pattern (a measurement helper, not a
 // step of the paper's method).  The probe runs the fused kernel's streaming skeleton with the arithmetic
 // taken out: the same persistent grid (one 512-thread workgroup per CU), the same tiles (eight 16-byte
-// vectors per thread, tile t owned by workgroup t mod G for every pass) and the same nontemporal loads and
-// stores, each element negated in place (read + write), or only read; full tiles take the same unchecked
-// path as the fused kernel's (per-vector bounds checks on every tile cost the stream 6 %, 5.40 against 5.73
-// TB/s in place on MI355X).  The narrow form moves the same tiles with 1024 threads of four vectors each,
-// the shape the fused kernel had before (5.66 against 5.77 TB/s in place).  In one launch the workgroups run
-// through the passes freely; with one launch per pass, every pass starts only when the previous one has
-// ended everywhere, as the fused kernel's grid barrier makes every iteration do, so that the whole grid
-// streams one window of the buffer at a time.  What it reaches is what an in-place streaming pass of this
-// shape can reach on the device; the fused kernel's own rate is then read against it.
+// vectors per thread, tile t owned by workgroup t mod G for every pass) and the same nontemporal buffer
+// loads and stores as for a complex64 state (one descriptor per tile, nt on both), each element negated in
+// place (read + write), or only read, or only written.  Full tiles take the same unchecked path as the
+// fused kernel's (per-vector bounds checks on every tile cost the stream 6 %, 5.40 against 5.73 TB/s in
+// place on MI355X).  The narrow form moves the same tiles with 1024 threads of four vectors each, the shape
+// the fused kernel keeps for complex bfloat16.  In one launch the workgroups run through the passes freely;
+// with one launch per pass, every pass starts only when the previous one has ended everywhere, as the fused
+// kernel's grid barrier makes every iteration do, so that the whole grid streams one window of the buffer
+// at a time.  What it reaches is what an in-place streaming pass of this shape can reach on the device; the
+// fused kernel's own rate is then read against it.
 #include "internal.h"
 
 namespace grover {
@@ -31,15 +32,16 @@ __global__ __launch_bounds__(B) void stream_probe_kernel(float4 *st, uint64_t nv
     const uint64_t ntiles = (nvec + kTile - 1) / kTile;
     const unsigned tid = threadIdx.x;
     uint32_t acc = 0u;
-    auto visit = [&](float4 (&x)[kUnroll], uint64_t v, int u) {
+    // w: the vector's index within its tile
+    auto visit = [&](float4 (&x)[kUnroll], __amdgpu_buffer_rsrc_t rs, uint32_t w, int u) {
         if (!READ) {
-            store16<true>(x[u], st + v);
+            bstore16<kBufNT>(x[u], rs, w * 16u);
         } else if (WRITE) {
             x[u].x = -x[u].x;
             x[u].y = -x[u].y;
             x[u].z = -x[u].z;
             x[u].w = -x[u].w;
-            store16<true>(x[u], st + v);
+            bstore16<kBufNT>(x[u], rs, w * 16u);
         } else {
             acc ^= __float_as_uint(x[u].x) ^ __float_as_uint(x[u].y) ^ __float_as_uint(x[u].z) ^
                    __float_as_uint(x[u].w);
@@ -48,28 +50,31 @@ __global__ __launch_bounds__(B) void stream_probe_kernel(float4 *st, uint64_t nv
     for (uint32_t p = 0; p < passes; ++p) {
         for (uint64_t t = blockIdx.x; t < ntiles; t += gridDim.x) {
             const uint64_t v0 = t * kTile;
+            const uint64_t n = nvec - v0 < uint64_t(kTile) ? nvec - v0 : uint64_t(kTile);
+            const auto rs = buffer_rsrc(st + v0, uint32_t(n * 16u));
             float4 x[kUnroll];
-            if (v0 + kTile <= nvec) {
+            if (n == uint64_t(kTile)) {
                 // a full tile, like the fused kernel's: no bounds checks
 #pragma unroll
                 for (int u = 0; u < kUnroll; ++u)
-                    x[u] = READ ? load16<true>(st + v0 + uint64_t(u) * kBlock + tid)
+                    x[u] = READ ? bload16<kBufNT, float4>(rs, (uint32_t(u) * kBlock + tid) * 16u)
                                 : make_float4(float(p), 0.0f, float(p), 0.0f);
 #pragma unroll
                 for (int u = 0; u < kUnroll; ++u)
-                    visit(x, v0 + uint64_t(u) * kBlock + tid, u);
+                    visit(x, rs, uint32_t(u) * kBlock + tid, u);
             } else {
 #pragma unroll
                 for (int u = 0; u < kUnroll; ++u) {
-                    const uint64_t v = v0 + uint64_t(u) * kBlock + tid;
-                    if (v < nvec)
-                        x[u] = READ ? load16<true>(st + v) : make_float4(float(p), 0.0f, float(p), 0.0f);
+                    const uint32_t w = uint32_t(u) * kBlock + tid;
+                    if (w < n)
+                        x[u] = READ ? bload16<kBufNT, float4>(rs, w * 16u)
+                                    : make_float4(float(p), 0.0f, float(p), 0.0f);
                 }
 #pragma unroll
                 for (int u = 0; u < kUnroll; ++u) {
-                    const uint64_t v = v0 + uint64_t(u) * kBlock + tid;
-                    if (v < nvec)
-                        visit(x, v, u);
+                    const uint32_t w = uint32_t(u) * kBlock + tid;
+                    if (w < n)
+                        visit(x, rs, w, u);
                 }
             }
         }

@@ -272,6 +272,24 @@ def test_n28_two_pass_form(G, orc, dtype):
     g.close()
 
 
+def test_n28_fused_complex128(G, orc):
+    """The fused kernel on the largest state of these tests, 2^28 16-byte vectors (complex128, 4 GiB: byte
+    addresses beyond 2^32, each tile through its own buffer resource): five iterations from the uniform
+    state against the oracle's two-class values, each class bitwise constant, so an amplitude the kernel
+    skipped or misplaced would show."""
+    w = workloads.HASH_N28
+    g = G.Grover(w.n, "c128", hash_seed=w.hash_seed, hash_bits=w.hash_bits, m=w.m, form="fused")
+    assert g.query(0) == 1
+    marks = g.marked()
+    g.iterate(5)
+    got = g.read_state()
+    mask = np.zeros(1 << w.n, dtype=bool)
+    mask[marks.astype(np.int64)] = True
+    a, b = orc.two_class(w.n, w.m, 5)
+    two_class_check(got, mask, a, b, 1e-12)
+    g.close()
+
+
 def test_n28_single_qubit_gate_iteration(G, orc):
     """The per-qubit gate path at n = 28 (58 passes, each thread over 128 butterfly pairs): one conventional
     iteration from the uniform state against the oracle's two-class values.  Rounding in the passes depends
