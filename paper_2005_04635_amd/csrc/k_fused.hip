@@ -28,10 +28,11 @@ namespace {
 
 // Tiles of 4096 16-byte vectors (64 KiB), moved by one persistent workgroup per CU in one of two shapes.
 // 512 threads of 8 vectors each (two waves per SIMD, so a thread may hold up to 256 VGPRs): on MI355X this
-// shape streams a 2 GiB in-place pass at 5.77 TB/s against 5.66 for 1024 threads of 4 vectors, and its
-// registers hold 4 tiles where the 1024-thread shape (128 VGPRs a thread) holds one; n = 28 complex64,
-// 27 complex128 and 27 binary64 searches ran 4.3-4.8 % faster with it.  Complex bfloat16, whose conversions
-// make it the most arithmetic per byte, keeps 1024 threads (the 512-thread shape ran 9 % slower at n = 27).
+// shape streamed a 2 GiB in-place pass at 5.77 TB/s against 5.66 for 1024 threads of 4 vectors (global
+// instructions; 5.82 against 5.76 with the buffer instructions used now), and its registers hold 4 tiles
+// where the 1024-thread shape (128 VGPRs a thread) holds one; n = 28 complex64, 27 complex128 and 27
+// binary64 searches ran 4.3-4.8 % faster with it.  Complex bfloat16, whose conversions make it the most
+// arithmetic per byte, keeps 1024 threads (the 512-thread shape ran 9 % slower at n = 27).
 constexpr int kTile = 4096;
 constexpr int kMaxBlock = 1024;
 
@@ -39,7 +40,7 @@ template <class T>
 struct Shape {
     static constexpr int block = T::EPV == 4 ? 1024 : 512;  // threads per workgroup
     static constexpr int unroll = kTile / block;             // 16-byte vectors per thread per tile
-    static constexpr int reg_tiles = T::EPV == 4 ? 1 : 4;    // held tiles in registers (32 VGPRs each)
+    static constexpr int reg_tiles = T::EPV == 4 ? 1 : 4;    // held tiles in registers (4 VGPRs per vector)
     // Nontemporal stores: nt sc1 streamed binary64 and complex128 states 1.6-1.9 % faster than nt alone on
     // MI355X (n = 26, 27), nt alone complex64 and complex bfloat16 states 0.4-1.6 % faster (n = 26-28).
     static constexpr int store_nt = T::kBytes == 16 || !T::kComplex ? kBufNTDevice : kBufNT;
