@@ -106,6 +106,36 @@ def test_large_index_range(G, orc):
     g.close()
 
 
+@pytest.mark.parametrize("n,dtype", [(34, "c64"), (33, "c128")])
+def test_maximum_size(G, orc, n, dtype):
+    """The largest states the library accepts: n = 34 (2^34 complex64 amplitudes) and complex128 at n = 33,
+    128 GiB each on one GPU, byte addresses up to 2^37.  Marks at both ends of the index range; three fused
+    iterations from the uniform state against the oracle's two-class values, every amplitude checked on the
+    device (each class bitwise constant)."""
+    import torch
+
+    N = 1 << n
+    marks = np.array([0, 5, N - 2, N - 1], dtype=np.uint64)
+    g = G.Grover(n, dtype, marks=marks, form="fused")
+    assert g.query(0) == 1
+    g.iterate(3)
+    torch.cuda.synchronize()
+    st = g.state
+    a, b = orc.two_class(n, marks.size, 3)
+    tol = 1e-5 if dtype == "c64" else 1e-12
+    idx = torch.from_numpy(marks.astype(np.int64)).cuda()
+    marked_vals = st[idx]
+    assert torch.all(marked_vals == marked_vals[0]).item()
+    assert abs(complex(marked_vals[0].item()) - a) <= tol
+    ref = st[1]
+    assert abs(complex(ref.item()) - b) <= tol
+    assert torch.all(st[1:5] == ref).item() and torch.all(st[6:N - 2] == ref).item()
+    assert abs(g.norm() - 1.0) < 1e-5
+    g.close()
+    del g, st, marked_vals, ref
+    torch.cuda.empty_cache()  # the 128 GiB state goes back to the device before the next case
+
+
 @pytest.mark.parametrize("storage,accum", [(s, a) for s in ("c128", "c64", "cbf16")
                                            for a in ("f64", "f32", "f32_kahan")])
 def test_n26_precision_sweep(G, orc, storage, accum):
