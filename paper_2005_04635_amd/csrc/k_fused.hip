@@ -105,10 +105,47 @@ __device__ inline bool wait_pair(const uint64_t *w, uint32_t tag, const FusedArg
     }
 }
 
+// Bounded wait until the pairs of up to four slots, w[i * stride .. i * stride + 3] for i < cnt, carry
+// generation `tag`: the loads of every slot not yet seen are issued together, so that the wait costs about
+// one memory round trip instead of one per slot.  Gives up as wait_pair does.
+__device__ inline bool wait_pairs4(const uint64_t *w, uint64_t stride, unsigned cnt, uint32_t tag,
+                                   const FusedArgs &a, double (&x)[4], double (&y)[4])
+{
+    const uint64_t t0 = wall_clock64();
+    const unsigned all = (1u << cnt) - 1u;
+    unsigned done = 0u;  // bit i: slot i seen
+    for (;;) {
+#pragma unroll
+        for (unsigned i = 0; i < 4u; ++i) {
+            if (i < cnt && ((done >> i) & 1u) == 0u) {
+                const uint64_t *s = w + uint64_t(i) * stride;
+                const uint64_t h0 = __hip_atomic_load(s, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                const uint64_t l0 = __hip_atomic_load(s + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                const uint64_t h1 = __hip_atomic_load(s + 2, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                const uint64_t l1 = __hip_atomic_load(s + 3, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                if (uint32_t(h0) == tag && uint32_t(l0) == tag && uint32_t(h1) == tag && uint32_t(l1) == tag) {
+                    x[i] = __longlong_as_double((long long)((h0 & 0xFFFFFFFF00000000ull) | (l0 >> 32)));
+                    y[i] = __longlong_as_double((long long)((h1 & 0xFFFFFFFF00000000ull) | (l1 >> 32)));
+                    done |= 1u << i;
+                }
+            }
+        }
+        if (done == all)
+            return true;
+        if (__hip_atomic_load(&a.sync->error, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0u)
+            return false;
+        if (uint64_t(wall_clock64()) - t0 > a.timeout_ticks) {
+            __hip_atomic_store(&a.sync->error, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            return false;
+        }
+        __builtin_amdgcn_s_sleep(1);
+    }
+}
+
 // Grid-wide sum of (xr, xi) at generation `gen`: every workgroup publishes its partial as tagged words in
 // its slot of the generation's parity; wave 0 gathers them (lane l waits for the slots of workgroups l,
-// l + 64, ... and adds them in that order; the lanes' values are then added by wave_total), so the sum is
-// reproducible run to run.  ALL: every workgroup gathers, and all of them compute the same bits in one
+// l + 64, ..., four of them at a time together, and adds them in that order; the lanes' values are then
+// added by wave_total), so the sum is reproducible run to run.  ALL: every workgroup gathers, and all of them compute the same bits in one
 // memory round trip.  Otherwise workgroup 0 gathers and publishes the sum as tagged words, which the other
 // workgroups poll: two round trips, but far fewer polls while other workgroups still stream (the form
 // for states too large for the memory-side cache).  A slot of parity p is rewritten two generations later:
@@ -147,11 +184,16 @@ __device__ __forceinline__ bool grid_sum(V &xr, V &xi, const FusedArgs &a, uint6
         if (wave == 0) {
             V pr = V(0), pi = V(0);
             bool ok = true;
-            for (unsigned w = lane; w < gridDim.x && ok; w += kWave) {
-                double x = 0.0, y = 0.0;
-                ok = wait_pair(slots + uint64_t(w) * 4u, tag, a, x, y);
-                pr += V(x);
-                pi += V(y);
+            for (unsigned g0 = 0; g0 < gridDim.x && ok; g0 += 4u * kWave) {
+                const unsigned first = g0 + lane;
+                const unsigned left = first < gridDim.x ? (gridDim.x - first + kWave - 1u) / kWave : 0u;
+                const unsigned cnt = left < 4u ? left : 4u;
+                double x[4], y[4];
+                ok = wait_pairs4(slots + uint64_t(first) * 4u, uint64_t(kWave) * 4u, cnt, tag, a, x, y);
+                for (unsigned i = 0; i < cnt && ok; ++i) {
+                    pr += V(x[i]);
+                    pi += V(y[i]);
+                }
             }
             pr = wave_total(pr);
             pi = wave_total(pi);
