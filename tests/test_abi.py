@@ -322,3 +322,14 @@ def test_stream_probe_rejects_bad_arguments_before_touching_the_device(lib):
     assert lib.grover_stream_probe(None, ctypes.c_void_p(0x1000), 256, 1, 32, ctypes.byref(ms)) == -1
     assert lib.grover_stream_probe(None, ctypes.c_void_p(0x1000), 256, 1, 5, ctypes.byref(ms)) == -1
     assert lib.grover_stream_probe(None, ctypes.c_void_p(0x1000), 256, 1, 0, None) == -1
+
+
+def test_bench_refuses_more_than_one_gpu():
+    """bench.py measures one GPU (a search's state is not sharded): --gpus above 1 exits with status 2 and
+    a message, before anything touches a device."""
+    import sys
+
+    r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"], capture_output=True,
+                       text=True, timeout=120)
+    assert r.returncode == 2
+    assert "one GPU" in (r.stdout + r.stderr)
