@@ -22,8 +22,12 @@ constexpr uint64_t kHashMarkCap = uint64_t(1) << 26;  // largest hash-defined ma
 
 // ------------------------------------------------------------------------------------ bfloat16 helpers
 // bfloat16 = the top 16 bits of an IEEE binary32.  Rounding from binary64 is done once, correctly: round
-// to odd into binary32 (truncate, then set the last bit when inexact), then round to nearest even into
-// bfloat16 — the intermediate has 16 more bits than the target, so no double rounding can occur.
+// to odd into binary32 (toward zero, then set the last bit when inexact), then round to nearest even into
+// bfloat16 — the intermediate has 16 more bits than the target, so no double rounding can occur.  The
+// rounding toward zero comes from the hardware's conversion to nearest: when that was inexact and moved
+// away from zero, the binary32 one step toward zero (its bit pattern minus one, as the magnitude bits are
+// contiguous; from infinity this gives the largest finite value) is the truncation.  About nine
+// instructions where the library's round-toward-zero conversion takes some twenty-five.
 __device__ __host__ inline float bf16_to_float(uint16_t b)
 {
     const uint32_t u = uint32_t(b) << 16;
@@ -34,10 +38,14 @@ __device__ __host__ inline float bf16_to_float(uint16_t b)
 
 __device__ inline uint16_t double_to_bf16(double d)
 {
-    const float t = __double2float_rz(d);
+    const float t = float(d);  // nearest
     uint32_t u = __float_as_uint(t);
-    if (double(t) != d)
-        u |= 1u;
+    const double dt = double(t);
+    if (dt != d) {
+        if (__builtin_fabs(dt) > __builtin_fabs(d))
+            u -= 1u;  // t rounded away from zero: step back to the truncation
+        u |= 1u;      // round to odd
+    }
     u += 0x7FFFu + ((u >> 16) & 1u);
     return uint16_t(u >> 16);
 }

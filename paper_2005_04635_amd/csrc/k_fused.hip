@@ -32,7 +32,8 @@ namespace {
 // instructions; 5.82 against 5.76 with the buffer instructions used now), and its registers hold 4 tiles
 // where the 1024-thread shape (128 VGPRs a thread) holds one; n = 28 complex64, 27 complex128 and 27
 // binary64 searches ran 4.3-4.8 % faster with it.  Complex bfloat16, whose conversions make it the most
-// arithmetic per byte, keeps 1024 threads (the 512-thread shape ran 9 % slower at n = 27).
+// arithmetic per byte, keeps 1024 threads (the 512-thread shape, with three register tiles, ran 1-8 %
+// slower at n = 25-27 and 0.6 % faster at n = 28).
 constexpr int kTile = 4096;
 constexpr int kMaxBlock = 1024;
 
