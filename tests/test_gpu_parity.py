@@ -202,6 +202,34 @@ def test_fused_access_form(G, orc, monkeypatch):
     assert np.array_equal(a.view(np.uint32), b.view(np.uint32))
 
 
+@pytest.mark.parametrize("n,dtype", [(24, "f64"), (23, "c128"), (24, "c64"), (25, "cbf16")])
+def test_fused_nontemporal_stores(G, orc, monkeypatch, n, dtype):
+    """128 MiB states, large enough that each workgroup streams tiles besides the six (bfloat16: three) it
+    holds on chip, in the kernel variant that streams every tile with nontemporal loads and stores (each
+    storage type's own store bits: nt sc1 for binary64 and complex128, nt for complex64 and bfloat16):
+    bit for bit the results of ordinary accesses, and for the binary64-sum types within tolerance of the
+    oracle."""
+    psi0 = workloads.random_state(n, 500 + n, real=(dtype == "f64"))
+    if dtype == "f64":
+        psi0 = psi0.real.astype(np.float64)
+    elif dtype != "cbf16":
+        psi0 = psi0.astype(np.complex64 if dtype == "c64" else np.complex128)
+    marks = workloads.distinct_marks(n, 5, seed=n)
+    out = {}
+    for forced in ("0", "1"):
+        monkeypatch.setenv("GROVER_FUSED_TEMPORAL", forced)
+        g = G.Grover(n, dtype, marks=marks, form="fused")
+        state = (1 << n) * g.query(G.grover.Q_ELEM_BYTES)
+        assert g.query(G.grover.Q_FUSED_TEMPORAL) == (state if forced == "1" else 0)
+        g.write_state(psi0).iterate(3).iterate(4)
+        out[forced] = g.read_state()
+        g.close()
+    monkeypatch.delenv("GROVER_FUSED_TEMPORAL", raising=False)
+    assert np.array_equal(out["0"].view(np.uint64), out["1"].view(np.uint64)), (n, dtype)
+    if dtype != "cbf16":
+        assert_close(out["0"], orc.iterate(as_c128(psi0), marks, 7), dtype, f"n={n} {dtype} nontemporal")
+
+
 # ----------------------------------------------------------------------------------- hash oracle
 @pytest.mark.parametrize("form", ["held", "fused"])
 def test_hash_predicate_marks_match_oracle(G, orc, form):
