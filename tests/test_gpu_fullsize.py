@@ -84,7 +84,8 @@ def test_n28_hash_workload(G, orc):
 
 def test_large_index_range(G, orc):
     """n = 31 (2^31 complex64 amplitudes, 16 GiB): indices past 2^31 and marks at the very end of the
-    state; three iterations against the oracle's two-class values."""
+    state; three iterations against the oracle's two-class values, then measurement shots against the
+    sampler's definition evaluated exactly."""
     import torch
 
     n = 31
@@ -103,6 +104,35 @@ def test_large_index_range(G, orc):
     assert torch.all(unmarked == st[0]).item() and torch.all(st[:5] == st[0]).item()
     assert abs(complex(st[0].item()) - b) <= 1e-5
     assert abs(g.norm() - 1.0) < 1e-5
+
+    # Measurement over the whole index range (a 16 GiB integer CDF, indices past 2^31): 10^5 shots from
+    # given 53-bit uniforms, each equal to the sampler's definition evaluated exactly for this two-class
+    # state: p = re^2 + im^2 in binary64, q = floor(p 2^62), t = floor(U Q_total / 2^53), index = the
+    # smallest i with Q_i > t, where Q_i counts the unmarked and marked indices up to i.
+    def q_of(z: complex) -> int:
+        return int((z.real * z.real + z.imag * z.imag) * 2.0 ** 62)
+
+    qa, qb = q_of(complex(marked_vals[0].item())), q_of(complex(st[0].item()))
+    ms = sorted(int(x) for x in marks)
+    total = (N - len(ms)) * qb + len(ms) * qa
+
+    def index_of(t: int) -> int:
+        acc, p = 0, 0
+        for k in ms:
+            if qb > 0 and t < acc + (k - p) * qb:
+                return p + (t - acc) // qb
+            acc += (k - p) * qb
+            if t < acc + qa:
+                return k
+            acc += qa
+            p = k + 1
+        return p + (t - acc) // qb
+
+    u = workloads.uniforms_u53(31, 100000)
+    shots = g.sample(100000, u53=u)
+    want = np.array([index_of((int(x) * total) >> 53) for x in u], dtype=np.uint64)
+    assert np.array_equal(shots, want), int(np.sum(shots != want))
+    assert shots.max() > (1 << 30)  # the shots reach the upper half of the index range
     g.close()
 
 
