@@ -82,6 +82,36 @@ def test_n28_hash_workload(G, orc):
     g.close()
 
 
+def two_class_shots(g, marks, a: complex, b: complex, seed: int, shots: int = 100000):
+    """10^5 measurement shots of a two-class state (every marked amplitude a, every other b) from given
+    53-bit uniforms, and the sampler's definition evaluated exactly for that state with integers: p = re^2 +
+    im^2 in binary64, q = floor(p 2^62), t = floor(U Q_total / 2^53), index = the smallest i with Q_i > t,
+    where Q_i counts the unmarked and marked indices up to i."""
+    def q_of(z: complex) -> int:
+        return int((z.real * z.real + z.imag * z.imag) * 2.0 ** 62)
+
+    qa, qb = q_of(a), q_of(b)
+    ms = sorted(int(x) for x in marks)
+    total = (g.N - len(ms)) * qb + len(ms) * qa
+
+    def index_of(t: int) -> int:
+        acc, p = 0, 0
+        for k in ms:
+            if qb > 0 and t < acc + (k - p) * qb:
+                return p + (t - acc) // qb
+            acc += (k - p) * qb
+            if t < acc + qa:
+                return k
+            acc += qa
+            p = k + 1
+        return p + (t - acc) // qb
+
+    u = workloads.uniforms_u53(seed, shots)
+    got = g.sample(shots, u53=u)
+    want = np.array([index_of((int(x) * total) >> 53) for x in u], dtype=np.uint64)
+    return got, want
+
+
 def test_large_index_range(G, orc):
     """n = 31 (2^31 complex64 amplitudes, 16 GiB): indices past 2^31 and marks at the very end of the
     state; three iterations against the oracle's two-class values, then measurement shots against the
@@ -105,32 +135,8 @@ def test_large_index_range(G, orc):
     assert abs(complex(st[0].item()) - b) <= 1e-5
     assert abs(g.norm() - 1.0) < 1e-5
 
-    # Measurement over the whole index range (a 16 GiB integer CDF, indices past 2^31): 10^5 shots from
-    # given 53-bit uniforms, each equal to the sampler's definition evaluated exactly for this two-class
-    # state: p = re^2 + im^2 in binary64, q = floor(p 2^62), t = floor(U Q_total / 2^53), index = the
-    # smallest i with Q_i > t, where Q_i counts the unmarked and marked indices up to i.
-    def q_of(z: complex) -> int:
-        return int((z.real * z.real + z.imag * z.imag) * 2.0 ** 62)
-
-    qa, qb = q_of(complex(marked_vals[0].item())), q_of(complex(st[0].item()))
-    ms = sorted(int(x) for x in marks)
-    total = (N - len(ms)) * qb + len(ms) * qa
-
-    def index_of(t: int) -> int:
-        acc, p = 0, 0
-        for k in ms:
-            if qb > 0 and t < acc + (k - p) * qb:
-                return p + (t - acc) // qb
-            acc += (k - p) * qb
-            if t < acc + qa:
-                return k
-            acc += qa
-            p = k + 1
-        return p + (t - acc) // qb
-
-    u = workloads.uniforms_u53(31, 100000)
-    shots = g.sample(100000, u53=u)
-    want = np.array([index_of((int(x) * total) >> 53) for x in u], dtype=np.uint64)
+    # measurement over the whole index range (a 16 GiB integer CDF, indices past 2^31)
+    shots, want = two_class_shots(g, marks, complex(marked_vals[0].item()), complex(st[0].item()), seed=31)
     assert np.array_equal(shots, want), int(np.sum(shots != want))
     assert shots.max() > (1 << 30)  # the shots reach the upper half of the index range
     g.close()
@@ -141,7 +147,8 @@ def test_maximum_size(G, orc, n, dtype):
     """The largest states the library accepts: n = 34 (2^34 complex64 amplitudes) and complex128 at n = 33,
     128 GiB each on one GPU, byte addresses up to 2^37.  Marks at both ends of the index range; three fused
     iterations from the uniform state against the oracle's two-class values, every amplitude checked on the
-    device (each class bitwise constant)."""
+    device (each class bitwise constant); at n = 33 also measurement shots against the sampler's
+    definition evaluated exactly."""
     import torch
 
     if torch.cuda.get_device_properties(0).total_memory < (150 << 30):
@@ -163,6 +170,10 @@ def test_maximum_size(G, orc, n, dtype):
     assert abs(complex(ref.item()) - b) <= tol
     assert torch.all(st[1:5] == ref).item() and torch.all(st[6:N - 2] == ref).item()
     assert abs(g.norm() - 1.0) < 1e-5
+    if dtype == "c128":  # its 64 GiB integer CDF fits beside the state (complex64 at n = 34 would need 128 GiB)
+        shots, want = two_class_shots(g, marks, complex(marked_vals[0].item()), complex(ref.item()), seed=n)
+        assert np.array_equal(shots, want), int(np.sum(shots != want))
+        assert shots.max() > (1 << 32)  # indices past 2^32
     g.close()
     del g, st, marked_vals, ref
     torch.cuda.empty_cache()  # the 128 GiB state goes back to the device before the next case
