@@ -7,6 +7,7 @@ per Grover iteration at n = 28, against the plain binary64 form.
     python bench.py --sweep batch       (4096 independent searches: tilings, the tuned graph, one-by-one)
     python bench.py --sweep adjoint     (generalized iteration with phases: forward + adjoint gradient)
     python bench.py --sweep update      (element update in binary32 against binary64: on-chip forms, batch)
+    python bench.py --sweep scaling     (one full search per n = 14 ... 28: the N^(3/2) growth of a search)
 
 Workload (synthetic by construction; the paper uses no dataset): the single large instance, n = 28
 (2^28 complex64 amplitudes, 2 GiB), M = 8 marked indices defined by the hash predicate
@@ -310,6 +311,44 @@ def sweep_table1(pkg, hip, stream) -> None:
             conv, prop = PAPER_TABLE1_S[n]
             res["paper_i3_1thread_s"] = {"conventional": conv, "proposed": prop, "speedup": conv / prop}
             res["cpu_oracle_1thread_s"] = cpu_table1_times(n, mark, k)
+        pkg.grover_destroy(ctx)
+        print(json.dumps(res), flush=True)
+
+
+def sweep_scaling(pkg, hip, stream, runs: int) -> None:
+    """The paper's complexity statement on this GPU: each iteration is one O(N) pass and a single-solution
+    search takes floor(pi/4 sqrt(N)) of them, so a search costs O(N^(3/2)) and grows about 8x for two more
+    qubits (Table 1's own ratio from n = 18 to n = 20 is 20.005 / 2.579 = 7.76).  One full search per
+    n = 14 ... 28 (complex64, one solution, the form AUTO picks), the median of `runs` searches below n = 26
+    and one above; one JSON line per n, with the ratio to the search two qubits smaller."""
+    import workloads
+
+    by_n = {}
+    for n in range(14, 29):
+        mark = [workloads.marked_index_from_seed(n, 2000 + n)]
+        cfg, keep = make_config(pkg, n, "c64", marks=mark, form="auto")
+        ctx = pkg.grover_init(cfg, stream.value, 0, 0)
+        k = pkg.grover_optimal_iterations(n, 1)
+        pkg.grover_iterate(ctx, 1)  # warm
+        times = []
+        for _ in range(runs if n < 26 else 1):
+            pkg.grover_reset(ctx)
+            pkg.grover_sync(ctx)
+            e0, e1 = hip.event(), hip.event()
+            hip.lib.hipEventRecord(e0, stream)
+            pkg.grover_iterate(ctx, k)
+            hip.lib.hipEventRecord(e1, stream)
+            times.append(hip.elapsed_ms(e0, e1))
+            hip.destroy_events(e0, e1)
+            pkg.grover_sync(ctx)
+        ms = sorted(times)[len(times) // 2]
+        res = {"sweep": "scaling", "n": n, "iterations": k, "storage": "c64",
+               "form": ["", "fused", "resident", "two_pass", "held"][pkg.grover_query(ctx, 0)],
+               "search_ms": ms, "us_per_iteration": ms * 1e3 / k,
+               "ns_per_amplitude_iteration": ms * 1e6 / (k * (1 << n))}
+        if n - 2 in by_n:
+            res["ratio_to_n_minus_2"] = ms / by_n[n - 2]
+        by_n[n] = ms
         pkg.grover_destroy(ctx)
         print(json.dumps(res), flush=True)
 
@@ -712,7 +751,7 @@ def main() -> int:
     ap.add_argument("--cpu-all-iters", type=int, default=4,
                     help="iterations per process of the all-core CPU baseline (one oracle process per host core)")
     ap.add_argument("--cpu-worker", type=str, default=None, help=argparse.SUPPRESS)
-    ap.add_argument("--sweep", choices=["table1", "precision", "batch", "adjoint", "update"], default=None,
+    ap.add_argument("--sweep", choices=["table1", "precision", "batch", "adjoint", "update", "scaling"], default=None,
                     help="instead of the headline line, print one JSON line per point of a sweep")
     args = ap.parse_args()
     if args.cpu_worker:
@@ -754,6 +793,9 @@ def run(args, pkg, hip, stream) -> int:
         return 0
     if args.sweep == "update":
         sweep_update(pkg, hip, stream, max(args.steps, 3))
+        return 0
+    if args.sweep == "scaling":
+        sweep_scaling(pkg, hip, stream, max(args.steps, 3))
         return 0
     w = workloads.HASH_N28
     N = 1 << w.n
